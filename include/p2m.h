@@ -1,0 +1,182 @@
+/*
+ * p2m.h -- C ABI of libp2m.so: particle<->mesh assignment on periodic P1 meshes
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * Method: D. Duque and P. Espanol, "Assignment of fields from particles to mesh",
+ * arXiv 1610.05258.  Particle->mesh ("P2M") finds nodal values Abar_i from particle
+ * values A_mu; mesh->particle ("M2P") finds particle values from nodal ones
+ * (Sec. 2).  The methods are the rows of Table 1: delta (Sec. 2.2), FLIP and PIC
+ * (Sec. 2.3) and the "mass" assignment (Sec. 2.4).
+ *
+ * Integrals.  Every integral of the method is evaluated with the particle
+ * quadrature int f = sum_mu v_mu f(r_mu) that the paper uses for int A (Sec. 2.1)
+ * and for the FLIP volume (Sec. 2.3, eq. (12)).  The mass matrix of Sec. 2.4 is
+ * therefore M_ij = sum_mu v_mu psi_i(r_mu) psi_j(r_mu) and the mass assignment
+ * solves M Abar = b with b_i = sum_mu v_mu A_mu psi_i(r_mu).
+ *
+ * Mesh.  A problem is one periodic structured mesh: nx (1D) or nx*ny (2D) nodes
+ * on [0,lx) x [0,ly), node i (1D) at i*hx, node k = i + nx*j (2D) at (i*hx, j*hy),
+ * hx = lx/nx, hy = ly/ny.  Cells are indexed like their lower-left node.  In 2D
+ * every cell is split by its "/" diagonal (lower-left to upper-right) into two
+ * triangles; psi_i is the P1 hat of node i.
+ *
+ * Conventions shared by every entry point.
+ *  - All array arguments are DEVICE pointers, allocated and owned by the caller;
+ *    the library never frees them and never allocates device memory inside a
+ *    call.  Scratch memory is the caller's workspace (p2m_workspace_size).
+ *  - Layouts are structure-of-arrays; a field index is always the outer index:
+ *    values[f*np + mu], nodal[f*nnodes + k].
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*,
+ *    NULL = the null stream) and returns synchronously only argument and launch
+ *    errors.  Problems found in the data on the device are written as flags into
+ *    a p2m_report that lives in device memory.
+ *  - Indices are int32: np < 2^31 and nnodes < 2^31, else P2M_ERR_UNSUPPORTED.
+ *  - dtype selects FP32 or FP64 for positions, volumes, values and nodal arrays
+ *    of a call; all of them share it.
+ *  - A context must not be used from two host threads at once.
+ */
+#ifndef P2M_H
+#define P2M_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    P2M_OK = 0,
+    P2M_ERR_INVALID_ARG = 1,   /* NULL pointer, dim not 1/2, n < 2, F not in [1,8], bad enum */
+    P2M_ERR_UNSUPPORTED = 2,   /* sizes beyond int32 indexing or beyond a kernel's limits */
+    P2M_ERR_WORKSPACE = 3,     /* ws NULL or ws_bytes smaller than p2m_workspace_size */
+    P2M_ERR_RANGE = 4,         /* lx, ly not > 0, or tol not > 0 */
+    P2M_ERR_NONFINITE = 5,     /* lx, ly or tol not finite */
+    P2M_ERR_HIP = 6            /* a HIP runtime call or kernel launch failed */
+} p2m_status;
+
+/* Report flags (p2m_report.flags).  Output contents are defined for every flag:
+ * ORPHAN nodes get 0; NOT_CONVERGED returns the last iterate; RANGE / NONFINITE
+ * particles are left out of P2M and get NaN in M2P. */
+enum {
+    P2M_FLAG_ORPHAN = 1u << 0,           /* some node has w_i == 0 (Sec. 2.3: vanishing FLIP volume) */
+    P2M_FLAG_NOT_CONVERGED = 1u << 1,    /* mass solve stopped above tol (maxit / max_refine) */
+    P2M_FLAG_BREAKDOWN = 1u << 2,        /* CG met p.Mp <= 0 or a non-finite scalar */
+    P2M_FLAG_RANGE = 1u << 3,            /* some position outside [0, L + h) */
+    P2M_FLAG_NONFINITE = 1u << 4,        /* some position is NaN or infinite */
+    P2M_FLAG_LEARNED_FALLBACK = 1u << 5  /* learned start was worse than FLIP and was replaced */
+};
+
+typedef enum { P2M_F32 = 0, P2M_F64 = 1 } p2m_dtype;
+
+/* One periodic P1 problem (64 bytes). */
+typedef struct {
+    int32_t dim;          /* 1 or 2 */
+    int32_t nx, ny;       /* nodes (= cells) per axis, >= 2; ny is ignored (treated as 1) in 1D */
+    int32_t dtype;        /* p2m_dtype of x, y, vol and of the values / nodal arrays of the call */
+    double lx, ly;        /* box [0,lx) x [0,ly); ly ignored in 1D */
+    int64_t np;           /* number of particles (may be 0) */
+    const void* x;        /* [np] positions; valid positions satisfy 0 <= x*(nx/lx) < nx+1 */
+    const void* y;        /* [np] (2D only, NULL in 1D) */
+    const void* vol;      /* [np] particle volumes v_mu (> 0), or NULL for uniform lx*ly/np */
+} p2m_problem;
+
+typedef enum {
+    P2M_DELTA = 0,        /* 1D only: Abar_i = particle interpolant at node i, eq. (9) */
+    P2M_FLIP = 1,         /* Abar_i = b_i / w_i, eqs. (11)-(12) */
+    P2M_PIC = 2           /* Abar_i = b_i / v_i with v_i = hx (1D) or hx*hy (2D), eqs. (11), (5) */
+} p2m_assign_kind;
+
+typedef enum {
+    P2M_START_FLIP = 0,     /* x0 = b/w (the FLIP values; equal to delta for regular particles, Sec. 3.1) */
+    P2M_START_ZERO = 1,
+    P2M_START_USER = 2,     /* x0 read from nodal_inout */
+    P2M_START_LEARNED = 3,  /* reserved for the learned warm start */
+    P2M_START_DELTA1D = 4   /* 1D only: the delta assignment as x0 */
+} p2m_start;
+
+/* Mass-solve options (32 bytes).  The solve is conjugate gradients on M Abar = b,
+ * restarted from the true residual r = b - M x evaluated in FP64 ("outer"
+ * iterations, iterative refinement).  It stops when ||r||_2 / ||b||_2 <= tol for
+ * every field (b == 0 gives x == 0). */
+typedef struct {
+    double tol;           /* relative FP64 residual target, > 0 (e.g. 1e-6) */
+    double inner_rtol;    /* each inner CG solve reduces its residual by this factor (0: to tol) */
+    int32_t maxit;        /* cap on CG iterations per field, summed over outer iterations */
+    int32_t max_refine;   /* cap on FP64 residual evaluations after the first (>= 0) */
+    int32_t start;        /* p2m_start */
+    int32_t reserved;     /* must be 0 */
+} p2m_solve_opts;
+
+/* Per-call report, written on the device (144 bytes, device memory, caller-owned). */
+typedef struct {
+    int32_t iters[8];          /* CG iterations per field */
+    int32_t refines[8];        /* FP64 residual evaluations per field */
+    double rel_residual[8];    /* final FP64 ||b - M x||_2 / ||b||_2 per field */
+    uint32_t flags;            /* P2M_FLAG_* */
+    int32_t n_orphan;          /* nodes with w_i == 0 */
+    int32_t n_invalid;         /* particles left out (range / non-finite) */
+    int32_t reserved;
+} p2m_report;
+
+/* Human-readable name of a status code (static storage). */
+const char* p2m_status_string(p2m_status s);
+
+/* Create a context on HIP device `device` (queries the device; allocates nothing
+ * on it).  Destroy releases the context. */
+p2m_status p2m_create(void** ctx, int device);
+p2m_status p2m_destroy(void* ctx);
+
+/* Bytes of workspace that every call below needs for this problem and field count
+ * (the maximum over the entry points, so one workspace serves all of them).
+ * The workspace must be 256-byte aligned device memory. */
+p2m_status p2m_workspace_size(void* ctx, const p2m_problem* prob, int32_t nfields, size_t* bytes);
+
+/* Stable binning of the particles by cell (the locality step of every P2M).
+ * perm[k] = original index of the k-th valid particle in (cell, original index)
+ * order, perm[k] = -1 for k >= number of valid particles; cell_start[c] = index in
+ * perm of the first particle of cell c, cell_start[ncells] = number of valid
+ * particles (ncells = nx or nx*ny).  Bit-exact and deterministic. */
+p2m_status p2m_bin(void* ctx, const p2m_problem* prob, int32_t* perm, int32_t* cell_start,
+                   p2m_report* rep, void* ws, size_t ws_bytes, void* stream);
+
+/* Scatter of the particle-quadrature system (Sec. 2.3 eqs. (11)-(12), Sec. 2.4):
+ *   b[f*nn + i] = sum_mu v_mu A_f,mu psi_i(r_mu)
+ *   w[i]        = sum_mu v_mu psi_i(r_mu)
+ *   coef (optional, may be NULL): the symmetric stencil of M,
+ *     2D: coef[0*nn+k] = M(k,k), coef[1*nn+k] = M(k,k+x), coef[2*nn+k] = M(k,k+y),
+ *         coef[3*nn+k] = M(k,k+x+y)  (neighbour indices periodic);
+ *     1D: coef[0*nn+k] = M(k,k), coef[1*nn+k] = M(k,k+1).
+ * Each sum runs over the particles of a cell in binned order and then over the
+ * cells around a node in a fixed order: deterministic, no global float atomics. */
+p2m_status p2m_assemble(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
+                        void* b, void* w, void* coef, p2m_report* rep,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Particle->mesh by delta (1D), FLIP or PIC (Table 1).  nodal_out is [F][nnodes];
+ * orphan nodes (w_i == 0) get 0 under FLIP and raise P2M_FLAG_ORPHAN. */
+p2m_status p2m_assign(void* ctx, const p2m_problem* prob, p2m_assign_kind kind, const void* values,
+                      int32_t nfields, void* nodal_out, p2m_report* rep,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Mesh->particle interpolation (Sec. 2.2 eq. (10), the M2P of delta, FLIP and
+ * mass-delta in Table 1): values_out[f*np + mu] = sum_i nodal[f*nn + i] psi_i(r_mu),
+ * in the caller's particle order.  Needs no workspace (ws may be NULL). */
+p2m_status p2m_interpolate(void* ctx, const p2m_problem* prob, const void* nodal, int32_t nfields,
+                           void* values_out, p2m_report* rep, void* ws, size_t ws_bytes, void* stream);
+
+/* Mass assignment (Sec. 2.4 eqs. (13), (19); Table 1 mass rows): assemble M and b
+ * and solve M Abar_f = b_f for every field with the precision split described at
+ * p2m_solve_opts (FP32 arithmetic when dtype is F32, FP64 residuals and dot
+ * products).  Orphan nodes (w_i == 0) are solved as Abar_i = 0.  nodal_inout is
+ * [F][nnodes]: read as the start when opts->start == P2M_START_USER, always
+ * written with the result.  rep is required. */
+p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
+                           const p2m_solve_opts* opts, void* nodal_inout, p2m_report* rep,
+                           void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* P2M_H */

@@ -386,3 +386,75 @@ def delta_1d(prob, values):
         A_b = values[:, idx_sorted[ib]]
         out[:, i] = A_a + (A_b - A_a) * (da / (da + db))
     return out
+
+
+def assemble_stencil(prob, values):
+    """The same scatter as ``assemble`` but accumulating the mass matrix directly
+    in its symmetric stencil storage with bincount (no sparse matrix), for large
+    problems.  2D: D, E = M(k,k+x), N = M(k,k+y), NE = M(k,k+x+y) as the pairs of
+    corners each particle's triangle touches; 1D: D, E = M(k,k+1).
+    Valid for n >= 3 per axis (for n == 2 a periodic neighbour pair is stored
+    twice and the split between the two slots differs from ``stencil_coefficients``).
+    """
+    values = np.atleast_2d(np.asarray(values, dtype=np.float64))
+    loc = locate(prob)
+    nn = n_nodes(prob)
+    npart = values.shape[1]
+    v = particle_volumes(prob, npart)
+    ok = loc["valid"]
+    vv = v[ok]
+    out = {}
+    if prob["dim"] == 1:
+        c = loc["key"][ok]
+        c1 = (c + 1) % prob["nx"]
+        l0, l1 = loc["lam"][0][ok], loc["lam"][1][ok]
+        out["D"] = np.bincount(c, vv * l0 * l0, nn) + np.bincount(c1, vv * l1 * l1, nn)
+        out["E"] = np.bincount(c, vv * l0 * l1, nn)
+        out["w"] = np.bincount(c, vv * l0, nn) + np.bincount(c1, vv * l1, nn)
+        out["b"] = np.stack([np.bincount(c, vv * values[f, ok] * l0, nn) +
+                             np.bincount(c1, vv * values[f, ok] * l1, nn)
+                             for f in range(values.shape[0])])
+        return out
+    nx, ny = prob["nx"], prob["ny"]
+    cx, cy = loc["cx"][ok], loc["cy"][ok]
+    xi, eta = loc["xi"][ok], loc["eta"][ok]
+    lower = xi >= eta
+    i1, j1 = (cx + 1) % nx, (cy + 1) % ny
+    n00, n10, n11, n01 = cx + nx * cy, i1 + nx * cy, i1 + nx * j1, cx + nx * j1
+    # corner weights (0 for the corner outside the particle's triangle)
+    w00 = np.where(lower, 1.0 - xi, 1.0 - eta)
+    w10 = np.where(lower, xi - eta, 0.0)
+    w11 = np.where(lower, eta, xi)
+    w01 = np.where(lower, 0.0, eta - xi)
+    bc = lambda idx, wt: np.bincount(idx, wt, nn)
+    out["D"] = bc(n00, vv * w00 * w00) + bc(n10, vv * w10 * w10) + bc(n11, vv * w11 * w11) + bc(n01, vv * w01 * w01)
+    out["E"] = bc(n00, vv * w00 * w10) + bc(n01, vv * w01 * w11)     # bottom and top edges
+    out["N"] = bc(n00, vv * w00 * w01) + bc(n10, vv * w10 * w11)     # left and right edges
+    out["NE"] = bc(n00, vv * w00 * w11)                               # the "/" diagonal
+    out["w"] = bc(n00, vv * w00) + bc(n10, vv * w10) + bc(n11, vv * w11) + bc(n01, vv * w01)
+    out["b"] = np.stack([bc(n00, vv * values[f, ok] * w00) + bc(n10, vv * values[f, ok] * w10) +
+                         bc(n11, vv * values[f, ok] * w11) + bc(n01, vv * values[f, ok] * w01)
+                         for f in range(values.shape[0])])
+    return out
+
+
+def stencil_matrix(prob, st):
+    """CSR matrix of a symmetric periodic stencil (D, E, N, NE in 2D; D, E in 1D)."""
+    nx = prob["nx"]
+    if prob["dim"] == 1:
+        k = np.arange(nx)
+        rows = np.concatenate([k, k, (k + 1) % nx])
+        cols = np.concatenate([k, (k + 1) % nx, k])
+        vals = np.concatenate([st["D"], st["E"], st["E"]])
+        return sp.coo_matrix((vals, (rows, cols)), shape=(nx, nx)).tocsr()
+    ny = prob["ny"]
+    nn = nx * ny
+    j, i = np.divmod(np.arange(nn), nx)
+    k = np.arange(nn)
+    kx = (i + 1) % nx + nx * j
+    ky = i + nx * ((j + 1) % ny)
+    kxy = (i + 1) % nx + nx * ((j + 1) % ny)
+    rows = np.concatenate([k, k, kx, k, ky, k, kxy])
+    cols = np.concatenate([k, kx, k, ky, k, kxy, k])
+    vals = np.concatenate([st["D"], st["E"], st["E"], st["N"], st["N"], st["NE"], st["NE"]])
+    return sp.coo_matrix((vals, (rows, cols)), shape=(nn, nn)).tocsr()

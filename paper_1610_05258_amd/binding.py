@@ -1,0 +1,319 @@
+"""Thin ctypes binding of libp2m.so (the C ABI in include/p2m.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI.  PyTorch provides device memory and the stream.  The
+functions carry the names of the C entry points; they take torch tensors on the
+context's device and return torch tensors plus a decoded report.
+
+If libp2m.so is missing this module raises on first use: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libp2m.so")
+
+P2M_F32, P2M_F64 = 0, 1
+DELTA, FLIP, PIC = 0, 1, 2
+START_FLIP, START_ZERO, START_USER, START_LEARNED, START_DELTA1D = 0, 1, 2, 3, 4
+FLAG_ORPHAN = 1 << 0
+FLAG_NOT_CONVERGED = 1 << 1
+FLAG_BREAKDOWN = 1 << 2
+FLAG_RANGE = 1 << 3
+FLAG_NONFINITE = 1 << 4
+FLAG_LEARNED_FALLBACK = 1 << 5
+REPORT_BYTES = 144
+MAX_FIELDS = 8
+
+EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size", "p2m_bin",
+           "p2m_assemble", "p2m_assign", "p2m_interpolate", "p2m_mass_assign")
+
+
+class P2MError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)}")
+
+
+class CProblem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+                ("np", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("vol", ctypes.c_void_p)]
+
+
+class CSolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
+                ("maxit", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+                ("start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+assert ctypes.sizeof(CProblem) == 64 and ctypes.sizeof(CSolveOpts) == 32
+
+_lib = None
+
+
+def lib():
+    """Open libp2m.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                               "(or python -m paper_1610_05258_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        pprob = ctypes.POINTER(CProblem)
+        L.p2m_status_string.restype = ctypes.c_char_p
+        L.p2m_status_string.argtypes = [ctypes.c_int]
+        L.p2m_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        L.p2m_destroy.argtypes = [vp]
+        L.p2m_workspace_size.argtypes = [vp, pprob, i32, ctypes.POINTER(sz)]
+        L.p2m_bin.argtypes = [vp, pprob, vp, vp, vp, vp, sz, vp]
+        L.p2m_assemble.argtypes = [vp, pprob, vp, i32, vp, vp, vp, vp, vp, sz, vp]
+        L.p2m_assign.argtypes = [vp, pprob, ctypes.c_int, vp, i32, vp, vp, vp, sz, vp]
+        L.p2m_interpolate.argtypes = [vp, pprob, vp, i32, vp, vp, vp, sz, vp]
+        L.p2m_mass_assign.argtypes = [vp, pprob, vp, i32, ctypes.POINTER(CSolveOpts), vp, vp, vp,
+                                      sz, vp]
+        for name in EXPORTS[1:]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(s):
+    return lib().p2m_status_string(int(s)).decode()
+
+
+def _check(status, where):
+    if status != 0:
+        raise P2MError(status, where)
+
+
+@dataclass
+class Report:
+    iters: np.ndarray
+    refines: np.ndarray
+    rel_residual: np.ndarray
+    flags: int
+    n_orphan: int
+    n_invalid: int
+
+    @staticmethod
+    def decode(raw: bytes, nfields=MAX_FIELDS):
+        a = np.frombuffer(raw, dtype=np.uint8)
+        iters = a[0:32].view(np.int32)[:nfields].copy()
+        refines = a[32:64].view(np.int32)[:nfields].copy()
+        relres = a[64:128].view(np.float64)[:nfields].copy()
+        tail = a[128:144].view(np.int32)
+        return Report(iters, refines, relres, int(np.uint32(tail[0])), int(tail[1]), int(tail[2]))
+
+
+@dataclass
+class Particles:
+    """One periodic P1 problem: mesh size, box and particle arrays on the device."""
+    dim: int
+    nx: int
+    ny: int
+    lx: float
+    ly: float
+    x: torch.Tensor
+    y: torch.Tensor | None = None
+    vol: torch.Tensor | None = None
+
+    @property
+    def n_nodes(self):
+        return self.nx * (self.ny if self.dim == 2 else 1)
+
+    @property
+    def n_particles(self):
+        return int(self.x.numel())
+
+    @property
+    def dtype(self):
+        return self.x.dtype
+
+    def cstruct(self):
+        dt = self.x.dtype
+        if dt not in (torch.float32, torch.float64):
+            raise TypeError("positions must be float32 or float64")
+        for t in (self.x, self.y, self.vol):
+            if t is not None:
+                if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() != self.x.numel():
+                    raise TypeError("x, y, vol must be contiguous device tensors of one dtype and length")
+        return CProblem(self.dim, self.nx, self.ny if self.dim == 2 else 1,
+                        P2M_F64 if dt == torch.float64 else P2M_F32, float(self.lx),
+                        float(self.ly if self.dim == 2 else 1.0), self.x.numel(),
+                        self.x.data_ptr(),
+                        self.y.data_ptr() if (self.dim == 2 and self.y is not None) else None,
+                        self.vol.data_ptr() if self.vol is not None else None)
+
+
+def particles_from(prob: dict, device="cuda", dtype=None) -> Particles:
+    """Build a device problem from a dict of host arrays (keys dim, nx, ny, lx, ly, x, y, vol)."""
+    def dev(a):
+        if a is None:
+            return None
+        t = torch.as_tensor(np.ascontiguousarray(a))
+        if dtype is not None:
+            t = t.to(dtype)
+        return t.to(device).contiguous()
+    return Particles(prob["dim"], prob["nx"], prob.get("ny", 1), prob["lx"], prob.get("ly", 1.0),
+                     dev(prob["x"]), dev(prob.get("y")) if prob["dim"] == 2 else None,
+                     dev(prob.get("vol")))
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A library context on one device plus a cached workspace."""
+
+    def __init__(self, device=0):
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib().p2m_create(ctypes.byref(h), int(device)), "p2m_create")
+        self.handle = h
+        self._ws = None
+
+    def close(self):
+        if self.handle:
+            lib().p2m_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_size(self, prob: Particles, nfields: int) -> int:
+        n = ctypes.c_size_t()
+        cp = prob.cstruct()
+        _check(lib().p2m_workspace_size(self.handle, ctypes.byref(cp), int(nfields), ctypes.byref(n)),
+               "p2m_workspace_size")
+        return int(n.value)
+
+    def workspace(self, nbytes: int) -> torch.Tensor:
+        nbytes = max(int(nbytes), 256)
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def new_report(self):
+        return torch.zeros(REPORT_BYTES, dtype=torch.uint8, device=f"cuda:{self.device}")
+
+
+def read_report(rep: torch.Tensor, nfields=MAX_FIELDS) -> Report:
+    return Report.decode(rep.cpu().numpy().tobytes(), nfields)
+
+
+def _values_tensor(values, prob: Particles):
+    if values.dim() == 1:
+        values = values[None, :]
+    if values.dtype != prob.dtype or not values.is_cuda or values.shape[1] != prob.n_particles:
+        raise TypeError("values must be a [F, np] device tensor of the positions' dtype")
+    F = values.shape[0]
+    if not 1 <= F <= MAX_FIELDS:
+        raise ValueError("1 <= F <= 8 fields")
+    return values.contiguous(), F
+
+
+def _ws_args(ctx, prob, F, ws):
+    need = ctx.workspace_size(prob, F)
+    w = ws if ws is not None else ctx.workspace(need)
+    return ctypes.c_void_p(w.data_ptr()), ctypes.c_size_t(w.numel())
+
+
+def p2m_bin(ctx: Context, prob: Particles, stream=None, ws=None, rep=None):
+    """Stable binning: (perm [np] int32, cell_start [ncells+1] int32, report tensor)."""
+    cp = prob.cstruct()
+    perm = torch.empty(max(prob.n_particles, 1), dtype=torch.int32, device=prob.x.device)
+    cs = torch.empty(prob.n_nodes + 1, dtype=torch.int32, device=prob.x.device)
+    rep = ctx.new_report() if rep is None else rep
+    wp, wn = _ws_args(ctx, prob, 1, ws)
+    _check(lib().p2m_bin(ctx.handle, ctypes.byref(cp), ctypes.c_void_p(perm.data_ptr()),
+                         ctypes.c_void_p(cs.data_ptr()), ctypes.c_void_p(rep.data_ptr()), wp, wn,
+                         _stream_ptr(stream)), "p2m_bin")
+    return perm[: prob.n_particles], cs, rep
+
+
+def p2m_assemble(ctx: Context, prob: Particles, values, want_coef=True, stream=None, ws=None, rep=None):
+    """(b [F, nn], w [nn], coef [4 or 2, nn] or None, report tensor)."""
+    values, F = _values_tensor(values, prob)
+    cp = prob.cstruct()
+    nn = prob.n_nodes
+    dev = prob.x.device
+    b = torch.empty((F, nn), dtype=prob.dtype, device=dev)
+    w = torch.empty(nn, dtype=prob.dtype, device=dev)
+    coef = torch.empty((4 if prob.dim == 2 else 2, nn), dtype=prob.dtype, device=dev) if want_coef else None
+    rep = ctx.new_report() if rep is None else rep
+    wp, wn = _ws_args(ctx, prob, F, ws)
+    _check(lib().p2m_assemble(ctx.handle, ctypes.byref(cp), ctypes.c_void_p(values.data_ptr()), F,
+                              ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                              ctypes.c_void_p(coef.data_ptr()) if coef is not None else None,
+                              ctypes.c_void_p(rep.data_ptr()), wp, wn, _stream_ptr(stream)),
+           "p2m_assemble")
+    return b, w, coef, rep
+
+
+def p2m_assign(ctx: Context, prob: Particles, kind: int, values, stream=None, ws=None, rep=None, out=None):
+    """Particle->mesh by DELTA (1D), FLIP or PIC: (nodal [F, nn], report tensor)."""
+    values, F = _values_tensor(values, prob)
+    cp = prob.cstruct()
+    out = torch.empty((F, prob.n_nodes), dtype=prob.dtype, device=prob.x.device) if out is None else out
+    rep = ctx.new_report() if rep is None else rep
+    wp, wn = _ws_args(ctx, prob, F, ws)
+    _check(lib().p2m_assign(ctx.handle, ctypes.byref(cp), int(kind), ctypes.c_void_p(values.data_ptr()),
+                            F, ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(rep.data_ptr()), wp, wn,
+                            _stream_ptr(stream)), "p2m_assign")
+    return out, rep
+
+
+def p2m_interpolate(ctx: Context, prob: Particles, nodal, stream=None, rep=None, out=None):
+    """Mesh->particle interpolation: (values [F, np], report tensor)."""
+    if nodal.dim() == 1:
+        nodal = nodal[None, :]
+    if nodal.dtype != prob.dtype or nodal.shape[1] != prob.n_nodes or not nodal.is_cuda:
+        raise TypeError("nodal must be a [F, nnodes] device tensor of the positions' dtype")
+    nodal = nodal.contiguous()
+    F = nodal.shape[0]
+    cp = prob.cstruct()
+    out = torch.empty((F, prob.n_particles), dtype=prob.dtype, device=prob.x.device) if out is None else out
+    rep = ctx.new_report() if rep is None else rep
+    _check(lib().p2m_interpolate(ctx.handle, ctypes.byref(cp), ctypes.c_void_p(nodal.data_ptr()), F,
+                                 ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(rep.data_ptr()),
+                                 None, 0, _stream_ptr(stream)), "p2m_interpolate")
+    return out, rep
+
+
+def solve_opts(tol=1e-6, inner_rtol=None, maxit=1000, max_refine=8, start=START_FLIP, fp64=False):
+    if inner_rtol is None:
+        inner_rtol = 0.0 if fp64 else 1e-4
+    return CSolveOpts(float(tol), float(inner_rtol), int(maxit), int(max_refine), int(start), 0)
+
+
+def p2m_mass_assign(ctx: Context, prob: Particles, values, opts: CSolveOpts | None = None,
+                    x0=None, stream=None, ws=None, rep=None, out=None):
+    """Mass assignment: (nodal [F, nn], report tensor).  x0 is read when opts.start is USER."""
+    values, F = _values_tensor(values, prob)
+    cp = prob.cstruct()
+    opts = opts if opts is not None else solve_opts(fp64=prob.dtype == torch.float64)
+    if out is None:
+        out = torch.empty((F, prob.n_nodes), dtype=prob.dtype, device=prob.x.device)
+    if x0 is not None:
+        out.copy_(x0)
+    rep = ctx.new_report() if rep is None else rep
+    wp, wn = _ws_args(ctx, prob, F, ws)
+    _check(lib().p2m_mass_assign(ctx.handle, ctypes.byref(cp), ctypes.c_void_p(values.data_ptr()), F,
+                                 ctypes.byref(opts), ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(rep.data_ptr()), wp, wn, _stream_ptr(stream)),
+           "p2m_mass_assign")
+    return out, rep

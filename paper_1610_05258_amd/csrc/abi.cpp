@@ -1,0 +1,370 @@
+// C ABI of libp2m (declared in include/p2m.h): argument validation, workspace
+// carving and the launch sequence of every entry point.  No device memory is
+// allocated here; every launch goes on the caller's stream.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <hip/hip_runtime.h>
+
+#include "p2m_internal.hpp"
+
+using namespace p2m;
+
+namespace {
+
+struct Context {
+    int device;
+    int cg_blocks_f32;
+    int cg_blocks_f64;
+};
+
+// Makes the context's device current for the duration of a call and restores
+// the caller's device afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace carve-up.  Offsets are fixed functions of (problem, F, cg blocks).
+struct Layout {
+    size_t key, counts, cell_start, perm, scan, b, w, coef, r, p0, p1, q, x64, partials, report, total;
+};
+
+Layout make_layout(const Mesh& m, int F, size_t tsize, int cg_blocks) {
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const size_t np = (size_t)m.np, nn = (size_t)m.nn;
+    const size_t cm = (m.dim == 2) ? 4 : 2;
+    L.key = take(np * sizeof(int32_t));
+    L.counts = take(nn * sizeof(int32_t));
+    L.cell_start = take((nn + 1) * sizeof(int32_t));
+    L.perm = take(np * sizeof(int32_t));
+    L.scan = take(scan_workspace_bytes((int)nn));
+    L.b = take((size_t)F * nn * tsize);
+    L.w = take(nn * tsize);
+    L.coef = take(cm * nn * tsize);
+    L.r = take((size_t)F * nn * tsize);
+    L.p0 = take((size_t)F * nn * tsize);
+    L.p1 = take((size_t)F * nn * tsize);
+    L.q = take((size_t)F * nn * tsize);
+    L.x64 = take((size_t)2 * F * nn * sizeof(double));
+    L.partials = take(cg_partials_bytes(cg_blocks));
+    L.report = take(sizeof(p2m_report));
+    L.total = off;
+    return L;
+}
+
+p2m_status check_problem(const p2m_problem* p, Mesh& m) {
+    if (!p) return P2M_ERR_INVALID_ARG;
+    if (p->dim != 1 && p->dim != 2) return P2M_ERR_INVALID_ARG;
+    if (p->dtype != P2M_F32 && p->dtype != P2M_F64) return P2M_ERR_INVALID_ARG;
+    if (p->nx < 2 || (p->dim == 2 && p->ny < 2)) return P2M_ERR_INVALID_ARG;
+    if (p->np < 0) return P2M_ERR_INVALID_ARG;
+    if (!isfinite(p->lx) || (p->dim == 2 && !isfinite(p->ly))) return P2M_ERR_NONFINITE;
+    if (!(p->lx > 0.0) || (p->dim == 2 && !(p->ly > 0.0))) return P2M_ERR_RANGE;
+    const int ny = (p->dim == 2) ? p->ny : 1;
+    const int64_t nn = (int64_t)p->nx * ny;
+    if (nn >= ((int64_t)1 << 31) - 1 || p->np >= ((int64_t)1 << 31) - 1) return P2M_ERR_UNSUPPORTED;
+    if (p->np > 0 && (!p->x || (p->dim == 2 && !p->y))) return P2M_ERR_INVALID_ARG;
+    m.dim = p->dim;
+    m.nx = p->nx;
+    m.ny = ny;
+    m.nn = (int)nn;
+    m.np = (int)p->np;
+    m.inv_hx = (double)p->nx / p->lx;
+    m.inv_hy = (p->dim == 2) ? (double)p->ny / p->ly : 1.0;
+    m.cell_measure = (p->dim == 2) ? (p->lx / p->nx) * (p->ly / p->ny) : p->lx / p->nx;
+    const double area = (p->dim == 2) ? p->lx * p->ly : p->lx;
+    m.v_uniform = (p->np > 0) ? area / (double)p->np : 0.0;
+    return P2M_OK;
+}
+
+inline size_t tsize_of(const p2m_problem* p) { return p->dtype == P2M_F64 ? 8 : 4; }
+
+int cg_blocks_for(const Context* c, const Mesh& m, int dtype) {
+    int maxb = dtype == P2M_F64 ? c->cg_blocks_f64 : c->cg_blocks_f32;
+    int need = (m.nn + 255) / 256;
+    int b = need < maxb ? need : maxb;
+    return b < 1 ? 1 : b;
+}
+
+template <typename T>
+Particles<T> particles_of(const p2m_problem* p) {
+    Particles<T> P;
+    P.x = (const T*)p->x;
+    P.y = (const T*)p->y;
+    P.vol = (const T*)p->vol;
+    return P;
+}
+
+inline p2m_status st(hipError_t e) { return e == hipSuccess ? P2M_OK : P2M_ERR_HIP; }
+#define P2M_TRY(expr)                               \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) return P2M_ERR_HIP;   \
+    } while (0)
+
+struct Prepared {
+    Mesh m;
+    Layout L;
+    char* ws;
+    hipStream_t stream;
+    p2m_report* rep;
+};
+
+p2m_status prepare(void* ctx, const p2m_problem* prob, int F, void* ws, size_t ws_bytes,
+                   void* stream, p2m_report* rep, Prepared& out) {
+    if (!ctx) return P2M_ERR_INVALID_ARG;
+    if (F < 1 || F > kMaxFields) return P2M_ERR_INVALID_ARG;
+    p2m_status s = check_problem(prob, out.m);
+    if (s != P2M_OK) return s;
+    const Context* c = (const Context*)ctx;
+    out.L = make_layout(out.m, F, tsize_of(prob), cg_blocks_for(c, out.m, prob->dtype));
+    if (!ws || ws_bytes < out.L.total) return P2M_ERR_WORKSPACE;
+    if (((uintptr_t)ws) % kAlign) return P2M_ERR_WORKSPACE;
+    out.ws = (char*)ws;
+    out.stream = (hipStream_t)stream;
+    out.rep = rep ? rep : (p2m_report*)(out.ws + out.L.report);
+    return P2M_OK;
+}
+
+template <typename T>
+p2m_status run_bin(const Prepared& pp, const p2m_problem* prob, int32_t* perm, int32_t* cs) {
+    const Mesh& m = pp.m;
+    int32_t* key = (int32_t*)(pp.ws + pp.L.key);
+    int32_t* counts = (int32_t*)(pp.ws + pp.L.counts);
+    int32_t* sums = (int32_t*)(pp.ws + pp.L.scan);
+    P2M_TRY(launch_fill_i32(counts, 0, (size_t)m.nn, pp.stream));
+    P2M_TRY(launch_locate_count<T>(m, particles_of<T>(prob), key, counts, pp.rep, pp.stream));
+    P2M_TRY(launch_exclusive_scan(counts, cs, m.nn, sums, pp.stream));
+    P2M_TRY(launch_fill_i32(counts, 0, (size_t)m.nn, pp.stream));
+    P2M_TRY(launch_place(m, key, cs, counts, perm, pp.stream));
+    P2M_TRY(launch_segment_sort(m, cs, perm, pp.stream));
+    return P2M_OK;
+}
+
+template <typename T>
+p2m_status run_assign(const Prepared& pp, const p2m_problem* prob, p2m_assign_kind kind,
+                      const void* values, int F, void* nodal_out) {
+    int32_t* perm = (int32_t*)(pp.ws + pp.L.perm);
+    int32_t* cs = (int32_t*)(pp.ws + pp.L.cell_start);
+    p2m_status s = run_bin<T>(pp, prob, perm, cs);
+    if (s != P2M_OK) return s;
+    if (kind == P2M_DELTA) {
+        P2M_TRY(launch_delta1d<T>(pp.m, particles_of<T>(prob), (const T*)values, F, perm, cs,
+                                  (T*)nodal_out, pp.stream));
+        return P2M_OK;
+    }
+    T* b = (T*)(pp.ws + pp.L.b);
+    T* w = (T*)(pp.ws + pp.L.w);
+    P2M_TRY(launch_assemble<T>(pp.m, particles_of<T>(prob), (const T*)values, F, perm, cs, b, w,
+                               nullptr, pp.stream));
+    P2M_TRY(launch_finalize<T>(pp.m, F, b, w, kind == P2M_PIC ? 1 : 0, (T*)nodal_out, pp.rep,
+                               pp.stream));
+    return P2M_OK;
+}
+
+template <typename T>
+p2m_status run_assemble(const Prepared& pp, const p2m_problem* prob, const void* values, int F,
+                        void* b, void* w, void* coef) {
+    int32_t* perm = (int32_t*)(pp.ws + pp.L.perm);
+    int32_t* cs = (int32_t*)(pp.ws + pp.L.cell_start);
+    p2m_status s = run_bin<T>(pp, prob, perm, cs);
+    if (s != P2M_OK) return s;
+    P2M_TRY(launch_assemble<T>(pp.m, particles_of<T>(prob), (const T*)values, F, perm, cs, (T*)b,
+                               (T*)w, (T*)coef, pp.stream));
+    return P2M_OK;
+}
+
+template <typename T>
+p2m_status run_mass(const Context* c, const Prepared& pp, const p2m_problem* prob,
+                    const void* values, int F, const p2m_solve_opts& opts, void* x) {
+    int32_t* perm = (int32_t*)(pp.ws + pp.L.perm);
+    int32_t* cs = (int32_t*)(pp.ws + pp.L.cell_start);
+    p2m_status s = run_bin<T>(pp, prob, perm, cs);
+    if (s != P2M_OK) return s;
+    T* b = (T*)(pp.ws + pp.L.b);
+    T* w = (T*)(pp.ws + pp.L.w);
+    T* coef = (T*)(pp.ws + pp.L.coef);
+    P2M_TRY(launch_assemble<T>(pp.m, particles_of<T>(prob), (const T*)values, F, perm, cs, b, w,
+                               coef, pp.stream));
+    int start = opts.start;
+    if (start == P2M_START_DELTA1D) {
+        P2M_TRY(launch_delta1d<T>(pp.m, particles_of<T>(prob), (const T*)values, F, perm, cs,
+                                  (T*)x, pp.stream));
+        start = P2M_START_USER;
+    }
+    double* x64 = (double*)(pp.ws + pp.L.x64);
+    P2M_TRY(launch_prepare_system<T>(pp.m, F, coef, b, w, (const T*)x, x64, start, pp.rep,
+                                     pp.stream));
+    CgWorkspace cw;
+    cw.r = pp.ws + pp.L.r;
+    cw.p0 = pp.ws + pp.L.p0;
+    cw.p1 = pp.ws + pp.L.p1;
+    cw.q = pp.ws + pp.L.q;
+    cw.x64 = x64;
+    cw.partials = (double*)(pp.ws + pp.L.partials);
+    cw.blocks = cg_blocks_for(c, pp.m, prob->dtype);
+    P2M_TRY(launch_cg<T>(pp.m, F, coef, b, (T*)x, cw, opts, pp.rep, pp.stream));
+    return P2M_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* p2m_status_string(p2m_status s) {
+    switch (s) {
+        case P2M_OK: return "P2M_OK";
+        case P2M_ERR_INVALID_ARG: return "P2M_ERR_INVALID_ARG";
+        case P2M_ERR_UNSUPPORTED: return "P2M_ERR_UNSUPPORTED";
+        case P2M_ERR_WORKSPACE: return "P2M_ERR_WORKSPACE";
+        case P2M_ERR_RANGE: return "P2M_ERR_RANGE";
+        case P2M_ERR_NONFINITE: return "P2M_ERR_NONFINITE";
+        case P2M_ERR_HIP: return "P2M_ERR_HIP";
+    }
+    return "P2M_UNKNOWN_STATUS";
+}
+
+p2m_status p2m_create(void** ctx, int device) {
+    if (!ctx) return P2M_ERR_INVALID_ARG;
+    *ctx = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess) return P2M_ERR_HIP;
+    if (device < 0 || device >= count) return P2M_ERR_INVALID_ARG;
+    DeviceGuard g(device);
+    if (!g.ok) return P2M_ERR_HIP;
+    Context* c = (Context*)calloc(1, sizeof(Context));
+    if (!c) return P2M_ERR_HIP;
+    c->device = device;
+    c->cg_blocks_f32 = cg_max_blocks<float>(device);
+    c->cg_blocks_f64 = cg_max_blocks<double>(device);
+    if (c->cg_blocks_f32 <= 0 || c->cg_blocks_f64 <= 0) {
+        free(c);
+        return P2M_ERR_HIP;
+    }
+    *ctx = c;
+    return P2M_OK;
+}
+
+p2m_status p2m_destroy(void* ctx) {
+    free(ctx);
+    return P2M_OK;
+}
+
+p2m_status p2m_workspace_size(void* ctx, const p2m_problem* prob, int32_t nfields, size_t* bytes) {
+    if (!ctx || !bytes) return P2M_ERR_INVALID_ARG;
+    if (nfields < 1 || nfields > kMaxFields) return P2M_ERR_INVALID_ARG;
+    Mesh m;
+    p2m_status s = check_problem(prob, m);
+    if (s != P2M_OK) return s;
+    const Context* c = (const Context*)ctx;
+    *bytes = make_layout(m, nfields, tsize_of(prob), cg_blocks_for(c, m, prob->dtype)).total;
+    return P2M_OK;
+}
+
+p2m_status p2m_bin(void* ctx, const p2m_problem* prob, int32_t* perm, int32_t* cell_start,
+                   p2m_report* rep, void* ws, size_t ws_bytes, void* stream) {
+    Prepared pp;
+    p2m_status s = prepare(ctx, prob, 1, ws, ws_bytes, stream, rep, pp);
+    if (s != P2M_OK) return s;
+    if ((pp.m.np > 0 && !perm) || !cell_start) return P2M_ERR_INVALID_ARG;
+    DeviceGuard g(((Context*)ctx)->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+    return prob->dtype == P2M_F64 ? run_bin<double>(pp, prob, perm, cell_start)
+                                  : run_bin<float>(pp, prob, perm, cell_start);
+}
+
+p2m_status p2m_assemble(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
+                        void* b, void* w, void* coef, p2m_report* rep, void* ws, size_t ws_bytes,
+                        void* stream) {
+    Prepared pp;
+    p2m_status s = prepare(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp);
+    if (s != P2M_OK) return s;
+    if ((pp.m.np > 0 && !values) || !b || !w) return P2M_ERR_INVALID_ARG;
+    DeviceGuard g(((Context*)ctx)->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+    return prob->dtype == P2M_F64 ? run_assemble<double>(pp, prob, values, nfields, b, w, coef)
+                                  : run_assemble<float>(pp, prob, values, nfields, b, w, coef);
+}
+
+p2m_status p2m_assign(void* ctx, const p2m_problem* prob, p2m_assign_kind kind, const void* values,
+                      int32_t nfields, void* nodal_out, p2m_report* rep, void* ws, size_t ws_bytes,
+                      void* stream) {
+    if (kind != P2M_DELTA && kind != P2M_FLIP && kind != P2M_PIC) return P2M_ERR_INVALID_ARG;
+    Prepared pp;
+    p2m_status s = prepare(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp);
+    if (s != P2M_OK) return s;
+    if (kind == P2M_DELTA && pp.m.dim != 1) return P2M_ERR_UNSUPPORTED;
+    if ((pp.m.np > 0 && !values) || !nodal_out) return P2M_ERR_INVALID_ARG;
+    DeviceGuard g(((Context*)ctx)->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+    return prob->dtype == P2M_F64 ? run_assign<double>(pp, prob, kind, values, nfields, nodal_out)
+                                  : run_assign<float>(pp, prob, kind, values, nfields, nodal_out);
+}
+
+p2m_status p2m_interpolate(void* ctx, const p2m_problem* prob, const void* nodal, int32_t nfields,
+                           void* values_out, p2m_report* rep, void* ws, size_t ws_bytes,
+                           void* stream) {
+    (void)ws;
+    (void)ws_bytes;
+    if (!ctx) return P2M_ERR_INVALID_ARG;
+    if (nfields < 1 || nfields > kMaxFields) return P2M_ERR_INVALID_ARG;
+    Mesh m;
+    p2m_status s = check_problem(prob, m);
+    if (s != P2M_OK) return s;
+    if (!nodal || (m.np > 0 && !values_out)) return P2M_ERR_INVALID_ARG;
+    DeviceGuard g(((Context*)ctx)->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    hipStream_t strm = (hipStream_t)stream;
+    P2M_TRY(launch_report_clear(rep, strm));
+    if (prob->dtype == P2M_F64)
+        return st(launch_gather<double>(m, particles_of<double>(prob), (const double*)nodal, nfields,
+                                        (double*)values_out, rep, strm));
+    return st(launch_gather<float>(m, particles_of<float>(prob), (const float*)nodal, nfields,
+                                   (float*)values_out, rep, strm));
+}
+
+p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
+                           const p2m_solve_opts* opts, void* nodal_inout, p2m_report* rep,
+                           void* ws, size_t ws_bytes, void* stream) {
+    if (!opts || !rep) return P2M_ERR_INVALID_ARG;
+    if (!isfinite(opts->tol) || !isfinite(opts->inner_rtol)) return P2M_ERR_NONFINITE;
+    if (!(opts->tol > 0.0) || opts->inner_rtol < 0.0 || opts->inner_rtol >= 1.0) return P2M_ERR_RANGE;
+    if (opts->maxit < 0 || opts->max_refine < 0 || opts->reserved != 0) return P2M_ERR_INVALID_ARG;
+    if (opts->start < P2M_START_FLIP || opts->start > P2M_START_DELTA1D) return P2M_ERR_INVALID_ARG;
+    if (opts->start == P2M_START_LEARNED) return P2M_ERR_UNSUPPORTED;
+    Prepared pp;
+    p2m_status s = prepare(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp);
+    if (s != P2M_OK) return s;
+    if (opts->start == P2M_START_DELTA1D && pp.m.dim != 1) return P2M_ERR_UNSUPPORTED;
+    if ((pp.m.np > 0 && !values) || !nodal_inout) return P2M_ERR_INVALID_ARG;
+    DeviceGuard g(((Context*)ctx)->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+    const Context* c = (const Context*)ctx;
+    return prob->dtype == P2M_F64
+               ? run_mass<double>(c, pp, prob, values, nfields, *opts, nodal_inout)
+               : run_mass<float>(c, pp, prob, values, nfields, *opts, nodal_inout);
+}
+
+}  // extern "C"

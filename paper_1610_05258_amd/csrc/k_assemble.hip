@@ -1,0 +1,275 @@
+// Scatter of the particle-quadrature system and the FLIP / PIC finalize.
+//
+// For a mesh tile of TS x TS nodes one workgroup
+//   1. walks the (TS+1) x (TS+1) cells that touch the tile (one extra row and
+//      column below / left of it, periodic), one thread per cell.  Each thread
+//      reads its cell's particles in binned order and accumulates, per cell, the
+//      corner parts of w_i = sum v psi_i, b_i = sum v A psi_i and of the mass
+//      matrix M_ij = sum v psi_i psi_j (Sec. 2.3 eqs. (11)-(12), Sec. 2.4) in
+//      registers, then stores them in LDS;
+//   2. one thread per node adds the parts of the (up to) four cells around the
+//      node in a fixed order and writes b, w and the stencil of M.
+// No float atomics: the sums are deterministic and independent of the launch.
+//
+// Per cell (corners c00, c10, c11, c01 = lower-left, lower-right, upper-right,
+// upper-left) the parts are: diagonal D_c for each corner; the bottom edge
+// (c00-c10) and top edge (c01-c11) entries of E; the left edge (c00-c01) and
+// right edge (c10-c11) entries of N; the diagonal edge (c00-c11) entry of NE;
+// w_c and b_f,c for each corner.
+#include "p2m_internal.hpp"
+
+namespace p2m {
+
+namespace {
+
+// quantity slots of the per-cell parts
+enum : int {
+    Q_D00 = 0, Q_D10, Q_D11, Q_D01,
+    Q_EB, Q_ET, Q_NL, Q_NR, Q_NE,
+    Q_W00, Q_W10, Q_W11, Q_W01,
+    Q_B = 13   // then 4 per field: b00, b10, b11, b01
+};
+
+template <typename T, int F, int TS>
+__global__ __launch_bounds__(TS * TS) void k_assemble2d(Mesh m, Particles<T> P,
+                                                       const T* __restrict__ values,
+                                                       const int32_t* __restrict__ perm,
+                                                       const int32_t* __restrict__ cell_start,
+                                                       T* __restrict__ b, T* __restrict__ w,
+                                                       T* __restrict__ coef, int tiles_x) {
+    constexpr int HS = TS + 1;
+    constexpr int HC = HS * HS;
+    constexpr int NQ = Q_B + 4 * F;
+    __shared__ T part[NQ][HC];
+
+    const int tile = blockIdx.x;
+    const int i0 = (tile % tiles_x) * TS;
+    const int j0 = (tile / tiles_x) * TS;
+    const T v_uni = (T)m.v_uniform;
+
+    for (int hc = threadIdx.x; hc < HC; hc += TS * TS) {
+        const int hx = hc % HS, hy = hc / HS;
+        int gi = i0 - 1 + hx, gj = j0 - 1 + hy;
+        if (gi >= m.nx || gj >= m.ny) continue;  // beyond the last tile's nodes: never read
+        if (gi < 0) gi += m.nx;
+        if (gj < 0) gj += m.ny;
+        const int c = gi + m.nx * gj;
+        T acc[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = (T)0;
+        const int s = cell_start[c], e = cell_start[c + 1];
+        for (int kk = s; kk < e; ++kk) {
+            const int i = perm[kk];
+            int cx, cy;
+            double xi, eta;
+            bool fx, fy;
+            locate_axis((double)P.x[i], m.nx, m.inv_hx, cx, xi, fx);
+            locate_axis((double)P.y[i], m.ny, m.inv_hy, cy, eta, fy);
+            T c00, c10, c11, c01;
+            corner_weights<T>(xi, eta, c00, c10, c11, c01);
+            const T v = P.vol ? P.vol[i] : v_uni;
+            const T v00 = v * c00, v10 = v * c10, v11 = v * c11, v01 = v * c01;
+            acc[Q_D00] += v00 * c00;
+            acc[Q_D10] += v10 * c10;
+            acc[Q_D11] += v11 * c11;
+            acc[Q_D01] += v01 * c01;
+            acc[Q_EB] += v00 * c10;
+            acc[Q_ET] += v01 * c11;
+            acc[Q_NL] += v00 * c01;
+            acc[Q_NR] += v10 * c11;
+            acc[Q_NE] += v00 * c11;
+            acc[Q_W00] += v00;
+            acc[Q_W10] += v10;
+            acc[Q_W11] += v11;
+            acc[Q_W01] += v01;
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const T a = values[(size_t)f * m.np + i];
+                acc[Q_B + 4 * f + 0] += v00 * a;
+                acc[Q_B + 4 * f + 1] += v10 * a;
+                acc[Q_B + 4 * f + 2] += v11 * a;
+                acc[Q_B + 4 * f + 3] += v01 * a;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) part[q][hc] = acc[q];
+    }
+    __syncthreads();
+
+    const int li = threadIdx.x % TS, lj = threadIdx.x / TS;
+    const int gi = i0 + li, gj = j0 + lj;
+    if (gi >= m.nx || gj >= m.ny) return;
+    const int k = gi + m.nx * gj;
+    // halo coordinates of the cells around node (gi, gj)
+    const int cA = (li + 1) + HS * (lj + 1);  // cell (i, j): node is its c00
+    const int cB = li + HS * (lj + 1);        // cell (i-1, j): node is its c10
+    const int cC = li + HS * lj;              // cell (i-1, j-1): node is its c11
+    const int cD = (li + 1) + HS * lj;        // cell (i, j-1): node is its c01
+    w[k] = ((part[Q_W00][cA] + part[Q_W10][cB]) + part[Q_W11][cC]) + part[Q_W01][cD];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        b[(size_t)f * m.nn + k] = ((part[Q_B + 4 * f + 0][cA] + part[Q_B + 4 * f + 1][cB]) +
+                                   part[Q_B + 4 * f + 2][cC]) +
+                                  part[Q_B + 4 * f + 3][cD];
+    }
+    if (coef) {
+        coef[k] = ((part[Q_D00][cA] + part[Q_D10][cB]) + part[Q_D11][cC]) + part[Q_D01][cD];
+        coef[(size_t)m.nn + k] = part[Q_EB][cA] + part[Q_ET][cD];       // M(k, k+x)
+        coef[(size_t)2 * m.nn + k] = part[Q_NL][cA] + part[Q_NR][cB];   // M(k, k+y)
+        coef[(size_t)3 * m.nn + k] = part[Q_NE][cA];                    // M(k, k+x+y)
+    }
+}
+
+// 1D: a tile of TS nodes and the TS+1 cells touching it (one extra on the left).
+// Per cell: diagonal parts at the left / right node, the edge entry, w and b at
+// both nodes.
+template <typename T, int F, int TS>
+__global__ __launch_bounds__(TS) void k_assemble1d(Mesh m, Particles<T> P,
+                                                  const T* __restrict__ values,
+                                                  const int32_t* __restrict__ perm,
+                                                  const int32_t* __restrict__ cell_start,
+                                                  T* __restrict__ b, T* __restrict__ w,
+                                                  T* __restrict__ coef) {
+    constexpr int HC = TS + 1;
+    constexpr int NQ = 5 + 2 * F;  // DL, DR, E, WL, WR, then bL, bR per field
+    __shared__ T part[NQ][HC];
+    const int i0 = blockIdx.x * TS;
+    const T v_uni = (T)m.v_uniform;
+    for (int hc = threadIdx.x; hc < HC; hc += TS) {
+        int gi = i0 - 1 + hc;
+        if (gi >= m.nx) continue;
+        if (gi < 0) gi += m.nx;
+        T acc[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = (T)0;
+        const int s = cell_start[gi], e = cell_start[gi + 1];
+        for (int kk = s; kk < e; ++kk) {
+            const int i = perm[kk];
+            int cx;
+            double xi;
+            bool fx;
+            locate_axis((double)P.x[i], m.nx, m.inv_hx, cx, xi, fx);
+            const T cl = (T)__dsub_rn(1.0, xi), cr = (T)xi;
+            const T v = P.vol ? P.vol[i] : v_uni;
+            const T vl = v * cl, vr = v * cr;
+            acc[0] += vl * cl;
+            acc[1] += vr * cr;
+            acc[2] += vl * cr;
+            acc[3] += vl;
+            acc[4] += vr;
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const T a = values[(size_t)f * m.np + i];
+                acc[5 + 2 * f] += vl * a;
+                acc[6 + 2 * f] += vr * a;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) part[q][hc] = acc[q];
+    }
+    __syncthreads();
+    const int gi = i0 + threadIdx.x;
+    if (gi >= m.nx) return;
+    const int cA = threadIdx.x + 1;  // cell i: node is its left end
+    const int cB = threadIdx.x;      // cell i-1: node is its right end
+    w[gi] = part[3][cA] + part[4][cB];
+#pragma unroll
+    for (int f = 0; f < F; ++f) b[(size_t)f * m.nn + gi] = part[5 + 2 * f][cA] + part[6 + 2 * f][cB];
+    if (coef) {
+        coef[gi] = part[0][cA] + part[1][cB];
+        coef[(size_t)m.nn + gi] = part[2][cA];
+    }
+}
+
+template <typename T>
+__global__ void k_finalize(int nn, int F, const T* __restrict__ b, const T* __restrict__ w,
+                           int pic, T measure, T* __restrict__ out,
+                           p2m_report* __restrict__ rep) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    bool orphan = false;
+    if (k < nn) {
+        const T wk = w[k];
+        orphan = !(wk > (T)0);
+        for (int f = 0; f < F; ++f) {
+            const T bk = b[(size_t)f * nn + k];
+            T o;
+            if (pic) o = bk / measure;
+            else o = orphan ? (T)0 : bk / wk;
+            out[(size_t)f * nn + k] = o;
+        }
+    }
+    if (rep) {
+        // one atomic per wave that holds an orphan
+        uint64_t mask = __ballot(k < nn && orphan);
+        if (mask && (threadIdx.x & 63) == __ffsll((unsigned long long)mask) - 1) {
+            atomicAdd(&rep->n_orphan, (int)__popcll(mask));
+            atomicOr(&rep->flags, (uint32_t)P2M_FLAG_ORPHAN);
+        }
+    }
+}
+
+template <typename T, int F>
+hipError_t assemble_f(const Mesh& m, Particles<T> P, const T* values, const int32_t* perm,
+                      const int32_t* cs, T* b, T* w, T* coef, hipStream_t stream) {
+    if (m.dim == 1) {
+        constexpr int TS = 256;
+        int grid = (m.nx + TS - 1) / TS;
+        hipLaunchKernelGGL((k_assemble1d<T, F, TS>), dim3(grid), dim3(TS), 0, stream, m, P, values,
+                           perm, cs, b, w, coef);
+        return hipGetLastError();
+    }
+    constexpr size_t lds16 = (size_t)(Q_B + 4 * F) * 17 * 17 * sizeof(T);
+    if constexpr (lds16 <= 65536) {
+        constexpr int TS = 16;
+        int tx = (m.nx + TS - 1) / TS, ty = (m.ny + TS - 1) / TS;
+        hipLaunchKernelGGL((k_assemble2d<T, F, TS>), dim3(tx * ty), dim3(TS * TS), 0, stream, m,
+                           P, values, perm, cs, b, w, coef, tx);
+    } else {
+        constexpr int TS = 8;
+        int tx = (m.nx + TS - 1) / TS, ty = (m.ny + TS - 1) / TS;
+        hipLaunchKernelGGL((k_assemble2d<T, F, TS>), dim3(tx * ty), dim3(TS * TS), 0, stream, m,
+                           P, values, perm, cs, b, w, coef, tx);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_assemble(const Mesh& m, Particles<T> P, const T* values, int F,
+                           const int32_t* perm, const int32_t* cell_start, T* b, T* w, T* coef,
+                           hipStream_t stream) {
+    switch (F) {
+        case 1: return assemble_f<T, 1>(m, P, values, perm, cell_start, b, w, coef, stream);
+        case 2: return assemble_f<T, 2>(m, P, values, perm, cell_start, b, w, coef, stream);
+        case 3: return assemble_f<T, 3>(m, P, values, perm, cell_start, b, w, coef, stream);
+        case 4: return assemble_f<T, 4>(m, P, values, perm, cell_start, b, w, coef, stream);
+        case 5: return assemble_f<T, 5>(m, P, values, perm, cell_start, b, w, coef, stream);
+        case 6: return assemble_f<T, 6>(m, P, values, perm, cell_start, b, w, coef, stream);
+        case 7: return assemble_f<T, 7>(m, P, values, perm, cell_start, b, w, coef, stream);
+        case 8: return assemble_f<T, 8>(m, P, values, perm, cell_start, b, w, coef, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_assemble<float>(const Mesh&, Particles<float>, const float*, int,
+                                           const int32_t*, const int32_t*, float*, float*, float*,
+                                           hipStream_t);
+template hipError_t launch_assemble<double>(const Mesh&, Particles<double>, const double*, int,
+                                            const int32_t*, const int32_t*, double*, double*,
+                                            double*, hipStream_t);
+
+template <typename T>
+hipError_t launch_finalize(const Mesh& m, int F, const T* b, const T* w, int pic, T* out,
+                           p2m_report* rep, hipStream_t stream) {
+    const int block = 256;
+    int grid = (m.nn + block - 1) / block;
+    hipLaunchKernelGGL(k_finalize<T>, dim3(grid), dim3(block), 0, stream, m.nn, F, b, w, pic,
+                       (T)m.cell_measure, out, rep);
+    return hipGetLastError();
+}
+template hipError_t launch_finalize<float>(const Mesh&, int, const float*, const float*, int,
+                                           float*, p2m_report*, hipStream_t);
+template hipError_t launch_finalize<double>(const Mesh&, int, const double*, const double*, int,
+                                            double*, p2m_report*, hipStream_t);
+
+}  // namespace p2m

@@ -1,0 +1,259 @@
+// Binning of particles by cell: a stable counting sort.
+//
+//   locate_count : FP64 locate of every particle, cell key, per-cell counts
+//                  (integer atomics: order-independent, so the counts are exact)
+//   exclusive_scan: cell_start = exclusive prefix sum of the counts
+//   place        : every particle takes a free slot of its cell (unordered)
+//   segment_sort : every cell sorts its slots by original index, which makes the
+//                  permutation exactly the stable (cell, original index) order
+//
+// The result does not depend on the order in which the atomics were served.
+#include "p2m_internal.hpp"
+
+namespace p2m {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void k_report_clear(p2m_report* rep) {
+    int t = threadIdx.x;
+    if (t < 8) {
+        rep->iters[t] = 0;
+        rep->refines[t] = 0;
+        rep->rel_residual[t] = 0.0;
+    }
+    if (t == 0) {
+        rep->flags = 0u;
+        rep->n_orphan = 0;
+        rep->n_invalid = 0;
+        rep->reserved = 0;
+    }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int32_t value, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = value;
+}
+
+template <typename T>
+__global__ void k_locate_count(Mesh m, Particles<T> P, int32_t* __restrict__ key,
+                               int32_t* __restrict__ counts, p2m_report* __restrict__ rep) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.np) return;
+    bool fin_x, fin_y = true;
+    int cx, cy = 0;
+    double xi, eta;
+    bool ok = locate_axis((double)P.x[i], m.nx, m.inv_hx, cx, xi, fin_x);
+    if (m.dim == 2) ok = locate_axis((double)P.y[i], m.ny, m.inv_hy, cy, eta, fin_y) && ok;
+    int k = -1;
+    if (ok) {
+        k = cx + m.nx * cy;
+        atomicAdd(&counts[k], 1);
+    } else if (rep) {
+        uint32_t f = (fin_x && fin_y) ? P2M_FLAG_RANGE : P2M_FLAG_NONFINITE;
+        atomicOr(&rep->flags, f);
+        atomicAdd(&rep->n_invalid, 1);
+    }
+    key[i] = k;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 counts (three phases: block sums, scan of the block
+// sums by one block, per-block scan plus offset)
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ int wave_inclusive_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int u = __shfl_up(v, d, 64);
+        if (lane >= d) v += u;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one int per thread (blockDim.x == kBlock); also
+// returns the block total.
+__device__ __forceinline__ int block_exclusive_scan(int v, int& total) {
+    __shared__ int wave_tot[kBlock / 64];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    int inc = wave_inclusive_scan(v);
+    if (lane == 63) wave_tot[wave] = inc;
+    __syncthreads();
+    int off = 0;
+    total = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wave) off += wave_tot[w];
+        total += wave_tot[w];
+    }
+    __syncthreads();
+    return off + inc - v;
+}
+
+__global__ void k_scan_block_sums(const int32_t* __restrict__ in, int n,
+                                  int32_t* __restrict__ block_sums) {
+    int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        int idx = base + j;
+        if (idx < n) s += in[idx];
+    }
+    int total;
+    (void)block_exclusive_scan(s, total);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+// One block scans the nb block sums in place (exclusive) and writes the grand
+// total to out[n].
+__global__ void k_scan_single(int32_t* __restrict__ sums, int nb, int32_t* __restrict__ out,
+                              int n) {
+    int carry = 0;
+    for (int base = 0; base < nb; base += kScanTile) {
+        int idx0 = base + threadIdx.x * kScanItems;
+        int vals[kScanItems];
+        int s = 0;
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            vals[j] = (idx0 + j < nb) ? sums[idx0 + j] : 0;
+            s += vals[j];
+        }
+        int total;
+        int ex = block_exclusive_scan(s, total) + carry;
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            if (idx0 + j < nb) sums[idx0 + j] = ex;
+            ex += vals[j];
+        }
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ void k_scan_apply(const int32_t* __restrict__ in, int n,
+                             const int32_t* __restrict__ block_off, int32_t* __restrict__ out) {
+    int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int vals[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        vals[j] = (base + j < n) ? in[base + j] : 0;
+        s += vals[j];
+    }
+    int total;
+    int ex = block_exclusive_scan(s, total) + block_off[blockIdx.x];
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        if (base + j < n) out[base + j] = ex;
+        ex += vals[j];
+    }
+}
+
+__global__ void k_place(int np, const int32_t* __restrict__ key,
+                        const int32_t* __restrict__ cell_start, int32_t* __restrict__ fill,
+                        int32_t* __restrict__ perm) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    int k = key[i];
+    if (k < 0) return;
+    int slot = cell_start[k] + atomicAdd(&fill[k], 1);
+    perm[slot] = i;
+}
+
+__global__ void k_perm_tail(int np, int ncells, const int32_t* __restrict__ cell_start,
+                            int32_t* __restrict__ perm) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    if (i >= cell_start[ncells]) perm[i] = -1;
+}
+
+// Insertion sort of every cell's slots by original index.  Segments are short
+// (a few particles per cell); the cost grows with the square of a cell's count.
+__global__ void k_segment_sort(int ncells, const int32_t* __restrict__ cell_start,
+                               int32_t* __restrict__ perm) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    int s = cell_start[c], e = cell_start[c + 1];
+    for (int i = s + 1; i < e; ++i) {
+        int v = perm[i];
+        int j = i - 1;
+        while (j >= s && perm[j] > v) {
+            perm[j + 1] = perm[j];
+            --j;
+        }
+        perm[j + 1] = v;
+    }
+}
+
+inline int grid_for(size_t n, int block) { return (int)((n + block - 1) / block); }
+
+}  // namespace
+
+hipError_t launch_report_clear(p2m_report* rep, hipStream_t stream) {
+    if (!rep) return hipSuccess;
+    hipLaunchKernelGGL(k_report_clear, dim3(1), dim3(64), 0, stream, rep);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t value, size_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    int grid = (int)((n + kBlock - 1) / kBlock);
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid), dim3(kBlock), 0, stream, p, value, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_locate_count(const Mesh& m, Particles<T> P, int32_t* key, int32_t* counts,
+                               p2m_report* rep, hipStream_t stream) {
+    if (m.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_locate_count<T>, dim3(grid_for(m.np, kBlock)), dim3(kBlock), 0, stream,
+                       m, P, key, counts, rep);
+    return hipGetLastError();
+}
+template hipError_t launch_locate_count<float>(const Mesh&, Particles<float>, int32_t*, int32_t*,
+                                               p2m_report*, hipStream_t);
+template hipError_t launch_locate_count<double>(const Mesh&, Particles<double>, int32_t*,
+                                                int32_t*, p2m_report*, hipStream_t);
+
+size_t scan_workspace_bytes(int n) {
+    size_t nb = (size_t)(n + kScanTile - 1) / kScanTile;
+    return nb * sizeof(int32_t);
+}
+
+hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, int32_t* block_sums,
+                                 hipStream_t stream) {
+    int nb = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_block_sums, dim3(nb), dim3(kBlock), 0, stream, counts, n,
+                       block_sums);
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kBlock), 0, stream, block_sums, nb, out, n);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, stream, counts, n, block_sums,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* cell_start,
+                        int32_t* fill, int32_t* perm, hipStream_t stream) {
+    if (m.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_place, dim3(grid_for(m.np, kBlock)), dim3(kBlock), 0, stream, m.np, key,
+                       cell_start, fill, perm);
+    hipLaunchKernelGGL(k_perm_tail, dim3(grid_for(m.np, kBlock)), dim3(kBlock), 0, stream, m.np,
+                       m.nn, cell_start, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_segment_sort(const Mesh& m, const int32_t* cell_start, int32_t* perm,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(k_segment_sort, dim3(grid_for(m.nn, kBlock)), dim3(kBlock), 0, stream,
+                       m.nn, cell_start, perm);
+    return hipGetLastError();
+}
+
+}  // namespace p2m

@@ -1,0 +1,509 @@
+// Mass-matrix solve M Abar = b (Sec. 2.4 eqs. (13), (19)) for F fields at once.
+//
+// Mixed-precision iterative refinement around conjugate gradients:
+//   outer: the solution is kept in FP64 (x64); the true residual
+//          r = b - M x64 is evaluated in FP64 from the stored coefficients;
+//          stop when ||r||_2 / ||b||_2 <= tol for every field;
+//   inner: CG in T (FP32 on the FP32 path) on the correction M d = r, with the
+//          stencil product, axpy and vector updates in T, every field sharing
+//          each coefficient read, and all dot products accumulated in FP64;
+//          the next outer step folds d into x64 in FP64.
+// The whole solve is one persistent cooperative kernel: grid-wide barriers
+// separate the phases; reductions are per-block FP64 partials that every block
+// sums in the same fixed order, so all blocks take identical decisions and the
+// result is deterministic.  Every loop is bounded (maxit, max_refine).
+//
+// Stencil storage (symmetric, periodic): D_k = M(k,k), E_k = M(k,k+x),
+// N_k = M(k,k+y), NE_k = M(k,k+x+y) in 2D; D_k, E_k = M(k,k+1) in 1D.
+#include "p2m_internal.hpp"
+
+#include <hip/hip_cooperative_groups.h>
+
+namespace cg = cooperative_groups;
+
+namespace p2m {
+
+namespace {
+
+constexpr int kCgBlock = 256;
+constexpr int kSlots = 3 * kMaxFields;  // partial slots per block and phase
+
+template <typename T>
+struct CgArgs {
+    Mesh m;
+    const T* coef;
+    const T* b;
+    T* xout;           // [F][nn] correction d during the solve, the result at the end
+    double* x64;       // [2][F][nn] solution in FP64 (ping-pong)
+    T* r;
+    T* p0;
+    T* p1;
+    T* q;
+    double* partials;  // [2][gridDim][kSlots]
+    p2m_solve_opts opts;
+    p2m_report* rep;
+};
+
+struct Nbr {
+    int k, xp, xm, yp, ym, pp, mm;
+};
+
+// neighbour indices of node k: k+x, k-x, k+y, k-y, k+x+y, k-x-y (2D); k+1, k-1 (1D)
+template <int DIM>
+__device__ __forceinline__ Nbr neighbours(const Mesh& m, int k) {
+    Nbr n;
+    n.k = k;
+    if (DIM == 1) {
+        n.xp = (k + 1 == m.nx) ? 0 : k + 1;
+        n.xm = (k == 0) ? m.nx - 1 : k - 1;
+        n.yp = n.ym = n.pp = n.mm = k;
+        return n;
+    }
+    const int j = k / m.nx, i = k - j * m.nx;
+    const int ip = (i + 1 == m.nx) ? 0 : i + 1, im = (i == 0) ? m.nx - 1 : i - 1;
+    const int jp = (j + 1 == m.ny) ? 0 : j + 1, jm = (j == 0) ? m.ny - 1 : j - 1;
+    n.xp = ip + m.nx * j;
+    n.xm = im + m.nx * j;
+    n.yp = i + m.nx * jp;
+    n.ym = i + m.nx * jm;
+    n.pp = ip + m.nx * jp;
+    n.mm = im + m.nx * jm;
+    return n;
+}
+
+// coefficients of row k: D_k, E_k, E_{k-x}, N_k, N_{k-y}, NE_k, NE_{k-x-y}
+template <typename T>
+struct Row {
+    T d, e, ew, n, ns, ne, nesw;
+};
+
+template <typename T, int DIM>
+__device__ __forceinline__ Row<T> load_row(const T* __restrict__ coef, int nn, const Nbr& n) {
+    Row<T> r;
+    r.d = coef[n.k];
+    r.e = coef[(size_t)nn + n.k];
+    r.ew = coef[(size_t)nn + n.xm];
+    if (DIM == 2) {
+        r.n = coef[(size_t)2 * nn + n.k];
+        r.ns = coef[(size_t)2 * nn + n.ym];
+        r.ne = coef[(size_t)3 * nn + n.k];
+        r.nesw = coef[(size_t)3 * nn + n.mm];
+    } else {
+        r.n = r.ns = r.ne = r.nesw = (T)0;
+    }
+    return r;
+}
+
+// (M v)_k for a vector given by an accessor v(idx), in arithmetic type A
+template <int DIM, typename A, typename T, typename V>
+__device__ __forceinline__ A apply_row(const Row<T>& c, const Nbr& n, V&& v) {
+    A s = (A)c.d * v(n.k) + (A)c.e * v(n.xp) + (A)c.ew * v(n.xm);
+    if (DIM == 2)
+        s += (A)c.n * v(n.yp) + (A)c.ns * v(n.ym) + (A)c.ne * v(n.pp) + (A)c.nesw * v(n.mm);
+    return s;
+}
+
+// block-wide sum of NV doubles per thread; result valid in thread 0
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* [4][NV] */) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double s = v[j];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) s += __shfl_down(s, d, 64);
+        v[j] = s;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) lds[wave * NV + j] = v[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double s = 0.0;
+            for (int w = 0; w < kCgBlock / 64; ++w) s += lds[w * NV + j];
+            v[j] = s;
+        }
+    }
+    __syncthreads();
+}
+
+template <int NV>
+__device__ __forceinline__ void store_partials(double* __restrict__ dst, const double (&v)[NV]) {
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) dst[(size_t)blockIdx.x * kSlots + j] = v[j];
+    }
+}
+
+// Sum of one phase's per-block partials over all blocks in a fixed order; every
+// block computes the same totals into tot[0..NV).
+template <int NV>
+__device__ __forceinline__ void grid_total(const double* __restrict__ part, int nblocks,
+                                           double* tot, double* lds) {
+    double acc[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) acc[j] = 0.0;
+    for (int bk = threadIdx.x; bk < nblocks; bk += kCgBlock) {
+        const double* pb = part + (size_t)bk * kSlots;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) acc[j] += pb[j];
+    }
+    block_sum<NV>(acc, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) tot[j] = acc[j];
+    }
+    __syncthreads();
+}
+
+template <typename T, int DIM, int F>
+__global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
+    cg::grid_group grid = cg::this_grid();
+    const Mesh& m = a.m;
+    const int nn = m.nn;
+    const int nblocks = gridDim.x;
+    const size_t pstride = (size_t)nblocks * kSlots;
+    const size_t xstride = (size_t)F * nn;
+
+    __shared__ double lds[(kCgBlock / 64) * kSlots];
+    __shared__ double tot[kSlots];
+    // per-field solver state, identical in every block
+    __shared__ double s_bb[F], s_rho[F], s_target[F], s_alpha[F], s_beta[F], s_relres[F];
+    __shared__ int s_iters[F], s_refines[F], s_done[F], s_inner[F], s_zero[F], s_xb[F];
+    __shared__ uint32_t s_flags;
+    __shared__ int s_any;
+
+    if (threadIdx.x < F) {
+        const int f = threadIdx.x;
+        s_iters[f] = 0;
+        s_refines[f] = 0;
+        s_done[f] = 0;
+        s_inner[f] = 0;
+        s_zero[f] = 0;
+        s_xb[f] = 0;
+        s_relres[f] = 0.0;
+        s_bb[f] = 0.0;
+        s_beta[f] = 0.0;
+    }
+    if (threadIdx.x == 0) s_flags = 0u;
+    __syncthreads();
+
+    int phase = 0;
+    const int k0 = blockIdx.x * kCgBlock + threadIdx.x;
+    const int kstride = nblocks * kCgBlock;
+    T* p_old = a.p0;
+    T* p_new = a.p1;
+
+    for (int outer = 0;; ++outer) {
+        // ---- R: fold the correction into x64 and evaluate r = b - M x64 in FP64 --
+        // slots: [f] ||r64||^2, [8+f] ||(T)r64||^2, [16+f] ||b||^2 (first pass)
+        {
+            double part[kSlots];
+#pragma unroll
+            for (int j = 0; j < kSlots; ++j) part[j] = 0.0;
+            for (int k = k0; k < nn; k += kstride) {
+                const Nbr n = neighbours<DIM>(m, k);
+                const Row<T> c = load_row<T, DIM>(a.coef, nn, n);
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    if (s_done[f]) continue;
+                    const double* xf = a.x64 + s_xb[f] * xstride + (size_t)f * nn;
+                    const T* df = a.xout + (size_t)f * nn;
+                    const bool fold = outer > 0;
+                    auto y = [&](int idx) -> double {
+                        return fold ? xf[idx] + (double)df[idx] : xf[idx];
+                    };
+                    const double mx = apply_row<DIM, double>(c, n, y);
+                    const double bk = (double)a.b[(size_t)f * nn + k];
+                    const double r64 = bk - mx;
+                    const T rt = (T)r64;
+                    a.r[(size_t)f * nn + k] = rt;
+                    a.x64[(s_xb[f] ^ 1) * xstride + (size_t)f * nn + k] = y(k);
+                    part[f] += r64 * r64;
+                    part[kMaxFields + f] += (double)rt * (double)rt;
+                    if (outer == 0) part[2 * kMaxFields + f] += bk * bk;
+                }
+            }
+            block_sum<kSlots>(part, lds);
+            store_partials<kSlots>(a.partials + (phase & 1) * pstride, part);
+        }
+        grid.sync();
+        grid_total<kSlots>(a.partials + (phase & 1) * pstride, nblocks, tot, lds);
+        ++phase;
+        if (threadIdx.x == 0) {
+            int any = 0;
+            for (int f = 0; f < F; ++f) {
+                if (s_done[f]) continue;
+                s_xb[f] ^= 1;  // the folded solution now lives in the other buffer
+                s_refines[f] += 1;
+                if (outer == 0) s_bb[f] = tot[2 * kMaxFields + f];
+                const double bb = s_bb[f];
+                if (bb == 0.0) {  // b == 0: the solution is 0
+                    s_zero[f] = 1;
+                    s_done[f] = 1;
+                    s_relres[f] = 0.0;
+                    continue;
+                }
+                const double rr = tot[f];
+                const double relres = sqrt(rr / bb);
+                s_relres[f] = relres;
+                if (relres <= a.opts.tol || outer >= a.opts.max_refine ||
+                    s_iters[f] >= a.opts.maxit || !(relres == relres)) {
+                    s_done[f] = 1;
+                    if (!(relres <= a.opts.tol)) s_flags |= P2M_FLAG_NOT_CONVERGED;
+                    continue;
+                }
+                s_rho[f] = tot[kMaxFields + f];
+                const double goal = 0.25 * a.opts.tol * a.opts.tol * bb;
+                const double rel = a.opts.inner_rtol * a.opts.inner_rtol * rr;
+                s_target[f] = goal > rel ? goal : rel;
+                s_inner[f] = 1;
+                any = 1;
+            }
+            s_any = any;
+        }
+        __syncthreads();
+        if (!s_any) break;
+
+        // ---- inner CG on M d = r, d starts at 0 ---------------------------------
+        for (int it = 0;; ++it) {
+            // A: p_new = r + beta p_old (at the node and its neighbours), q = M p_new
+            {
+                double part[kMaxFields];
+#pragma unroll
+                for (int j = 0; j < kMaxFields; ++j) part[j] = 0.0;
+                for (int k = k0; k < nn; k += kstride) {
+                    const Nbr n = neighbours<DIM>(m, k);
+                    const Row<T> c = load_row<T, DIM>(a.coef, nn, n);
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        if (!s_inner[f]) continue;
+                        const T* rf = a.r + (size_t)f * nn;
+                        const T* pf = p_old + (size_t)f * nn;
+                        const T beta = (T)s_beta[f];
+                        const bool first = (it == 0);
+                        auto pv = [&](int idx) -> T {
+                            return first ? rf[idx] : rf[idx] + beta * pf[idx];
+                        };
+                        const T pk = pv(n.k);
+                        const T qk = apply_row<DIM, T>(c, n, pv);
+                        p_new[(size_t)f * nn + k] = pk;
+                        a.q[(size_t)f * nn + k] = qk;
+                        part[f] += (double)pk * (double)qk;
+                    }
+                }
+                block_sum<kMaxFields>(part, lds);
+                store_partials<kMaxFields>(a.partials + (phase & 1) * pstride, part);
+            }
+            grid.sync();
+            grid_total<kMaxFields>(a.partials + (phase & 1) * pstride, nblocks, tot, lds);
+            ++phase;
+            if (threadIdx.x == 0) {
+                for (int f = 0; f < F; ++f) {
+                    if (!s_inner[f]) continue;
+                    const double pq = tot[f];
+                    if (!(pq > 0.0) || !(s_rho[f] == s_rho[f])) {
+                        // indefinite or non-finite: stop this field with its last x64
+                        s_inner[f] = 0;
+                        s_done[f] = 1;
+                        s_flags |= P2M_FLAG_BREAKDOWN | P2M_FLAG_NOT_CONVERGED;
+                        continue;
+                    }
+                    s_alpha[f] = s_rho[f] / pq;
+                }
+            }
+            __syncthreads();
+            // B: d += alpha p_new (d = alpha p_new on the first step), r -= alpha q
+            {
+                double part[kMaxFields];
+#pragma unroll
+                for (int j = 0; j < kMaxFields; ++j) part[j] = 0.0;
+                for (int k = k0; k < nn; k += kstride) {
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        if (!s_inner[f]) continue;
+                        const T al = (T)s_alpha[f];
+                        const size_t o = (size_t)f * nn + k;
+                        const T dk = (it == 0) ? (T)0 : a.xout[o];
+                        a.xout[o] = dk + al * p_new[o];
+                        const T rn = a.r[o] - al * a.q[o];
+                        a.r[o] = rn;
+                        part[f] += (double)rn * (double)rn;
+                    }
+                }
+                block_sum<kMaxFields>(part, lds);
+                store_partials<kMaxFields>(a.partials + (phase & 1) * pstride, part);
+            }
+            grid.sync();
+            grid_total<kMaxFields>(a.partials + (phase & 1) * pstride, nblocks, tot, lds);
+            ++phase;
+            if (threadIdx.x == 0) {
+                int any = 0;
+                for (int f = 0; f < F; ++f) {
+                    if (!s_inner[f]) continue;
+                    const double rho_new = tot[f];
+                    s_beta[f] = rho_new / s_rho[f];
+                    s_rho[f] = rho_new;
+                    s_iters[f] += 1;
+                    if (!(rho_new > s_target[f]) || s_iters[f] >= a.opts.maxit) {
+                        s_inner[f] = 0;
+                        continue;
+                    }
+                    any = 1;
+                }
+                s_any = any;
+            }
+            __syncthreads();
+            T* tmp = p_old;
+            p_old = p_new;
+            p_new = tmp;
+            if (!s_any) break;
+        }
+    }
+
+    // result: the FP64 solution rounded to T (0 for fields with b == 0)
+    for (int k = k0; k < nn; k += kstride) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            const size_t o = (size_t)f * nn + k;
+            a.xout[o] = s_zero[f] ? (T)0 : (T)a.x64[s_xb[f] * xstride + o];
+        }
+    }
+
+    if (blockIdx.x == 0 && threadIdx.x == 0 && a.rep) {
+        for (int f = 0; f < F; ++f) {
+            a.rep->iters[f] = s_iters[f];
+            a.rep->refines[f] = s_refines[f];
+            a.rep->rel_residual[f] = s_relres[f];
+        }
+        if (s_flags) atomicOr(&a.rep->flags, s_flags);
+    }
+}
+
+// Orphan regularisation (identity row where w_i == 0, which makes every
+// coefficient of row and column i zero, with b_i = 0) and the start vector in
+// FP64 (buffer 0 of x64).  start: FLIP = b/w, ZERO, USER = the values in x.
+template <typename T>
+__global__ void k_prepare(int nn, int F, T* __restrict__ coef, T* __restrict__ b,
+                          const T* __restrict__ w, const T* __restrict__ x,
+                          double* __restrict__ x64, int start, p2m_report* __restrict__ rep) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    bool orphan = false;
+    if (k < nn) {
+        const T wk = w[k];
+        orphan = !(wk > (T)0);
+        if (orphan) coef[k] = (T)1;
+        for (int f = 0; f < F; ++f) {
+            const size_t o = (size_t)f * nn + k;
+            double x0;
+            if (orphan) {
+                b[o] = (T)0;
+                x0 = 0.0;
+            } else if (start == P2M_START_FLIP) {
+                x0 = (double)b[o] / (double)wk;
+            } else if (start == P2M_START_ZERO) {
+                x0 = 0.0;
+            } else {
+                x0 = (double)x[o];
+            }
+            x64[o] = x0;
+        }
+    }
+    if (rep) {
+        uint64_t mask = __ballot(k < nn && orphan);
+        if (mask && (threadIdx.x & 63) == __ffsll((unsigned long long)mask) - 1) {
+            atomicAdd(&rep->n_orphan, (int)__popcll(mask));
+            atomicOr(&rep->flags, (uint32_t)P2M_FLAG_ORPHAN);
+        }
+    }
+}
+
+template <typename T, int DIM>
+const void* cg_kernel(int F) {
+    switch (F) {
+        case 1: return (const void*)k_cg<T, DIM, 1>;
+        case 2: return (const void*)k_cg<T, DIM, 2>;
+        case 3: return (const void*)k_cg<T, DIM, 3>;
+        case 4: return (const void*)k_cg<T, DIM, 4>;
+        case 5: return (const void*)k_cg<T, DIM, 5>;
+        case 6: return (const void*)k_cg<T, DIM, 6>;
+        case 7: return (const void*)k_cg<T, DIM, 7>;
+        case 8: return (const void*)k_cg<T, DIM, 8>;
+    }
+    return nullptr;
+}
+
+}  // namespace
+
+size_t cg_partials_bytes(int blocks) { return (size_t)2 * blocks * kSlots * sizeof(double); }
+
+template <typename T>
+int cg_max_blocks(int device) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+        return 0;
+    int per = 1 << 30;
+    for (int F = 1; F <= kMaxFields; ++F) {
+        for (int dim = 1; dim <= 2; ++dim) {
+            int b = 0;
+            const void* fn = dim == 1 ? cg_kernel<T, 1>(F) : cg_kernel<T, 2>(F);
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, kCgBlock, 0) != hipSuccess)
+                return 0;
+            if (b < per) per = b;
+        }
+    }
+    if (per > 2) per = 2;
+    if (per < 1) return 0;
+    return per * cus;
+}
+template int cg_max_blocks<float>(int);
+template int cg_max_blocks<double>(int);
+
+template <typename T>
+hipError_t launch_prepare_system(const Mesh& m, int F, T* coef, T* b, const T* w, const T* x,
+                                 double* x64, int start, p2m_report* rep, hipStream_t stream) {
+    const int block = 256;
+    const int grid = (m.nn + block - 1) / block;
+    hipLaunchKernelGGL(k_prepare<T>, dim3(grid), dim3(block), 0, stream, m.nn, F, coef, b, w, x,
+                       x64, start, rep);
+    return hipGetLastError();
+}
+template hipError_t launch_prepare_system<float>(const Mesh&, int, float*, float*, const float*,
+                                                 const float*, double*, int, p2m_report*,
+                                                 hipStream_t);
+template hipError_t launch_prepare_system<double>(const Mesh&, int, double*, double*,
+                                                  const double*, const double*, double*, int,
+                                                  p2m_report*, hipStream_t);
+
+template <typename T>
+hipError_t launch_cg(const Mesh& m, int F, const T* coef, const T* b, T* x, const CgWorkspace& ws,
+                     const p2m_solve_opts& opts, p2m_report* rep, hipStream_t stream) {
+    CgArgs<T> a;
+    a.m = m;
+    a.coef = coef;
+    a.b = b;
+    a.xout = x;
+    a.x64 = ws.x64;
+    a.r = (T*)ws.r;
+    a.p0 = (T*)ws.p0;
+    a.p1 = (T*)ws.p1;
+    a.q = (T*)ws.q;
+    a.partials = ws.partials;
+    a.opts = opts;
+    a.rep = rep;
+    void* args[] = {&a};
+    const void* fn = (m.dim == 1) ? cg_kernel<T, 1>(F) : cg_kernel<T, 2>(F);
+    if (!fn) return hipErrorInvalidValue;
+    return hipLaunchCooperativeKernel(fn, dim3(ws.blocks), dim3(kCgBlock), args, 0, stream);
+}
+template hipError_t launch_cg<float>(const Mesh&, int, const float*, const float*, float*,
+                                     const CgWorkspace&, const p2m_solve_opts&, p2m_report*,
+                                     hipStream_t);
+template hipError_t launch_cg<double>(const Mesh&, int, const double*, const double*, double*,
+                                      const CgWorkspace&, const p2m_solve_opts&, p2m_report*,
+                                      hipStream_t);
+
+}  // namespace p2m

@@ -1,0 +1,138 @@
+// Internal declarations shared by the HIP translation units of libp2m.
+// Not part of the public ABI (see include/p2m.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/p2m.h"
+
+namespace p2m {
+
+constexpr int kMaxFields = 8;
+constexpr size_t kAlign = 256;
+
+// Geometry of one periodic structured problem, computed once on the host in FP64.
+struct Mesh {
+    int dim;          // 1 or 2
+    int nx, ny;       // ny == 1 in 1D
+    int nn;           // nodes = cells = nx*ny
+    int np;           // particles
+    double inv_hx;    // nx / lx   (one FP64 division on the host)
+    double inv_hy;    // ny / ly
+    double cell_measure;  // hx*hy (2D) or hx (1D): the mesh volume v_i of every node
+    double v_uniform;     // lx*ly/np (2D) or lx/np (1D): particle volume when none is given
+};
+
+template <typename T>
+struct Particles {
+    const T* x;
+    const T* y;
+    const T* vol;     // may be null
+};
+
+// ---------------------------------------------------------------------------
+// locate: cell of a coordinate and the offset inside it, in FP64.
+// t = x * (n/L); c = floor(t); xi = t - c (exact); c == n wraps to 0.
+// Valid iff t is finite and 0 <= t < n + 1.  Same operations, same rounding as
+// a plain FP64 evaluation, so the cell key is bit-exact.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool locate_axis(double x, int n, double inv, int& c, double& xi,
+                                            bool& finite) {
+    double t = __dmul_rn(x, inv);
+    finite = __builtin_isfinite(t);
+    bool valid = finite && t >= 0.0 && t < (double)n + 1.0;
+    if (!valid) t = 0.0;
+    double cf = floor(t);
+    xi = __dsub_rn(t, cf);
+    c = (int)cf;
+    if (c == n) c = 0;
+    return valid;
+}
+
+// P1 weights of the four corners of a cell for a particle at offsets (xi, eta)
+// on the "/"-split square: xi >= eta is the lower triangle (n00, n10, n11) with
+// barycentrics (1-xi, xi-eta, eta); otherwise the upper triangle (n00, n11, n01)
+// with (1-eta, xi, eta-xi).  The corner not in the triangle gets 0.  The
+// differences are taken in FP64 and rounded once to T.
+template <typename T>
+__device__ __forceinline__ void corner_weights(double xi, double eta, T& c00, T& c10, T& c11,
+                                               T& c01) {
+    if (xi >= eta) {
+        c00 = (T)__dsub_rn(1.0, xi);
+        c10 = (T)__dsub_rn(xi, eta);
+        c11 = (T)eta;
+        c01 = (T)0;
+    } else {
+        c00 = (T)__dsub_rn(1.0, eta);
+        c11 = (T)xi;
+        c01 = (T)__dsub_rn(eta, xi);
+        c10 = (T)0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers implemented in the .hip translation units.  All are asynchronous on
+// `stream`; they return hipSuccess or the launch error.
+// ---------------------------------------------------------------------------
+
+// report: zero it (a fill kernel, so the call stays capturable into graphs)
+hipError_t launch_report_clear(p2m_report* rep, hipStream_t stream);
+hipError_t launch_fill_i32(int32_t* p, int32_t value, size_t n, hipStream_t stream);
+
+// binning
+template <typename T>
+hipError_t launch_locate_count(const Mesh& m, Particles<T> P, int32_t* key, int32_t* counts,
+                               p2m_report* rep, hipStream_t stream);
+size_t scan_workspace_bytes(int n);
+hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, int32_t* block_sums,
+                                 hipStream_t stream);
+hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* cell_start,
+                        int32_t* fill, int32_t* perm, hipStream_t stream);
+hipError_t launch_segment_sort(const Mesh& m, const int32_t* cell_start, int32_t* perm,
+                               hipStream_t stream);
+
+// scatter-assemble: b [F][nn], w [nn], coef [c_M][nn] or null
+template <typename T>
+hipError_t launch_assemble(const Mesh& m, Particles<T> P, const T* values, int F,
+                           const int32_t* perm, const int32_t* cell_start, T* b, T* w, T* coef,
+                           hipStream_t stream);
+
+// finalize: FLIP (divide by w, orphans 0) or PIC (divide by the mesh volume)
+template <typename T>
+hipError_t launch_finalize(const Mesh& m, int F, const T* b, const T* w, int pic, T* out,
+                           p2m_report* rep, hipStream_t stream);
+
+// M2P gather in caller order
+template <typename T>
+hipError_t launch_gather(const Mesh& m, Particles<T> P, const T* nodal, int F, T* out,
+                         p2m_report* rep, hipStream_t stream);
+
+// 1D delta P2M from the binned particles
+template <typename T>
+hipError_t launch_delta1d(const Mesh& m, Particles<T> P, const T* values, int F,
+                          const int32_t* perm, const int32_t* cell_start, T* out,
+                          hipStream_t stream);
+
+// mass solve
+struct CgWorkspace {
+    void* r;          // [F][nn] T
+    void* p0;         // [F][nn] T   (ping)
+    void* p1;         // [F][nn] T   (pong)
+    void* q;          // [F][nn] T
+    double* x64;      // [2][F][nn] FP64 solution (ping-pong)
+    double* partials; // [2][blocks][3*kMaxFields]
+    int blocks;       // grid size of the persistent kernel
+};
+size_t cg_partials_bytes(int blocks);
+template <typename T>
+hipError_t launch_prepare_system(const Mesh& m, int F, T* coef, T* b, const T* w, const T* x,
+                                 double* x64, int start, p2m_report* rep, hipStream_t stream);
+template <typename T>
+hipError_t launch_cg(const Mesh& m, int F, const T* coef, const T* b, T* x, const CgWorkspace& ws,
+                     const p2m_solve_opts& opts, p2m_report* rep, hipStream_t stream);
+template <typename T>
+int cg_max_blocks(int device);
+
+}  // namespace p2m

@@ -1,0 +1,71 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+entry point that include/p2m.h declares, and the ctypes layouts match the header."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "p2m.h")
+LIB = os.path.join(ROOT, "paper_1610_05258_amd", "libp2m.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+char\s*\*|p2m_status)\s+(p2m_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("p2m_create", "p2m_destroy", "p2m_workspace_size", "p2m_bin", "p2m_assemble",
+              "p2m_assign", "p2m_interpolate", "p2m_mass_assign", "p2m_status_string"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libp2m.so not built (run __graft_entry__.build())")
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(p2m_\w+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    L = ctypes.CDLL(LIB)
+    for n in declared_functions():
+        assert hasattr(L, n)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libp2m.so not built")
+def test_status_strings_and_struct_layouts():
+    from paper_1610_05258_amd import binding as B
+    assert B.status_string(0) == "P2M_OK"
+    assert B.status_string(3) == "P2M_ERR_WORKSPACE"
+    assert B.status_string(99) == "P2M_UNKNOWN_STATUS"
+    assert ctypes.sizeof(B.CProblem) == 64 and ctypes.sizeof(B.CSolveOpts) == 32
+    # header field order of the report (144 bytes)
+    raw = bytearray(144)
+    raw[128:132] = (5).to_bytes(4, "little")
+    raw[132:136] = (7).to_bytes(4, "little")
+    rep = B.Report.decode(bytes(raw))
+    assert rep.flags == 5 and rep.n_orphan == 7
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libp2m.so not built")
+def test_argument_errors_without_a_device():
+    """Argument checks that need no GPU: NULL context / problem are rejected."""
+    from paper_1610_05258_amd import binding as B
+    L = B.lib()
+    n = ctypes.c_size_t()
+    assert L.p2m_workspace_size(None, None, 1, ctypes.byref(n)) == 1
+    h = ctypes.c_void_p()
+    st = L.p2m_create(ctypes.byref(h), 0)
+    if st == 0:          # a GPU is present: exercise problem validation too
+        bad = B.CProblem(3, 8, 8, 0, 1.0, 1.0, 0, None, None, None)
+        assert L.p2m_workspace_size(h, ctypes.byref(bad), 1, ctypes.byref(n)) == 1
+        bad = B.CProblem(2, 8, 8, 0, float("nan"), 1.0, 0, None, None, None)
+        assert L.p2m_workspace_size(h, ctypes.byref(bad), 1, ctypes.byref(n)) == 5
+        bad = B.CProblem(2, 8, 8, 0, -1.0, 1.0, 0, None, None, None)
+        assert L.p2m_workspace_size(h, ctypes.byref(bad), 1, ctypes.byref(n)) == 4
+        L.p2m_destroy(h)
+    else:
+        assert st in (1, 6)

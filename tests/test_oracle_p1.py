@@ -394,3 +394,18 @@ def test_delta_1d_ties_and_single_particle():
     assert out[0, 1] == 2.0             # the later of two coincident particles wins at its node
     one = dict(prob, x=np.array([0.3]))
     assert np.all(p1.delta_1d(one, np.array([[7.0]])) == 7.0)
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_stencil_assembly_matches_sparse_assembly(dim):
+    prob = random_prob_2d(81, 7, 5, 900, with_vol=True) if dim == 2 else random_prob_1d(81, 9, 200, with_vol=True)
+    g = np.random.Generator(np.random.PCG64(12))
+    A = g.normal(size=(2, prob["x"].size))
+    a = p1.assemble(prob, A)
+    st = p1.assemble_stencil(prob, A)
+    ref = p1.stencil_coefficients(prob, a["M"])
+    for key in ref:
+        assert np.allclose(st[key], ref[key], atol=1e-15)
+    assert np.allclose(st["w"], a["w"], atol=1e-15) and np.allclose(st["b"], a["b"], atol=1e-15)
+    M2 = p1.stencil_matrix(prob, st)
+    assert abs(M2 - a["M"]).max() < 1e-15
