@@ -127,6 +127,15 @@ const char* p2m_status_string(p2m_status s);
 p2m_status p2m_create(void** ctx, int device);
 p2m_status p2m_destroy(void* ctx);
 
+/* Context options (p2m_set_option).  P2M_OPT_SOLVER selects the mass-solve
+ * kernel: 0 = automatic (the register-resident kernel when the problem is 2D
+ * FP32 with F <= 3 and its tiles fit one workgroup per tile on the device, the
+ * streaming kernel otherwise), 1 = always the streaming kernel, 2 = the resident
+ * kernel where it fits (same as 0).  Both solve the same system to the same
+ * tolerance; their rounding differs. */
+enum { P2M_OPT_SOLVER = 0 };
+p2m_status p2m_set_option(void* ctx, int32_t option, int32_t value);
+
 /* Bytes of workspace that every call below needs for this problem and field count
  * (the maximum over the entry points, so one workspace serves all of them).
  * The workspace must be 256-byte aligned device memory. */
@@ -174,6 +183,16 @@ p2m_status p2m_interpolate(void* ctx, const p2m_problem* prob, const void* nodal
 p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
                            const p2m_solve_opts* opts, void* nodal_inout, p2m_report* rep,
                            void* ws, size_t ws_bytes, void* stream);
+
+/* The solve step of p2m_mass_assign alone, for a system assembled by
+ * p2m_assemble with the same problem and field count (b [F][nn], w [nn], coef
+ * [4 or 2][nn] as documented there).  b and coef are modified in place: orphan
+ * rows (w_i == 0) become identity rows with b_i = 0.  opts->start may be FLIP
+ * (b/w), ZERO or USER (read from nodal_inout); DELTA1D needs the particles and is
+ * P2M_ERR_UNSUPPORTED here.  Launches exactly one kernel.  rep is required. */
+p2m_status p2m_mass_solve(void* ctx, const p2m_problem* prob, int32_t nfields, void* b,
+                          const void* w, void* coef, const p2m_solve_opts* opts, void* nodal_inout,
+                          p2m_report* rep, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -30,9 +30,11 @@ FLAG_NONFINITE = 1 << 4
 FLAG_LEARNED_FALLBACK = 1 << 5
 REPORT_BYTES = 144
 MAX_FIELDS = 8
+SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT = 0, 1, 2
 
 EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size", "p2m_bin",
-           "p2m_assemble", "p2m_assign", "p2m_interpolate", "p2m_mass_assign")
+           "p2m_assemble", "p2m_assign", "p2m_interpolate", "p2m_mass_assign", "p2m_mass_solve",
+           "p2m_set_option")
 
 
 class P2MError(RuntimeError):
@@ -73,6 +75,7 @@ def lib():
         L.p2m_status_string.argtypes = [ctypes.c_int]
         L.p2m_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
         L.p2m_destroy.argtypes = [vp]
+        L.p2m_set_option.argtypes = [vp, i32, i32]
         L.p2m_workspace_size.argtypes = [vp, pprob, i32, ctypes.POINTER(sz)]
         L.p2m_bin.argtypes = [vp, pprob, vp, vp, vp, vp, sz, vp]
         L.p2m_assemble.argtypes = [vp, pprob, vp, i32, vp, vp, vp, vp, vp, sz, vp]
@@ -80,6 +83,8 @@ def lib():
         L.p2m_interpolate.argtypes = [vp, pprob, vp, i32, vp, vp, vp, sz, vp]
         L.p2m_mass_assign.argtypes = [vp, pprob, vp, i32, ctypes.POINTER(CSolveOpts), vp, vp, vp,
                                       sz, vp]
+        L.p2m_mass_solve.argtypes = [vp, pprob, i32, vp, vp, vp, ctypes.POINTER(CSolveOpts), vp, vp,
+                                     vp, sz, vp]
         for name in EXPORTS[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -193,6 +198,10 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_solver(self, kind: int):
+        """0 = automatic, 1 = streaming kernel, 2 = register-resident where it fits."""
+        _check(lib().p2m_set_option(self.handle, 0, int(kind)), "p2m_set_option")
 
     def workspace_size(self, prob: Particles, nfields: int) -> int:
         n = ctypes.c_size_t()
@@ -316,4 +325,28 @@ def p2m_mass_assign(ctx: Context, prob: Particles, values, opts: CSolveOpts | No
                                  ctypes.byref(opts), ctypes.c_void_p(out.data_ptr()),
                                  ctypes.c_void_p(rep.data_ptr()), wp, wn, _stream_ptr(stream)),
            "p2m_mass_assign")
+    return out, rep
+
+
+def p2m_mass_solve(ctx: Context, prob: Particles, b, w, coef, opts: CSolveOpts | None = None,
+                   x0=None, stream=None, ws=None, rep=None, out=None):
+    """Solve step alone on a system from p2m_assemble (b and coef are modified in place:
+    orphan rows become identity rows).  Returns (nodal [F, nn], report tensor)."""
+    F = b.shape[0]
+    for t in (b, w, coef):
+        if t.dtype != prob.dtype or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("b, w, coef must be contiguous device tensors of the positions' dtype")
+    cp = prob.cstruct()
+    opts = opts if opts is not None else solve_opts(fp64=prob.dtype == torch.float64)
+    if out is None:
+        out = torch.empty((F, prob.n_nodes), dtype=prob.dtype, device=prob.x.device)
+    if x0 is not None:
+        out.copy_(x0)
+    rep = ctx.new_report() if rep is None else rep
+    wp, wn = _ws_args(ctx, prob, F, ws)
+    _check(lib().p2m_mass_solve(ctx.handle, ctypes.byref(cp), F, ctypes.c_void_p(b.data_ptr()),
+                                ctypes.c_void_p(w.data_ptr()), ctypes.c_void_p(coef.data_ptr()),
+                                ctypes.byref(opts), ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(rep.data_ptr()), wp, wn, _stream_ptr(stream)),
+           "p2m_mass_solve")
     return out, rep

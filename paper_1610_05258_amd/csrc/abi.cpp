@@ -17,6 +17,7 @@ struct Context {
     int device;
     int cg_blocks_f32;
     int cg_blocks_f64;
+    int resident_enabled;   // 1: use the register-resident solve where it fits
 };
 
 // Makes the context's device current for the duration of a call and restores
@@ -38,7 +39,7 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace carve-up.  Offsets are fixed functions of (problem, F, cg blocks).
 struct Layout {
-    size_t key, counts, cell_start, perm, scan, b, w, coef, r, p0, p1, q, x64, partials, report, total;
+    size_t key, counts, cell_start, perm, scan, b, w, coef, r, p0, p1, q, x64, partials, resident, report, total;
 };
 
 Layout make_layout(const Mesh& m, int F, size_t tsize, int cg_blocks) {
@@ -65,6 +66,8 @@ Layout make_layout(const Mesh& m, int F, size_t tsize, int cg_blocks) {
     L.q = take((size_t)F * nn * tsize);
     L.x64 = take((size_t)2 * F * nn * sizeof(double));
     L.partials = take(cg_partials_bytes(cg_blocks));
+    L.resident = take((m.dim == 2 && F <= kResidentMaxFields && tsize == 4)
+                          ? cgr_workspace_bytes(m, F, cgr_tiles(m)) : 0);
     L.report = take(sizeof(p2m_report));
     L.total = off;
     return L;
@@ -193,6 +196,27 @@ p2m_status run_assemble(const Prepared& pp, const p2m_problem* prob, const void*
 }
 
 template <typename T>
+p2m_status run_solve(const Context* c, const Prepared& pp, int F, T* b, const T* w, T* coef,
+                     int start, const p2m_solve_opts& opts, void* x) {
+    if (sizeof(T) == 4 && c->resident_enabled && pp.m.dim == 2 && F <= kResidentMaxFields &&
+        cgr_supported(pp.m, F, c->device)) {
+        P2M_TRY(launch_cg_resident(pp.m, F, (float*)coef, (float*)b, (const float*)w, (float*)x,
+                                   start, pp.ws + pp.L.resident, opts, pp.rep, pp.stream));
+        return P2M_OK;
+    }
+    CgWorkspace cw;
+    cw.r = pp.ws + pp.L.r;
+    cw.p0 = pp.ws + pp.L.p0;
+    cw.p1 = pp.ws + pp.L.p1;
+    cw.q = pp.ws + pp.L.q;
+    cw.x64 = (double*)(pp.ws + pp.L.x64);
+    cw.partials = (double*)(pp.ws + pp.L.partials);
+    cw.blocks = cg_blocks_for(c, pp.m, sizeof(T) == 8 ? P2M_F64 : P2M_F32);
+    P2M_TRY(launch_cg<T>(pp.m, F, coef, b, w, (T*)x, start, cw, opts, pp.rep, pp.stream));
+    return P2M_OK;
+}
+
+template <typename T>
 p2m_status run_mass(const Context* c, const Prepared& pp, const p2m_problem* prob,
                     const void* values, int F, const p2m_solve_opts& opts, void* x) {
     int32_t* perm = (int32_t*)(pp.ws + pp.L.perm);
@@ -210,18 +234,16 @@ p2m_status run_mass(const Context* c, const Prepared& pp, const p2m_problem* pro
                                   (T*)x, pp.stream));
         start = P2M_START_USER;
     }
-    double* x64 = (double*)(pp.ws + pp.L.x64);
-    P2M_TRY(launch_prepare_system<T>(pp.m, F, coef, b, w, (const T*)x, x64, start, pp.rep,
-                                     pp.stream));
-    CgWorkspace cw;
-    cw.r = pp.ws + pp.L.r;
-    cw.p0 = pp.ws + pp.L.p0;
-    cw.p1 = pp.ws + pp.L.p1;
-    cw.q = pp.ws + pp.L.q;
-    cw.x64 = x64;
-    cw.partials = (double*)(pp.ws + pp.L.partials);
-    cw.blocks = cg_blocks_for(c, pp.m, prob->dtype);
-    P2M_TRY(launch_cg<T>(pp.m, F, coef, b, (T*)x, cw, opts, pp.rep, pp.stream));
+    return run_solve<T>(c, pp, F, b, w, coef, start, opts, x);
+}
+
+p2m_status check_opts(const p2m_solve_opts* opts) {
+    if (!opts) return P2M_ERR_INVALID_ARG;
+    if (!isfinite(opts->tol) || !isfinite(opts->inner_rtol)) return P2M_ERR_NONFINITE;
+    if (!(opts->tol > 0.0) || opts->inner_rtol < 0.0 || opts->inner_rtol >= 1.0) return P2M_ERR_RANGE;
+    if (opts->maxit < 0 || opts->max_refine < 0 || opts->reserved != 0) return P2M_ERR_INVALID_ARG;
+    if (opts->start < P2M_START_FLIP || opts->start > P2M_START_DELTA1D) return P2M_ERR_INVALID_ARG;
+    if (opts->start == P2M_START_LEARNED) return P2M_ERR_UNSUPPORTED;
     return P2M_OK;
 }
 
@@ -255,12 +277,24 @@ p2m_status p2m_create(void** ctx, int device) {
     c->device = device;
     c->cg_blocks_f32 = cg_max_blocks<float>(device);
     c->cg_blocks_f64 = cg_max_blocks<double>(device);
+    c->resident_enabled = 1;
     if (c->cg_blocks_f32 <= 0 || c->cg_blocks_f64 <= 0) {
         free(c);
         return P2M_ERR_HIP;
     }
     *ctx = c;
     return P2M_OK;
+}
+
+p2m_status p2m_set_option(void* ctx, int32_t option, int32_t value) {
+    if (!ctx) return P2M_ERR_INVALID_ARG;
+    Context* c = (Context*)ctx;
+    if (option == P2M_OPT_SOLVER) {
+        if (value < 0 || value > 2) return P2M_ERR_INVALID_ARG;
+        c->resident_enabled = (value == 1) ? 0 : 1;
+        return P2M_OK;
+    }
+    return P2M_ERR_INVALID_ARG;
 }
 
 p2m_status p2m_destroy(void* ctx) {
@@ -347,14 +381,11 @@ p2m_status p2m_interpolate(void* ctx, const p2m_problem* prob, const void* nodal
 p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
                            const p2m_solve_opts* opts, void* nodal_inout, p2m_report* rep,
                            void* ws, size_t ws_bytes, void* stream) {
-    if (!opts || !rep) return P2M_ERR_INVALID_ARG;
-    if (!isfinite(opts->tol) || !isfinite(opts->inner_rtol)) return P2M_ERR_NONFINITE;
-    if (!(opts->tol > 0.0) || opts->inner_rtol < 0.0 || opts->inner_rtol >= 1.0) return P2M_ERR_RANGE;
-    if (opts->maxit < 0 || opts->max_refine < 0 || opts->reserved != 0) return P2M_ERR_INVALID_ARG;
-    if (opts->start < P2M_START_FLIP || opts->start > P2M_START_DELTA1D) return P2M_ERR_INVALID_ARG;
-    if (opts->start == P2M_START_LEARNED) return P2M_ERR_UNSUPPORTED;
+    if (!rep) return P2M_ERR_INVALID_ARG;
+    p2m_status s = check_opts(opts);
+    if (s != P2M_OK) return s;
     Prepared pp;
-    p2m_status s = prepare(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp);
+    s = prepare(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp);
     if (s != P2M_OK) return s;
     if (opts->start == P2M_START_DELTA1D && pp.m.dim != 1) return P2M_ERR_UNSUPPORTED;
     if ((pp.m.np > 0 && !values) || !nodal_inout) return P2M_ERR_INVALID_ARG;
@@ -365,6 +396,28 @@ p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* value
     return prob->dtype == P2M_F64
                ? run_mass<double>(c, pp, prob, values, nfields, *opts, nodal_inout)
                : run_mass<float>(c, pp, prob, values, nfields, *opts, nodal_inout);
+}
+
+p2m_status p2m_mass_solve(void* ctx, const p2m_problem* prob, int32_t nfields, void* b, const void* w,
+                          void* coef, const p2m_solve_opts* opts, void* nodal_inout, p2m_report* rep,
+                          void* ws, size_t ws_bytes, void* stream) {
+    if (!rep) return P2M_ERR_INVALID_ARG;
+    p2m_status s = check_opts(opts);
+    if (s != P2M_OK) return s;
+    if (opts->start == P2M_START_DELTA1D) return P2M_ERR_UNSUPPORTED;
+    Prepared pp;
+    s = prepare(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp);
+    if (s != P2M_OK) return s;
+    if (!b || !w || !coef || !nodal_inout) return P2M_ERR_INVALID_ARG;
+    DeviceGuard g(((Context*)ctx)->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+    const Context* c = (const Context*)ctx;
+    if (prob->dtype == P2M_F64)
+        return run_solve<double>(c, pp, nfields, (double*)b, (const double*)w, (double*)coef,
+                                 opts->start, *opts, nodal_inout);
+    return run_solve<float>(c, pp, nfields, (float*)b, (const float*)w, (float*)coef, opts->start,
+                            *opts, nodal_inout);
 }
 
 }  // extern "C"

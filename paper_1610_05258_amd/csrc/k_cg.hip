@@ -31,8 +31,8 @@ constexpr int kSlots = 3 * kMaxFields;  // partial slots per block and phase
 template <typename T>
 struct CgArgs {
     Mesh m;
-    const T* coef;
-    const T* b;
+    T* coef;           // stencil of M; the diagonal of orphan rows is set to 1 here
+    T* b;              // right-hand sides; orphan entries are set to 0 here
     T* xout;           // [F][nn] correction d during the solve, the result at the end
     double* x64;       // [2][F][nn] solution in FP64 (ping-pong)
     T* r;
@@ -40,6 +40,8 @@ struct CgArgs {
     T* p1;
     T* q;
     double* partials;  // [2][gridDim][kSlots]
+    const T* w;        // [nn] FLIP volumes (orphans: w == 0)
+    int start;         // P2M_START_FLIP / ZERO / USER (xout holds the user start)
     p2m_solve_opts opts;
     p2m_report* rep;
 };
@@ -196,6 +198,37 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
     const int kstride = nblocks * kCgBlock;
     T* p_old = a.p0;
     T* p_new = a.p1;
+
+    // ---- P: orphan regularisation and the FP64 start vector -------------------
+    // A node with w_i == 0 has every coefficient of its row and column equal to 0
+    // (all particle weights of that node vanish); its row becomes the identity
+    // with b_i = 0, so Abar_i = 0.  Start: FLIP = b/w, ZERO, USER = xout.
+    for (int k = k0; k < nn; k += kstride) {
+        const T wk = a.w[k];
+        const bool orphan = !(wk > (T)0);
+        if (orphan) a.coef[k] = (T)1;
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            const size_t o = (size_t)f * nn + k;
+            double x0;
+            if (orphan) {
+                a.b[o] = (T)0;
+                x0 = 0.0;
+            } else if (a.start == P2M_START_FLIP) {
+                x0 = (double)a.b[o] / (double)wk;
+            } else if (a.start == P2M_START_ZERO) {
+                x0 = 0.0;
+            } else {
+                x0 = (double)a.xout[o];
+            }
+            a.x64[o] = x0;
+        }
+        if (orphan && a.rep) {
+            atomicAdd(&a.rep->n_orphan, 1);
+            atomicOr(&a.rep->flags, (uint32_t)P2M_FLAG_ORPHAN);
+        }
+    }
+    grid.sync();
 
     for (int outer = 0;; ++outer) {
         // ---- R: fold the correction into x64 and evaluate r = b - M x64 in FP64 --
@@ -383,44 +416,6 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
     }
 }
 
-// Orphan regularisation (identity row where w_i == 0, which makes every
-// coefficient of row and column i zero, with b_i = 0) and the start vector in
-// FP64 (buffer 0 of x64).  start: FLIP = b/w, ZERO, USER = the values in x.
-template <typename T>
-__global__ void k_prepare(int nn, int F, T* __restrict__ coef, T* __restrict__ b,
-                          const T* __restrict__ w, const T* __restrict__ x,
-                          double* __restrict__ x64, int start, p2m_report* __restrict__ rep) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    bool orphan = false;
-    if (k < nn) {
-        const T wk = w[k];
-        orphan = !(wk > (T)0);
-        if (orphan) coef[k] = (T)1;
-        for (int f = 0; f < F; ++f) {
-            const size_t o = (size_t)f * nn + k;
-            double x0;
-            if (orphan) {
-                b[o] = (T)0;
-                x0 = 0.0;
-            } else if (start == P2M_START_FLIP) {
-                x0 = (double)b[o] / (double)wk;
-            } else if (start == P2M_START_ZERO) {
-                x0 = 0.0;
-            } else {
-                x0 = (double)x[o];
-            }
-            x64[o] = x0;
-        }
-    }
-    if (rep) {
-        uint64_t mask = __ballot(k < nn && orphan);
-        if (mask && (threadIdx.x & 63) == __ffsll((unsigned long long)mask) - 1) {
-            atomicAdd(&rep->n_orphan, (int)__popcll(mask));
-            atomicOr(&rep->flags, (uint32_t)P2M_FLAG_ORPHAN);
-        }
-    }
-}
-
 template <typename T, int DIM>
 const void* cg_kernel(int F) {
     switch (F) {
@@ -463,28 +458,15 @@ template int cg_max_blocks<float>(int);
 template int cg_max_blocks<double>(int);
 
 template <typename T>
-hipError_t launch_prepare_system(const Mesh& m, int F, T* coef, T* b, const T* w, const T* x,
-                                 double* x64, int start, p2m_report* rep, hipStream_t stream) {
-    const int block = 256;
-    const int grid = (m.nn + block - 1) / block;
-    hipLaunchKernelGGL(k_prepare<T>, dim3(grid), dim3(block), 0, stream, m.nn, F, coef, b, w, x,
-                       x64, start, rep);
-    return hipGetLastError();
-}
-template hipError_t launch_prepare_system<float>(const Mesh&, int, float*, float*, const float*,
-                                                 const float*, double*, int, p2m_report*,
-                                                 hipStream_t);
-template hipError_t launch_prepare_system<double>(const Mesh&, int, double*, double*,
-                                                  const double*, const double*, double*, int,
-                                                  p2m_report*, hipStream_t);
-
-template <typename T>
-hipError_t launch_cg(const Mesh& m, int F, const T* coef, const T* b, T* x, const CgWorkspace& ws,
-                     const p2m_solve_opts& opts, p2m_report* rep, hipStream_t stream) {
+hipError_t launch_cg(const Mesh& m, int F, T* coef, T* b, const T* w, T* x, int start,
+                     const CgWorkspace& ws, const p2m_solve_opts& opts, p2m_report* rep,
+                     hipStream_t stream) {
     CgArgs<T> a;
     a.m = m;
     a.coef = coef;
     a.b = b;
+    a.w = w;
+    a.start = start;
     a.xout = x;
     a.x64 = ws.x64;
     a.r = (T*)ws.r;
@@ -499,11 +481,11 @@ hipError_t launch_cg(const Mesh& m, int F, const T* coef, const T* b, T* x, cons
     if (!fn) return hipErrorInvalidValue;
     return hipLaunchCooperativeKernel(fn, dim3(ws.blocks), dim3(kCgBlock), args, 0, stream);
 }
-template hipError_t launch_cg<float>(const Mesh&, int, const float*, const float*, float*,
+template hipError_t launch_cg<float>(const Mesh&, int, float*, float*, const float*, float*, int,
                                      const CgWorkspace&, const p2m_solve_opts&, p2m_report*,
                                      hipStream_t);
-template hipError_t launch_cg<double>(const Mesh&, int, const double*, const double*, double*,
-                                      const CgWorkspace&, const p2m_solve_opts&, p2m_report*,
+template hipError_t launch_cg<double>(const Mesh&, int, double*, double*, const double*, double*,
+                                      int, const CgWorkspace&, const p2m_solve_opts&, p2m_report*,
                                       hipStream_t);
 
 }  // namespace p2m

@@ -126,13 +126,24 @@ struct CgWorkspace {
     int blocks;       // grid size of the persistent kernel
 };
 size_t cg_partials_bytes(int blocks);
+// One persistent cooperative kernel: orphan regularisation of (coef, b) in
+// place, the start vector (FLIP b/w, zero, or the values in x), then the solve;
+// x receives the result.
 template <typename T>
-hipError_t launch_prepare_system(const Mesh& m, int F, T* coef, T* b, const T* w, const T* x,
-                                 double* x64, int start, p2m_report* rep, hipStream_t stream);
-template <typename T>
-hipError_t launch_cg(const Mesh& m, int F, const T* coef, const T* b, T* x, const CgWorkspace& ws,
-                     const p2m_solve_opts& opts, p2m_report* rep, hipStream_t stream);
+hipError_t launch_cg(const Mesh& m, int F, T* coef, T* b, const T* w, T* x, int start,
+                     const CgWorkspace& ws, const p2m_solve_opts& opts, p2m_report* rep,
+                     hipStream_t stream);
 template <typename T>
 int cg_max_blocks(int device);
+
+// register-resident solve for 2D FP32 problems whose tiles fit one workgroup per
+// tile on the device (k_cgr.hip)
+constexpr int kResidentMaxFields = 3;
+size_t cgr_workspace_bytes(const Mesh& m, int F, int blocks);
+int cgr_tiles(const Mesh& m);
+bool cgr_supported(const Mesh& m, int F, int device);
+hipError_t launch_cg_resident(const Mesh& m, int F, float* coef, float* b, const float* w,
+                              float* x, int start, void* ws, const p2m_solve_opts& opts,
+                              p2m_report* rep, hipStream_t stream);
 
 }  // namespace p2m

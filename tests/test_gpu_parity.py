@@ -298,3 +298,39 @@ def test_argument_errors(B, ctx):
     small = torch.empty(1024, dtype=torch.uint8).cuda()
     with pytest.raises(B.P2MError):
         B.p2m_assign(ctx, d, B.FLIP, tens(B, vals, dt), ws=small)
+
+
+def test_mass_solve_matches_mass_assign(B, ctx):
+    """assemble + mass_solve is the same computation as mass_assign, bit for bit."""
+    prob, vals, dt = make_case("tg64_f32")
+    say("[mass_solve] tg64_f32")
+    d = to_dev(B, prob, dt)
+    v = tens(B, vals, dt)
+    o1, _ = B.p2m_mass_assign(ctx, d, v, mass_opts(B, dt))
+    o1 = o1.clone()
+    b, w, coef, _ = B.p2m_assemble(ctx, d, v)
+    o2, rep = B.p2m_mass_solve(ctx, d, b, w, coef, mass_opts(B, dt))
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2)
+    with pytest.raises(B.P2MError):
+        B.p2m_mass_solve(ctx, d, b, w, coef, mass_opts(B, dt, B.START_DELTA1D))
+
+
+@pytest.mark.parametrize("case", ["ragged2d_f32", "tg64_f32", "onecell_f32"])
+@pytest.mark.parametrize("solver", ["streaming", "resident"])
+def test_mass_assign_both_solvers(B, ctx, case, solver):
+    """The streaming and the register-resident solve kernels both meet the bar."""
+    say(f"[mass_assign solver={solver}] {case}")
+    prob, vals, dt = make_case(case)
+    d = to_dev(B, prob, dt)
+    ctx.set_solver(B.SOLVER_STREAMING if solver == "streaming" else B.SOLVER_RESIDENT)
+    try:
+        out, rep = B.p2m_mass_assign(ctx, d, tens(B, vals, dt), mass_opts(B, dt))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_solver(B.SOLVER_AUTO)
+    r = B.read_report(rep, vals.shape[0])
+    say(f"  iters={r.iters} refines={r.refines} relres={r.rel_residual} flags={r.flags}")
+    assert not (r.flags & (B.FLAG_NOT_CONVERGED | B.FLAG_BREAKDOWN))
+    ref, _ = p1.mass_assign(f64(prob), vals.astype(np.float64), solver="direct")
+    check_rel(out.cpu().numpy(), ref, TOL[dt], "mass")
