@@ -14,8 +14,8 @@ kernels of p2m_mass_assign.  value = fields x steps / wall time of the timed ste
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--tol 1e-8] [--no-cpu]
 
 Prints one JSON line.  Besides the contract keys it carries
-  roofline     : HBM roofline of the dominant kernel (the persistent CG solve),
-                 algorithmic bytes per launch / its event-timed duration;
+  roofline     : HBM roofline of the dominant kernel (the mass solve, one launch
+                 per step), algorithmic bytes per launch / its event-timed duration;
   cpu_baseline : the FP64 CPU oracle timed on this host on a bounded sample;
   accuracy     : relative l2 error of the GPU result against the FP64 oracle
                  solution of the same input, per field;
@@ -194,7 +194,8 @@ def main():
     if k_ref is not None:
         kk = max(k_ref)
         achieved = cg_algorithmic_bytes(kk, nn, F) / (cg_ms * 1e-3) / 1e9
-        result["roofline"] = dict(bound="hbm", kernel="k_cg (persistent CG solve)", achieved=achieved,
+        result["roofline"] = dict(bound="hbm", kernel="k_cgr<3> (register-resident mass solve)",
+                                  achieved=achieved,
                                   peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
                                   traffic=None, k_ref=kk,
                                   bytes_per_launch=cg_algorithmic_bytes(kk, nn, F))

@@ -30,36 +30,83 @@ enum : int {
     Q_B = 13   // then 4 per field: b00, b10, b11, b01
 };
 
-template <typename T, int F, int TS>
-__global__ __launch_bounds__(TS * TS) void k_assemble2d(Mesh m, Particles<T> P,
-                                                       const T* __restrict__ values,
-                                                       const int32_t* __restrict__ perm,
-                                                       const int32_t* __restrict__ cell_start,
-                                                       T* __restrict__ b, T* __restrict__ w,
-                                                       T* __restrict__ coef, int tiles_x) {
+// Staged 2D scatter.  A workgroup owns a TS x TS node tile and the (TS+1)^2 cells
+// around it.  The particles of those cells (their perm segments) are processed in
+// chunks of CH slots: first every thread loads particles slot-parallel (perm reads
+// coalesced, coordinate gathers independent of each other), locates them in FP64
+// and stages the four corner weights, the volume and the values in LDS; then one
+// thread per cell walks its slots in binned order and accumulates the cell's parts
+// in registers.  Chunks run in order, so every sum keeps the binned particle order.
+template <typename T, int F, int TS, int CH>
+__global__ __launch_bounds__(((TS + 1) * (TS + 1) + 63) / 64 * 64) void k_assemble2d(
+    Mesh m, Particles<T> P, const T* __restrict__ values, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ cell_start, T* __restrict__ b, T* __restrict__ w,
+    T* __restrict__ coef, int tiles_x) {
     constexpr int HS = TS + 1;
     constexpr int HC = HS * HS;
+    constexpr int NT = (HC + 63) / 64 * 64;     // threads: one per cell
     constexpr int NQ = Q_B + 4 * F;
-    __shared__ T part[NQ][HC];
+    constexpr int NS = 5 + F;                   // staged values per slot
+    constexpr size_t SLOT_B = (size_t)NS * CH * sizeof(T);
+    constexpr size_t PART_B = (size_t)NQ * HC * sizeof(T);
+    __shared__ __align__(16) unsigned char smem[SLOT_B > PART_B ? SLOT_B : PART_B];
+    __shared__ int c_seg[HC], c_off[HC + 1];
+    __shared__ short cmap[CH];                  // slot of the chunk -> its cell
+    __shared__ int wsum[NT / 64];
+    T* st = (T*)smem;                           // st[q * CH + slot]
+    T(*part)[HC] = (T(*)[HC])smem;              // after the chunks: part[q][cell]
 
     const int tile = blockIdx.x;
     const int i0 = (tile % tiles_x) * TS;
     const int j0 = (tile / tiles_x) * TS;
     const T v_uni = (T)m.v_uniform;
+    const int t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6;
 
-    for (int hc = threadIdx.x; hc < HC; hc += TS * TS) {
-        const int hx = hc % HS, hy = hc / HS;
+    // cell segments and their exclusive prefix (cells beyond the mesh: empty)
+    int cnt = 0;
+    if (t < HC) {
+        const int hx = t % HS, hy = t / HS;
         int gi = i0 - 1 + hx, gj = j0 - 1 + hy;
-        if (gi >= m.nx || gj >= m.ny) continue;  // beyond the last tile's nodes: never read
-        if (gi < 0) gi += m.nx;
-        if (gj < 0) gj += m.ny;
-        const int c = gi + m.nx * gj;
-        T acc[NQ];
+        int s0 = 0;
+        if (gi < m.nx && gj < m.ny) {
+            if (gi < 0) gi += m.nx;
+            if (gj < 0) gj += m.ny;
+            const int c = gi + m.nx * gj;
+            s0 = cell_start[c];
+            cnt = cell_start[c + 1] - s0;
+        }
+        c_seg[t] = s0;
+    }
+    int inc = cnt;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] = (T)0;
-        const int s = cell_start[c], e = cell_start[c + 1];
-        for (int kk = s; kk < e; ++kk) {
-            const int i = perm[kk];
+    for (int d = 1; d < 64; d <<= 1) {
+        const int u = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += u;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    int woff = 0;
+    for (int wv = 0; wv < wave; ++wv) woff += wsum[wv];
+    if (t < HC) c_off[t] = woff + inc - cnt;
+    if (t == NT - 1) c_off[HC] = woff + inc;
+    __syncthreads();
+    const int total = c_off[HC];
+    const int my_lo = (t < HC) ? c_off[t] : 0, my_hi = (t < HC) ? c_off[t + 1] : 0;
+
+    T acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = (T)0;
+
+    for (int cb = 0; cb < total; cb += CH) {
+        const int ce = min(cb + CH, total);
+        const int a0 = max(my_lo, cb), a1 = min(my_hi, ce);
+        for (int sl = a0; sl < a1; ++sl) cmap[sl - cb] = (short)t;
+        __syncthreads();
+        // stage: slot-parallel loads and FP64 locate
+        for (int sl = cb + t; sl < ce; sl += NT) {
+            const int hc = cmap[sl - cb];
+            const int i = perm[c_seg[hc] + (sl - c_off[hc])];
             int cx, cy;
             double xi, eta;
             bool fx, fy;
@@ -67,7 +114,21 @@ __global__ __launch_bounds__(TS * TS) void k_assemble2d(Mesh m, Particles<T> P,
             locate_axis((double)P.y[i], m.ny, m.inv_hy, cy, eta, fy);
             T c00, c10, c11, c01;
             corner_weights<T>(xi, eta, c00, c10, c11, c01);
-            const T v = P.vol ? P.vol[i] : v_uni;
+            const int o = sl - cb;
+            st[0 * CH + o] = c00;
+            st[1 * CH + o] = c10;
+            st[2 * CH + o] = c11;
+            st[3 * CH + o] = c01;
+            st[4 * CH + o] = P.vol ? P.vol[i] : v_uni;
+#pragma unroll
+            for (int f = 0; f < F; ++f) st[(5 + f) * CH + o] = values[(size_t)f * m.np + i];
+        }
+        __syncthreads();
+        // accumulate: one thread per cell, its slots in order
+        for (int sl = a0; sl < a1; ++sl) {
+            const int o = sl - cb;
+            const T c00 = st[0 * CH + o], c10 = st[1 * CH + o], c11 = st[2 * CH + o],
+                    c01 = st[3 * CH + o], v = st[4 * CH + o];
             const T v00 = v * c00, v10 = v * c10, v11 = v * c11, v01 = v * c01;
             acc[Q_D00] += v00 * c00;
             acc[Q_D10] += v10 * c10;
@@ -84,19 +145,23 @@ __global__ __launch_bounds__(TS * TS) void k_assemble2d(Mesh m, Particles<T> P,
             acc[Q_W01] += v01;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
-                const T a = values[(size_t)f * m.np + i];
+                const T a = st[(5 + f) * CH + o];
                 acc[Q_B + 4 * f + 0] += v00 * a;
                 acc[Q_B + 4 * f + 1] += v10 * a;
                 acc[Q_B + 4 * f + 2] += v11 * a;
                 acc[Q_B + 4 * f + 3] += v01 * a;
             }
         }
+        __syncthreads();
+    }
+    if (t < HC) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) part[q][hc] = acc[q];
+        for (int q = 0; q < NQ; ++q) part[q][t] = acc[q];
     }
     __syncthreads();
 
-    const int li = threadIdx.x % TS, lj = threadIdx.x / TS;
+    if (t >= TS * TS) return;
+    const int li = t % TS, lj = t / TS;
     const int gi = i0 + li, gj = j0 + lj;
     if (gi >= m.nx || gj >= m.ny) return;
     const int k = gi + m.nx * gj;
@@ -218,18 +283,16 @@ hipError_t assemble_f(const Mesh& m, Particles<T> P, const T* values, const int3
                            perm, cs, b, w, coef);
         return hipGetLastError();
     }
-    constexpr size_t lds16 = (size_t)(Q_B + 4 * F) * 17 * 17 * sizeof(T);
-    if constexpr (lds16 <= 65536) {
-        constexpr int TS = 16;
-        int tx = (m.nx + TS - 1) / TS, ty = (m.ny + TS - 1) / TS;
-        hipLaunchKernelGGL((k_assemble2d<T, F, TS>), dim3(tx * ty), dim3(TS * TS), 0, stream, m,
-                           P, values, perm, cs, b, w, coef, tx);
-    } else {
-        constexpr int TS = 8;
-        int tx = (m.nx + TS - 1) / TS, ty = (m.ny + TS - 1) / TS;
-        hipLaunchKernelGGL((k_assemble2d<T, F, TS>), dim3(tx * ty), dim3(TS * TS), 0, stream, m,
-                           P, values, perm, cs, b, w, coef, tx);
-    }
+    // tile 16x16 unless the per-cell parts of its 17x17 cells exceed 64 KB; chunk
+    // of staged slots sized to keep the staging area within 32 KB
+    constexpr size_t part16 = (size_t)(Q_B + 4 * F) * 17 * 17 * sizeof(T);
+    constexpr int TS = part16 <= 65536 ? 16 : 8;
+    constexpr int CHr = (int)(32768 / ((5 + F) * sizeof(T)));
+    constexpr int CH = (CHr > 2048 ? 2048 : CHr) / 64 * 64;
+    constexpr int NT = ((TS + 1) * (TS + 1) + 63) / 64 * 64;
+    const int tx = (m.nx + TS - 1) / TS, ty = (m.ny + TS - 1) / TS;
+    hipLaunchKernelGGL((k_assemble2d<T, F, TS, CH>), dim3(tx * ty), dim3(NT), 0, stream, m, P,
+                       values, perm, cs, b, w, coef, tx);
     return hipGetLastError();
 }
 

@@ -37,26 +37,52 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int32_t value, size_t n) {
     for (; i < n; i += stride) p[i] = value;
 }
 
+// Lanes of a wave whose keys are equal form a group; returns the mask of this
+// lane's group (0 for inactive lanes).  Wave-uniform loop over distinct keys.
+__device__ __forceinline__ uint64_t match_any(int key, bool active) {
+    uint64_t remaining = __ballot(active);
+    uint64_t mine = 0;
+    while (remaining) {
+        const int leader = __ffsll((unsigned long long)remaining) - 1;
+        const int lkey = __shfl(key, leader, 64);
+        const bool same = active && key == lkey;
+        const uint64_t grp = __ballot(same);
+        if (same) mine = grp;
+        remaining &= ~grp;
+    }
+    return mine;
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int lane = threadIdx.x & 63;
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// One atomic per distinct cell per wave: particles arrive spatially coherent in
+// typical inputs, so this removes most same-address atomic traffic.
 template <typename T>
 __global__ void k_locate_count(Mesh m, Particles<T> P, int32_t* __restrict__ key,
                                int32_t* __restrict__ counts, p2m_report* __restrict__ rep) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m.np) return;
-    bool fin_x, fin_y = true;
-    int cx, cy = 0;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = i < m.np;
+    bool fin_x = true, fin_y = true;
+    int cx = 0, cy = 0;
     double xi, eta;
-    bool ok = locate_axis((double)P.x[i], m.nx, m.inv_hx, cx, xi, fin_x);
-    if (m.dim == 2) ok = locate_axis((double)P.y[i], m.ny, m.inv_hy, cy, eta, fin_y) && ok;
-    int k = -1;
-    if (ok) {
-        k = cx + m.nx * cy;
-        atomicAdd(&counts[k], 1);
-    } else if (rep) {
-        uint32_t f = (fin_x && fin_y) ? P2M_FLAG_RANGE : P2M_FLAG_NONFINITE;
+    bool ok = false;
+    if (in) {
+        ok = locate_axis((double)P.x[i], m.nx, m.inv_hx, cx, xi, fin_x);
+        if (m.dim == 2) ok = locate_axis((double)P.y[i], m.ny, m.inv_hy, cy, eta, fin_y) && ok;
+    }
+    const int k = ok ? cx + m.nx * cy : -1;
+    const uint64_t grp = match_any(k, ok);
+    if (ok && (threadIdx.x & 63) == __ffsll((unsigned long long)grp) - 1)
+        atomicAdd(&counts[k], (int)__popcll(grp));
+    if (in && !ok && rep) {
+        const uint32_t f = (fin_x && fin_y) ? P2M_FLAG_RANGE : P2M_FLAG_NONFINITE;
         atomicOr(&rep->flags, f);
         atomicAdd(&rep->n_invalid, 1);
     }
-    key[i] = k;
+    if (in) key[i] = k;
 }
 
 // ---------------------------------------------------------------------------
@@ -156,15 +182,20 @@ __global__ void k_scan_apply(const int32_t* __restrict__ in, int n,
     }
 }
 
+// Every particle takes a free slot of its cell: one atomic per distinct cell per
+// wave reserves a run of slots, filled in lane (= original index) order.
 __global__ void k_place(int np, const int32_t* __restrict__ key,
                         const int32_t* __restrict__ cell_start, int32_t* __restrict__ fill,
                         int32_t* __restrict__ perm) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= np) return;
-    int k = key[i];
-    if (k < 0) return;
-    int slot = cell_start[k] + atomicAdd(&fill[k], 1);
-    perm[slot] = i;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = (i < np) ? key[i] : -1;
+    const bool ok = k >= 0;
+    const uint64_t grp = match_any(k, ok);
+    const int leader = ok ? __ffsll((unsigned long long)grp) - 1 : 0;
+    int base = 0;
+    if (ok && (threadIdx.x & 63) == leader) base = atomicAdd(&fill[k], (int)__popcll(grp));
+    base = __shfl(base, leader, 64);
+    if (ok) perm[cell_start[k] + base + (int)__popcll(grp & lanemask_lt())] = i;
 }
 
 __global__ void k_perm_tail(int np, int ncells, const int32_t* __restrict__ cell_start,
@@ -174,13 +205,27 @@ __global__ void k_perm_tail(int np, int ncells, const int32_t* __restrict__ cell
     if (i >= cell_start[ncells]) perm[i] = -1;
 }
 
-// Insertion sort of every cell's slots by original index.  Segments are short
-// (a few particles per cell); the cost grows with the square of a cell's count.
+// Insertion sort of every cell's slots by original index.  Segments are short (a
+// few particles per cell) and usually already in order: up to 16 entries are
+// checked from registers and nothing is written when they are sorted; longer or
+// unsorted segments are sorted in place (cost grows with the square of a cell's
+// count).
 __global__ void k_segment_sort(int ncells, const int32_t* __restrict__ cell_start,
                                int32_t* __restrict__ perm) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncells) return;
-    int s = cell_start[c], e = cell_start[c + 1];
+    const int s = cell_start[c], e = cell_start[c + 1];
+    const int n = e - s;
+    if (n <= 1) return;
+    if (n <= 16) {
+        int v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = (j < n) ? perm[s + j] : 0x7fffffff;
+        bool sorted = true;
+#pragma unroll
+        for (int j = 1; j < 16; ++j) sorted = sorted && (j >= n || v[j - 1] < v[j]);
+        if (sorted) return;
+    }
     for (int i = s + 1; i < e; ++i) {
         int v = perm[i];
         int j = i - 1;

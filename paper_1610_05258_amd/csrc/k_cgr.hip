@@ -32,8 +32,8 @@ namespace {
 
 constexpr int RX = 128;           // tile width in nodes
 constexpr int RY = 32;            // tile height
-constexpr int RNPT = 8;           // nodes per thread: a horizontal strip
-constexpr int RBS = RX * RY / RNPT;  // threads per workgroup (512): 8 waves of 4 rows each
+constexpr int RNPT = 8;           // nodes per thread
+constexpr int RBS = RX * RY / RNPT;  // threads per workgroup; a wave covers RNPT/2 rows
 constexpr int LW = RX + 2;        // LDS row stride including the halo ring
 constexpr int LH = RY + 2;
 constexpr int kGroups = 16;       // fan-in of the first barrier level
@@ -57,7 +57,6 @@ struct RArgs {
     const float* w;    // [nn]
     float* xout;       // [F][nn]  start (USER) on entry, result on exit
     double* x64;       // [F][nn]  FP64 solution, owner-only
-    float* pdir;       // [F][nn]  CG direction p, owner-only
     float* pubR;       // [2][F][nn] published boundary values
     float* pubW;
     float* pubS;
@@ -229,11 +228,11 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     const int i0 = (tile % a.tiles_x) * RX;
     const int j0 = (tile / a.tiles_x) * RY;
     const int txa = min(RX, m.nx - i0), tya = min(RY, m.ny - j0);
-    // node j of this thread: tile row 4*wave + j/2, column lane + 64*(j%2); a wave
-    // covers four whole rows, so every global access of a wave is two 64-wide
-    // contiguous runs and LDS accesses are conflict-free
+    // node j of this thread: tile row (RNPT/2)*wave + j/2, column lane + 64*(j%2);
+    // a wave covers whole rows, so every global access of a wave is a 64-wide
+    // contiguous run and LDS accesses are conflict-free
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row0 = 4 * wave;
+    const int row0 = (RNPT / 2) * wave;
     const int nhalo = 2 * (txa + 2) + 2 * tya;
     auto nrow = [&](int j) { return row0 + (j >> 1); };
     auto ncol = [&](int j) { return lane + 64 * (j & 1); };
@@ -244,7 +243,6 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     const size_t fb4 = (size_t)nn * 4, fb8 = (size_t)nn * 8;
     auto rs_x64 = [&](int f) { return mkrs(a.x64 + (size_t)f * nn, fb8); };
     auto rs_d = [&](int f) { return mkrs(a.xout + (size_t)f * nn, fb4); };
-    auto rs_p = [&](int f) { return mkrs(a.pdir + (size_t)f * nn, fb4); };
     auto rs_b = [&](int f) { return mkrs(a.b + (size_t)f * nn, fb4); };
     auto rs_pubX = [&](int f) { return mkrs(a.pubX + (size_t)f * nn, fb8); };
     auto rs_pub = [&](float* base, int par, int f) {
@@ -270,6 +268,14 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     __shared__ int s_any;
 
     auto lidx = [&](int lc, int lr) { return (lr + 1) * LW + (lc + 1); };
+    // per-field flags read once into a register after each decision point
+    auto inner_mask = [&]() {
+        uint32_t mk = 0;
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+            if (s_inner[f]) mk |= 1u << f;
+        return mk;
+    };
     auto cidx = [&](int lc, int lr) { return (lr + 1) * CW + (lc + 1); };
     const int q0 = lidx(lane, row0);   // LDS index of node 0; node j: + (j/2)*LW + 64*(j%2)
     const int qc0 = cidx(lane, row0);
@@ -351,7 +357,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
 
     // w = M r at the owned nodes for every inner-active field (r in the exchange
     // planes); node-major so each node's seven coefficients are read once
-    auto spmv_all = [&]() {
+    auto spmv_all = [&](uint32_t imask) {
 #pragma unroll
         for (int j = 0; j < RNPT; ++j) {
             const int qc = qcj(j), q = qj(j);
@@ -361,7 +367,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
             const bool on = amask & (1u << j);
 #pragma unroll
             for (int f = 0; f < F; ++f) {
-                if (!s_inner[f]) continue;
+                if (!(imask & (1u << f))) continue;
                 const float* L = lf + (size_t)f * LH * LW;
                 float acc = cD * L[q];
                 acc = fmaf(cE, L[q + 1], acc);
@@ -476,9 +482,10 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         if (!s_any) break;
 
         // ---- CG start: w = M r, delta = (w, r); p = s = d = 0 -------------------
+        uint32_t imask = inner_mask();
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-            if (!s_inner[f]) continue;
+            if (!(imask & (1u << f))) continue;
             float* L = lf + (size_t)f * LH * LW;
             const rsrc_t rd = rs_d(f);
 #pragma unroll
@@ -500,18 +507,18 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
             for (int f = 0; f < F; ++f) hv[f] = ldf<kCoherent>(rs_pub(a.pubR, ex, f), gh);
 #pragma unroll
             for (int f = 0; f < F; ++f)
-                if (s_inner[f]) lf[(size_t)f * LH * LW + lidx(lc, lr)] = hv[f];
+                if (imask & (1u << f)) lf[(size_t)f * LH * LW + lidx(lc, lr)] = hv[f];
         }
         __syncthreads();
         ex ^= 1;
         {
-            spmv_all();
+            spmv_all(imask);
             double pd[F];
 #pragma unroll
             for (int f = 0; f < F; ++f) pd[f] = 0.0;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
-                if (!s_inner[f]) continue;
+                if (!(imask & (1u << f))) continue;
                 const rsrc_t rr = rs_pub(a.pubR, ex, f), rw = rs_pub(a.pubW, ex, f),
                              rs = rs_pub(a.pubS, ex, f);
 #pragma unroll
@@ -550,6 +557,13 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
 
         // ---- inner iterations (one barrier each) -------------------------------
         while (alive) {
+            imask = inner_mask();
+            float af[F], bf[F];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                af[f] = s_af[f];
+                bf[f] = s_bf[f];
+            }
             // halo first (its loads are the longest latency): the neighbours' new
             // residual from their published state, all fields' loads in flight
             for (int h = threadIdx.x; h < nhalo; h += RBS) {
@@ -565,16 +579,16 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                 }
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
-                    if (!s_inner[f]) continue;
-                    const float sn = fmaf(s_bf[f], so[f], wo[f]);
-                    lf[(size_t)f * LH * LW + lidx(lc, lr)] = fmaf(-s_af[f], sn, ro[f]);
+                    if (!(imask & (1u << f))) continue;
+                    const float sn = fmaf(bf[f], so[f], wo[f]);
+                    lf[(size_t)f * LH * LW + lidx(lc, lr)] = fmaf(-af[f], sn, ro[f]);
                 }
             }
             // local updates and the new residual into LDS
 #pragma unroll
             for (int f = 0; f < F; ++f) {
-                if (!s_inner[f]) continue;
-                const float al = s_af[f], be = s_bf[f];
+                if (!(imask & (1u << f))) continue;
+                const float al = af[f], be = bf[f];
                 float* L = lf + (size_t)f * LH * LW;
 #pragma unroll
                 for (int j = 0; j < RNPT; ++j) {
@@ -588,13 +602,13 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
             __syncthreads();
             ex ^= 1;
             {
-                spmv_all();
+                spmv_all(imask);
                 double pg[2 * F];
 #pragma unroll
                 for (int q = 0; q < 2 * F; ++q) pg[q] = 0.0;
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
-                    if (!s_inner[f]) continue;
+                    if (!(imask & (1u << f))) continue;
                     const rsrc_t rr = rs_pub(a.pubR, ex, f), rw = rs_pub(a.pubW, ex, f),
                                  rs = rs_pub(a.pubS, ex, f);
 #pragma unroll
@@ -688,7 +702,6 @@ size_t cgr_workspace_bytes(const Mesh& m, int F, int blocks) {
     auto al = [](size_t v) { return (v + kAlign - 1) / kAlign * kAlign; };
     size_t s = 0;
     s += al((size_t)F * m.nn * sizeof(double));           // x64
-    s += al((size_t)F * m.nn * sizeof(float));            // pdir
     s += 3 * al((size_t)2 * F * m.nn * sizeof(float));    // pubR, pubW, pubS
     s += al((size_t)F * m.nn * sizeof(double));           // pubX
     s += al((size_t)kGroups * 32 * sizeof(unsigned));     // ctr
@@ -730,7 +743,6 @@ hipError_t launch_cg_resident(const Mesh& m, int F, float* coef, float* b, const
     a.opts = opts;
     a.rep = rep;
     a.x64 = (double*)p; p += al((size_t)F * m.nn * sizeof(double));
-    a.pdir = (float*)p; p += al((size_t)F * m.nn * sizeof(float));
     a.pubR = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubW = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubS = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
