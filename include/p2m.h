@@ -189,10 +189,60 @@ p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* value
  * [4 or 2][nn] as documented there).  b and coef are modified in place: orphan
  * rows (w_i == 0) become identity rows with b_i = 0.  opts->start may be FLIP
  * (b/w), ZERO or USER (read from nodal_inout); DELTA1D needs the particles and is
- * P2M_ERR_UNSUPPORTED here.  Launches exactly one kernel.  rep is required. */
+ * P2M_ERR_UNSUPPORTED here.  Launches one solver kernel (after a report clear and,
+ * for the tile solvers, a counter clear).  rep is required. */
 p2m_status p2m_mass_solve(void* ctx, const p2m_problem* prob, int32_t nfields, void* b,
                           const void* w, void* coef, const p2m_solve_opts* opts, void* nodal_inout,
                           p2m_report* rep, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches: many independent problems in one launch.
+ *
+ * A batch is nprob independent 2D FP32 problems (each its own mesh size, box,
+ * particles and volumes) with the same field count F, 1 <= F <= 3, nprob <= 128
+ * and nprob * F <= 256.  Every instance is mass-assigned exactly as
+ * p2m_mass_assign would do it alone with the register-resident solver
+ * (P2M_OPT_SOLVER 0 or 2): the same binning, the same scatter sums and the same
+ * solver arithmetic in the same order, so each instance's nodal values and
+ * report equal the single-problem ones bit for bit, whatever the other
+ * instances are.
+ *
+ * The whole batch is one HIP graph: clears, binning, scatter of all instances
+ * and one persistent solve kernel over the solver tiles of all instances (tiles
+ * are shared out over at most one workgroup per compute unit; the kernel's
+ * grid-wide barriers rely on all its workgroups being resident, which holds on a
+ * device not shared with other work, and its waits are bounded: a timed-out wait
+ * ends the solve with P2M_FLAG_BREAKDOWN | P2M_FLAG_NOT_CONVERGED).
+ *
+ * The context caches the graph of the last batch.  A call whose instance table
+ * (problems, particle / value / nodal pointers), F, options, workspace and
+ * reports are those of the previous call relaunches the cached graph (one
+ * hipGraphLaunch, nothing else); any other call builds a new graph first, which
+ * copies the instance table and tile maps (host memory) to the head of the
+ * workspace and synchronises `stream` once.
+ * --------------------------------------------------------------------------- */
+
+/* Workspace bytes of p2m_mass_assign_batched for this batch (256-byte aligned
+ * device memory).  P2M_ERR_UNSUPPORTED for problems that are not 2D FP32, for
+ * F > 3, nprob > 128, nprob * F > 256, or batches beyond int32 indexing or the
+ * solve kernel's tile capacity (32 solver tiles of 128 x 32 nodes per compute
+ * unit). */
+p2m_status p2m_batch_workspace_size(void* ctx, const p2m_problem* probs, int32_t nprob,
+                                    int32_t nfields, size_t* bytes);
+
+/* Mass assignment of every instance of a batch (Sec. 2.4, as p2m_mass_assign).
+ *   probs        host array [nprob] of problems (dim 2, dtype P2M_F32)
+ *   values       host array [nprob] of device pointers, values[k] is [F][np_k]
+ *                (may be NULL when np_k == 0)
+ *   opts         one set of options for all instances; start FLIP, ZERO or USER
+ *   nodal_inout  host array [nprob] of device pointers, [F][nn_k] each: the start
+ *                when opts->start == P2M_START_USER, always the result
+ *   reps         device array [nprob] of reports, reps[k] for instance k (required)
+ * Asynchronous on `stream` apart from the graph build described above. */
+p2m_status p2m_mass_assign_batched(void* ctx, const p2m_problem* probs, int32_t nprob,
+                                   const void* const* values, int32_t nfields,
+                                   const p2m_solve_opts* opts, void* const* nodal_inout,
+                                   p2m_report* reps, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

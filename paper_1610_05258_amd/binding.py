@@ -34,7 +34,7 @@ SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT = 0, 1, 2
 
 EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size", "p2m_bin",
            "p2m_assemble", "p2m_assign", "p2m_interpolate", "p2m_mass_assign", "p2m_mass_solve",
-           "p2m_set_option")
+           "p2m_set_option", "p2m_batch_workspace_size", "p2m_mass_assign_batched")
 
 
 class P2MError(RuntimeError):
@@ -85,6 +85,10 @@ def lib():
                                       sz, vp]
         L.p2m_mass_solve.argtypes = [vp, pprob, i32, vp, vp, vp, ctypes.POINTER(CSolveOpts), vp, vp,
                                      vp, sz, vp]
+        L.p2m_batch_workspace_size.argtypes = [vp, pprob, i32, i32, ctypes.POINTER(sz)]
+        L.p2m_mass_assign_batched.argtypes = [vp, pprob, i32, ctypes.POINTER(vp), i32,
+                                              ctypes.POINTER(CSolveOpts), ctypes.POINTER(vp), vp, vp,
+                                              sz, vp]
         for name in EXPORTS[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -350,3 +354,60 @@ def p2m_mass_solve(ctx: Context, prob: Particles, b, w, coef, opts: CSolveOpts |
                                 ctypes.c_void_p(rep.data_ptr()), wp, wn, _stream_ptr(stream)),
            "p2m_mass_solve")
     return out, rep
+
+
+class Batch:
+    """A batch of independent 2D FP32 problems for p2m_mass_assign_batched, with its
+    value tensors, outputs ([F, nn_k] each), reports ([nprob] x 144 bytes) and
+    workspace.  Every run() passes the same instance table, so after the first call
+    the library relaunches its cached graph."""
+
+    def __init__(self, ctx: Context, probs, values, opts: CSolveOpts | None = None):
+        if len(probs) != len(values) or not probs:
+            raise ValueError("one value tensor per problem")
+        self.ctx = ctx
+        self.probs = list(probs)
+        self.values = []
+        F = None
+        for p, v in zip(self.probs, values):
+            v, f = _values_tensor(v, p)
+            if F is not None and f != F:
+                raise ValueError("every instance needs the same field count")
+            F = f
+            self.values.append(v)
+        self.F = F
+        self.n = len(self.probs)
+        self.opts = opts if opts is not None else solve_opts()
+        dev = f"cuda:{ctx.device}"
+        self.out = [torch.empty((F, p.n_nodes), dtype=torch.float32, device=dev) for p in self.probs]
+        self.reps = torch.zeros((self.n, REPORT_BYTES), dtype=torch.uint8, device=dev)
+        self._cprobs = (CProblem * self.n)(*[p.cstruct() for p in self.probs])
+        self._vptr = (ctypes.c_void_p * self.n)(*[v.data_ptr() for v in self.values])
+        self._optr = (ctypes.c_void_p * self.n)(*[o.data_ptr() for o in self.out])
+        nb = ctypes.c_size_t()
+        _check(lib().p2m_batch_workspace_size(ctx.handle, self._cprobs, self.n, F, ctypes.byref(nb)),
+               "p2m_batch_workspace_size")
+        self.ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=dev)
+
+    def run(self, stream=None):
+        _check(lib().p2m_mass_assign_batched(
+            self.ctx.handle, self._cprobs, self.n, self._vptr, self.F, ctypes.byref(self.opts),
+            self._optr, ctypes.c_void_p(self.reps.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+            ctypes.c_size_t(self.ws.numel()), _stream_ptr(stream)), "p2m_mass_assign_batched")
+        return self.out
+
+    def reports(self):
+        raw = self.reps.cpu().numpy()
+        return [Report.decode(raw[k].tobytes(), self.F) for k in range(self.n)]
+
+
+def p2m_mass_assign_batched(ctx: Context, probs, values, opts: CSolveOpts | None = None, x0=None,
+                            stream=None):
+    """Mass assignment of a batch in one graph launch: (list of nodal [F, nn_k], Batch).
+    x0 (a list) is read when opts.start is USER."""
+    b = Batch(ctx, probs, values, opts)
+    if x0 is not None:
+        for o, x in zip(b.out, x0):
+            o.copy_(x)
+    b.run(stream)
+    return b.out, b

@@ -5,6 +5,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <new>
+#include <vector>
+
 #include <hip/hip_runtime.h>
 
 #include "p2m_internal.hpp"
@@ -13,11 +16,33 @@ using namespace p2m;
 
 namespace {
 
+// The graph of the last batch submitted on a context, relaunched as long as the
+// batch (instance table, field count, options, workspace, reports) is unchanged.
+struct BatchCache {
+    std::vector<unsigned char> key;
+    std::vector<unsigned char> upload;   // instance table and tile maps (host copy)
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void release() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        key.clear();
+    }
+    ~BatchCache() {
+        release();
+        if (capture) (void)hipStreamDestroy(capture);
+    }
+};
+
 struct Context {
     int device;
     int cg_blocks_f32;
     int cg_blocks_f64;
     int resident_enabled;   // 1: use the register-resident solve where it fits
+    BatchCache* batch;      // created on the first batched call
 };
 
 // Makes the context's device current for the duration of a call and restores
@@ -237,6 +262,154 @@ p2m_status run_mass(const Context* c, const Prepared& pp, const p2m_problem* pro
     return run_solve<T>(c, pp, F, b, w, coef, start, opts, x);
 }
 
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+    int nprob = 0, F = 0;
+    int64_t np = 0, nn = 0;              // particles and nodes of the whole batch
+    int nlb = 0, nat = 0, nrt = 0;       // locate blocks, scatter tiles, solver tiles
+    int grid = 0;                        // workgroups of the batched solve
+    std::vector<BatchInst> inst;
+    std::vector<int32_t> lmap, amap, rmap;
+    size_t inst_b = 0, lmap_b = 0, amap_b = 0, rmap_b = 0;   // upload sections
+    size_t o_key = 0, o_counts = 0, o_cs = 0, o_perm = 0, o_scan = 0, o_b = 0, o_w = 0,
+           o_coef = 0, o_solve = 0, total = 0;
+};
+
+// Validates the batch and lays out its workspace.  values / outs / reps may be
+// null for a size query.
+p2m_status plan_batch(const Context* c, const p2m_problem* probs, int nprob, int F,
+                      const void* const* values, void* const* outs, p2m_report* reps,
+                      BatchPlan& P) {
+    if (!probs || nprob < 1 || F < 1 || F > kMaxFields) return P2M_ERR_INVALID_ARG;
+    if (F > kResidentMaxFields || nprob > kBatchMaxInstances || nprob * F > kBatchMaxPairs)
+        return P2M_ERR_UNSUPPORTED;
+    P.nprob = nprob;
+    P.F = F;
+    P.inst.resize(nprob);
+    const int ts = assemble_tile(F, 4);
+    int64_t np = 0, nn = 0, nlb = 0, nat = 0, nrt = 0;
+    for (int k = 0; k < nprob; ++k) {
+        Mesh m;
+        p2m_status s = check_problem(&probs[k], m);
+        if (s != P2M_OK) return s;
+        if (m.dim != 2 || probs[k].dtype != P2M_F32) return P2M_ERR_UNSUPPORTED;
+        BatchInst& I = P.inst[k];
+        memset(&I, 0, sizeof(I));
+        I.m = m;
+        I.P = particles_of<float>(&probs[k]);
+        if (values) {
+            if (m.np > 0 && !values[k]) return P2M_ERR_INVALID_ARG;
+            I.values = (const float*)values[k];
+        }
+        if (outs) {
+            if (!outs[k]) return P2M_ERR_INVALID_ARG;
+            I.out = (float*)outs[k];
+        }
+        I.rep = reps ? reps + k : nullptr;
+        const int atx = (m.nx + ts - 1) / ts, aty = (m.ny + ts - 1) / ts;
+        const int rtx = (m.nx + kSolveTileX - 1) / kSolveTileX;
+        const int rty = (m.ny + kSolveTileY - 1) / kSolveTileY;
+        const int lbk = (m.np + kBinBlock - 1) / kBinBlock;
+        I.po = (int32_t)np;
+        I.no = (int32_t)nn;
+        I.lb = (int32_t)nlb;
+        I.at = (int32_t)nat;
+        I.atx = atx;
+        I.rt = (int32_t)nrt;
+        I.rtx = rtx;
+        I.nrt = rtx * rty;
+        np += m.np;
+        nn += m.nn;
+        nlb += lbk;
+        nat += (int64_t)atx * aty;
+        nrt += (int64_t)rtx * rty;
+        if (np >= ((int64_t)1 << 31) - 1 || nn >= ((int64_t)1 << 31) - 1 ||
+            nat >= ((int64_t)1 << 31) - 1)
+            return P2M_ERR_UNSUPPORTED;
+    }
+    P.np = np;
+    P.nn = nn;
+    P.nlb = (int)nlb;
+    P.nat = (int)nat;
+    P.nrt = (int)nrt;
+    P.lmap.resize(P.nlb);
+    P.amap.resize(P.nat);
+    P.rmap.resize(P.nrt);
+    for (int k = 0; k < nprob; ++k) {
+        const BatchInst& I = P.inst[k];
+        const int lbk = (I.m.np + kBinBlock - 1) / kBinBlock;
+        const int ts2 = (I.m.ny + ts - 1) / ts;
+        for (int b = 0; b < lbk; ++b) P.lmap[I.lb + b] = k;
+        for (int t = 0; t < I.atx * ts2; ++t) P.amap[I.at + t] = k;
+        for (int t = 0; t < I.nrt; ++t) P.rmap[I.rt + t] = k;
+    }
+    P.grid = cgb_grid(F, P.nrt, c->device);
+    if (P.grid < 1) return P2M_ERR_UNSUPPORTED;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    P.inst_b = align_up(sizeof(BatchInst) * nprob);
+    P.lmap_b = align_up(sizeof(int32_t) * P.nlb);
+    P.amap_b = align_up(sizeof(int32_t) * P.nat);
+    P.rmap_b = align_up(sizeof(int32_t) * P.nrt);
+    take(P.inst_b + P.lmap_b + P.amap_b + P.rmap_b);
+    P.o_key = take(sizeof(int32_t) * (size_t)np);
+    P.o_counts = take(sizeof(int32_t) * (size_t)nn);
+    P.o_cs = take(sizeof(int32_t) * ((size_t)nn + 1));
+    P.o_perm = take(sizeof(int32_t) * (size_t)np);
+    P.o_scan = take(scan_workspace_bytes((int)nn));
+    P.o_b = take(sizeof(float) * (size_t)F * nn);
+    P.o_w = take(sizeof(float) * (size_t)nn);
+    P.o_coef = take(sizeof(float) * (size_t)4 * nn);
+    P.o_solve = take(cgb_workspace_bytes(F, nprob, P.nrt, (size_t)nn));
+    P.total = off;
+    return P2M_OK;
+}
+
+// The launch sequence of a batch on `stream` (captured into the batch graph).
+hipError_t enqueue_batch(const BatchPlan& P, char* ws, p2m_report* reps, const p2m_solve_opts& opts,
+                         hipStream_t stream) {
+    const BatchInst* inst = (const BatchInst*)ws;
+    const int32_t* lmap = (const int32_t*)(ws + P.inst_b);
+    const int32_t* amap = (const int32_t*)(ws + P.inst_b + P.lmap_b);
+    const int32_t* rmap = (const int32_t*)(ws + P.inst_b + P.lmap_b + P.amap_b);
+    int32_t* key = (int32_t*)(ws + P.o_key);
+    int32_t* counts = (int32_t*)(ws + P.o_counts);
+    int32_t* cs = (int32_t*)(ws + P.o_cs);
+    int32_t* perm = (int32_t*)(ws + P.o_perm);
+    int32_t* sums = (int32_t*)(ws + P.o_scan);
+    float* b = (float*)(ws + P.o_b);
+    float* w = (float*)(ws + P.o_w);
+    float* coef = (float*)(ws + P.o_coef);
+    hipError_t e;
+    if ((e = launch_report_clear_n(reps, P.nprob, stream)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(counts, 0, (size_t)P.nn, stream)) != hipSuccess) return e;
+    if ((e = launch_locate_count_batch(inst, lmap, P.nlb, key, counts, stream)) != hipSuccess)
+        return e;
+    if ((e = launch_exclusive_scan(counts, cs, (int)P.nn, sums, stream)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(counts, 0, (size_t)P.nn, stream)) != hipSuccess) return e;
+    if ((e = launch_place_flat((int)P.np, key, cs, counts, perm, stream)) != hipSuccess) return e;
+    if ((e = launch_segment_sort_flat((int)P.nn, cs, perm, stream)) != hipSuccess) return e;
+    if ((e = launch_assemble_batch(P.F, inst, amap, P.nat, perm, cs, b, w, coef, stream)) !=
+        hipSuccess)
+        return e;
+    BatchSolveBufs bb;
+    bb.inst = inst;
+    bb.nprob = P.nprob;
+    bb.rmap = rmap;
+    bb.ntiles = P.nrt;
+    bb.coef = coef;
+    bb.b = b;
+    bb.w = w;
+    bb.ws = ws + P.o_solve;
+    return launch_cg_batch(P.F, bb, (size_t)P.nn, P.grid, opts.start, opts, stream);
+}
+
 p2m_status check_opts(const p2m_solve_opts* opts) {
     if (!opts) return P2M_ERR_INVALID_ARG;
     if (!isfinite(opts->tol) || !isfinite(opts->inner_rtol)) return P2M_ERR_NONFINITE;
@@ -298,6 +471,13 @@ p2m_status p2m_set_option(void* ctx, int32_t option, int32_t value) {
 }
 
 p2m_status p2m_destroy(void* ctx) {
+    if (ctx) {
+        Context* c = (Context*)ctx;
+        if (c->batch) {
+            DeviceGuard g(c->device);
+            delete c->batch;
+        }
+    }
     free(ctx);
     return P2M_OK;
 }
@@ -418,6 +598,86 @@ p2m_status p2m_mass_solve(void* ctx, const p2m_problem* prob, int32_t nfields, v
                                  opts->start, *opts, nodal_inout);
     return run_solve<float>(c, pp, nfields, (float*)b, (const float*)w, (float*)coef, opts->start,
                             *opts, nodal_inout);
+}
+
+p2m_status p2m_batch_workspace_size(void* ctx, const p2m_problem* probs, int32_t nprob,
+                                    int32_t nfields, size_t* bytes) {
+    if (!ctx || !bytes) return P2M_ERR_INVALID_ARG;
+    DeviceGuard g(((const Context*)ctx)->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    BatchPlan P;
+    p2m_status s = plan_batch((const Context*)ctx, probs, nprob, nfields, nullptr, nullptr,
+                              nullptr, P);
+    if (s != P2M_OK) return s;
+    *bytes = P.total;
+    return P2M_OK;
+}
+
+p2m_status p2m_mass_assign_batched(void* ctx, const p2m_problem* probs, int32_t nprob,
+                                   const void* const* values, int32_t nfields,
+                                   const p2m_solve_opts* opts, void* const* nodal_inout,
+                                   p2m_report* reps, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !values || !nodal_inout || !reps) return P2M_ERR_INVALID_ARG;
+    p2m_status s = check_opts(opts);
+    if (s != P2M_OK) return s;
+    if (opts->start == P2M_START_DELTA1D) return P2M_ERR_UNSUPPORTED;
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    BatchPlan P;
+    s = plan_batch(c, probs, nprob, nfields, values, nodal_inout, reps, P);
+    if (s != P2M_OK) return s;
+    if (!ws || ws_bytes < P.total || ((uintptr_t)ws) % kAlign) return P2M_ERR_WORKSPACE;
+    hipStream_t strm = (hipStream_t)stream;
+    if (!c->batch) {
+        c->batch = new (std::nothrow) BatchCache();
+        if (!c->batch) return P2M_ERR_HIP;
+        if (hipStreamCreateWithFlags(&c->batch->capture, hipStreamNonBlocking) != hipSuccess) {
+            c->batch->capture = nullptr;
+            return P2M_ERR_HIP;
+        }
+    }
+    BatchCache& bc = *c->batch;
+    // the graph is a function of the instance table, the field count, the options,
+    // the workspace and the reports
+    std::vector<unsigned char> key;
+    auto put = [&](const void* p, size_t n) {
+        key.insert(key.end(), (const unsigned char*)p, (const unsigned char*)p + n);
+    };
+    put(P.inst.data(), sizeof(BatchInst) * P.inst.size());
+    put(&P.F, sizeof(P.F));
+    put(opts, sizeof(*opts));
+    put(&ws, sizeof(ws));
+    put(&reps, sizeof(reps));
+    if (!bc.exec || key != bc.key) {
+        bc.release();
+        // the instance table and tile maps go to the head of the workspace
+        bc.upload.assign(P.inst_b + P.lmap_b + P.amap_b + P.rmap_b, 0);
+        unsigned char* u = bc.upload.data();
+        memcpy(u, P.inst.data(), sizeof(BatchInst) * P.nprob);
+        memcpy(u + P.inst_b, P.lmap.data(), sizeof(int32_t) * P.nlb);
+        memcpy(u + P.inst_b + P.lmap_b, P.amap.data(), sizeof(int32_t) * P.nat);
+        memcpy(u + P.inst_b + P.lmap_b + P.amap_b, P.rmap.data(), sizeof(int32_t) * P.nrt);
+        P2M_TRY(hipMemcpyAsync(ws, u, bc.upload.size(), hipMemcpyHostToDevice, strm));
+        P2M_TRY(hipStreamSynchronize(strm));
+        P2M_TRY(hipStreamBeginCapture(bc.capture, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue_batch(P, (char*)ws, reps, *opts, bc.capture);
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(bc.capture, &graph);
+        if (e != hipSuccess || e2 != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return P2M_ERR_HIP;
+        }
+        bc.graph = graph;
+        if (hipGraphInstantiate(&bc.exec, bc.graph, nullptr, nullptr, 0) != hipSuccess) {
+            bc.exec = nullptr;
+            bc.release();
+            return P2M_ERR_HIP;
+        }
+        bc.key.swap(key);
+    }
+    P2M_TRY(hipGraphLaunch(bc.exec, strm));
+    return P2M_OK;
 }
 
 }  // extern "C"

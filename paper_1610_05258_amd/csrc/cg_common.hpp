@@ -1,0 +1,274 @@
+// Device-side pieces shared by the two tile solvers (k_cgr.hip: one tile per
+// workgroup, state in registers; k_cgb.hip: several tiles and instances per
+// workgroup, state streamed): the tile geometry, the device-coherent accesses,
+// buffer descriptors, the fixed-order block and grid reductions and the
+// two-level barrier.  Both solvers take every floating-point decision through
+// these helpers, so a tile computes the same bits in either kernel.
+#pragma once
+
+#include "p2m_internal.hpp"
+
+namespace p2m {
+
+namespace {
+
+constexpr int RX = kSolveTileX;     // tile width in nodes
+constexpr int RY = kSolveTileY;     // tile height
+constexpr int RNPT = 8;           // nodes per thread
+constexpr int RBS = RX * RY / RNPT;  // threads per workgroup; a wave covers RNPT/2 rows
+constexpr int LW = RX + 2;        // LDS row stride including the halo ring
+constexpr int LH = RY + 2;
+constexpr int kGroups = 16;       // fan-in of the first barrier level
+constexpr int kNV = 3 * kMaxFields;
+constexpr long kSpinMax = 1L << 22;
+
+struct RSync {
+    unsigned* ctr;    // [kGroups * 32] group arrival counters (128-byte apart)
+    unsigned* root;   // root arrival counter
+    unsigned* rel;    // release epoch
+    unsigned* abort;  // set on a timed-out wait
+    double* part;     // [2][nblocks][kNV] per-workgroup partials
+    double* tot;      // [2][kNV] totals
+};
+// device-coherent (L2-bypassing) accesses for data that crosses workgroups
+__device__ __forceinline__ void st_c(float* p, float v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_c(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ld_c(const float* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_c(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ld_c(const unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Buffer-resource accesses: a 128-bit descriptor (base, size) in scalar
+// registers plus a 32-bit element offset, so the per-node offsets are shared by
+// all arrays.  AUX 0 = plain (owner-only data), 16 = device-coherent (sc1).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kPlain = 0, kCoherent = 16;
+__device__ __forceinline__ rsrc_t mkrs(const void* p, size_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
+template <int AUX>
+__device__ __forceinline__ float ldf(rsrc_t r, int i) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, AUX));
+}
+template <int AUX>
+__device__ __forceinline__ void stf(rsrc_t r, int i, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, i * 4, 0, AUX);
+}
+template <int AUX>
+__device__ __forceinline__ double ldd(rsrc_t r, int i) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8, 0, AUX));
+}
+template <int AUX>
+__device__ __forceinline__ void std8(rsrc_t r, int i, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, i * 8, 0, AUX);
+}
+
+// Block sum of NV doubles per thread in a fixed order; totals land in out[0..NV).
+template <int NV>
+__device__ __forceinline__ void block_sum_to(double (&v)[NV], double* lds /* [RBS/64][NV] */,
+                                             double* out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double s = v[j];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) s += __shfl_down(s, d, 64);
+        if (lane == 0) lds[wave * NV + j] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int wv = 0; wv < RBS / 64; ++wv) s += lds[wv * NV + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// Sum of the partials part[bk * kNV + jv] over bk < nblocks for every jv < nv,
+// written to tot[jv] (device-coherent).  The fixed order that every solve uses:
+// value jv is summed by the 32 lanes of segment jv, lane l over blocks l, l+32,
+// ... in increasing order, then a fixed shuffle tree over the 32 lanes.  Called
+// by all threads of one workgroup.
+__device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int nv,
+                                                double* tot) {
+    const int seg = threadIdx.x >> 5, l = threadIdx.x & 31;
+    for (int jv = seg; jv < kNV; jv += RBS / 32) {
+        double acc = 0.0;
+        if (jv < nv)
+            for (int bk = l; bk < nblocks; bk += 32) acc += ld_c(&part[(size_t)bk * kNV + jv]);
+#pragma unroll
+        for (int d = 16; d >= 1; d >>= 1) acc += __shfl_down(acc, d, 32);
+        if (jv < nv && l == 0) st_c(&tot[jv], acc);
+    }
+}
+
+// Arrival at the two-level barrier tree (thread 0 only): the group counter of
+// this workgroup, then, for the last of its group, the root counter.  Counters
+// only grow; epoch e is complete when they reach e times their fan-in.  Returns
+// true in the last arriving workgroup of the grid.
+__device__ __forceinline__ bool tree_arrive(const RSync& s, unsigned epoch, int nblocks) {
+    const int ng = nblocks < kGroups ? nblocks : kGroups;
+    const int g = blockIdx.x % kGroups;
+    const unsigned gsize = (unsigned)((nblocks - g + kGroups - 1) / kGroups);
+    const unsigned old = __hip_atomic_fetch_add(&s.ctr[g * 32], 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 == epoch * gsize) {
+        const unsigned o2 = __hip_atomic_fetch_add(s.root, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (o2 + 1 == epoch * (unsigned)ng) return true;
+    }
+    return false;
+}
+
+// Bounded wait for the release of `epoch` (thread 0 only).  A wait that times
+// out, or that sees the abort flag, raises the abort flag and returns false.
+__device__ __forceinline__ bool tree_wait(const RSync& s, unsigned epoch) {
+    long spins = 0;
+    while (ld_c(s.rel) < epoch) {
+        if (ld_c(s.abort) != 0u || ++spins > kSpinMax) {
+            __hip_atomic_store(s.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+    }
+    return true;
+}
+
+__device__ __forceinline__ void tree_release(const RSync& s, unsigned epoch) {
+    __hip_atomic_store(s.rel, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Grid barrier that also sums the workgroups' partials vals[0..nv) (FP64).  On
+// return vals[0..nv) holds the totals in every workgroup.  Returns false after
+// an abort.
+__device__ bool sync_reduce(const RSync& s, unsigned epoch, double* vals, int nv, int nblocks) {
+    __shared__ int s_role;
+    __shared__ int s_ok;
+    double* part = s.part + (size_t)(epoch & 1) * nblocks * kNV;
+    double* tot = s.tot + (size_t)(epoch & 1) * kNV;
+    if (threadIdx.x < nv) st_c(&part[(size_t)blockIdx.x * kNV + threadIdx.x], vals[threadIdx.x]);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) s_role = tree_arrive(s, epoch, nblocks) ? 1 : 0;
+    __syncthreads();
+    if (s_role) {
+        reduce_partials(part, nblocks, nv, tot);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) tree_release(s, epoch);
+    }
+    if (threadIdx.x == 0) s_ok = tree_wait(s, epoch) ? 1 : 0;
+    __syncthreads();
+    if (threadIdx.x < nv) vals[threadIdx.x] = ld_c(&tot[threadIdx.x]);
+    __syncthreads();
+    return s_ok != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Floating-point steps, written with explicit fused operations so that the
+// rounding of every value is fixed by the source and not by contraction.
+// ---------------------------------------------------------------------------
+
+// FP64 accumulation of the product of two FP32 values (exact product, one
+// rounding)
+__device__ __forceinline__ double dot_acc(double acc, float a, float b) {
+    return __fma_rn((double)a, (double)b, acc);
+}
+__device__ __forceinline__ double sq_acc(double acc, double a) { return __fma_rn(a, a, acc); }
+
+// FP64 stencil product (M x)_k from seven coefficients and the seven values
+// (centre, +x, -x, +y, -y, +x+y, -x-y)
+__device__ __forceinline__ double stencil64(float cD, float cE, float cEw, float cN, float cNs,
+                                            float cNE, float cNEsw, double x0, double xe,
+                                            double xw, double xn, double xs, double xne,
+                                            double xsw) {
+    double acc = __dmul_rn((double)cD, x0);
+    acc = __fma_rn((double)cE, xe, acc);
+    acc = __fma_rn((double)cEw, xw, acc);
+    acc = __fma_rn((double)cN, xn, acc);
+    acc = __fma_rn((double)cNs, xs, acc);
+    acc = __fma_rn((double)cNE, xne, acc);
+    acc = __fma_rn((double)cNEsw, xsw, acc);
+    return acc;
+}
+
+// FP32 stencil product, same order
+__device__ __forceinline__ float stencil32(float cD, float cE, float cEw, float cN, float cNs,
+                                           float cNE, float cNEsw, float x0, float xe, float xw,
+                                           float xn, float xs, float xne, float xsw) {
+    float acc = __fmul_rn(cD, x0);
+    acc = fmaf(cE, xe, acc);
+    acc = fmaf(cEw, xw, acc);
+    acc = fmaf(cN, xn, acc);
+    acc = fmaf(cNs, xs, acc);
+    acc = fmaf(cNE, xne, acc);
+    acc = fmaf(cNEsw, xsw, acc);
+    return acc;
+}
+
+// Jacobi preconditioner: the inverse of the regularised diagonal, 1 / M(k,k)
+// (correctly rounded), and 1 for an orphan node (w_k == 0, identity row).
+__device__ __forceinline__ float jacobi_inv(float diag, float wk) {
+    return wk > 0.f ? __frcp_rn(diag) : 1.0f;
+}
+
+// Jacobi-preconditioned Chronopoulos-Gear updates of one node, u = r / M(k,k):
+// p = u + beta p, d = d + alpha p, s = w + beta s, r = r - alpha s (w = M u of the
+// previous iteration).  Returns the new u.
+__device__ __forceinline__ float pcg_update(float al, float be, float dinv, float& p, float& d,
+                                            float& s, float& r, float w) {
+    const float u = __fmul_rn(r, dinv);
+    p = fmaf(be, p, u);
+    d = fmaf(al, p, d);
+    s = fmaf(be, s, w);
+    r = fmaf(-al, s, r);
+    return __fmul_rn(r, dinv);
+}
+
+// a neighbour's new preconditioned residual from its published (r, w, s):
+// (r - alpha (w + beta s)) / M(k,k), the same operations as pcg_update
+__device__ __forceinline__ float halo_u(float al, float be, float dinv, float r, float w,
+                                        float s) {
+    return __fmul_rn(fmaf(-al, fmaf(be, s, w), r), dinv);
+}
+
+// global index of local tile coordinate (lc, lr), periodic
+__device__ __forceinline__ int gidx(const Mesh& m, int i0, int j0, int lc, int lr) {
+    int gc = i0 + lc, gr = j0 + lr;
+    if (gc < 0) gc += m.nx;
+    if (gc >= m.nx) gc -= m.nx;
+    if (gr < 0) gr += m.ny;
+    if (gr >= m.ny) gr -= m.ny;
+    return gc + m.nx * gr;
+}
+
+// halo slot h -> local (lc, lr) on the ring around a TXa x TYa tile
+__device__ __forceinline__ bool halo_slot(int h, int txa, int tya, int& lc, int& lr) {
+    const int row = txa + 2;
+    if (h < row) { lr = -1; lc = h - 1; return true; }
+    h -= row;
+    if (h < row) { lr = tya; lc = h - 1; return true; }
+    h -= row;
+    if (h < tya) { lc = -1; lr = h; return true; }
+    h -= tya;
+    if (h < tya) { lc = txa; lr = h; return true; }
+    return false;
+}
+
+__device__ __forceinline__ bool on_boundary(int lc, int lr, int txa, int tya) {
+    return lc == 0 || lr == 0 || lc == txa - 1 || lr == tya - 1;
+}
+
+
+}  // namespace
+
+}  // namespace p2m

@@ -37,11 +37,15 @@ enum : int {
 // and stages the four corner weights, the volume and the values in LDS; then one
 // thread per cell walks its slots in binned order and accumulates the cell's parts
 // in registers.  Chunks run in order, so every sum keeps the binned particle order.
+// perm holds particle numbers offset by po (batches number all particles in one
+// space); tile is the tile index within the problem.
 template <typename T, int F, int TS, int CH>
-__global__ __launch_bounds__(((TS + 1) * (TS + 1) + 63) / 64 * 64) void k_assemble2d(
-    Mesh m, Particles<T> P, const T* __restrict__ values, const int32_t* __restrict__ perm,
-    const int32_t* __restrict__ cell_start, T* __restrict__ b, T* __restrict__ w,
-    T* __restrict__ coef, int tiles_x) {
+__device__ __forceinline__ void assemble2d_tile(const Mesh& m, const Particles<T>& P,
+                                                const T* __restrict__ values,
+                                                const int32_t* __restrict__ perm, int po,
+                                                const int32_t* __restrict__ cell_start,
+                                                T* __restrict__ b, T* __restrict__ w,
+                                                T* __restrict__ coef, int tiles_x, int tile) {
     constexpr int HS = TS + 1;
     constexpr int HC = HS * HS;
     constexpr int NT = (HC + 63) / 64 * 64;     // threads: one per cell
@@ -56,7 +60,6 @@ __global__ __launch_bounds__(((TS + 1) * (TS + 1) + 63) / 64 * 64) void k_assemb
     T* st = (T*)smem;                           // st[q * CH + slot]
     T(*part)[HC] = (T(*)[HC])smem;              // after the chunks: part[q][cell]
 
-    const int tile = blockIdx.x;
     const int i0 = (tile % tiles_x) * TS;
     const int j0 = (tile / tiles_x) * TS;
     const T v_uni = (T)m.v_uniform;
@@ -106,7 +109,7 @@ __global__ __launch_bounds__(((TS + 1) * (TS + 1) + 63) / 64 * 64) void k_assemb
         // stage: slot-parallel loads and FP64 locate
         for (int sl = cb + t; sl < ce; sl += NT) {
             const int hc = cmap[sl - cb];
-            const int i = perm[c_seg[hc] + (sl - c_off[hc])];
+            const int i = perm[c_seg[hc] + (sl - c_off[hc])] - po;
             int cx, cy;
             double xi, eta;
             bool fx, fy;
@@ -183,6 +186,28 @@ __global__ __launch_bounds__(((TS + 1) * (TS + 1) + 63) / 64 * 64) void k_assemb
         coef[(size_t)2 * m.nn + k] = part[Q_NL][cA] + part[Q_NR][cB];   // M(k, k+y)
         coef[(size_t)3 * m.nn + k] = part[Q_NE][cA];                    // M(k, k+x+y)
     }
+}
+
+template <typename T, int F, int TS, int CH>
+__global__ __launch_bounds__(((TS + 1) * (TS + 1) + 63) / 64 * 64) void k_assemble2d(
+    Mesh m, Particles<T> P, const T* __restrict__ values, const int32_t* __restrict__ perm,
+    const int32_t* __restrict__ cell_start, T* __restrict__ b, T* __restrict__ w,
+    T* __restrict__ coef, int tiles_x) {
+    assemble2d_tile<T, F, TS, CH>(m, P, values, perm, 0, cell_start, b, w, coef, tiles_x,
+                                  blockIdx.x);
+}
+
+// batch: tile t belongs to instance amap[t]; the instance's b, w and coef blocks
+// start at F*no, no and 4*no
+template <int F, int TS, int CH>
+__global__ __launch_bounds__(((TS + 1) * (TS + 1) + 63) / 64 * 64) void k_assemble2d_batch(
+    const BatchInst* __restrict__ inst, const int32_t* __restrict__ amap,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ cell_start,
+    float* __restrict__ b, float* __restrict__ w, float* __restrict__ coef) {
+    const BatchInst& I = inst[amap[blockIdx.x]];
+    assemble2d_tile<float, F, TS, CH>(I.m, I.P, I.values, perm, I.po, cell_start + I.no,
+                                      b + (size_t)F * I.no, w + I.no, coef + (size_t)4 * I.no,
+                                      I.atx, blockIdx.x - I.at);
 }
 
 // 1D: a tile of TS nodes and the TS+1 cells touching it (one extra on the left).
@@ -273,6 +298,26 @@ __global__ void k_finalize(int nn, int F, const T* __restrict__ b, const T* __re
     }
 }
 
+// staged slots per chunk: the staging area stays within 32 KB
+template <typename T, int F>
+constexpr int stage_chunk() {
+    return ((int)(32768 / ((5 + F) * sizeof(T))) > 2048 ? 2048
+                                                        : (int)(32768 / ((5 + F) * sizeof(T)))) /
+           64 * 64;
+}
+
+template <int F>
+hipError_t assemble_batch_f(const BatchInst* inst, const int32_t* amap, int ntiles,
+                            const int32_t* perm, const int32_t* cs, float* b, float* w,
+                            float* coef, hipStream_t stream) {
+    constexpr int TS = assemble_tile(F, 4);
+    constexpr int CH = stage_chunk<float, F>();
+    constexpr int NT = ((TS + 1) * (TS + 1) + 63) / 64 * 64;
+    hipLaunchKernelGGL((k_assemble2d_batch<F, TS, CH>), dim3(ntiles), dim3(NT), 0, stream, inst,
+                       amap, perm, cs, b, w, coef);
+    return hipGetLastError();
+}
+
 template <typename T, int F>
 hipError_t assemble_f(const Mesh& m, Particles<T> P, const T* values, const int32_t* perm,
                       const int32_t* cs, T* b, T* w, T* coef, hipStream_t stream) {
@@ -285,10 +330,9 @@ hipError_t assemble_f(const Mesh& m, Particles<T> P, const T* values, const int3
     }
     // tile 16x16 unless the per-cell parts of its 17x17 cells exceed 64 KB; chunk
     // of staged slots sized to keep the staging area within 32 KB
-    constexpr size_t part16 = (size_t)(Q_B + 4 * F) * 17 * 17 * sizeof(T);
-    constexpr int TS = part16 <= 65536 ? 16 : 8;
-    constexpr int CHr = (int)(32768 / ((5 + F) * sizeof(T)));
-    constexpr int CH = (CHr > 2048 ? 2048 : CHr) / 64 * 64;
+    static_assert(Q_B == 13, "assemble_tile assumes 13 + 4F parts per cell");
+    constexpr int TS = assemble_tile(F, (int)sizeof(T));
+    constexpr int CH = stage_chunk<T, F>();
     constexpr int NT = ((TS + 1) * (TS + 1) + 63) / 64 * 64;
     const int tx = (m.nx + TS - 1) / TS, ty = (m.ny + TS - 1) / TS;
     hipLaunchKernelGGL((k_assemble2d<T, F, TS, CH>), dim3(tx * ty), dim3(NT), 0, stream, m, P,
@@ -320,6 +364,18 @@ template hipError_t launch_assemble<float>(const Mesh&, Particles<float>, const 
 template hipError_t launch_assemble<double>(const Mesh&, Particles<double>, const double*, int,
                                             const int32_t*, const int32_t*, double*, double*,
                                             double*, hipStream_t);
+
+hipError_t launch_assemble_batch(int F, const BatchInst* inst, const int32_t* amap, int ntiles,
+                                 const int32_t* perm, const int32_t* cell_start, float* b,
+                                 float* w, float* coef, hipStream_t stream) {
+    if (ntiles == 0) return hipSuccess;
+    switch (F) {
+        case 1: return assemble_batch_f<1>(inst, amap, ntiles, perm, cell_start, b, w, coef, stream);
+        case 2: return assemble_batch_f<2>(inst, amap, ntiles, perm, cell_start, b, w, coef, stream);
+        case 3: return assemble_batch_f<3>(inst, amap, ntiles, perm, cell_start, b, w, coef, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 template <typename T>
 hipError_t launch_finalize(const Mesh& m, int F, const T* b, const T* w, int pic, T* out,

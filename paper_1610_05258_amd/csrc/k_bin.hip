@@ -14,7 +14,7 @@ namespace p2m {
 
 namespace {
 
-constexpr int kBlock = 256;
+constexpr int kBlock = kBinBlock;
 
 __global__ void k_report_clear(p2m_report* rep) {
     int t = threadIdx.x;
@@ -58,12 +58,15 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane ? (~0ull >> (64 - lane)) : 0ull;
 }
 
-// One atomic per distinct cell per wave: particles arrive spatially coherent in
+// Locate of particle i of one problem (lanes with i >= np take part in the wave
+// operations only), its key cell0 + cell or -1, and the count of its cell.  One
+// atomic per distinct cell per wave: particles arrive spatially coherent in
 // typical inputs, so this removes most same-address atomic traffic.
 template <typename T>
-__global__ void k_locate_count(Mesh m, Particles<T> P, int32_t* __restrict__ key,
-                               int32_t* __restrict__ counts, p2m_report* __restrict__ rep) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void locate_count_one(const Mesh& m, const Particles<T>& P, int i,
+                                                 int cell0, int32_t* __restrict__ key,
+                                                 int32_t* __restrict__ counts,
+                                                 p2m_report* __restrict__ rep) {
     const bool in = i < m.np;
     bool fin_x = true, fin_y = true;
     int cx = 0, cy = 0;
@@ -73,7 +76,7 @@ __global__ void k_locate_count(Mesh m, Particles<T> P, int32_t* __restrict__ key
         ok = locate_axis((double)P.x[i], m.nx, m.inv_hx, cx, xi, fin_x);
         if (m.dim == 2) ok = locate_axis((double)P.y[i], m.ny, m.inv_hy, cy, eta, fin_y) && ok;
     }
-    const int k = ok ? cx + m.nx * cy : -1;
+    const int k = ok ? cell0 + cx + m.nx * cy : -1;
     const uint64_t grp = match_any(k, ok);
     if (ok && (threadIdx.x & 63) == __ffsll((unsigned long long)grp) - 1)
         atomicAdd(&counts[k], (int)__popcll(grp));
@@ -83,6 +86,39 @@ __global__ void k_locate_count(Mesh m, Particles<T> P, int32_t* __restrict__ key
         atomicAdd(&rep->n_invalid, 1);
     }
     if (in) key[i] = k;
+}
+
+template <typename T>
+__global__ void k_locate_count(Mesh m, Particles<T> P, int32_t* __restrict__ key,
+                               int32_t* __restrict__ counts, p2m_report* __restrict__ rep) {
+    locate_count_one<T>(m, P, blockIdx.x * blockDim.x + threadIdx.x, 0, key, counts, rep);
+}
+
+// batch: block b covers particles [(b - lb) * kBinBlock, ...) of instance lmap[b]
+__global__ void k_locate_count_batch(const BatchInst* __restrict__ inst,
+                                     const int32_t* __restrict__ lmap, int32_t* __restrict__ key,
+                                     int32_t* __restrict__ counts) {
+    const BatchInst& I = inst[lmap[blockIdx.x]];
+    locate_count_one<float>(I.m, I.P, (blockIdx.x - I.lb) * kBinBlock + threadIdx.x, I.no,
+                            key + I.po, counts, I.rep);
+}
+
+__global__ void k_report_clear_n(p2m_report* __restrict__ reps, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = t / 32, q = t % 32;
+    if (r >= n) return;
+    p2m_report* rep = reps + r;
+    if (q < 8) {
+        rep->iters[q] = 0;
+        rep->refines[q] = 0;
+        rep->rel_residual[q] = 0.0;
+    }
+    if (q == 8) {
+        rep->flags = 0u;
+        rep->n_orphan = 0;
+        rep->n_invalid = 0;
+        rep->reserved = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -291,6 +327,37 @@ hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* cell_s
                        cell_start, fill, perm);
     hipLaunchKernelGGL(k_perm_tail, dim3(grid_for(m.np, kBlock)), dim3(kBlock), 0, stream, m.np,
                        m.nn, cell_start, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_report_clear_n(p2m_report* reps, int n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_report_clear_n, dim3(grid_for((size_t)n * 32, kBlock)), dim3(kBlock), 0,
+                       stream, reps, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_locate_count_batch(const BatchInst* inst, const int32_t* lmap, int nblocks,
+                                     int32_t* key, int32_t* counts, hipStream_t stream) {
+    if (nblocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_locate_count_batch, dim3(nblocks), dim3(kBinBlock), 0, stream, inst, lmap,
+                       key, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_place_flat(int np, const int32_t* key, const int32_t* cell_start,
+                             int32_t* fill, int32_t* perm, hipStream_t stream) {
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_place, dim3(grid_for(np, kBlock)), dim3(kBlock), 0, stream, np, key,
+                       cell_start, fill, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_segment_sort_flat(int ncells, const int32_t* cell_start, int32_t* perm,
+                                    hipStream_t stream) {
+    if (ncells == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_segment_sort, dim3(grid_for(ncells, kBlock)), dim3(kBlock), 0, stream,
+                       ncells, cell_start, perm);
     return hipGetLastError();
 }
 

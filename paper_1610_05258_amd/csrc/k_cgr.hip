@@ -13,41 +13,23 @@
 //  * across tiles only the boundary values travel, published to full-size
 //    exchange arrays with device-coherent stores and read back with
 //    device-coherent loads, so no cache flush is ever needed;
-//  * the inner CG is the Chronopoulos-Gear variant: both dot products of an
-//    iteration are reduced together, so an iteration needs one grid barrier.
-//    The new residual r' = r - alpha (w + beta s) of a neighbour tile's boundary
-//    node is recomputed from its published (r, w, s) with the same FP32
-//    operations its owner uses, so the halo is bit-identical;
+//  * the inner CG is the Chronopoulos-Gear variant of Jacobi-preconditioned CG
+//    (u = r / diag M, w = M u): the three dot products of an iteration, (r, u),
+//    (w, u) and (r, r), are reduced together, so an iteration needs one grid
+//    barrier.  The new u' = (r - alpha (w + beta s)) / diag M of a neighbour
+//    tile's boundary node is recomputed from its published (r, w, s) with the
+//    same FP32 operations its owner uses, so the halo is bit-identical;
 //  * the grid barrier is a two-level arrival tree on counters (no single
 //    serialised atomic); the last arriving workgroup reduces the per-workgroup
 //    FP64 partials in a fixed order and publishes the totals, so every workgroup
 //    takes identical decisions and the result is deterministic.
 //  Every wait is bounded: a timed-out wait raises an abort flag that ends the
 //  solve in every workgroup.
-#include "p2m_internal.hpp"
+#include "cg_common.hpp"
 
 namespace p2m {
 
 namespace {
-
-constexpr int RX = 128;           // tile width in nodes
-constexpr int RY = 32;            // tile height
-constexpr int RNPT = 8;           // nodes per thread
-constexpr int RBS = RX * RY / RNPT;  // threads per workgroup; a wave covers RNPT/2 rows
-constexpr int LW = RX + 2;        // LDS row stride including the halo ring
-constexpr int LH = RY + 2;
-constexpr int kGroups = 16;       // fan-in of the first barrier level
-constexpr int kNV = 3 * kMaxFields;
-constexpr long kSpinMax = 1L << 22;
-
-struct RSync {
-    unsigned* ctr;    // [kGroups * 32] group arrival counters (128-byte apart)
-    unsigned* root;   // root arrival counter
-    unsigned* rel;    // release epoch
-    unsigned* abort;  // set on a timed-out wait
-    double* part;     // [2][nblocks][kNV] per-workgroup partials
-    double* tot;      // [2][kNV] totals
-};
 
 struct RArgs {
     Mesh m;
@@ -66,158 +48,6 @@ struct RArgs {
     p2m_solve_opts opts;
     p2m_report* rep;
 };
-
-// device-coherent (L2-bypassing) accesses for data that crosses workgroups
-__device__ __forceinline__ void st_c(float* p, float v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_c(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ float ld_c(const float* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_c(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned ld_c(const unsigned* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Buffer-resource accesses: a 128-bit descriptor (base, size) in scalar
-// registers plus a 32-bit element offset, so the per-node offsets are shared by
-// all arrays.  AUX 0 = plain (owner-only data), 16 = device-coherent (sc1).
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-constexpr int kPlain = 0, kCoherent = 16;
-__device__ __forceinline__ rsrc_t mkrs(const void* p, size_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
-}
-template <int AUX>
-__device__ __forceinline__ float ldf(rsrc_t r, int i) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, AUX));
-}
-template <int AUX>
-__device__ __forceinline__ void stf(rsrc_t r, int i, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, i * 4, 0, AUX);
-}
-template <int AUX>
-__device__ __forceinline__ double ldd(rsrc_t r, int i) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8, 0, AUX));
-}
-template <int AUX>
-__device__ __forceinline__ void std8(rsrc_t r, int i, double v) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, i * 8, 0, AUX);
-}
-
-// Block sum of NV doubles per thread in a fixed order; totals land in out[0..NV).
-template <int NV>
-__device__ __forceinline__ void block_sum_to(double (&v)[NV], double* lds /* [RBS/64][NV] */,
-                                             double* out) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        double s = v[j];
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) s += __shfl_down(s, d, 64);
-        if (lane == 0) lds[wave * NV + j] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < NV) {
-        double s = 0.0;
-        for (int wv = 0; wv < RBS / 64; ++wv) s += lds[wv * NV + threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-    __syncthreads();
-}
-
-// Grid barrier that also sums the workgroups' partials vals[0..nv) (FP64).  On
-// return vals[0..nv) holds the totals in every workgroup.  Returns false after
-// an abort.
-__device__ bool sync_reduce(const RSync& s, unsigned epoch, double* vals, int nv, int nblocks) {
-    __shared__ int s_role;
-    __shared__ int s_ok;
-    double* part = s.part + (size_t)(epoch & 1) * nblocks * kNV;
-    double* tot = s.tot + (size_t)(epoch & 1) * kNV;
-    if (threadIdx.x < nv) st_c(&part[(size_t)blockIdx.x * kNV + threadIdx.x], vals[threadIdx.x]);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    const int ng = nblocks < kGroups ? nblocks : kGroups;
-    if (threadIdx.x == 0) {
-        int role = 0;
-        const int g = blockIdx.x % kGroups;
-        const unsigned gsize = (unsigned)((nblocks - g + kGroups - 1) / kGroups);
-        const unsigned old = __hip_atomic_fetch_add(&s.ctr[g * 32], 1u, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        if (old + 1 == epoch * gsize) {
-            const unsigned o2 = __hip_atomic_fetch_add(s.root, 1u, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-            if (o2 + 1 == epoch * (unsigned)ng) role = 1;
-        }
-        s_role = role;
-    }
-    __syncthreads();
-    if (s_role) {
-        // the last arriver: value j is summed by the 32 lanes of segment j, lane l
-        // over blocks l, l+32, ..., then a fixed shuffle tree
-        const int seg = threadIdx.x >> 5, l = threadIdx.x & 31;
-        for (int jv = seg; jv < kNV; jv += RBS / 32) {
-            double acc = 0.0;
-            if (jv < nv)
-                for (int bk = l; bk < nblocks; bk += 32) acc += ld_c(&part[(size_t)bk * kNV + jv]);
-#pragma unroll
-            for (int d = 16; d >= 1; d >>= 1) acc += __shfl_down(acc, d, 32);
-            if (jv < nv && l == 0) st_c(&tot[jv], acc);
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_store(s.rel, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        long spins = 0;
-        while (ld_c(s.rel) < epoch) {
-            if (ld_c(s.abort) != 0u || ++spins > kSpinMax) {
-                __hip_atomic_store(s.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                ok = 0;
-                break;
-            }
-        }
-        s_ok = ok;
-    }
-    __syncthreads();
-    if (threadIdx.x < nv) vals[threadIdx.x] = ld_c(&tot[threadIdx.x]);
-    __syncthreads();
-    return s_ok != 0;
-}
-
-// global index of local tile coordinate (lc, lr), periodic
-__device__ __forceinline__ int gidx(const Mesh& m, int i0, int j0, int lc, int lr) {
-    int gc = i0 + lc, gr = j0 + lr;
-    if (gc < 0) gc += m.nx;
-    if (gc >= m.nx) gc -= m.nx;
-    if (gr < 0) gr += m.ny;
-    if (gr >= m.ny) gr -= m.ny;
-    return gc + m.nx * gr;
-}
-
-// halo slot h -> local (lc, lr) on the ring around a TXa x TYa tile
-__device__ __forceinline__ bool halo_slot(int h, int txa, int tya, int& lc, int& lr) {
-    const int row = txa + 2;
-    if (h < row) { lr = -1; lc = h - 1; return true; }
-    h -= row;
-    if (h < row) { lr = tya; lc = h - 1; return true; }
-    h -= row;
-    if (h < tya) { lc = -1; lr = h; return true; }
-    h -= tya;
-    if (h < tya) { lc = txa; lr = h; return true; }
-    return false;
-}
-
-__device__ __forceinline__ bool on_boundary(int lc, int lr, int txa, int tya) {
-    return lc == 0 || lr == 0 || lc == txa - 1 || lr == tya - 1;
-}
 
 template <int F>
 __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
@@ -256,6 +86,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                               ? (size_t)F * LH * LW * sizeof(float)
                               : (size_t)LH * LW * sizeof(double);
     __shared__ float cf[4 * CN];
+    __shared__ float dv[LH * LW];   // Jacobi inverse diagonal of the tile and its ring
     __shared__ __align__(16) unsigned char xbuf[XB];
     float* lf = (float*)xbuf;       // plane f at lf + f * LH * LW
     double* ld64 = (double*)xbuf;
@@ -308,8 +139,10 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         const int q = qcj(j);
         const float wk = a.w[k];
         const bool orphan = !(wk > 0.f);
+        const float dk = a.coef[k];
         if (orphan) a.coef[k] = 1.f;
-        cf[q] = orphan ? 1.f : a.coef[k];
+        cf[q] = orphan ? 1.f : dk;
+        dv[qj(j)] = jacobi_inv(dk, wk);
         cf[CN + q] = a.coef[(size_t)nn + k];
         cf[2 * CN + q] = a.coef[(size_t)2 * nn + k];
         cf[3 * CN + q] = a.coef[(size_t)3 * nn + k];
@@ -345,6 +178,13 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         cf[2 * CN + q] = a.coef[(size_t)2 * nn + k];
         cf[3 * CN + q] = a.coef[(size_t)3 * nn + k];
     }
+    // the ring's inverse diagonals (an orphan's is 1 whatever its stored diagonal)
+    for (int h = threadIdx.x; h < nhalo; h += RBS) {
+        int lc, lr;
+        if (!halo_slot(h, txa, tya, lc, lr)) continue;
+        const int k = gidx(m, i0, j0, lc, lr);
+        dv[lidx(lc, lr)] = jacobi_inv(a.coef[k], a.w[k]);
+    }
 #pragma unroll
     for (int f = 0; f < F; ++f)
 #pragma unroll
@@ -355,7 +195,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     int ex = 0;  // exchange parity of pubR / pubW / pubS
     bool alive = true;
 
-    // w = M r at the owned nodes for every inner-active field (r in the exchange
+    // w = M u at the owned nodes for every inner-active field (u in the exchange
     // planes); node-major so each node's seven coefficients are read once
     auto spmv_all = [&](uint32_t imask) {
 #pragma unroll
@@ -369,13 +209,9 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
             for (int f = 0; f < F; ++f) {
                 if (!(imask & (1u << f))) continue;
                 const float* L = lf + (size_t)f * LH * LW;
-                float acc = cD * L[q];
-                acc = fmaf(cE, L[q + 1], acc);
-                acc = fmaf(cEw, L[q - 1], acc);
-                acc = fmaf(cN, L[q + LW], acc);
-                acc = fmaf(cNs, L[q - LW], acc);
-                acc = fmaf(cNE, L[q + LW + 1], acc);
-                acc = fmaf(cNEsw, L[q - LW - 1], acc);
+                const float acc = stencil32(cD, cE, cEw, cN, cNs, cNE, cNEsw, L[q], L[q + 1],
+                                            L[q - 1], L[q + LW], L[q - LW], L[q + LW + 1],
+                                            L[q - LW - 1]);
                 vw[f][j] = on ? acc : 0.f;
             }
         }
@@ -427,20 +263,18 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                 for (int j = 0; j < RNPT; ++j) {
                     if (!(amask & (1u << j))) continue;
                     const int q = qj(j), qc = qcj(j);
-                    const double mx = (double)cf[qc] * ld64[q] + (double)cf[CN + qc] * ld64[q + 1] +
-                                      (double)cf[CN + qc - 1] * ld64[q - 1] +
-                                      (double)cf[2 * CN + qc] * ld64[q + LW] +
-                                      (double)cf[2 * CN + qc - CW] * ld64[q - LW] +
-                                      (double)cf[3 * CN + qc] * ld64[q + LW + 1] +
-                                      (double)cf[3 * CN + qc - CW - 1] * ld64[q - LW - 1];
+                    const double mx = stencil64(
+                        cf[qc], cf[CN + qc], cf[CN + qc - 1], cf[2 * CN + qc], cf[2 * CN + qc - CW],
+                        cf[3 * CN + qc], cf[3 * CN + qc - CW - 1], ld64[q], ld64[q + 1],
+                        ld64[q - 1], ld64[q + LW], ld64[q - LW], ld64[q + LW + 1],
+                        ld64[q - LW - 1]);
                     const int kk = gk(j);
                     const double bk = (double)ldf<kPlain>(rb, kk);
                     const double r64 = bk - mx;
                     const float rt = (float)r64;
                     stf<kPlain>(rd, kk, rt);
-                    pr[f] += r64 * r64;
-                    pr[F + f] += (double)rt * (double)rt;
-                    if (outer == 0) pr[2 * F + f] += bk * bk;
+                    pr[f] = sq_acc(pr[f], r64);
+                    if (outer == 0) pr[2 * F + f] = sq_acc(pr[2 * F + f], bk);
                     if (bmask & (1u << j)) stf<kCoherent>(rpr, kk, rt);
                 }
                 __syncthreads();
@@ -469,7 +303,6 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     if (!(relres <= a.opts.tol)) s_flags |= P2M_FLAG_NOT_CONVERGED;
                     continue;
                 }
-                s_gam[f] = vals[F + f];
                 const double goal = 0.25 * a.opts.tol * a.opts.tol * bb;
                 const double rel = a.opts.inner_rtol * a.opts.inner_rtol * rr;
                 s_target[f] = goal > rel ? goal : rel;
@@ -481,7 +314,8 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         __syncthreads();
         if (!s_any) break;
 
-        // ---- CG start: w = M r, delta = (w, r); p = s = d = 0 -------------------
+        // ---- CG start: u = r / diag, w = M u, delta = (w, u), gamma = (r, u);
+        //      p = s = d = 0 -----------------------------------------------------
         uint32_t imask = inner_mask();
 #pragma unroll
         for (int f = 0; f < F; ++f) {
@@ -494,7 +328,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                 if (amask & (1u << j)) {
                     vr[f][j] = ldf<kPlain>(rd, gk(j));
                     stf<kPlain>(rd, gk(j), 0.f);
-                    L[qj(j)] = vr[f][j];
+                    L[qj(j)] = __fmul_rn(vr[f][j], dv[qj(j)]);
                 }
             }
         }
@@ -505,17 +339,18 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
             float hv[F];
 #pragma unroll
             for (int f = 0; f < F; ++f) hv[f] = ldf<kCoherent>(rs_pub(a.pubR, ex, f), gh);
+            const float dh = dv[lidx(lc, lr)];
 #pragma unroll
             for (int f = 0; f < F; ++f)
-                if (imask & (1u << f)) lf[(size_t)f * LH * LW + lidx(lc, lr)] = hv[f];
+                if (imask & (1u << f)) lf[(size_t)f * LH * LW + lidx(lc, lr)] = __fmul_rn(hv[f], dh);
         }
         __syncthreads();
         ex ^= 1;
         {
             spmv_all(imask);
-            double pd[F];
+            double pd[2 * F];
 #pragma unroll
-            for (int f = 0; f < F; ++f) pd[f] = 0.0;
+            for (int f = 0; f < 2 * F; ++f) pd[f] = 0.0;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 if (!(imask & (1u << f))) continue;
@@ -527,7 +362,9 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     vp[f][j] = 0.f;
                     vd[f][j] = 0.f;
                     if (!(amask & (1u << j))) continue;
-                    pd[f] += (double)vw[f][j] * (double)vr[f][j];
+                    const float uj = lf[(size_t)f * LH * LW + qj(j)];
+                    pd[f] = dot_acc(pd[f], vw[f][j], uj);
+                    pd[F + f] = dot_acc(pd[F + f], vr[f][j], uj);
                     if (bmask & (1u << j)) {
                         stf<kCoherent>(rr, gk(j), vr[f][j]);
                         stf<kCoherent>(rw, gk(j), vw[f][j]);
@@ -536,19 +373,21 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                 }
             }
             __syncthreads();
-            block_sum_to<F>(pd, red_lds, vals);
+            block_sum_to<2 * F>(pd, red_lds, vals);
         }
-        alive = sync_reduce(a.sy, ++epoch, vals, F, nblocks);
+        alive = sync_reduce(a.sy, ++epoch, vals, 2 * F, nblocks);
         if (!alive) break;
         if (threadIdx.x == 0) {
             for (int f = 0; f < F; ++f) {
                 if (!s_inner[f]) continue;
-                if (!(vals[f] > 0.0)) {
+                const double del = vals[f], gam = vals[F + f];
+                if (!(del > 0.0) || !(gam > 0.0)) {
                     s_inner[f] = 0; s_done[f] = 1;
                     s_flags |= P2M_FLAG_BREAKDOWN | P2M_FLAG_NOT_CONVERGED;
                     continue;
                 }
-                s_alpha[f] = s_gam[f] / vals[f];
+                s_gam[f] = gam;
+                s_alpha[f] = gam / del;
                 s_af[f] = (float)s_alpha[f];
                 s_bf[f] = 0.f;
             }
@@ -580,8 +419,8 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     if (!(imask & (1u << f))) continue;
-                    const float sn = fmaf(bf[f], so[f], wo[f]);
-                    lf[(size_t)f * LH * LW + lidx(lc, lr)] = fmaf(-af[f], sn, ro[f]);
+                    lf[(size_t)f * LH * LW + lidx(lc, lr)] =
+                        halo_u(af[f], bf[f], dv[lidx(lc, lr)], ro[f], wo[f], so[f]);
                 }
             }
             // local updates and the new residual into LDS
@@ -592,20 +431,18 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                 float* L = lf + (size_t)f * LH * LW;
 #pragma unroll
                 for (int j = 0; j < RNPT; ++j) {
-                    vp[f][j] = fmaf(be, vp[f][j], vr[f][j]);
-                    vd[f][j] = fmaf(al, vp[f][j], vd[f][j]);
-                    vs[f][j] = fmaf(be, vs[f][j], vw[f][j]);
-                    vr[f][j] = fmaf(-al, vs[f][j], vr[f][j]);
-                    if (amask & (1u << j)) L[qj(j)] = vr[f][j];
+                    const float un = pcg_update(al, be, dv[qj(j)], vp[f][j], vd[f][j], vs[f][j],
+                                                vr[f][j], vw[f][j]);
+                    if (amask & (1u << j)) L[qj(j)] = un;
                 }
             }
             __syncthreads();
             ex ^= 1;
             {
                 spmv_all(imask);
-                double pg[2 * F];
+                double pg[3 * F];
 #pragma unroll
-                for (int q = 0; q < 2 * F; ++q) pg[q] = 0.0;
+                for (int q = 0; q < 3 * F; ++q) pg[q] = 0.0;
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     if (!(imask & (1u << f))) continue;
@@ -614,8 +451,10 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
 #pragma unroll
                     for (int j = 0; j < RNPT; ++j) {
                         if (!(amask & (1u << j))) continue;
-                        pg[f] += (double)vr[f][j] * (double)vr[f][j];
-                        pg[F + f] += (double)vw[f][j] * (double)vr[f][j];
+                        const float uj = lf[(size_t)f * LH * LW + qj(j)];
+                        pg[f] = dot_acc(pg[f], vr[f][j], uj);
+                        pg[F + f] = dot_acc(pg[F + f], vw[f][j], uj);
+                        pg[2 * F + f] = dot_acc(pg[2 * F + f], vr[f][j], vr[f][j]);
                         if (bmask & (1u << j)) {
                             stf<kCoherent>(rr, gk(j), vr[f][j]);
                             stf<kCoherent>(rw, gk(j), vw[f][j]);
@@ -624,23 +463,23 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     }
                 }
                 __syncthreads();
-                block_sum_to<2 * F>(pg, red_lds, vals);
+                block_sum_to<3 * F>(pg, red_lds, vals);
             }
-            alive = sync_reduce(a.sy, ++epoch, vals, 2 * F, nblocks);
+            alive = sync_reduce(a.sy, ++epoch, vals, 3 * F, nblocks);
             if (!alive) break;
             if (threadIdx.x == 0) {
                 int any = 0;
                 for (int f = 0; f < F; ++f) {
                     if (!s_inner[f]) continue;
-                    const double gam = vals[f], del = vals[F + f];
+                    const double gam = vals[f], del = vals[F + f], rho = vals[2 * F + f];
                     s_iters[f] += 1;
-                    if (!(gam > s_target[f]) || s_iters[f] >= a.opts.maxit) {
+                    if (!(rho > s_target[f]) || s_iters[f] >= a.opts.maxit) {
                         s_inner[f] = 0;
                         continue;
                     }
                     const double beta = gam / s_gam[f];
                     const double den = del - beta * gam / s_alpha[f];
-                    if (!(den > 0.0) || !(gam == gam)) {
+                    if (!(den > 0.0) || !(gam > 0.0)) {
                         s_inner[f] = 0;
                         s_flags |= P2M_FLAG_BREAKDOWN;
                         continue;

@@ -32,6 +32,34 @@ struct Particles {
     const T* vol;     // may be null
 };
 
+// Launch geometry shared by the host planner and the kernels.
+constexpr int kBinBlock = 256;       // particles per block of the locate / place kernels
+constexpr int kSolveTileX = 128;     // node tile of the tile solvers (one workgroup per tile)
+constexpr int kSolveTileY = 32;
+
+// Node tile of the 2D scatter for F fields of element size tsize: 16 x 16 unless
+// the per-cell parts of its 17 x 17 cells exceed 64 KB of LDS, then 8 x 8.
+constexpr int assemble_tile(int F, int tsize) {
+    return (size_t)(13 + 4 * F) * 17 * 17 * tsize <= 65536 ? 16 : 8;
+}
+
+// One instance of a batch of independent 2D FP32 problems (an entry of the
+// device-side instance table).  Particles, cells / nodes and tiles of all
+// instances are numbered in one space each; an instance owns the contiguous
+// ranges starting at po (particles), no (nodes = cells), lb (locate blocks),
+// at (scatter tiles) and rt (solver tiles).  Node-sized work arrays hold the
+// instance's block of F * nn values at F * no.
+struct BatchInst {
+    Mesh m;
+    Particles<float> P;
+    const float* values;   // [F][np]
+    float* out;            // [F][nn] start (USER) on entry, result on exit
+    p2m_report* rep;
+    int32_t po, no, lb;
+    int32_t at, atx;       // first scatter tile, scatter tiles per row
+    int32_t rt, rtx, nrt;  // first solver tile, solver tiles per row, solver tiles
+};
+
 // ---------------------------------------------------------------------------
 // locate: cell of a coordinate and the offset inside it, in FP64.
 // t = x * (n/L); c = floor(t); xi = t - c (exact); c == n wraps to 0.
@@ -145,5 +173,46 @@ bool cgr_supported(const Mesh& m, int F, int device);
 hipError_t launch_cg_resident(const Mesh& m, int F, float* coef, float* b, const float* w,
                               float* x, int start, void* ws, const p2m_solve_opts& opts,
                               p2m_report* rep, hipStream_t stream);
+
+// ---------------------------------------------------------------------------
+// batches (k_bin.hip, k_assemble.hip, k_cgb.hip)
+// ---------------------------------------------------------------------------
+hipError_t launch_report_clear_n(p2m_report* reps, int n, hipStream_t stream);
+// locate + count of every particle of the batch; block b belongs to instance
+// lmap[b]; keys are batch cell numbers (or -1)
+hipError_t launch_locate_count_batch(const BatchInst* inst, const int32_t* lmap, int nblocks,
+                                     int32_t* key, int32_t* counts, hipStream_t stream);
+// place / segment sort over the whole batch (keys and cell_start in batch numbering,
+// perm receives batch particle numbers); no tail is written
+hipError_t launch_place_flat(int np, const int32_t* key, const int32_t* cell_start,
+                             int32_t* fill, int32_t* perm, hipStream_t stream);
+hipError_t launch_segment_sort_flat(int ncells, const int32_t* cell_start, int32_t* perm,
+                                    hipStream_t stream);
+// scatter of every instance: tile t belongs to instance amap[t]; b, w, coef hold
+// the instances' blocks (b at F*no, w at no, coef at 4*no)
+hipError_t launch_assemble_batch(int F, const BatchInst* inst, const int32_t* amap, int ntiles,
+                                 const int32_t* perm, const int32_t* cell_start, float* b,
+                                 float* w, float* coef, hipStream_t stream);
+
+// Batched mass solve: one persistent kernel for all instances, several solver
+// tiles per workgroup with the CG state streamed from owner-only arrays.
+constexpr int kBatchMaxInstances = 128;
+constexpr int kBatchMaxPairs = 256;      // instances x fields
+constexpr int kBatchMaxOwn = 32;         // solver tiles per workgroup
+struct BatchSolveBufs {
+    const BatchInst* inst;
+    int nprob;
+    const int32_t* rmap;   // solver tile -> instance
+    int ntiles;
+    float* coef;           // instance blocks [4][nn] at 4*no
+    float* b;              // [F][nn] at F*no
+    const float* w;        // [nn] at no
+    void* ws;              // cgb_workspace_bytes of scratch
+};
+int cgb_grid(int F, int ntiles, int device);   // 0: does not fit
+size_t cgb_workspace_bytes(int F, int nprob, int ntiles, size_t nodes);
+hipError_t launch_cg_batch(int F, const BatchSolveBufs& bb, size_t nodes, int grid, int start,
+                           const p2m_solve_opts& opts, hipStream_t stream);
+const void* cgb_kernel(int F);
 
 }  // namespace p2m

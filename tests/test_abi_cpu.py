@@ -20,7 +20,9 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("p2m_create", "p2m_destroy", "p2m_workspace_size", "p2m_bin", "p2m_assemble",
-              "p2m_assign", "p2m_interpolate", "p2m_mass_assign", "p2m_status_string"):
+              "p2m_assign", "p2m_interpolate", "p2m_mass_assign", "p2m_status_string",
+              "p2m_mass_solve", "p2m_set_option", "p2m_batch_workspace_size",
+              "p2m_mass_assign_batched"):
         assert n in names
 
 
@@ -57,6 +59,8 @@ def test_argument_errors_without_a_device():
     L = B.lib()
     n = ctypes.c_size_t()
     assert L.p2m_workspace_size(None, None, 1, ctypes.byref(n)) == 1
+    assert L.p2m_batch_workspace_size(None, None, 1, 1, ctypes.byref(n)) == 1
+    assert L.p2m_mass_assign_batched(None, None, 1, None, 1, None, None, None, None, 0, None) == 1
     h = ctypes.c_void_p()
     st = L.p2m_create(ctypes.byref(h), 0)
     if st == 0:          # a GPU is present: exercise problem validation too
