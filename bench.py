@@ -16,10 +16,15 @@ kernels of p2m_mass_assign.  value = fields x steps / wall time of the timed ste
 Prints one JSON line.  Besides the contract keys it carries
   roofline     : HBM roofline of the dominant kernel (the mass solve, one launch
                  per step), algorithmic bytes per launch / its event-timed duration;
-  cpu_baseline : the FP64 CPU oracle timed on this host on a bounded sample;
+  cpu_baseline : the FP64 CPU oracle timed on this host, one thread, on the full input;
   accuracy     : relative l2 error of the GPU result against the FP64 oracle
                  solution of the same input, per field;
-  phases       : event-timed milliseconds of the two calls of a step.
+  phases       : event-timed milliseconds of the two calls of a step;
+  batched      : the uneven batch (64 independent TG problems, sides log-uniform
+                 in [32, 512], 2-16 particles per cell, F = 2, seed 3) as one
+                 p2m_mass_assign_batched graph launch: aggregate projections/s,
+                 the same 64 problems as 64 p2m_mass_assign calls, and the worst
+                 per-instance error against the FP64 oracle (--no-batch skips it).
 """
 from __future__ import annotations
 
@@ -50,8 +55,9 @@ def cg_algorithmic_bytes(k_ref, nn, F, c_m=4):
 
 
 def oracle_reference(prob, vals, tol):
-    """FP64 oracle on the full input: the solution (to 1e-12) and the FP64 CG
-    iteration count from the FLIP start to ``tol`` (the roofline's K_ref)."""
+    """FP64 oracle on the full input: the solution (to 1e-12) and the iteration
+    count of FP64 Jacobi-preconditioned CG (the solver's iteration) from the FLIP
+    start to ``tol`` (the roofline's K_ref)."""
     from oracle import p1
     pr = dict(prob, x=prob["x"].astype(np.float64), y=prob["y"].astype(np.float64))
     st = p1.assemble_stencil(pr, vals.astype(np.float64))
@@ -61,30 +67,94 @@ def oracle_reference(prob, vals, tol):
     for f in range(vals.shape[0]):
         b = np.where(w > 0, st["b"][f], 0.0)
         x0 = np.where(w > 0, b / np.where(w > 0, w, 1.0), 0.0)
-        _, it = p1.cg_fp64(M, b, x0=x0, rtol=tol)
+        _, it = p1.pcg_jacobi_fp64(M, b, x0=x0, rtol=tol)
         k_ref.append(it)
         x, _ = p1.cg_fp64(M, b, x0=x0, rtol=1e-12)
         xs.append(x)
     return np.stack(xs), k_ref
 
 
-def cpu_baseline(sample_n=512):
-    """The FP64 oracle's mass assignment (as it stands) on a bounded sample of the
-    workload: the same recipe at sample_n^2 nodes; scaled to 1024^2 by node count."""
+def cpu_baseline(prob, vals):
+    """The FP64 oracle's mass assignment (as it stands, p1.mass_assign) on the
+    benchmark input itself, one call, with every BLAS / OpenMP pool held to one
+    thread (numpy's bincount and scipy's sparse products are single-threaded)."""
+    from threadpoolctl import threadpool_limits
     from oracle import p1
-    from paper_1610_05258_amd import workloads as wl
-    prob, vals = wl.taylor_green_2d(seed=2, n=sample_n, ppc=8, steps=50, dt=1e-3)
     pr = dict(prob, x=prob["x"].astype(np.float64), y=prob["y"].astype(np.float64))
     v = vals.astype(np.float64)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        p1.mass_assign(pr, v)
+        dt = time.perf_counter() - t0
+    return dict(value=vals.shape[0] / dt, unit="projections/s", cores=1, kind="oracle",
+                sample=f"the full workload (1024x1024, 8 ppc, F=3), one FP64 oracle mass_assign "
+                       f"(scipy sparse assembly + CG) in {dt:.2f} s on 1 thread of "
+                       f"{os.cpu_count()} host cores")
+
+
+def batched_leg(B, ctx, check, reps=10, tol=1e-9):
+    """The uneven batch as one graph launch, and as one call per problem."""
+    import torch
+    from paper_1610_05258_amd import workloads as wl
+    insts = wl.uneven_batch(seed=3, count=64)
+    probs = [B.particles_from(p, dtype=torch.float32) for p, _ in insts]
+    vals = [torch.as_tensor(v).cuda() for _, v in insts]
+    F = insts[0][1].shape[0]
+    opts = B.solve_opts(tol=tol, inner_rtol=1e-4, maxit=2000, max_refine=10)
+    bt = B.Batch(ctx, probs, vals, opts)
+    for _ in range(2):
+        bt.run()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    p1.mass_assign(pr, v)
-    dt = time.perf_counter() - t0
-    scale = (sample_n * sample_n) / (1024 * 1024)
-    # numpy bincount / scipy sparse products and solves run on one thread
-    return dict(value=vals.shape[0] / dt * scale, unit="projections/s", cores=1, kind="oracle",
-                sample=f"{sample_n}x{sample_n} mesh, 8 ppc, same TG recipe, F=3, one FP64 oracle "
-                       f"mass_assign in {dt:.2f} s on 1 thread of {os.cpu_count()} host cores; "
-                       f"scaled by nodes ({sample_n}^2/1024^2)")
+    for _ in range(reps):
+        bt.run()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    outs = [torch.empty_like(o) for o in bt.out]
+    rep_s = [ctx.new_report() for _ in insts]
+    ws = ctx.workspace(max(ctx.workspace_size(p, F) for p in probs))
+
+    def singles():
+        for k in range(len(insts)):
+            B.p2m_mass_assign(ctx, probs[k], vals[k], opts, ws=ws, rep=rep_s[k], out=outs[k])
+    singles()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        singles()
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / reps
+    r = bt.reports()
+    bitwise = all(torch.equal(a, b) for a, b in zip(bt.out, outs))
+    res = dict(workload="64 independent taylor-green u,v problems, side log-uniform [32,512], "
+                        "2-16 stratified particles per cell, seed 3, F=2, tol=%g" % tol,
+               nodes=int(sum(p.n_nodes for p in probs)),
+               particles=int(sum(p.n_particles for p in probs)),
+               value=len(insts) * F / t_batch, unit="projections/s", ms_per_batch=t_batch * 1e3,
+               single_calls_ms=t_single * 1e3, speedup_vs_single_calls=t_single / t_batch,
+               bitwise_equal_to_single_calls=bool(bitwise),
+               max_iters=int(max(int(x.iters[:F].max()) for x in r)),
+               max_rel_residual=float(max(float(x.rel_residual[:F].max()) for x in r)),
+               flags=int(np.bitwise_or.reduce([x.flags for x in r])))
+    log(f"bench: batched {t_batch * 1e3:.3f} ms ({res['value']:.0f} projections/s), "
+        f"single calls {t_single * 1e3:.3f} ms, bitwise {bitwise}")
+    if check:
+        from oracle import metrics
+        from oracle import p1
+        worst, worst_inf = 0.0, 0.0
+        for k, (p, v) in enumerate(insts):
+            pr = dict(p, x=p["x"].astype(np.float64), y=p["y"].astype(np.float64))
+            st = p1.assemble_stencil(pr, v.astype(np.float64))
+            M = p1.regularised_matrix(p1.stencil_matrix(pr, st), st["w"])
+            got = bt.out[k].cpu().numpy().astype(np.float64)
+            for f in range(F):
+                x, _ = p1.cg_fp64(M, st["b"][f], rtol=1e-12)
+                worst = max(worst, metrics.rel_l2(got[f], x))
+                worst_inf = max(worst_inf, metrics.rel_linf(got[f], x))
+        res["max_instance_rel_l2"] = worst
+        res["max_instance_rel_linf"] = worst_inf
+        log(f"bench: batched worst instance rel_l2 {worst:.2e}")
+    return res
 
 
 def main():
@@ -95,6 +165,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -190,7 +261,9 @@ def main():
                       "inputs, CG to 1e-12")
         log(f"bench: accuracy {result['accuracy']['rel_l2']}, K_ref {k_ref}")
         log("bench: CPU baseline (oracle on a bounded sample)")
-        result["cpu_baseline"] = cpu_baseline()
+        result["cpu_baseline"] = cpu_baseline(prob, vals)
+    if not args.no_batch:
+        result["batched"] = batched_leg(B, ctx, check=not args.no_cpu)
     if k_ref is not None:
         kk = max(k_ref)
         achieved = cg_algorithmic_bytes(kk, nn, F) / (cg_ms * 1e-3) / 1e9

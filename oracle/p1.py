@@ -282,6 +282,34 @@ def cg_fp64(A, b, x0=None, rtol=1e-14, maxit=10000):
     return x, maxit
 
 
+def pcg_jacobi_fp64(A, b, x0=None, rtol=1e-14, maxit=10000):
+    """Textbook preconditioned CG in FP64 with the diagonal (Jacobi) preconditioner
+    u = r / diag(A); stop at the unpreconditioned ||r|| <= rtol*||b||.  Same solution
+    as cg_fp64 (the iteration, not the system, changes); with a unit diagonal the
+    iterates are those of cg_fp64.  Returns (x, iterations)."""
+    x = np.zeros_like(b) if x0 is None else x0.astype(np.float64).copy()
+    dinv = 1.0 / A.diagonal()
+    r = b - A @ x
+    bn = np.linalg.norm(b)
+    if bn == 0.0:
+        return np.zeros_like(b), 0
+    u = dinv * r
+    p = u.copy()
+    ru = r @ u
+    for it in range(maxit):
+        if np.linalg.norm(r) <= rtol * bn:
+            return x, it
+        q = A @ p
+        alpha = ru / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        u = dinv * r
+        ru_new = r @ u
+        p = u + (ru_new / ru) * p
+        ru = ru_new
+    return x, maxit
+
+
 def mass_solve(M, w, b, solver="auto", rtol=1e-14):
     """Solve M Abar_f = b_f for every field (Sec. 2.4 eqs. (13), (19); Table 1, mass rows)."""
     A = regularised_matrix(M, w)

@@ -525,37 +525,31 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                     af[f] = s_af[k * F + f];
                     bf[f] = s_bf[k * F + f];
                 }
-                load_coef(true);
-                __syncthreads();
-                for (int h = threadIdx.x; h < nhalo; h += RBS) {
-                    int lc, lr;
-                    if (!halo_slot(h, txa, tya, lc, lr)) continue;
-                    const int gh = ghalo(lc, lr);
-                    float ro[F], wo[F], so[F];
+                // every load of the tile is issued before any result is used: own
+                // coefficients and state, then the ring (diagonal and weight, the
+                // published state, and the edge coefficients of the left column and
+                // bottom row); one ring slot per thread (nhalo < RBS)
+                const float* c = a.coef + (size_t)4 * no;
+                const float* w = a.w + no;
+                float cD[RNPT], cE[RNPT], cN[RNPT], cNE[RNPT];
 #pragma unroll
-                    for (int f = 0; f < F; ++f) {
-                        ro[f] = ldf<kCoherent>(rs_pub(a.pubR, ex, f), gh);
-                        wo[f] = ldf<kCoherent>(rs_pub(a.pubW, ex, f), gh);
-                        so[f] = ldf<kCoherent>(rs_pub(a.pubS, ex, f), gh);
-                    }
-#pragma unroll
-                    for (int f = 0; f < F; ++f) {
-                        if (!(imask & (1u << f))) continue;
-                        lf[(size_t)f * LH * LW + lidx(lc, lr)] =
-                            halo_u(af[f], bf[f], dv[lidx(lc, lr)], ro[f], wo[f], so[f]);
-                    }
+                for (int j = 0; j < RNPT; ++j) {
+                    cD[j] = cE[j] = cN[j] = cNE[j] = 0.f;
+                    if (!(amask & (1u << j))) continue;
+                    const int kk = gk(j);
+                    cD[j] = c[kk];
+                    cE[j] = c[(size_t)nn + kk];
+                    cN[j] = c[(size_t)2 * nn + kk];
+                    cNE[j] = c[(size_t)3 * nn + kk];
                 }
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
-                    if (!(imask & (1u << f))) continue;
-                    const float al = af[f], be = bf[f];
-                    float* L = lf + (size_t)f * LH * LW;
                     const rsrc_t sP = rs_f4(a.sP, f), sD = rs_f4(a.sD, f), sS = rs_f4(a.sS, f),
                                  sR = rs_f4(a.sR, f), sW = rs_f4(a.sW, f);
 #pragma unroll
                     for (int j = 0; j < RNPT; ++j) {
                         vp[f][j] = vd[f][j] = vs[f][j] = vr[f][j] = vw[f][j] = 0.f;
-                        if (!(amask & (1u << j))) continue;
+                        if (!(imask & (1u << f)) || !(amask & (1u << j))) continue;
                         const int kk = gk(j);
                         vp[f][j] = ldf<kPlain>(sP, kk);
                         vd[f][j] = ldf<kPlain>(sD, kk);
@@ -563,11 +557,61 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                         vr[f][j] = ldf<kPlain>(sR, kk);
                         vw[f][j] = ldf<kPlain>(sW, kk);
                     }
+                }
+                {
+                    int lc = 0, lr = 0;
+                    if (threadIdx.x < nhalo && halo_slot(threadIdx.x, txa, tya, lc, lr)) {
+                        const int gh = ghalo(lc, lr);
+                        // a neighbour's stored diagonal may predate its owner's orphan
+                        // fix in this launch: the orphan test reads w, never rewritten
+                        const float dh = jacobi_inv(c[gh], w[gh]);
+                        float ro[F], wo[F], so[F];
+#pragma unroll
+                        for (int f = 0; f < F; ++f) {
+                            ro[f] = ldf<kCoherent>(rs_pub(a.pubR, ex, f), gh);
+                            wo[f] = ldf<kCoherent>(rs_pub(a.pubW, ex, f), gh);
+                            so[f] = ldf<kCoherent>(rs_pub(a.pubS, ex, f), gh);
+                        }
+                        // edge coefficients: bottom row lc in [-1, txa), left column
+                        // lr in [0, tya) (the only ring slots the stencil reads)
+                        if ((lr == -1 && lc < txa) || (lc == -1 && lr >= 0 && lr < tya)) {
+                            const int q = cidx(lc, lr);
+                            cf[CN + q] = c[(size_t)nn + gh];
+                            cf[2 * CN + q] = c[(size_t)2 * nn + gh];
+                            cf[3 * CN + q] = c[(size_t)3 * nn + gh];
+                        }
+#pragma unroll
+                        for (int f = 0; f < F; ++f) {
+                            if (!(imask & (1u << f))) continue;
+                            lf[(size_t)f * LH * LW + lidx(lc, lr)] =
+                                halo_u(af[f], bf[f], dh, ro[f], wo[f], so[f]);
+                        }
+                    }
+                }
+                // own nodes: coefficients into LDS, the updates, u into the planes.
+                // The own diagonal is already regularised (1 for an orphan, written
+                // by this workgroup), so its reciprocal is the Jacobi factor.
+#pragma unroll
+                for (int j = 0; j < RNPT; ++j) {
+                    if (!(amask & (1u << j))) continue;
+                    const int qc = qcj(j);
+                    cf[qc] = cD[j];
+                    cf[CN + qc] = cE[j];
+                    cf[2 * CN + qc] = cN[j];
+                    cf[3 * CN + qc] = cNE[j];
+                }
+#pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    if (!(imask & (1u << f))) continue;
+                    const float al = af[f], be = bf[f];
+                    float* L = lf + (size_t)f * LH * LW;
+                    const rsrc_t sP = rs_f4(a.sP, f), sD = rs_f4(a.sD, f), sS = rs_f4(a.sS, f),
+                                 sR = rs_f4(a.sR, f);
 #pragma unroll
                     for (int j = 0; j < RNPT; ++j) {
                         if (!(amask & (1u << j))) continue;
-                        const float un = pcg_update(al, be, dv[qj(j)], vp[f][j], vd[f][j],
-                                                    vs[f][j], vr[f][j], vw[f][j]);
+                        const float un = pcg_update(al, be, jacobi_inv(cD[j], 1.f), vp[f][j],
+                                                    vd[f][j], vs[f][j], vr[f][j], vw[f][j]);
                         const int kk = gk(j);
                         stf<kPlain>(sP, kk, vp[f][j]);
                         stf<kPlain>(sD, kk, vd[f][j]);

@@ -299,6 +299,37 @@ def test_mass_solver_paths_agree():
     assert np.all(p1.relative_residual(a["M"], a["w"], a["b"], xd) < 1e-13)
 
 
+def test_jacobi_pcg_pins():
+    """The preconditioned solver used for iteration counts: its solution is the
+    direct solve's; with a unit diagonal its iterates are plain CG's; on a
+    diagonal matrix it converges in one step (the preconditioner is exact)."""
+    import scipy.sparse as sp
+    prob, vals = tg_small(n=24, ppc=2, steps=60)
+    a = p1.assemble(prob, vals)
+    A = p1.regularised_matrix(a["M"], a["w"])
+    xd = p1.mass_solve(a["M"], a["w"], a["b"], solver="direct")
+    b = np.where(a["w"] > 0, a["b"][0], 0.0)
+    xp, kp = p1.pcg_jacobi_fp64(A, b, rtol=1e-14)
+    assert metrics.rel_l2(xp, xd[0]) < 1e-12
+    _, kc = p1.cg_fp64(A, b, rtol=1e-10)
+    _, kp10 = p1.pcg_jacobi_fp64(A, b, rtol=1e-10)
+    assert kp10 < kc          # 2 particles per cell: the diagonal scaling pays off
+    # unit diagonal: identical to plain CG
+    dh = 1.0 / np.sqrt(A.diagonal())
+    S = sp.diags(dh) @ A @ sp.diags(dh)
+    S = sp.csr_matrix(S)
+    S.setdiag(1.0)
+    bs = dh * b
+    x1, k1 = p1.cg_fp64(S, bs, rtol=1e-9)
+    x2, k2 = p1.pcg_jacobi_fp64(S, bs, rtol=1e-9)
+    assert k1 == k2 and np.allclose(x1, x2, rtol=0, atol=1e-13 * np.abs(x1).max())
+    # diagonal matrix: exact after one step
+    Dm = sp.diags(np.linspace(1.0, 50.0, 40)).tocsr()
+    rhs = np.cos(np.arange(40.0))
+    x3, k3 = p1.pcg_jacobi_fp64(Dm, rhs, rtol=1e-14)
+    assert k3 == 1 and np.allclose(x3, rhs / np.linspace(1.0, 50.0, 40), rtol=1e-15)
+
+
 def test_translation_covariance_whole_cells():
     """Shifting every particle by whole cells (dyadic L: exact in FP64) shifts the nodal result."""
     n = 8
