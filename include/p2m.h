@@ -91,7 +91,7 @@ typedef enum {
     P2M_START_FLIP = 0,     /* x0 = b/w (the FLIP values; equal to delta for regular particles, Sec. 3.1) */
     P2M_START_ZERO = 1,
     P2M_START_USER = 2,     /* x0 read from nodal_inout */
-    P2M_START_LEARNED = 3,  /* reserved for the learned warm start */
+    P2M_START_LEARNED = 3,  /* the learned warm start (p2m_set_learned); 2D FP32 only */
     P2M_START_DELTA1D = 4   /* 1D only: the delta assignment as x0 */
 } p2m_start;
 
@@ -179,7 +179,10 @@ p2m_status p2m_interpolate(void* ctx, const p2m_problem* prob, const void* nodal
  * p2m_solve_opts (FP32 arithmetic when dtype is F32, FP64 residuals and dot
  * products).  Orphan nodes (w_i == 0) are solved as Abar_i = 0.  nodal_inout is
  * [F][nnodes]: read as the start when opts->start == P2M_START_USER, always
- * written with the result.  rep is required. */
+ * written with the result.  With P2M_START_LEARNED (2D FP32, parameters set with
+ * p2m_set_learned) the network proposes the start; a field whose proposed start
+ * has a larger FP64 residual ||b - M x0|| than the FLIP start is started from
+ * FLIP instead and P2M_FLAG_LEARNED_FALLBACK is raised.  rep is required. */
 p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
                            const p2m_solve_opts* opts, void* nodal_inout, p2m_report* rep,
                            void* ws, size_t ws_bytes, void* stream);
@@ -243,6 +246,74 @@ p2m_status p2m_mass_assign_batched(void* ctx, const p2m_problem* probs, int32_t 
                                    const void* const* values, int32_t nfields,
                                    const p2m_solve_opts* opts, void* const* nodal_inout,
                                    p2m_report* reps, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start (not part of the paper's method: a start vector for the
+ * mass solve; the solve, its tolerance and the residual test are unchanged).
+ *
+ * Node features.  The receptive field of node i is the support of psi_i, the
+ * four cells sharing the node: a = (ix, iy), b = (ix-1, iy), c = (ix-1, iy-1),
+ * d = (ix, iy-1) (periodic).  Their particles are taken cell by cell in that
+ * order, each cell in binned order (ascending original index), and the first
+ * P2M_LEARNED_KMAX are kept; n counts them all.  A kept particle contributes
+ * three inputs: its offset from the node in cell units, (xi - [cell b or c],
+ * eta - [cell c or d]) from the FP64 locate, and (A - base) / s, where base =
+ * b_i / w_i is the FLIP value (0 at an orphan) and s the RMS of A - base over the
+ * kept particles.  Input 144 is min(n, 48) / 48; inputs of absent particles and
+ * inputs 145..159 are 0.  A node is usable when 1 <= n <= 48, w_i > 0 and
+ * s > 2^-20 max |A| over its kept particles.
+ *
+ * Network.  z1 = W1 x + b1, h1 = relu(z1), z2 = W2 h1 + b2, h2 = relu(z2),
+ * z3 = W3 h2 + b3, h3 = relu(z3), y = W4 . h3 + b4.  W1..W3, x, h1, h2 are
+ * rounded to BF16 (to nearest even) and multiplied on the matrix cores with
+ * FP32 accumulation; biases, W4 and h3 are FP32.  The start value of a usable
+ * node is base + s * y, of any other node base.
+ *
+ * Parameters: one FP32 device vector of P2M_LEARNED_NPARAM entries, in order
+ * W1 [64][160] (row-major, columns 145..159 unused), b1 [64], W2 [64][64],
+ * b2 [64], W3 [64][64], b3 [64], W4 [64], b4 [1].
+ * --------------------------------------------------------------------------- */
+enum {
+    P2M_LEARNED_KMAX = 48,
+    P2M_LEARNED_NIN = 160,
+    P2M_LEARNED_HIDDEN = 64,
+    P2M_LEARNED_NPARAM = 18689
+};
+
+/* Parameters used by P2M_START_LEARNED on this context (device pointer, read at
+ * every call; NULL disables the learned start).  For callers that train a
+ * network or load trained weights. */
+p2m_status p2m_set_learned(void* ctx, const float* params);
+
+/* Feature rows of nodes[0..nrows) (nodes NULL: every node, nrows = nnodes) of a
+ * 2D FP32 problem: bins and scatters the particles (b and w), then writes
+ *   x_out     [nrows][F][160] BF16 (2-byte elements, layout above),
+ *   base_out  [nrows][F] the FLIP values, scale_out [nrows][F] s, or 0 where the
+ *             node is not usable.
+ * Needs the workspace of p2m_workspace_size. */
+p2m_status p2m_learned_features(void* ctx, const p2m_problem* prob, const void* values,
+                                int32_t nfields, const int32_t* nodes, int32_t nrows, void* x_out,
+                                float* base_out, float* scale_out, p2m_report* rep, void* ws,
+                                size_t ws_bytes, void* stream);
+
+/* Network outputs y_out[r] of feature rows x [nrows][160] (BF16) with params. */
+p2m_status p2m_learned_forward(void* ctx, const float* params, const void* x, int32_t nrows,
+                               float* y_out, void* stream);
+
+/* Workspace bytes of p2m_learned_train_step for a batch size. */
+p2m_status p2m_learned_workspace_size(void* ctx, int32_t batch, size_t* bytes);
+
+/* One training step on the rows rows[0..batch) of x [.][160] (BF16) with targets
+ * target[row] (FP32): the loss (1/batch) sum (y - target)^2 goes to loss_out[0]
+ * (device), its gradient to grad_out (device, P2M_LEARNED_NPARAM, may be NULL);
+ * with apply != 0 one Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected
+ * with step >= 1, learning rate lr) updates params, adam_m and adam_v in place.
+ * Deterministic: every sum has a fixed order. */
+p2m_status p2m_learned_train_step(void* ctx, float* params, float* adam_m, float* adam_v,
+                                  int32_t step, float lr, const void* x, const float* target,
+                                  const int32_t* rows, int32_t batch, float* loss_out,
+                                  float* grad_out, int32_t apply, void* ws, size_t ws_bytes,
+                                  void* stream);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,10 @@ SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT = 0, 1, 2
 
 EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size", "p2m_bin",
            "p2m_assemble", "p2m_assign", "p2m_interpolate", "p2m_mass_assign", "p2m_mass_solve",
-           "p2m_set_option", "p2m_batch_workspace_size", "p2m_mass_assign_batched")
+           "p2m_set_option", "p2m_batch_workspace_size", "p2m_mass_assign_batched",
+           "p2m_set_learned", "p2m_learned_features", "p2m_learned_forward",
+           "p2m_learned_workspace_size", "p2m_learned_train_step")
+LEARNED_KMAX, LEARNED_NIN, LEARNED_HIDDEN, LEARNED_NPARAM = 48, 160, 64, 18689
 
 
 class P2MError(RuntimeError):
@@ -89,6 +92,14 @@ def lib():
         L.p2m_mass_assign_batched.argtypes = [vp, pprob, i32, ctypes.POINTER(vp), i32,
                                               ctypes.POINTER(CSolveOpts), ctypes.POINTER(vp), vp, vp,
                                               sz, vp]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.p2m_set_learned.argtypes = [vp, vp]
+        L.p2m_learned_features.argtypes = [vp, pprob, vp, i32, vp, i32, vp, vp, vp, vp, vp, sz, vp]
+        L.p2m_learned_forward.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.p2m_learned_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
+        L.p2m_learned_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, i32,
+                                             vp, vp, i32, vp, sz, vp]
+        del fp
         for name in EXPORTS[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -411,3 +422,79 @@ def p2m_mass_assign_batched(ctx: Context, probs, values, opts: CSolveOpts | None
             o.copy_(x)
     b.run(stream)
     return b.out, b
+
+
+# ----------------------------------------------------------------------------
+# learned warm start
+# ----------------------------------------------------------------------------
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def set_learned(ctx: Context, params):
+    """Parameters (FP32 device tensor of LEARNED_NPARAM) for START_LEARNED, or None."""
+    if params is not None:
+        if params.dtype != torch.float32 or not params.is_cuda or params.numel() != LEARNED_NPARAM:
+            raise TypeError("params must be a float32 device tensor of LEARNED_NPARAM entries")
+        params = params.contiguous()
+    ctx._learned = params
+    _check(lib().p2m_set_learned(ctx.handle, _ptr(params)), "p2m_set_learned")
+
+
+def learned_features(ctx: Context, prob: Particles, values, nodes=None, stream=None, ws=None):
+    """Feature rows of the nodes (all when None): X [nrows, F, 160] bfloat16, base and
+    scale [nrows, F] (scale 0 = node not usable)."""
+    values, F = _values_tensor(values, prob)
+    dev = prob.x.device
+    nrows = prob.n_nodes if nodes is None else int(nodes.numel())
+    if nodes is not None:
+        nodes = nodes.to(device=dev, dtype=torch.int32).contiguous()
+    X = torch.empty((nrows, F, LEARNED_NIN), dtype=torch.bfloat16, device=dev)
+    base = torch.empty((nrows, F), dtype=torch.float32, device=dev)
+    scale = torch.empty((nrows, F), dtype=torch.float32, device=dev)
+    rep = ctx.new_report()
+    cp = prob.cstruct()
+    wp, wn = _ws_args(ctx, prob, F, ws)
+    _check(lib().p2m_learned_features(ctx.handle, ctypes.byref(cp), _ptr(values), F, _ptr(nodes),
+                                      nrows, _ptr(X), _ptr(base), _ptr(scale), _ptr(rep), wp, wn,
+                                      _stream_ptr(stream)), "p2m_learned_features")
+    return X, base, scale
+
+
+def learned_forward(ctx: Context, params, X, stream=None):
+    """Network outputs of rows X [n, 160] (bfloat16)."""
+    X = X.reshape(-1, LEARNED_NIN).contiguous()
+    y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(lib().p2m_learned_forward(ctx.handle, _ptr(params), _ptr(X), X.shape[0], _ptr(y),
+                                     _stream_ptr(stream)), "p2m_learned_forward")
+    return y
+
+
+class Trainer:
+    """Adam state and workspace for p2m_learned_train_step on one feature table."""
+
+    def __init__(self, ctx: Context, params, batch):
+        self.ctx = ctx
+        self.params = params
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.step = 0
+        self.batch = int(batch)
+        n = ctypes.c_size_t()
+        _check(lib().p2m_learned_workspace_size(ctx.handle, self.batch, ctypes.byref(n)),
+               "p2m_learned_workspace_size")
+        self.ws = torch.empty(int(n.value), dtype=torch.uint8, device=params.device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+
+    def run(self, X, target, rows, lr=1e-3, apply=True, grad=None, stream=None):
+        """One step on rows of X [N, 160] with targets [N]; returns the loss tensor."""
+        if rows.numel() > self.batch:
+            raise ValueError("more rows than the batch size")
+        if apply:
+            self.step += 1
+        _check(lib().p2m_learned_train_step(
+            self.ctx.handle, _ptr(self.params), _ptr(self.m), _ptr(self.v), max(self.step, 1),
+            float(lr), _ptr(X), _ptr(target), _ptr(rows), int(rows.numel()), _ptr(self.loss),
+            _ptr(grad), 1 if apply else 0, _ptr(self.ws), ctypes.c_size_t(self.ws.numel()),
+            _stream_ptr(stream)), "p2m_learned_train_step")
+        return self.loss

@@ -43,6 +43,7 @@ struct Context {
     int cg_blocks_f64;
     int resident_enabled;   // 1: use the register-resident solve where it fits
     BatchCache* batch;      // created on the first batched call
+    const float* learned;   // parameters of the learned start (device), or null
 };
 
 // Makes the context's device current for the duration of a call and restores
@@ -64,7 +65,8 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace carve-up.  Offsets are fixed functions of (problem, F, cg blocks).
 struct Layout {
-    size_t key, counts, cell_start, perm, scan, b, w, coef, r, p0, p1, q, x64, partials, resident, report, total;
+    size_t key, counts, cell_start, perm, scan, b, w, coef, r, p0, p1, q, x64, partials, resident,
+        learned, report, total;
 };
 
 Layout make_layout(const Mesh& m, int F, size_t tsize, int cg_blocks) {
@@ -93,6 +95,7 @@ Layout make_layout(const Mesh& m, int F, size_t tsize, int cg_blocks) {
     L.partials = take(cg_partials_bytes(cg_blocks));
     L.resident = take((m.dim == 2 && F <= kResidentMaxFields && tsize == 4)
                           ? cgr_workspace_bytes(m, F, cgr_tiles(m)) : 0);
+    L.learned = take((m.dim == 2 && tsize == 4) ? learned_start_workspace_bytes(m, F) : 0);
     L.report = take(sizeof(p2m_report));
     L.total = off;
     return L;
@@ -254,6 +257,14 @@ p2m_status run_mass(const Context* c, const Prepared& pp, const p2m_problem* pro
     P2M_TRY(launch_assemble<T>(pp.m, particles_of<T>(prob), (const T*)values, F, perm, cs, b, w,
                                coef, pp.stream));
     int start = opts.start;
+    if (start == P2M_START_LEARNED) {
+        if (sizeof(T) != 4) return P2M_ERR_UNSUPPORTED;
+        P2M_TRY(launch_learned_start(pp.m, particles_of<float>(prob), (const float*)values, F, perm,
+                                     cs, (const float*)b, (const float*)w, (const float*)coef,
+                                     c->learned, (float*)x, pp.ws + pp.L.learned, pp.rep,
+                                     pp.stream));
+        start = P2M_START_USER;
+    }
     if (start == P2M_START_DELTA1D) {
         P2M_TRY(launch_delta1d<T>(pp.m, particles_of<T>(prob), (const T*)values, F, perm, cs,
                                   (T*)x, pp.stream));
@@ -416,7 +427,6 @@ p2m_status check_opts(const p2m_solve_opts* opts) {
     if (!(opts->tol > 0.0) || opts->inner_rtol < 0.0 || opts->inner_rtol >= 1.0) return P2M_ERR_RANGE;
     if (opts->maxit < 0 || opts->max_refine < 0 || opts->reserved != 0) return P2M_ERR_INVALID_ARG;
     if (opts->start < P2M_START_FLIP || opts->start > P2M_START_DELTA1D) return P2M_ERR_INVALID_ARG;
-    if (opts->start == P2M_START_LEARNED) return P2M_ERR_UNSUPPORTED;
     return P2M_OK;
 }
 
@@ -568,6 +578,9 @@ p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* value
     s = prepare(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp);
     if (s != P2M_OK) return s;
     if (opts->start == P2M_START_DELTA1D && pp.m.dim != 1) return P2M_ERR_UNSUPPORTED;
+    if (opts->start == P2M_START_LEARNED &&
+        (pp.m.dim != 2 || prob->dtype != P2M_F32 || !((const Context*)ctx)->learned))
+        return P2M_ERR_UNSUPPORTED;
     if ((pp.m.np > 0 && !values) || !nodal_inout) return P2M_ERR_INVALID_ARG;
     DeviceGuard g(((Context*)ctx)->device);
     if (!g.ok) return P2M_ERR_HIP;
@@ -584,7 +597,8 @@ p2m_status p2m_mass_solve(void* ctx, const p2m_problem* prob, int32_t nfields, v
     if (!rep) return P2M_ERR_INVALID_ARG;
     p2m_status s = check_opts(opts);
     if (s != P2M_OK) return s;
-    if (opts->start == P2M_START_DELTA1D) return P2M_ERR_UNSUPPORTED;
+    if (opts->start == P2M_START_DELTA1D || opts->start == P2M_START_LEARNED)
+        return P2M_ERR_UNSUPPORTED;
     Prepared pp;
     s = prepare(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp);
     if (s != P2M_OK) return s;
@@ -620,7 +634,8 @@ p2m_status p2m_mass_assign_batched(void* ctx, const p2m_problem* probs, int32_t 
     if (!ctx || !values || !nodal_inout || !reps) return P2M_ERR_INVALID_ARG;
     p2m_status s = check_opts(opts);
     if (s != P2M_OK) return s;
-    if (opts->start == P2M_START_DELTA1D) return P2M_ERR_UNSUPPORTED;
+    if (opts->start == P2M_START_DELTA1D || opts->start == P2M_START_LEARNED)
+        return P2M_ERR_UNSUPPORTED;
     Context* c = (Context*)ctx;
     DeviceGuard g(c->device);
     if (!g.ok) return P2M_ERR_HIP;
@@ -678,6 +693,71 @@ p2m_status p2m_mass_assign_batched(void* ctx, const p2m_problem* probs, int32_t 
     }
     P2M_TRY(hipGraphLaunch(bc.exec, strm));
     return P2M_OK;
+}
+
+p2m_status p2m_set_learned(void* ctx, const float* params) {
+    if (!ctx) return P2M_ERR_INVALID_ARG;
+    ((Context*)ctx)->learned = params;
+    return P2M_OK;
+}
+
+p2m_status p2m_learned_features(void* ctx, const p2m_problem* prob, const void* values,
+                                int32_t nfields, const int32_t* nodes, int32_t nrows, void* x_out,
+                                float* base_out, float* scale_out, p2m_report* rep, void* ws,
+                                size_t ws_bytes, void* stream) {
+    Prepared pp;
+    p2m_status s = prepare(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp);
+    if (s != P2M_OK) return s;
+    if (pp.m.dim != 2 || prob->dtype != P2M_F32) return P2M_ERR_UNSUPPORTED;
+    if (nrows < 0 || (!nodes && nrows != pp.m.nn)) return P2M_ERR_INVALID_ARG;
+    if ((pp.m.np > 0 && !values) || (nrows > 0 && (!x_out || !base_out || !scale_out)))
+        return P2M_ERR_INVALID_ARG;
+    if ((size_t)nrows * nfields * P2M_LEARNED_NIN >= ((size_t)1 << 40)) return P2M_ERR_UNSUPPORTED;
+    DeviceGuard g(((Context*)ctx)->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+    int32_t* perm = (int32_t*)(pp.ws + pp.L.perm);
+    int32_t* cs = (int32_t*)(pp.ws + pp.L.cell_start);
+    s = run_bin<float>(pp, prob, perm, cs);
+    if (s != P2M_OK) return s;
+    float* b = (float*)(pp.ws + pp.L.b);
+    float* w = (float*)(pp.ws + pp.L.w);
+    P2M_TRY(launch_assemble<float>(pp.m, particles_of<float>(prob), (const float*)values, nfields,
+                                   perm, cs, b, w, nullptr, pp.stream));
+    P2M_TRY(launch_learn_features(pp.m, particles_of<float>(prob), (const float*)values, nfields,
+                                  perm, cs, b, w, nodes, nrows, x_out, base_out, scale_out,
+                                  pp.stream));
+    return P2M_OK;
+}
+
+p2m_status p2m_learned_forward(void* ctx, const float* params, const void* x, int32_t nrows,
+                               float* y_out, void* stream) {
+    if (!ctx || !params || nrows < 0 || (nrows > 0 && (!x || !y_out))) return P2M_ERR_INVALID_ARG;
+    DeviceGuard g(((Context*)ctx)->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    return st(launch_learn_forward(params, x, nrows, y_out, (hipStream_t)stream));
+}
+
+p2m_status p2m_learned_workspace_size(void* ctx, int32_t batch, size_t* bytes) {
+    if (!ctx || !bytes || batch < 1) return P2M_ERR_INVALID_ARG;
+    *bytes = learn_workspace_bytes(batch);
+    return P2M_OK;
+}
+
+p2m_status p2m_learned_train_step(void* ctx, float* params, float* adam_m, float* adam_v,
+                                  int32_t step, float lr, const void* x, const float* target,
+                                  const int32_t* rows, int32_t batch, float* loss_out,
+                                  float* grad_out, int32_t apply, void* ws, size_t ws_bytes,
+                                  void* stream) {
+    if (!ctx || !params || !x || !target || !rows || batch < 1) return P2M_ERR_INVALID_ARG;
+    if (apply && (!adam_m || !adam_v || step < 1 || !(lr >= 0.f) || !isfinite(lr)))
+        return P2M_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < learn_workspace_bytes(batch) || ((uintptr_t)ws) % kAlign)
+        return P2M_ERR_WORKSPACE;
+    DeviceGuard g(((Context*)ctx)->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    return st(launch_learn_train(params, adam_m, adam_v, step, lr, x, target, rows, batch,
+                                 loss_out, grad_out, apply, ws, (hipStream_t)stream));
 }
 
 }  // extern "C"

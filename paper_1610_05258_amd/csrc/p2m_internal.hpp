@@ -215,4 +215,23 @@ hipError_t launch_cg_batch(int F, const BatchSolveBufs& bb, size_t nodes, int gr
                            const p2m_solve_opts& opts, hipStream_t stream);
 const void* cgb_kernel(int F);
 
+// learned warm start (k_learn.hip); X rows are BF16 [.][160]
+hipError_t launch_learn_features(const Mesh& m, Particles<float> P, const float* values, int F,
+                                 const int32_t* perm, const int32_t* cs, const float* b,
+                                 const float* w, const int32_t* nodes, int nrows, void* X,
+                                 float* base, float* scale, hipStream_t stream);
+hipError_t launch_learn_forward(const float* params, const void* X, int nrows, float* y,
+                                hipStream_t stream);
+size_t learn_workspace_bytes(int batch);
+hipError_t launch_learn_train(float* params, float* am, float* av, int step, float lr,
+                              const void* X, const float* target, const int32_t* rows, int batch,
+                              float* loss_out, float* grad_out, int apply, void* ws,
+                              hipStream_t stream);
+// the start vector x0 [F][nn] from the network, judged against the FLIP start
+size_t learned_start_workspace_bytes(const Mesh& m, int F);
+hipError_t launch_learned_start(const Mesh& m, Particles<float> P, const float* values, int F,
+                                const int32_t* perm, const int32_t* cs, const float* b,
+                                const float* w, const float* coef, const float* params, float* x0,
+                                void* ws, p2m_report* rep, hipStream_t stream);
+
 }  // namespace p2m

@@ -175,6 +175,25 @@ def taylor_green_2d(seed=2, n=1024, ppc=8, steps=50, dt=1e-3, noise=1e-3, fields
     return prob, vals.astype(np.float32)
 
 
+def tg_disordered(seed, n=1024, ppc=8, steps=200, dt=1e-3, noise=1e-3, fields=3, random_phase=True):
+    """TG-like fields on particles disordered by the flow: ``ppc`` stratified particles
+    per cell of an n x n mesh on [0, 2 pi)^2; fields u, v, p of the TG solution with a
+    random phase (phi_x, phi_y in [0, 2 pi)) and amplitude in [0.5, 2] (seeded), plus
+    N(0, noise^2); the positions are then advected ``steps`` RK2 steps of ``dt`` by the
+    TG velocity.  FP32 positions and values."""
+    g = rng(seed + 7_000_000)
+    phx, phy = (g.uniform(0.0, TWO_PI, 2) if random_phase else (0.0, 0.0))
+    amp = g.uniform(0.5, 2.0) if random_phase else 1.0
+    x, y = stratified_2d(seed, n, n, ppc, TWO_PI, TWO_PI)
+    vals = amp * taylor_green(x + phx, y + phy)[:fields]
+    if noise > 0.0:
+        vals = vals + g.normal(0.0, noise, vals.shape)
+    x, y = tg_advect_rk2(x, y, steps, dt)
+    prob = dict(dim=2, nx=n, ny=n, lx=TWO_PI, ly=TWO_PI, x=to_f32_positions(x, TWO_PI),
+                y=to_f32_positions(y, TWO_PI), vol=None)
+    return prob, vals.astype(np.float32)
+
+
 def uneven_batch(seed=3, count=64, side_lo=32, side_hi=512, ppc_lo=2, ppc_hi=16, fields=2):
     """``count`` independent TG problems with log-uniform mesh side and uniform ppc (no noise, no advection)."""
     g = rng(seed)
