@@ -76,27 +76,35 @@ __device__ void load_weights(const float* __restrict__ th, const LWeights& w, __
 }
 
 // One hidden layer for the wave's 16 rows: out[row][n] = bf16(relu(in . W[n] + b[n])),
-// K = 32 * KS.  Lane holds rows 4q .. 4q+3 of columns 16t + r.
+// K = 32 * KS.  Lane holds rows 4q .. 4q+3 of columns 16t + r.  Every product is
+// formed before the barrier and written after it, so out may be the input.
 template <int KS>
 __device__ __forceinline__ void dense_relu_bf16(const __bf16* in, int in_stride, const __bf16* W,
                                                 int w_stride, const float* b, __bf16* out) {
     const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+    f32x4 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc[t] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < KS; ++s)
-            acc = mfma16(ld8(in + r * in_stride + 32 * s + 8 * q),
-                         ld8(W + (16 * t + r) * w_stride + 32 * s + 8 * q), acc);
+            acc[t] = mfma16(ld8(in + r * in_stride + 32 * s + 8 * q),
+                            ld8(W + (16 * t + r) * w_stride + 32 * s + 8 * q), acc[t]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
         const float bb = b[16 * t + r];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) out[(4 * q + i) * HS + 16 * t + r] = (__bf16)fmaxf(acc[i] + bb, 0.f);
+        for (int i = 0; i < 4; ++i)
+            out[(4 * q + i) * HS + 16 * t + r] = (__bf16)fmaxf(acc[t][i] + bb, 0.f);
     }
 }
 
 // Forward of the wave's 16 rows of x (row stride XS).  h1, h2: [16][HS] scratch of
-// this wave.  Returns h3 (FP32, [t][i] = row 4q+i, column 16t+r) and y for rows
-// 4q .. 4q+3 (every lane of a 16-lane group holds its group's four y).
+// this wave (they may be the same buffer).  Returns h3 (FP32, [t][i] = row 4q+i,
+// column 16t+r) and y for rows 4q .. 4q+3 (every lane of a 16-lane group holds
+// its group's four y).
 __device__ __forceinline__ void forward16(const __bf16* x, const LWeights& w, __bf16* h1,
                                           __bf16* h2, float (&h3)[4][4], float (&y)[4]) {
     const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
@@ -299,7 +307,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_learned_start(GatherIn g, int F
                                                               float* __restrict__ xflip) {
     __shared__ __align__(16) __bf16 W1[kLH * XS], W2[kLH * HS], W3[kLH * HS];
     __shared__ float b1[kLH], b2[kLH], b3[kLH], W4[kLH];
-    __shared__ __align__(16) __bf16 xt[kWaves][16 * XS], h1[kWaves][16 * HS], h2[kWaves][16 * HS];
+    __shared__ __align__(16) __bf16 xt[kWaves][16 * XS], h1[kWaves][16 * HS];
     __shared__ float sbase[kWaves][16], sscale[kWaves][16];
     __shared__ int suse[kWaves][16];
     LWeights w{W1, W2, W3, b1, b2, b3, W4, th[ob4]};
@@ -320,7 +328,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_learned_start(GatherIn g, int F
         }
         __syncthreads();
         float h3[4][4], y[4];
-        forward16(xt[wave], w, h1[wave], h2[wave], h3, y);
+        forward16(xt[wave], w, h1[wave], h1[wave], h3, y);
         if (r == 0) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {

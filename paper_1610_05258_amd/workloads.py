@@ -105,16 +105,17 @@ def taylor_green(x, y):
                      0.25 * (np.cos(2.0 * x) + np.cos(2.0 * y))])
 
 
-def tg_advect_rk2(x, y, steps, dt):
+def tg_advect_rk2(x, y, steps, dt, device="cpu"):
     """Midpoint-rule (RK2) advection of positions by the TG velocity, wrapped mod 2 pi each step.
 
-    Runs in FP64 on the CPU with torch (multi-threaded elementwise maths).
+    Runs in FP64 with torch (multi-threaded elementwise maths) on ``device``; the
+    CPU is the reproducible default (other devices round sin / cos differently).
     """
     if steps == 0:
         return np.asarray(x, np.float64).copy(), np.asarray(y, np.float64).copy()
     import torch
-    X = torch.from_numpy(np.asarray(x, dtype=np.float64).copy())
-    Y = torch.from_numpy(np.asarray(y, dtype=np.float64).copy())
+    X = torch.from_numpy(np.asarray(x, dtype=np.float64).copy()).to(device)
+    Y = torch.from_numpy(np.asarray(y, dtype=np.float64).copy()).to(device)
     for _ in range(steps):
         u = torch.sin(X) * torch.cos(Y)
         v = -torch.cos(X) * torch.sin(Y)
@@ -124,7 +125,7 @@ def tg_advect_rk2(x, y, steps, dt):
         v = -torch.cos(Xm) * torch.sin(Ym)
         X = torch.remainder(X + dt * u, TWO_PI)
         Y = torch.remainder(Y + dt * v, TWO_PI)
-    return X.numpy(), Y.numpy()
+    return X.cpu().numpy(), Y.cpu().numpy()
 
 
 def to_f32_positions(x, length):
@@ -175,7 +176,8 @@ def taylor_green_2d(seed=2, n=1024, ppc=8, steps=50, dt=1e-3, noise=1e-3, fields
     return prob, vals.astype(np.float32)
 
 
-def tg_disordered(seed, n=1024, ppc=8, steps=200, dt=1e-3, noise=1e-3, fields=3, random_phase=True):
+def tg_disordered(seed, n=1024, ppc=8, steps=200, dt=1e-3, noise=1e-3, fields=3, random_phase=True,
+                  device="cpu"):
     """TG-like fields on particles disordered by the flow: ``ppc`` stratified particles
     per cell of an n x n mesh on [0, 2 pi)^2; fields u, v, p of the TG solution with a
     random phase (phi_x, phi_y in [0, 2 pi)) and amplitude in [0.5, 2] (seeded), plus
@@ -188,7 +190,7 @@ def tg_disordered(seed, n=1024, ppc=8, steps=200, dt=1e-3, noise=1e-3, fields=3,
     vals = amp * taylor_green(x + phx, y + phy)[:fields]
     if noise > 0.0:
         vals = vals + g.normal(0.0, noise, vals.shape)
-    x, y = tg_advect_rk2(x, y, steps, dt)
+    x, y = tg_advect_rk2(x, y, steps, dt, device)
     prob = dict(dim=2, nx=n, ny=n, lx=TWO_PI, ly=TWO_PI, x=to_f32_positions(x, TWO_PI),
                 y=to_f32_positions(y, TWO_PI), vol=None)
     return prob, vals.astype(np.float32)

@@ -223,3 +223,56 @@ def test_learned_start_in_mass_solve(B, ctx, case, trained):
     for f in range(3):
         assert metrics.rel_l2(got2[f], ref[f]) <= 1e-6
     B.set_learned(ctx, None)
+
+
+# ----------------------------------------------------------------------------
+# the gain of the trained network on a held-out configuration of the learned-start
+# workload: 1024^2, 8 ppc, TG fields disordered by 200 RK2 steps (seed 20000, not
+# among the training seeds 10000-10015 or the validation seed 19999)
+# ----------------------------------------------------------------------------
+def test_trained_network_gain(B, ctx):
+    import os
+    import time
+    wpath = os.path.join(os.path.dirname(B.__file__), "learned_tg.npy")
+    if not os.path.exists(wpath):
+        pytest.skip("no trained parameters (python -m paper_1610_05258_amd.train_learned)")
+    say("[learned gain] held-out seed 20000, 1024^2, 8 ppc, 200 disorder steps (GPU advection)")
+    prob, vals = wl.tg_disordered(20000, n=1024, ppc=8, steps=200, dt=1e-3, device="cuda")
+    d = B.particles_from(prob, dtype=torch.float32)
+    v = torch.as_tensor(vals).cuda()
+    B.set_learned(ctx, torch.as_tensor(np.load(wpath, allow_pickle=False)).cuda())
+    out = torch.empty((3, 1024 * 1024), dtype=torch.float32, device="cuda")
+    rep = ctx.new_report()
+
+    def run(start, tol, maxit=2000, max_refine=10, reps=5):
+        opts = B.solve_opts(tol=tol, inner_rtol=1e-4, maxit=maxit, max_refine=max_refine, start=start)
+        B.p2m_mass_assign(ctx, d, v, opts, rep=rep, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            B.p2m_mass_assign(ctx, d, v, opts, rep=rep, out=out)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3, B.read_report(rep, 3)
+
+    # the starts themselves: no iteration, the report holds the start's FP64 residual
+    _, r0f = run(B.START_FLIP, 1e-6, maxit=0, max_refine=0, reps=1)
+    _, r0l = run(B.START_LEARNED, 1e-6, maxit=0, max_refine=0, reps=1)
+    say(f"  start residual FLIP {r0f.rel_residual.tolist()}  learned {r0l.rel_residual.tolist()}")
+    assert not (r0l.flags & B.FLAG_LEARNED_FALLBACK)
+    assert np.all(r0l.rel_residual < r0f.rel_residual)
+    for tol in (1e-6, 1e-8):
+        tf, rf = run(B.START_FLIP, tol)
+        tl, rl = run(B.START_LEARNED, tol)
+        say(f"  tol {tol:g}: FLIP {tf:.3f} ms iters {rf.iters.tolist()} | learned {tl:.3f} ms "
+            f"iters {rl.iters.tolist()}")
+        assert rl.iters.sum() <= rf.iters.sum()
+        assert np.all(rl.rel_residual <= tol)
+    # the learned-start answer still meets the gate against the FP64 oracle
+    got = out.cpu().numpy().astype(np.float64)
+    pr = f64(prob)
+    st = p1.assemble_stencil(pr, vals.astype(np.float64))
+    M = p1.regularised_matrix(p1.stencil_matrix(pr, st), st["w"])
+    for f in range(3):
+        x, _ = p1.cg_fp64(M, st["b"][f], rtol=1e-12)
+        assert metrics.rel_l2(got[f], x) <= 1e-6
+    B.set_learned(ctx, None)
