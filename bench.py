@@ -54,6 +54,30 @@ def cg_algorithmic_bytes(k_ref, nn, F, c_m=4):
     return float(k_ref) * nn * (4 * c_m + 24 * F)
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "counters_k_cgr3_tg1024.md")
+SOLVER_SOURCES = ("k_cgr.hip", "cg_common.hpp", "p2m_internal.hpp")
+
+
+def measured_traffic():
+    """HBM bytes per k_cgr<3> launch from the committed counter summary (FETCH_SIZE
+    and WRITE_SIZE runs scaled by a copy of known size), or None when the solver
+    sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    if not os.path.exists(COUNTERS):
+        return None
+    text = open(COUNTERS).read()
+    m_t = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
+    m_h = re.search(r"^source_sha256: ([0-9a-f]{64})", text, re.M)
+    if not (m_t and m_h):
+        return None
+    h = hashlib.sha256()
+    for f in SOLVER_SOURCES:
+        with open(os.path.join(ROOT, "paper_1610_05258_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return float(m_t.group(1)) if h.hexdigest() == m_h.group(1) else None
+
+
 def oracle_reference(prob, vals, tol):
     """FP64 oracle on the full input: the solution (to 1e-12) and the iteration
     count of FP64 Jacobi-preconditioned CG (the solver's iteration) from the FLIP
@@ -170,6 +194,9 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the timed steps, copy MIB MiB device-to-device three times "
+                         "(a kernel of known traffic for scaling memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -237,6 +264,14 @@ def main():
         one_step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if args.calibrate_copy > 0:
+        src = torch.ones(args.calibrate_copy << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"bench: copied {args.calibrate_copy} MiB three times (counter calibration)")
+        del src, dst
     asm_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     cg_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     r = B.read_report(rep_s, F)
@@ -274,7 +309,7 @@ def main():
         result["roofline"] = dict(bound="hbm", kernel="k_cgr<3> (register-resident mass solve)",
                                   achieved=achieved,
                                   peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                                  traffic=None, k_ref=kk,
+                                  traffic=measured_traffic(), k_ref=kk,
                                   bytes_per_launch=cg_algorithmic_bytes(kk, nn, F))
     print(json.dumps(result), flush=True)
 
