@@ -127,13 +127,25 @@ const char* p2m_status_string(p2m_status s);
 p2m_status p2m_create(void** ctx, int device);
 p2m_status p2m_destroy(void* ctx);
 
-/* Context options (p2m_set_option).  P2M_OPT_SOLVER selects the mass-solve
- * kernel: 0 = automatic (the register-resident kernel when the problem is 2D
- * FP32 with F <= 3 and its tiles fit one workgroup per tile on the device, the
- * streaming kernel otherwise), 1 = always the streaming kernel, 2 = the resident
- * kernel where it fits (same as 0).  Both solve the same system to the same
- * tolerance; their rounding differs. */
-enum { P2M_OPT_SOLVER = 0 };
+/* Mass-solve kernels.  Every one solves the same system to the same tolerance;
+ * their rounding differs, except that the resident and the tile-streaming kernels
+ * give identical bits (the same per-tile arithmetic and reduction order).
+ *   P2M_SOLVER_AUTO       the register-resident kernel where it applies (2D FP32,
+ *                         F <= 3, at most one 128 x 32 node tile per workgroup that
+ *                         fits the device at once), else the tile-streaming
+ *                         kernel (2D FP32, F <= 3, any size), else the streaming
+ *                         kernel; a tuned plan of the problem's shape class
+ *                         (p2m_tune) overrides this choice
+ *   P2M_SOLVER_STREAMING  grid-synchronised streaming kernel (any problem)
+ *   P2M_SOLVER_RESIDENT   register-resident kernel where it applies (as AUTO)
+ *   P2M_SOLVER_TILES      tile-streaming kernel where it applies */
+enum { P2M_SOLVER_AUTO = 0, P2M_SOLVER_STREAMING = 1, P2M_SOLVER_RESIDENT = 2, P2M_SOLVER_TILES = 3 };
+
+/* Context options (p2m_set_option).
+ *   P2M_OPT_SOLVER  a P2M_SOLVER_* value (default AUTO); anything but AUTO forces
+ *                   that kernel where it applies, tuned plans notwithstanding
+ *   P2M_OPT_PLANS   1 (default): apply tuned plans; 0: ignore them */
+enum { P2M_OPT_SOLVER = 0, P2M_OPT_PLANS = 1 };
 p2m_status p2m_set_option(void* ctx, int32_t option, int32_t value);
 
 /* Bytes of workspace that every call below needs for this problem and field count
@@ -314,6 +326,42 @@ p2m_status p2m_learned_train_step(void* ctx, float* params, float* adam_m, float
                                   const int32_t* rows, int32_t batch, float* loss_out,
                                   float* grad_out, int32_t apply, void* ws, size_t ws_bytes,
                                   void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Autotuning.  A plan fixes the launch choices of p2m_assemble / p2m_mass_assign /
+ * p2m_mass_solve for a shape class: dimension, dtype, field count, and the mesh
+ * sides and particles per cell rounded to powers of two.  Plans live in the
+ * context (applied while P2M_OPT_PLANS is 1) and can be saved to and loaded from
+ * a JSON file.
+ * --------------------------------------------------------------------------- */
+typedef struct {
+    int32_t solver;        /* P2M_SOLVER_* */
+    int32_t groups;        /* workgroups of the tile-streaming solve (0: one per compute unit) */
+    int32_t scatter_tile;  /* 2D scatter node tile: 0 = default (16 x 16 where it fits), 8 = 8 x 8 */
+    int32_t reserved;      /* 0 */
+    double time_ms;        /* measured time of one p2m_mass_assign with this plan when tuned */
+} p2m_plan;
+
+/* Times p2m_mass_assign of this problem under every applicable plan (each solve
+ * kernel; the tile-streaming kernel with one and with half a workgroup per
+ * compute unit; the default and the 8 x 8 scatter tile), three runs each after a
+ * warm-up, on `stream`; keeps the fastest plan whose solve converged for the
+ * problem's shape class and returns it.  Synchronises `stream`.  opts->start must
+ * be FLIP or ZERO; nodal_out and rep receive the chosen plan's result. */
+p2m_status p2m_tune(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
+                    const p2m_solve_opts* opts, void* nodal_out, p2m_report* rep, void* ws,
+                    size_t ws_bytes, void* stream, p2m_plan* best);
+
+/* The stored plan of this problem's shape class (P2M_ERR_UNSUPPORTED: none). */
+p2m_status p2m_plan_get(void* ctx, const p2m_problem* prob, int32_t nfields, p2m_plan* plan);
+
+/* Write every stored plan to `path` (JSON object: shape class -> plan); read
+ * plans from such a file into the context (entries of the file replace stored
+ * ones of the same class; P2M_ERR_INVALID_ARG for a malformed file, then nothing
+ * is loaded); forget every stored plan. */
+p2m_status p2m_plan_save(void* ctx, const char* path);
+p2m_status p2m_plan_load(void* ctx, const char* path);
+p2m_status p2m_plan_clear(void* ctx);
 
 #ifdef __cplusplus
 }

@@ -30,13 +30,15 @@ FLAG_NONFINITE = 1 << 4
 FLAG_LEARNED_FALLBACK = 1 << 5
 REPORT_BYTES = 144
 MAX_FIELDS = 8
-SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT = 0, 1, 2
+SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT, SOLVER_TILES = 0, 1, 2, 3
+OPT_SOLVER, OPT_PLANS = 0, 1
 
 EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size", "p2m_bin",
            "p2m_assemble", "p2m_assign", "p2m_interpolate", "p2m_mass_assign", "p2m_mass_solve",
            "p2m_set_option", "p2m_batch_workspace_size", "p2m_mass_assign_batched",
            "p2m_set_learned", "p2m_learned_features", "p2m_learned_forward",
-           "p2m_learned_workspace_size", "p2m_learned_train_step")
+           "p2m_learned_workspace_size", "p2m_learned_train_step", "p2m_tune", "p2m_plan_get",
+           "p2m_plan_save", "p2m_plan_load", "p2m_plan_clear")
 LEARNED_KMAX, LEARNED_NIN, LEARNED_HIDDEN, LEARNED_NPARAM = 48, 160, 64, 18689
 
 
@@ -51,6 +53,15 @@ class CProblem(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double),
                 ("np", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("vol", ctypes.c_void_p)]
+
+
+class CPlan(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int32), ("groups", ctypes.c_int32), ("scatter_tile", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("time_ms", ctypes.c_double)]
+
+    def __repr__(self):
+        return (f"CPlan(solver={self.solver}, groups={self.groups}, scatter_tile={self.scatter_tile}, "
+                f"time_ms={self.time_ms:.4f})")
 
 
 class CSolveOpts(ctypes.Structure):
@@ -100,6 +111,12 @@ def lib():
         L.p2m_learned_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, i32,
                                              vp, vp, i32, vp, sz, vp]
         del fp
+        pplan = ctypes.POINTER(CPlan)
+        L.p2m_tune.argtypes = [vp, pprob, vp, i32, ctypes.POINTER(CSolveOpts), vp, vp, vp, sz, vp, pplan]
+        L.p2m_plan_get.argtypes = [vp, pprob, i32, pplan]
+        L.p2m_plan_save.argtypes = [vp, ctypes.c_char_p]
+        L.p2m_plan_load.argtypes = [vp, ctypes.c_char_p]
+        L.p2m_plan_clear.argtypes = [vp]
         for name in EXPORTS[1:]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -215,8 +232,27 @@ class Context:
             pass
 
     def set_solver(self, kind: int):
-        """0 = automatic, 1 = streaming kernel, 2 = register-resident where it fits."""
-        _check(lib().p2m_set_option(self.handle, 0, int(kind)), "p2m_set_option")
+        """SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT or SOLVER_TILES."""
+        _check(lib().p2m_set_option(self.handle, OPT_SOLVER, int(kind)), "p2m_set_option")
+
+    def use_plans(self, on: bool):
+        _check(lib().p2m_set_option(self.handle, OPT_PLANS, 1 if on else 0), "p2m_set_option")
+
+    def plan(self, prob, nfields):
+        """The stored plan of the problem's shape class, or None."""
+        p = CPlan()
+        cp = prob.cstruct()
+        st = lib().p2m_plan_get(self.handle, ctypes.byref(cp), int(nfields), ctypes.byref(p))
+        return p if st == 0 else None
+
+    def save_plans(self, path):
+        _check(lib().p2m_plan_save(self.handle, str(path).encode()), "p2m_plan_save")
+
+    def load_plans(self, path):
+        _check(lib().p2m_plan_load(self.handle, str(path).encode()), "p2m_plan_load")
+
+    def clear_plans(self):
+        _check(lib().p2m_plan_clear(self.handle), "p2m_plan_clear")
 
     def workspace_size(self, prob: Particles, nfields: int) -> int:
         n = ctypes.c_size_t()
@@ -498,3 +534,18 @@ class Trainer:
             _ptr(grad), 1 if apply else 0, _ptr(self.ws), ctypes.c_size_t(self.ws.numel()),
             _stream_ptr(stream)), "p2m_learned_train_step")
         return self.loss
+
+
+def p2m_tune(ctx: Context, prob: Particles, values, opts: CSolveOpts | None = None, stream=None):
+    """Time every applicable plan on this problem, keep the fastest for its shape class.
+    Returns (plan, nodal [F, nn] of the chosen plan, report tensor)."""
+    values, F = _values_tensor(values, prob)
+    cp = prob.cstruct()
+    opts = opts if opts is not None else solve_opts(fp64=prob.dtype == torch.float64)
+    out = torch.empty((F, prob.n_nodes), dtype=prob.dtype, device=prob.x.device)
+    rep = ctx.new_report()
+    wp, wn = _ws_args(ctx, prob, F, None)
+    plan = CPlan()
+    _check(lib().p2m_tune(ctx.handle, ctypes.byref(cp), _ptr(values), F, ctypes.byref(opts), _ptr(out),
+                          _ptr(rep), wp, wn, _stream_ptr(stream), ctypes.byref(plan)), "p2m_tune")
+    return plan, out, rep

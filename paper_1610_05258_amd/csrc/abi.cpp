@@ -2,10 +2,13 @@
 // carving and the launch sequence of every entry point.  No device memory is
 // allocated here; every launch goes on the caller's stream.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -37,13 +40,21 @@ struct BatchCache {
     }
 };
 
+// Tuned plans by shape class (see shape_key).
+struct PlanCache {
+    std::map<std::string, p2m_plan> plans;
+};
+
 struct Context {
     int device;
     int cg_blocks_f32;
     int cg_blocks_f64;
-    int resident_enabled;   // 1: use the register-resident solve where it fits
+    int solver_mode;        // P2M_SOLVER_*: AUTO or a forced solve kernel
+    int use_plans;          // 1: apply tuned plans of the problem's shape class
     BatchCache* batch;      // created on the first batched call
     const float* learned;   // parameters of the learned start (device), or null
+    PlanCache* plans;       // created on the first tuned or loaded plan
+    const p2m_plan* forced; // the candidate being timed by p2m_tune
 };
 
 // Makes the context's device current for the duration of a call and restores
@@ -65,8 +76,8 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace carve-up.  Offsets are fixed functions of (problem, F, cg blocks).
 struct Layout {
-    size_t key, counts, cell_start, perm, scan, b, w, coef, r, p0, p1, q, x64, partials, resident,
-        learned, report, total;
+    size_t key, counts, cell_start, perm, scan, b, w, coef, r, p0, p1, q, dinv, x64, partials,
+        resident, tiles, learned, report, total;
 };
 
 Layout make_layout(const Mesh& m, int F, size_t tsize, int cg_blocks) {
@@ -91,10 +102,13 @@ Layout make_layout(const Mesh& m, int F, size_t tsize, int cg_blocks) {
     L.p0 = take((size_t)F * nn * tsize);
     L.p1 = take((size_t)F * nn * tsize);
     L.q = take((size_t)F * nn * tsize);
+    L.dinv = take(nn * tsize);
     L.x64 = take((size_t)2 * F * nn * sizeof(double));
     L.partials = take(cg_partials_bytes(cg_blocks));
     L.resident = take((m.dim == 2 && F <= kResidentMaxFields && tsize == 4)
                           ? cgr_workspace_bytes(m, F, cgr_tiles(m)) : 0);
+    L.tiles = take((m.dim == 2 && F <= kResidentMaxFields && tsize == 4) ? cgt_workspace_bytes(m, F)
+                                                                         : 0);
     L.learned = take((m.dim == 2 && tsize == 4) ? learned_start_workspace_bytes(m, F) : 0);
     L.report = take(sizeof(p2m_report));
     L.total = off;
@@ -142,6 +156,43 @@ Particles<T> particles_of(const p2m_problem* p) {
     P.y = (const T*)p->y;
     P.vol = (const T*)p->vol;
     return P;
+}
+
+// Shape class of a problem for tuned plans: dimension, dtype, field count, the
+// mesh sides and the particles per cell, each rounded to a power of two.
+std::string shape_key(const Mesh& m, int dtype, int F) {
+    auto lg = [](double v) { return (int)floor(log2(v) + 0.5); };
+    const double ppc = m.np > 0 ? (double)m.np / (double)m.nn : 0.125;
+    char buf[96];
+    snprintf(buf, sizeof buf, "%dd-%s-F%d-nx%d-ny%d-ppc%d", m.dim, dtype == P2M_F64 ? "f64" : "f32", F,
+             lg(m.nx), lg(m.ny), lg(ppc < 0.125 ? 0.125 : ppc));
+    return std::string(buf);
+}
+
+struct Choice {
+    int solver = P2M_SOLVER_AUTO;
+    int groups = 0;
+    int tile = 0;
+};
+
+Choice choose(const Context* c, const Mesh& m, int dtype, int F) {
+    Choice ch;
+    if (c->forced) {
+        ch.solver = c->forced->solver;
+        ch.groups = c->forced->groups;
+        ch.tile = c->forced->scatter_tile;
+        return ch;
+    }
+    if (c->use_plans && c->plans) {
+        auto it = c->plans->plans.find(shape_key(m, dtype, F));
+        if (it != c->plans->plans.end()) {
+            ch.solver = it->second.solver;
+            ch.groups = it->second.groups;
+            ch.tile = it->second.scatter_tile;
+        }
+    }
+    if (c->solver_mode != P2M_SOLVER_AUTO) ch.solver = c->solver_mode;
+    return ch;
 }
 
 inline p2m_status st(hipError_t e) { return e == hipSuccess ? P2M_OK : P2M_ERR_HIP; }
@@ -213,23 +264,33 @@ p2m_status run_assign(const Prepared& pp, const p2m_problem* prob, p2m_assign_ki
 
 template <typename T>
 p2m_status run_assemble(const Prepared& pp, const p2m_problem* prob, const void* values, int F,
-                        void* b, void* w, void* coef) {
+                        void* b, void* w, void* coef, const Choice& ch) {
     int32_t* perm = (int32_t*)(pp.ws + pp.L.perm);
     int32_t* cs = (int32_t*)(pp.ws + pp.L.cell_start);
     p2m_status s = run_bin<T>(pp, prob, perm, cs);
     if (s != P2M_OK) return s;
     P2M_TRY(launch_assemble<T>(pp.m, particles_of<T>(prob), (const T*)values, F, perm, cs, (T*)b,
-                               (T*)w, (T*)coef, pp.stream));
+                               (T*)w, (T*)coef, pp.stream, ch.tile));
     return P2M_OK;
 }
 
+// Solve kernel: the choice's kernel where it applies; AUTO and RESIDENT take the
+// register-resident kernel where the mesh fits, else the tile-streaming one, else
+// the grid-synchronised streaming kernel (1D, FP64, F > 3).
 template <typename T>
 p2m_status run_solve(const Context* c, const Prepared& pp, int F, T* b, const T* w, T* coef,
-                     int start, const p2m_solve_opts& opts, void* x) {
-    if (sizeof(T) == 4 && c->resident_enabled && pp.m.dim == 2 && F <= kResidentMaxFields &&
+                     int start, const p2m_solve_opts& opts, void* x, const Choice& ch) {
+    const bool tiled = sizeof(T) == 4 && pp.m.dim == 2 && F <= kResidentMaxFields;
+    const int kind = ch.solver;
+    if (tiled && (kind == P2M_SOLVER_AUTO || kind == P2M_SOLVER_RESIDENT) &&
         cgr_supported(pp.m, F, c->device)) {
         P2M_TRY(launch_cg_resident(pp.m, F, (float*)coef, (float*)b, (const float*)w, (float*)x,
                                    start, pp.ws + pp.L.resident, opts, pp.rep, pp.stream));
+        return P2M_OK;
+    }
+    if (tiled && kind != P2M_SOLVER_STREAMING && cgt_grid(pp.m, F, ch.groups, c->device) > 0) {
+        P2M_TRY(launch_cg_tiles(pp.m, F, (float*)coef, (float*)b, (const float*)w, (float*)x, start,
+                                pp.ws + pp.L.tiles, opts, pp.rep, ch.groups, c->device, pp.stream));
         return P2M_OK;
     }
     CgWorkspace cw;
@@ -239,6 +300,7 @@ p2m_status run_solve(const Context* c, const Prepared& pp, int F, T* b, const T*
     cw.q = pp.ws + pp.L.q;
     cw.x64 = (double*)(pp.ws + pp.L.x64);
     cw.partials = (double*)(pp.ws + pp.L.partials);
+    cw.dinv = pp.ws + pp.L.dinv;
     cw.blocks = cg_blocks_for(c, pp.m, sizeof(T) == 8 ? P2M_F64 : P2M_F32);
     P2M_TRY(launch_cg<T>(pp.m, F, coef, b, w, (T*)x, start, cw, opts, pp.rep, pp.stream));
     return P2M_OK;
@@ -246,7 +308,8 @@ p2m_status run_solve(const Context* c, const Prepared& pp, int F, T* b, const T*
 
 template <typename T>
 p2m_status run_mass(const Context* c, const Prepared& pp, const p2m_problem* prob,
-                    const void* values, int F, const p2m_solve_opts& opts, void* x) {
+                    const void* values, int F, const p2m_solve_opts& opts, void* x,
+                    const Choice& ch) {
     int32_t* perm = (int32_t*)(pp.ws + pp.L.perm);
     int32_t* cs = (int32_t*)(pp.ws + pp.L.cell_start);
     p2m_status s = run_bin<T>(pp, prob, perm, cs);
@@ -255,7 +318,7 @@ p2m_status run_mass(const Context* c, const Prepared& pp, const p2m_problem* pro
     T* w = (T*)(pp.ws + pp.L.w);
     T* coef = (T*)(pp.ws + pp.L.coef);
     P2M_TRY(launch_assemble<T>(pp.m, particles_of<T>(prob), (const T*)values, F, perm, cs, b, w,
-                               coef, pp.stream));
+                               coef, pp.stream, ch.tile));
     int start = opts.start;
     if (start == P2M_START_LEARNED) {
         if (sizeof(T) != 4) return P2M_ERR_UNSUPPORTED;
@@ -270,7 +333,7 @@ p2m_status run_mass(const Context* c, const Prepared& pp, const p2m_problem* pro
                                   (T*)x, pp.stream));
         start = P2M_START_USER;
     }
-    return run_solve<T>(c, pp, F, b, w, coef, start, opts, x);
+    return run_solve<T>(c, pp, F, b, w, coef, start, opts, x, ch);
 }
 
 // ---------------------------------------------------------------------------
@@ -460,7 +523,8 @@ p2m_status p2m_create(void** ctx, int device) {
     c->device = device;
     c->cg_blocks_f32 = cg_max_blocks<float>(device);
     c->cg_blocks_f64 = cg_max_blocks<double>(device);
-    c->resident_enabled = 1;
+    c->solver_mode = P2M_SOLVER_AUTO;
+    c->use_plans = 1;
     if (c->cg_blocks_f32 <= 0 || c->cg_blocks_f64 <= 0) {
         free(c);
         return P2M_ERR_HIP;
@@ -473,8 +537,13 @@ p2m_status p2m_set_option(void* ctx, int32_t option, int32_t value) {
     if (!ctx) return P2M_ERR_INVALID_ARG;
     Context* c = (Context*)ctx;
     if (option == P2M_OPT_SOLVER) {
-        if (value < 0 || value > 2) return P2M_ERR_INVALID_ARG;
-        c->resident_enabled = (value == 1) ? 0 : 1;
+        if (value < P2M_SOLVER_AUTO || value > P2M_SOLVER_TILES) return P2M_ERR_INVALID_ARG;
+        c->solver_mode = value;
+        return P2M_OK;
+    }
+    if (option == P2M_OPT_PLANS) {
+        if (value != 0 && value != 1) return P2M_ERR_INVALID_ARG;
+        c->use_plans = value;
         return P2M_OK;
     }
     return P2M_ERR_INVALID_ARG;
@@ -487,6 +556,7 @@ p2m_status p2m_destroy(void* ctx) {
             DeviceGuard g(c->device);
             delete c->batch;
         }
+        delete c->plans;
     }
     free(ctx);
     return P2M_OK;
@@ -526,8 +596,9 @@ p2m_status p2m_assemble(void* ctx, const p2m_problem* prob, const void* values, 
     DeviceGuard g(((Context*)ctx)->device);
     if (!g.ok) return P2M_ERR_HIP;
     P2M_TRY(launch_report_clear(pp.rep, pp.stream));
-    return prob->dtype == P2M_F64 ? run_assemble<double>(pp, prob, values, nfields, b, w, coef)
-                                  : run_assemble<float>(pp, prob, values, nfields, b, w, coef);
+    const Choice ch = choose((const Context*)ctx, pp.m, prob->dtype, nfields);
+    return prob->dtype == P2M_F64 ? run_assemble<double>(pp, prob, values, nfields, b, w, coef, ch)
+                                  : run_assemble<float>(pp, prob, values, nfields, b, w, coef, ch);
 }
 
 p2m_status p2m_assign(void* ctx, const p2m_problem* prob, p2m_assign_kind kind, const void* values,
@@ -586,9 +657,10 @@ p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* value
     if (!g.ok) return P2M_ERR_HIP;
     P2M_TRY(launch_report_clear(pp.rep, pp.stream));
     const Context* c = (const Context*)ctx;
+    const Choice ch = choose(c, pp.m, prob->dtype, nfields);
     return prob->dtype == P2M_F64
-               ? run_mass<double>(c, pp, prob, values, nfields, *opts, nodal_inout)
-               : run_mass<float>(c, pp, prob, values, nfields, *opts, nodal_inout);
+               ? run_mass<double>(c, pp, prob, values, nfields, *opts, nodal_inout, ch)
+               : run_mass<float>(c, pp, prob, values, nfields, *opts, nodal_inout, ch);
 }
 
 p2m_status p2m_mass_solve(void* ctx, const p2m_problem* prob, int32_t nfields, void* b, const void* w,
@@ -607,11 +679,12 @@ p2m_status p2m_mass_solve(void* ctx, const p2m_problem* prob, int32_t nfields, v
     if (!g.ok) return P2M_ERR_HIP;
     P2M_TRY(launch_report_clear(pp.rep, pp.stream));
     const Context* c = (const Context*)ctx;
+    const Choice ch = choose(c, pp.m, prob->dtype, nfields);
     if (prob->dtype == P2M_F64)
         return run_solve<double>(c, pp, nfields, (double*)b, (const double*)w, (double*)coef,
-                                 opts->start, *opts, nodal_inout);
+                                 opts->start, *opts, nodal_inout, ch);
     return run_solve<float>(c, pp, nfields, (float*)b, (const float*)w, (float*)coef, opts->start,
-                            *opts, nodal_inout);
+                            *opts, nodal_inout, ch);
 }
 
 p2m_status p2m_batch_workspace_size(void* ctx, const p2m_problem* probs, int32_t nprob,
@@ -758,6 +831,163 @@ p2m_status p2m_learned_train_step(void* ctx, float* params, float* adam_m, float
     if (!g.ok) return P2M_ERR_HIP;
     return st(launch_learn_train(params, adam_m, adam_v, step, lr, x, target, rows, batch,
                                  loss_out, grad_out, apply, ws, (hipStream_t)stream));
+}
+
+p2m_status p2m_tune(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
+                    const p2m_solve_opts* opts, void* nodal_out, p2m_report* rep, void* ws,
+                    size_t ws_bytes, void* stream, p2m_plan* best) {
+    if (!ctx || !best || !rep) return P2M_ERR_INVALID_ARG;
+    p2m_status s = check_opts(opts);
+    if (s != P2M_OK) return s;
+    if (opts->start != P2M_START_FLIP && opts->start != P2M_START_ZERO) return P2M_ERR_UNSUPPORTED;
+    Context* c = (Context*)ctx;
+    Prepared pp;
+    s = prepare(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp);
+    if (s != P2M_OK) return s;
+    if ((pp.m.np > 0 && !values) || !nodal_out) return P2M_ERR_INVALID_ARG;
+    DeviceGuard g(c->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    // candidates: every solve kernel that applies, with the default and the 8 x 8
+    // scatter tile; the tile-streaming solve with one and with half a workgroup per CU
+    std::vector<p2m_plan> cand;
+    auto add = [&](int solver, int groups, int tile) {
+        p2m_plan p;
+        memset(&p, 0, sizeof(p));
+        p.solver = solver;
+        p.groups = groups;
+        p.scatter_tile = tile;
+        cand.push_back(p);
+    };
+    const bool tiled = prob->dtype == P2M_F32 && pp.m.dim == 2 && nfields <= kResidentMaxFields;
+    const int tiles[2] = {0, 8};
+    for (int ti = 0; ti < (pp.m.dim == 2 ? 2 : 1); ++ti) {
+        const int tile = tiles[ti];
+        if (tiled && cgr_supported(pp.m, nfields, c->device)) add(P2M_SOLVER_RESIDENT, 0, tile);
+        if (tiled) {
+            const int cap = cgt_grid(pp.m, nfields, 0, c->device);
+            if (cap > 0) add(P2M_SOLVER_TILES, cap, tile);
+            const int half = cgt_grid(pp.m, nfields, cap / 2, c->device);
+            if (half > 0 && half < cap) add(P2M_SOLVER_TILES, half, tile);
+        }
+        add(P2M_SOLVER_STREAMING, 0, tile);
+    }
+    hipStream_t strm = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return P2M_ERR_HIP;
+    }
+    p2m_status result = P2M_OK;
+    int best_i = -1;
+    p2m_report host_rep;
+    for (size_t i = 0; i < cand.size() && result == P2M_OK; ++i) {
+        c->forced = &cand[i];
+        float ms = 0.f;
+        const int reps = 3;
+        for (int r = 0; r <= reps && result == P2M_OK; ++r) {
+            if (r == 1 && hipEventRecord(e0, strm) != hipSuccess) result = P2M_ERR_HIP;
+            if (result == P2M_OK)
+                result = p2m_mass_assign(ctx, prob, values, nfields, opts, nodal_out, rep, ws,
+                                         ws_bytes, stream);
+        }
+        if (result == P2M_OK && (hipEventRecord(e1, strm) != hipSuccess ||
+                                 hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+                                 hipMemcpy(&host_rep, rep, sizeof(host_rep), hipMemcpyDeviceToHost) !=
+                                     hipSuccess))
+            result = P2M_ERR_HIP;
+        if (result != P2M_OK) break;
+        cand[i].time_ms = ms / reps;
+        const bool ok = !(host_rep.flags & (P2M_FLAG_NOT_CONVERGED | P2M_FLAG_BREAKDOWN));
+        if (ok && (best_i < 0 || cand[i].time_ms < cand[best_i].time_ms)) best_i = (int)i;
+    }
+    c->forced = nullptr;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != P2M_OK) return result;
+    if (best_i < 0) return P2M_ERR_UNSUPPORTED;   // no candidate converged
+    if (!c->plans) {
+        c->plans = new (std::nothrow) PlanCache();
+        if (!c->plans) return P2M_ERR_HIP;
+    }
+    *best = cand[best_i];
+    c->plans->plans[shape_key(pp.m, prob->dtype, nfields)] = *best;
+    // leave the chosen plan's result in nodal_out and rep
+    c->forced = best;
+    result = p2m_mass_assign(ctx, prob, values, nfields, opts, nodal_out, rep, ws, ws_bytes, stream);
+    c->forced = nullptr;
+    return result;
+}
+
+p2m_status p2m_plan_get(void* ctx, const p2m_problem* prob, int32_t nfields, p2m_plan* plan) {
+    if (!ctx || !plan || nfields < 1 || nfields > kMaxFields) return P2M_ERR_INVALID_ARG;
+    Mesh m;
+    p2m_status s = check_problem(prob, m);
+    if (s != P2M_OK) return s;
+    const Context* c = (const Context*)ctx;
+    if (!c->plans) return P2M_ERR_UNSUPPORTED;
+    auto it = c->plans->plans.find(shape_key(m, prob->dtype, nfields));
+    if (it == c->plans->plans.end()) return P2M_ERR_UNSUPPORTED;
+    *plan = it->second;
+    return P2M_OK;
+}
+
+p2m_status p2m_plan_save(void* ctx, const char* path) {
+    if (!ctx || !path) return P2M_ERR_INVALID_ARG;
+    const Context* c = (const Context*)ctx;
+    FILE* f = fopen(path, "w");
+    if (!f) return P2M_ERR_INVALID_ARG;
+    fprintf(f, "{\n");
+    size_t i = 0, n = c->plans ? c->plans->plans.size() : 0;
+    if (c->plans)
+        for (const auto& kv : c->plans->plans) {
+            const p2m_plan& p = kv.second;
+            fprintf(f, "  \"%s\": {\"solver\": %d, \"groups\": %d, \"scatter_tile\": %d, \"time_ms\": %.6f}%s\n",
+                    kv.first.c_str(), p.solver, p.groups, p.scatter_tile, p.time_ms,
+                    ++i < n ? "," : "");
+        }
+    fprintf(f, "}\n");
+    return fclose(f) == 0 ? P2M_OK : P2M_ERR_INVALID_ARG;
+}
+
+p2m_status p2m_plan_load(void* ctx, const char* path) {
+    if (!ctx || !path) return P2M_ERR_INVALID_ARG;
+    Context* c = (Context*)ctx;
+    FILE* f = fopen(path, "r");
+    if (!f) return P2M_ERR_INVALID_ARG;
+    std::map<std::string, p2m_plan> got;
+    char line[512];
+    p2m_status s = P2M_OK;
+    while (fgets(line, sizeof line, f)) {
+        char key[128];
+        p2m_plan p;
+        memset(&p, 0, sizeof(p));
+        const char* q = strchr(line, '"');
+        if (!q) continue;   // braces
+        if (sscanf(q, "\"%127[^\"]\": {\"solver\": %d, \"groups\": %d, \"scatter_tile\": %d, \"time_ms\": %lf}",
+                   key, &p.solver, &p.groups, &p.scatter_tile, &p.time_ms) != 5 ||
+            p.solver < P2M_SOLVER_AUTO || p.solver > P2M_SOLVER_TILES || p.groups < 0 ||
+            (p.scatter_tile != 0 && p.scatter_tile != 8)) {
+            s = P2M_ERR_INVALID_ARG;
+            break;
+        }
+        got[key] = p;
+    }
+    fclose(f);
+    if (s != P2M_OK) return s;
+    if (!c->plans) {
+        c->plans = new (std::nothrow) PlanCache();
+        if (!c->plans) return P2M_ERR_HIP;
+    }
+    for (const auto& kv : got) c->plans->plans[kv.first] = kv.second;
+    return P2M_OK;
+}
+
+p2m_status p2m_plan_clear(void* ctx) {
+    if (!ctx) return P2M_ERR_INVALID_ARG;
+    Context* c = (Context*)ctx;
+    if (c->plans) c->plans->plans.clear();
+    return P2M_OK;
 }
 
 }  // extern "C"

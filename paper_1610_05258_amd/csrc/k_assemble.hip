@@ -318,9 +318,22 @@ hipError_t assemble_batch_f(const BatchInst* inst, const int32_t* amap, int ntil
     return hipGetLastError();
 }
 
+template <typename T, int F, int TS>
+hipError_t assemble2d_ts(const Mesh& m, Particles<T> P, const T* values, const int32_t* perm,
+                         const int32_t* cs, T* b, T* w, T* coef, hipStream_t stream) {
+    constexpr int CH = stage_chunk<T, F>();
+    constexpr int NT = ((TS + 1) * (TS + 1) + 63) / 64 * 64;
+    const int tx = (m.nx + TS - 1) / TS, ty = (m.ny + TS - 1) / TS;
+    hipLaunchKernelGGL((k_assemble2d<T, F, TS, CH>), dim3(tx * ty), dim3(NT), 0, stream, m, P,
+                       values, perm, cs, b, w, coef, tx);
+    return hipGetLastError();
+}
+
+// tile: 0 = the default node tile (16 x 16 where its parts fit 64 KB of LDS, else
+// 8 x 8), 8 = 8 x 8
 template <typename T, int F>
 hipError_t assemble_f(const Mesh& m, Particles<T> P, const T* values, const int32_t* perm,
-                      const int32_t* cs, T* b, T* w, T* coef, hipStream_t stream) {
+                      const int32_t* cs, T* b, T* w, T* coef, int tile, hipStream_t stream) {
     if (m.dim == 1) {
         constexpr int TS = 256;
         int grid = (m.nx + TS - 1) / TS;
@@ -332,12 +345,9 @@ hipError_t assemble_f(const Mesh& m, Particles<T> P, const T* values, const int3
     // of staged slots sized to keep the staging area within 32 KB
     static_assert(Q_B == 13, "assemble_tile assumes 13 + 4F parts per cell");
     constexpr int TS = assemble_tile(F, (int)sizeof(T));
-    constexpr int CH = stage_chunk<T, F>();
-    constexpr int NT = ((TS + 1) * (TS + 1) + 63) / 64 * 64;
-    const int tx = (m.nx + TS - 1) / TS, ty = (m.ny + TS - 1) / TS;
-    hipLaunchKernelGGL((k_assemble2d<T, F, TS, CH>), dim3(tx * ty), dim3(NT), 0, stream, m, P,
-                       values, perm, cs, b, w, coef, tx);
-    return hipGetLastError();
+    if (tile == 8 && TS != 8)
+        return assemble2d_ts<T, F, 8>(m, P, values, perm, cs, b, w, coef, stream);
+    return assemble2d_ts<T, F, TS>(m, P, values, perm, cs, b, w, coef, stream);
 }
 
 }  // namespace
@@ -345,25 +355,25 @@ hipError_t assemble_f(const Mesh& m, Particles<T> P, const T* values, const int3
 template <typename T>
 hipError_t launch_assemble(const Mesh& m, Particles<T> P, const T* values, int F,
                            const int32_t* perm, const int32_t* cell_start, T* b, T* w, T* coef,
-                           hipStream_t stream) {
+                           hipStream_t stream, int tile) {
     switch (F) {
-        case 1: return assemble_f<T, 1>(m, P, values, perm, cell_start, b, w, coef, stream);
-        case 2: return assemble_f<T, 2>(m, P, values, perm, cell_start, b, w, coef, stream);
-        case 3: return assemble_f<T, 3>(m, P, values, perm, cell_start, b, w, coef, stream);
-        case 4: return assemble_f<T, 4>(m, P, values, perm, cell_start, b, w, coef, stream);
-        case 5: return assemble_f<T, 5>(m, P, values, perm, cell_start, b, w, coef, stream);
-        case 6: return assemble_f<T, 6>(m, P, values, perm, cell_start, b, w, coef, stream);
-        case 7: return assemble_f<T, 7>(m, P, values, perm, cell_start, b, w, coef, stream);
-        case 8: return assemble_f<T, 8>(m, P, values, perm, cell_start, b, w, coef, stream);
+        case 1: return assemble_f<T, 1>(m, P, values, perm, cell_start, b, w, coef, tile, stream);
+        case 2: return assemble_f<T, 2>(m, P, values, perm, cell_start, b, w, coef, tile, stream);
+        case 3: return assemble_f<T, 3>(m, P, values, perm, cell_start, b, w, coef, tile, stream);
+        case 4: return assemble_f<T, 4>(m, P, values, perm, cell_start, b, w, coef, tile, stream);
+        case 5: return assemble_f<T, 5>(m, P, values, perm, cell_start, b, w, coef, tile, stream);
+        case 6: return assemble_f<T, 6>(m, P, values, perm, cell_start, b, w, coef, tile, stream);
+        case 7: return assemble_f<T, 7>(m, P, values, perm, cell_start, b, w, coef, tile, stream);
+        case 8: return assemble_f<T, 8>(m, P, values, perm, cell_start, b, w, coef, tile, stream);
         default: return hipErrorInvalidValue;
     }
 }
 template hipError_t launch_assemble<float>(const Mesh&, Particles<float>, const float*, int,
                                            const int32_t*, const int32_t*, float*, float*, float*,
-                                           hipStream_t);
+                                           hipStream_t, int);
 template hipError_t launch_assemble<double>(const Mesh&, Particles<double>, const double*, int,
                                             const int32_t*, const int32_t*, double*, double*,
-                                            double*, hipStream_t);
+                                            double*, hipStream_t, int);
 
 hipError_t launch_assemble_batch(int F, const BatchInst* inst, const int32_t* amap, int ntiles,
                                  const int32_t* perm, const int32_t* cell_start, float* b,

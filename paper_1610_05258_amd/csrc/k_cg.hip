@@ -4,10 +4,11 @@
 //   outer: the solution is kept in FP64 (x64); the true residual
 //          r = b - M x64 is evaluated in FP64 from the stored coefficients;
 //          stop when ||r||_2 / ||b||_2 <= tol for every field;
-//   inner: CG in T (FP32 on the FP32 path) on the correction M d = r, with the
-//          stencil product, axpy and vector updates in T, every field sharing
-//          each coefficient read, and all dot products accumulated in FP64;
-//          the next outer step folds d into x64 in FP64.
+//   inner: Jacobi-preconditioned CG in T (FP32 on the FP32 path) on the
+//          correction M d = r (u = r / diag M), with the stencil product, axpy
+//          and vector updates in T, every field sharing each coefficient read,
+//          and all dot products accumulated in FP64; the next outer step folds
+//          d into x64 in FP64.
 // The whole solve is one persistent cooperative kernel: grid-wide barriers
 // separate the phases; reductions are per-block FP64 partials that every block
 // sums in the same fixed order, so all blocks take identical decisions and the
@@ -40,6 +41,7 @@ struct CgArgs {
     T* p1;
     T* q;
     double* partials;  // [2][gridDim][kSlots]
+    T* dinv;           // [nn] inverse of the regularised diagonal (written here)
     const T* w;        // [nn] FLIP volumes (orphans: w == 0)
     int start;         // P2M_START_FLIP / ZERO / USER (xout holds the user start)
     p2m_solve_opts opts;
@@ -161,6 +163,9 @@ __device__ __forceinline__ void grid_total(const double* __restrict__ part, int 
     __syncthreads();
 }
 
+__device__ __forceinline__ float recip(float d) { return __frcp_rn(d); }
+__device__ __forceinline__ double recip(double d) { return 1.0 / d; }
+
 template <typename T, int DIM, int F>
 __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
     cg::grid_group grid = cg::this_grid();
@@ -207,6 +212,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
         const T wk = a.w[k];
         const bool orphan = !(wk > (T)0);
         if (orphan) a.coef[k] = (T)1;
+        a.dinv[k] = orphan ? (T)1 : recip(a.coef[k]);
 #pragma unroll
         for (int f = 0; f < F; ++f) {
             const size_t o = (size_t)f * nn + k;
@@ -232,7 +238,8 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
 
     for (int outer = 0;; ++outer) {
         // ---- R: fold the correction into x64 and evaluate r = b - M x64 in FP64 --
-        // slots: [f] ||r64||^2, [8+f] ||(T)r64||^2, [16+f] ||b||^2 (first pass)
+        // slots: [f] ||r64||^2, [8+f] (r_T, u) with r_T = (T)r64, u = r_T / diag,
+        // [16+f] ||b||^2 (first pass)
         {
             double part[kSlots];
 #pragma unroll
@@ -256,7 +263,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                     a.r[(size_t)f * nn + k] = rt;
                     a.x64[(s_xb[f] ^ 1) * xstride + (size_t)f * nn + k] = y(k);
                     part[f] += r64 * r64;
-                    part[kMaxFields + f] += (double)rt * (double)rt;
+                    part[kMaxFields + f] += (double)rt * (double)(rt * a.dinv[k]);
                     if (outer == 0) part[2 * kMaxFields + f] += bk * bk;
                 }
             }
@@ -303,7 +310,8 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
 
         // ---- inner CG on M d = r, d starts at 0 ---------------------------------
         for (int it = 0;; ++it) {
-            // A: p_new = r + beta p_old (at the node and its neighbours), q = M p_new
+            // A: p_new = u + beta p_old with u = r / diag (at the node and its
+            //    neighbours), q = M p_new
             {
                 double part[kMaxFields];
 #pragma unroll
@@ -319,7 +327,8 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                         const T beta = (T)s_beta[f];
                         const bool first = (it == 0);
                         auto pv = [&](int idx) -> T {
-                            return first ? rf[idx] : rf[idx] + beta * pf[idx];
+                            const T u = rf[idx] * a.dinv[idx];
+                            return first ? u : u + beta * pf[idx];
                         };
                         const T pk = pv(n.k);
                         const T qk = apply_row<DIM, T>(c, n, pv);
@@ -349,11 +358,12 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                 }
             }
             __syncthreads();
-            // B: d += alpha p_new (d = alpha p_new on the first step), r -= alpha q
+            // B: d += alpha p_new (d = alpha p_new on the first step), r -= alpha q;
+            //    partials (r, u) and (r, r)
             {
-                double part[kMaxFields];
+                double part[2 * kMaxFields];
 #pragma unroll
-                for (int j = 0; j < kMaxFields; ++j) part[j] = 0.0;
+                for (int j = 0; j < 2 * kMaxFields; ++j) part[j] = 0.0;
                 for (int k = k0; k < nn; k += kstride) {
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
@@ -364,24 +374,25 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                         a.xout[o] = dk + al * p_new[o];
                         const T rn = a.r[o] - al * a.q[o];
                         a.r[o] = rn;
-                        part[f] += (double)rn * (double)rn;
+                        part[f] += (double)rn * (double)(rn * a.dinv[k]);
+                        part[kMaxFields + f] += (double)rn * (double)rn;
                     }
                 }
-                block_sum<kMaxFields>(part, lds);
-                store_partials<kMaxFields>(a.partials + (phase & 1) * pstride, part);
+                block_sum<2 * kMaxFields>(part, lds);
+                store_partials<2 * kMaxFields>(a.partials + (phase & 1) * pstride, part);
             }
             grid.sync();
-            grid_total<kMaxFields>(a.partials + (phase & 1) * pstride, nblocks, tot, lds);
+            grid_total<2 * kMaxFields>(a.partials + (phase & 1) * pstride, nblocks, tot, lds);
             ++phase;
             if (threadIdx.x == 0) {
                 int any = 0;
                 for (int f = 0; f < F; ++f) {
                     if (!s_inner[f]) continue;
-                    const double rho_new = tot[f];
+                    const double rho_new = tot[f], rr = tot[kMaxFields + f];
                     s_beta[f] = rho_new / s_rho[f];
                     s_rho[f] = rho_new;
                     s_iters[f] += 1;
-                    if (!(rho_new > s_target[f]) || s_iters[f] >= a.opts.maxit) {
+                    if (!(rr > s_target[f]) || s_iters[f] >= a.opts.maxit) {
                         s_inner[f] = 0;
                         continue;
                     }
@@ -474,6 +485,7 @@ hipError_t launch_cg(const Mesh& m, int F, T* coef, T* b, const T* w, T* x, int 
     a.p1 = (T*)ws.p1;
     a.q = (T*)ws.q;
     a.partials = ws.partials;
+    a.dinv = (T*)ws.dinv;
     a.opts = opts;
     a.rep = rep;
     void* args[] = {&a};

@@ -27,6 +27,8 @@
 // Each (instance, field) pair therefore performs the operations of the resident
 // solve of that instance alone, in the same order: the batched result equals the
 // single-problem result bit for bit.
+#include <string.h>
+
 #include "cg_common.hpp"
 
 namespace p2m {
@@ -731,6 +733,17 @@ __global__ void k_sync_clear_b(unsigned* ctr, unsigned* root, unsigned* rel, uns
 
 size_t al(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// one-instance table for a single problem solved by k_cgb: the entry is copied
+// word by word from the kernel argument, every tile maps to instance 0
+__global__ void k_single_table(BatchInst inst, int ntiles, uint32_t* __restrict__ tbl,
+                               int32_t* __restrict__ rmap) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int kWords = (int)(sizeof(BatchInst) / sizeof(uint32_t));
+    static_assert(sizeof(BatchInst) % sizeof(uint32_t) == 0, "table entry in words");
+    if (t < kWords) tbl[t] = reinterpret_cast<const uint32_t*>(&inst)[t];
+    if (t < ntiles) rmap[t] = 0;
+}
+
 }  // namespace
 
 const void* cgb_kernel(int F) {
@@ -770,6 +783,61 @@ size_t cgb_workspace_bytes(int F, int nprob, int ntiles, size_t nodes) {
     s += al((size_t)2 * ntiles * kNV * sizeof(double));   // part
     s += al((size_t)2 * nprob * kNV * sizeof(double));    // tot
     return s;
+}
+
+static int single_tiles(const Mesh& m) {
+    return ((m.nx + RX - 1) / RX) * ((m.ny + RY - 1) / RY);
+}
+
+size_t cgt_workspace_bytes(const Mesh& m, int F) {
+    const int nt = single_tiles(m);
+    return al(sizeof(BatchInst)) + al((size_t)nt * sizeof(int32_t)) +
+           cgb_workspace_bytes(F, 1, nt, (size_t)m.nn);
+}
+
+int cgt_grid(const Mesh& m, int F, int groups, int device) {
+    if (m.dim != 2 || F < 1 || F > kResidentMaxFields) return 0;
+    const int nt = single_tiles(m);
+    const int cap = cgb_grid(F, nt, device);
+    if (cap < 1) return 0;
+    int G = groups > 0 && groups < cap ? groups : cap;
+    if ((long)G * kBatchMaxOwn < nt) G = cap;
+    return G;
+}
+
+hipError_t launch_cg_tiles(const Mesh& m, int F, float* coef, float* b, const float* w, float* x,
+                           int start, void* ws, const p2m_solve_opts& opts, p2m_report* rep,
+                           int groups, int device, hipStream_t stream) {
+    const int nt = single_tiles(m);
+    const int G = cgt_grid(m, F, groups, device);
+    if (G < 1) return hipErrorInvalidValue;
+    char* p = (char*)ws;
+    BatchInst inst;
+    memset(&inst, 0, sizeof(inst));
+    inst.m = m;
+    inst.out = x;
+    inst.rep = rep;
+    inst.rtx = (m.nx + RX - 1) / RX;
+    inst.nrt = nt;
+    BatchInst* tbl = (BatchInst*)p;
+    p += al(sizeof(BatchInst));
+    int32_t* rmap = (int32_t*)p;
+    p += al((size_t)nt * sizeof(int32_t));
+    const int nthreads = nt > 64 ? nt : 64;
+    hipLaunchKernelGGL(k_single_table, dim3((nthreads + 255) / 256), dim3(256), 0, stream, inst, nt,
+                       (uint32_t*)tbl, rmap);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    BatchSolveBufs bb;
+    bb.inst = tbl;
+    bb.nprob = 1;
+    bb.rmap = rmap;
+    bb.ntiles = nt;
+    bb.coef = coef;
+    bb.b = b;
+    bb.w = w;
+    bb.ws = p;
+    return launch_cg_batch(F, bb, (size_t)m.nn, G, start, opts, stream);
 }
 
 hipError_t launch_cg_batch(int F, const BatchSolveBufs& bb, size_t nodes, int grid, int start,

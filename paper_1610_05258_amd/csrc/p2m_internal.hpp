@@ -121,11 +121,12 @@ hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* cell_s
 hipError_t launch_segment_sort(const Mesh& m, const int32_t* cell_start, int32_t* perm,
                                hipStream_t stream);
 
-// scatter-assemble: b [F][nn], w [nn], coef [c_M][nn] or null
+// scatter-assemble: b [F][nn], w [nn], coef [c_M][nn] or null; tile 0 = the default
+// 2D node tile, 8 = 8 x 8
 template <typename T>
 hipError_t launch_assemble(const Mesh& m, Particles<T> P, const T* values, int F,
                            const int32_t* perm, const int32_t* cell_start, T* b, T* w, T* coef,
-                           hipStream_t stream);
+                           hipStream_t stream, int tile = 0);
 
 // finalize: FLIP (divide by w, orphans 0) or PIC (divide by the mesh volume)
 template <typename T>
@@ -151,6 +152,7 @@ struct CgWorkspace {
     void* q;          // [F][nn] T
     double* x64;      // [2][F][nn] FP64 solution (ping-pong)
     double* partials; // [2][blocks][3*kMaxFields]
+    void* dinv;       // [nn] T, inverse of the regularised diagonal
     int blocks;       // grid size of the persistent kernel
 };
 size_t cg_partials_bytes(int blocks);
@@ -214,6 +216,13 @@ size_t cgb_workspace_bytes(int F, int nprob, int ntiles, size_t nodes);
 hipError_t launch_cg_batch(int F, const BatchSolveBufs& bb, size_t nodes, int grid, int start,
                            const p2m_solve_opts& opts, hipStream_t stream);
 const void* cgb_kernel(int F);
+// a single 2D FP32 problem (F <= 3) through the tile-streaming solve: any mesh
+// size; groups = workgroups (0 or more than fit: one per compute unit)
+size_t cgt_workspace_bytes(const Mesh& m, int F);
+int cgt_grid(const Mesh& m, int F, int groups, int device);   // 0: not available
+hipError_t launch_cg_tiles(const Mesh& m, int F, float* coef, float* b, const float* w, float* x,
+                           int start, void* ws, const p2m_solve_opts& opts, p2m_report* rep,
+                           int groups, int device, hipStream_t stream);
 
 // learned warm start (k_learn.hip); X rows are BF16 [.][160]
 hipError_t launch_learn_features(const Mesh& m, Particles<float> P, const float* values, int F,
