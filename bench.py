@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip p2m_tune (the library's default launch choices are timed)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy MIB MiB device-to-device three times "
                          "(a kernel of known traffic for scaling memory counters)")
@@ -252,6 +254,11 @@ def main():
         if ev is not None:
             ev[2].record(stream)
 
+    plan = None
+    if not args.no_tune:
+        plan, _, _ = B.p2m_tune(ctx, d, v, opts)
+        torch.cuda.synchronize()
+        log(f"bench: tuned plan {plan}")
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
         one_step()
@@ -284,6 +291,10 @@ def main():
                   config=dict(workload=f"taylor-green 2D periodic {n}x{n} P1, 8 ppc stratified seed 2, "
                                        f"50 RK2 steps dt=1e-3, F=3 (u,v,p + N(0,1e-3)), tol={args.tol:g}",
                               nodes=nn, particles=int(vals.shape[1]), fields=F, tol=args.tol),
+                  plan=None if plan is None else dict(solver={1: "streaming (k_cg)", 2: "resident (k_cgr)",
+                                                              3: "tile-streaming (k_cgb)"}[plan.solver],
+                                                      groups=plan.groups, scatter_tile=plan.scatter_tile or 16,
+                                                      tuned_ms=plan.time_ms),
                   phases=dict(assemble_ms=asm_ms, solve_ms=cg_ms, cg_iters=r.iters.tolist(),
                               refines=r.refines.tolist(), rel_residual=r.rel_residual.tolist(),
                               flags=r.flags))
@@ -306,10 +317,14 @@ def main():
     if k_ref is not None:
         kk = max(k_ref)
         achieved = cg_algorithmic_bytes(kk, nn, F) / (cg_ms * 1e-3) / 1e9
-        result["roofline"] = dict(bound="hbm", kernel="k_cgr<3> (register-resident mass solve)",
+        solver = plan.solver if plan is not None else 2
+        kernel = {1: f"k_cg<float,2,{F}> (grid-synchronised mass solve)",
+                  2: f"k_cgr<{F}> (register-resident mass solve)",
+                  3: f"k_cgb<{F}> (tile-streaming mass solve)"}[solver]
+        result["roofline"] = dict(bound="hbm", kernel=kernel,
                                   achieved=achieved,
                                   peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                                  traffic=measured_traffic(), k_ref=kk,
+                                  traffic=measured_traffic() if solver == 2 else None, k_ref=kk,
                                   bytes_per_launch=cg_algorithmic_bytes(kk, nn, F))
     print(json.dumps(result), flush=True)
 
