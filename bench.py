@@ -58,10 +58,10 @@ COUNTERS = os.path.join(ROOT, "profiles", "counters_k_cgr3_tg1024.md")
 SOLVER_SOURCES = ("k_cgr.hip", "cg_common.hpp", "p2m_internal.hpp")
 
 
-def measured_traffic():
+def measured_traffic(inner_rtol):
     """HBM bytes per k_cgr<3> launch from the committed counter summary (FETCH_SIZE
     and WRITE_SIZE runs scaled by a copy of known size), or None when the solver
-    sources have changed since the counters were taken."""
+    sources or the solve schedule (inner_rtol) differ from those of the counted run."""
     import hashlib
     import re
     if not os.path.exists(COUNTERS):
@@ -69,7 +69,8 @@ def measured_traffic():
     text = open(COUNTERS).read()
     m_t = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
     m_h = re.search(r"^source_sha256: ([0-9a-f]{64})", text, re.M)
-    if not (m_t and m_h):
+    m_r = re.search(r"^inner_rtol: (\S+)", text, re.M)
+    if not (m_t and m_h and m_r) or float(m_r.group(1)) != float(inner_rtol):
         return None
     h = hashlib.sha256()
     for f in SOLVER_SOURCES:
@@ -294,6 +295,8 @@ def main():
                   plan=None if plan is None else dict(solver={1: "streaming (k_cg)", 2: "resident (k_cgr)",
                                                               3: "tile-streaming (k_cgb)"}[plan.solver],
                                                       groups=plan.groups, scatter_tile=plan.scatter_tile or 16,
+                                                      inner_rtol=(plan.inner_rtol if plan.inner_rtol >= 0
+                                                                  else opts.inner_rtol),
                                                       tuned_ms=plan.time_ms),
                   phases=dict(assemble_ms=asm_ms, solve_ms=cg_ms, cg_iters=r.iters.tolist(),
                               refines=r.refines.tolist(), rel_residual=r.rel_residual.tolist(),
@@ -324,7 +327,9 @@ def main():
         result["roofline"] = dict(bound="hbm", kernel=kernel,
                                   achieved=achieved,
                                   peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                                  traffic=measured_traffic() if solver == 2 else None, k_ref=kk,
+                                  traffic=(measured_traffic(result["plan"]["inner_rtol"] if plan is not None
+                                                            else opts.inner_rtol)
+                                           if solver == 2 else None), k_ref=kk,
                                   bytes_per_launch=cg_algorithmic_bytes(kk, nn, F))
     print(json.dumps(result), flush=True)
 

@@ -339,14 +339,16 @@ typedef struct {
     int32_t groups;        /* workgroups of the tile-streaming solve (0: one per compute unit) */
     int32_t scatter_tile;  /* 2D scatter node tile: 0 = default (16 x 16 where it fits), 8 = 8 x 8 */
     int32_t reserved;      /* 0 */
+    double inner_rtol;     /* replaces opts->inner_rtol when >= 0 (the inner / outer schedule;
+                              the FP64 stopping test on tol is unchanged); < 0: keep opts */
     double time_ms;        /* measured time of one p2m_mass_assign with this plan when tuned */
 } p2m_plan;
 
 /* Times p2m_mass_assign of this problem under every applicable plan (each solve
  * kernel; the tile-streaming kernel with one and with half a workgroup per
- * compute unit; the default and the 8 x 8 scatter tile), three runs each after a
- * warm-up, on `stream`; keeps the fastest plan whose solve converged for the
- * problem's shape class and returns it.  Synchronises `stream`.  opts->start must
+ * compute unit; the default and the 8 x 8 scatter tile; the caller's inner_rtol,
+ * 3e-5 and 0), three runs each after a warm-up, on `stream`; keeps the fastest
+ * plan whose solve converged for the problem's shape class and returns it.  Synchronises `stream`.  opts->start must
  * be FLIP or ZERO; nodal_out and rep receive the chosen plan's result. */
 p2m_status p2m_tune(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
                     const p2m_solve_opts* opts, void* nodal_out, p2m_report* rep, void* ws,

@@ -57,11 +57,11 @@ class CProblem(ctypes.Structure):
 
 class CPlan(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int32), ("groups", ctypes.c_int32), ("scatter_tile", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("time_ms", ctypes.c_double)]
+                ("reserved", ctypes.c_int32), ("inner_rtol", ctypes.c_double), ("time_ms", ctypes.c_double)]
 
     def __repr__(self):
         return (f"CPlan(solver={self.solver}, groups={self.groups}, scatter_tile={self.scatter_tile}, "
-                f"time_ms={self.time_ms:.4f})")
+                f"inner_rtol={self.inner_rtol:g}, time_ms={self.time_ms:.4f})")
 
 
 class CSolveOpts(ctypes.Structure):

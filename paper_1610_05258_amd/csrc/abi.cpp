@@ -173,6 +173,7 @@ struct Choice {
     int solver = P2M_SOLVER_AUTO;
     int groups = 0;
     int tile = 0;
+    double inner_rtol = -1.0;   // < 0: the caller's
 };
 
 Choice choose(const Context* c, const Mesh& m, int dtype, int F) {
@@ -181,6 +182,7 @@ Choice choose(const Context* c, const Mesh& m, int dtype, int F) {
         ch.solver = c->forced->solver;
         ch.groups = c->forced->groups;
         ch.tile = c->forced->scatter_tile;
+        ch.inner_rtol = c->forced->inner_rtol;
         return ch;
     }
     if (c->use_plans && c->plans) {
@@ -189,6 +191,7 @@ Choice choose(const Context* c, const Mesh& m, int dtype, int F) {
             ch.solver = it->second.solver;
             ch.groups = it->second.groups;
             ch.tile = it->second.scatter_tile;
+            ch.inner_rtol = it->second.inner_rtol;
         }
     }
     if (c->solver_mode != P2M_SOLVER_AUTO) ch.solver = c->solver_mode;
@@ -279,7 +282,9 @@ p2m_status run_assemble(const Prepared& pp, const p2m_problem* prob, const void*
 // the grid-synchronised streaming kernel (1D, FP64, F > 3).
 template <typename T>
 p2m_status run_solve(const Context* c, const Prepared& pp, int F, T* b, const T* w, T* coef,
-                     int start, const p2m_solve_opts& opts, void* x, const Choice& ch) {
+                     int start, const p2m_solve_opts& caller_opts, void* x, const Choice& ch) {
+    p2m_solve_opts opts = caller_opts;
+    if (ch.inner_rtol >= 0.0 && ch.inner_rtol < 1.0) opts.inner_rtol = ch.inner_rtol;
     const bool tiled = sizeof(T) == 4 && pp.m.dim == 2 && F <= kResidentMaxFields;
     const int kind = ch.solver;
     if (tiled && (kind == P2M_SOLVER_AUTO || kind == P2M_SOLVER_RESIDENT) &&
@@ -850,13 +855,18 @@ p2m_status p2m_tune(void* ctx, const p2m_problem* prob, const void* values, int3
     // candidates: every solve kernel that applies, with the default and the 8 x 8
     // scatter tile; the tile-streaming solve with one and with half a workgroup per CU
     std::vector<p2m_plan> cand;
+    const double rtols[3] = {-1.0, 3e-5, 0.0};
     auto add = [&](int solver, int groups, int tile) {
-        p2m_plan p;
-        memset(&p, 0, sizeof(p));
-        p.solver = solver;
-        p.groups = groups;
-        p.scatter_tile = tile;
-        cand.push_back(p);
+        for (double rt : rtols) {
+            if (rt >= 0.0 && rt == opts->inner_rtol) continue;
+            p2m_plan p;
+            memset(&p, 0, sizeof(p));
+            p.solver = solver;
+            p.groups = groups;
+            p.scatter_tile = tile;
+            p.inner_rtol = rt;
+            cand.push_back(p);
+        }
     };
     const bool tiled = prob->dtype == P2M_F32 && pp.m.dim == 2 && nfields <= kResidentMaxFields;
     const int tiles[2] = {0, 8};
@@ -942,8 +952,10 @@ p2m_status p2m_plan_save(void* ctx, const char* path) {
     if (c->plans)
         for (const auto& kv : c->plans->plans) {
             const p2m_plan& p = kv.second;
-            fprintf(f, "  \"%s\": {\"solver\": %d, \"groups\": %d, \"scatter_tile\": %d, \"time_ms\": %.6f}%s\n",
-                    kv.first.c_str(), p.solver, p.groups, p.scatter_tile, p.time_ms,
+            fprintf(f,
+                    "  \"%s\": {\"solver\": %d, \"groups\": %d, \"scatter_tile\": %d, "
+                    "\"inner_rtol\": %.17g, \"time_ms\": %.6f}%s\n",
+                    kv.first.c_str(), p.solver, p.groups, p.scatter_tile, p.inner_rtol, p.time_ms,
                     ++i < n ? "," : "");
         }
     fprintf(f, "}\n");
@@ -964,10 +976,13 @@ p2m_status p2m_plan_load(void* ctx, const char* path) {
         memset(&p, 0, sizeof(p));
         const char* q = strchr(line, '"');
         if (!q) continue;   // braces
-        if (sscanf(q, "\"%127[^\"]\": {\"solver\": %d, \"groups\": %d, \"scatter_tile\": %d, \"time_ms\": %lf}",
-                   key, &p.solver, &p.groups, &p.scatter_tile, &p.time_ms) != 5 ||
+        if (sscanf(q,
+                   "\"%127[^\"]\": {\"solver\": %d, \"groups\": %d, \"scatter_tile\": %d, "
+                   "\"inner_rtol\": %lf, \"time_ms\": %lf}",
+                   key, &p.solver, &p.groups, &p.scatter_tile, &p.inner_rtol, &p.time_ms) != 6 ||
             p.solver < P2M_SOLVER_AUTO || p.solver > P2M_SOLVER_TILES || p.groups < 0 ||
-            (p.scatter_tile != 0 && p.scatter_tile != 8)) {
+            (p.scatter_tile != 0 && p.scatter_tile != 8) || !(p.inner_rtol < 1.0) ||
+            !isfinite(p.inner_rtol)) {
             s = P2M_ERR_INVALID_ARG;
             break;
         }

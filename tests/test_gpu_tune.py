@@ -107,8 +107,8 @@ def test_tune_store_save_load(B, tmp_path):
     assert plan.solver in (B.SOLVER_STREAMING, B.SOLVER_RESIDENT, B.SOLVER_TILES)
     assert plan.scatter_tile in (0, 8) and plan.time_ms > 0.0
     got = ctx.plan(d, 3)
-    assert got is not None and (got.solver, got.groups, got.scatter_tile) == (plan.solver, plan.groups,
-                                                                             plan.scatter_tile)
+    assert got is not None and (got.solver, got.groups, got.scatter_tile, got.inner_rtol) == (
+        plan.solver, plan.groups, plan.scatter_tile, plan.inner_rtol)
     # a later call applies the plan: the tuned result again, bit for bit
     again, _ = B.p2m_mass_assign(ctx, d, v, opts)
     torch.cuda.synchronize()
@@ -123,7 +123,8 @@ def test_tune_store_save_load(B, tmp_path):
     ctx2 = B.Context(0)
     ctx2.load_plans(path)
     p2 = ctx2.plan(d, 3)
-    assert (p2.solver, p2.groups, p2.scatter_tile) == (plan.solver, plan.groups, plan.scatter_tile)
+    assert (p2.solver, p2.groups, p2.scatter_tile, p2.inner_rtol) == (plan.solver, plan.groups,
+                                                                      plan.scatter_tile, plan.inner_rtol)
     out2, _ = B.p2m_mass_assign(ctx2, d, v, opts)
     torch.cuda.synchronize()
     assert torch.equal(out2, tuned)
@@ -133,7 +134,8 @@ def test_tune_store_save_load(B, tmp_path):
     ctx2.clear_plans()
     assert ctx2.plan(d, 3) is None
     bad = tmp_path / "bad.json"
-    bad.write_text('{\n  "2d-f32-F3-nx8-ny8-ppc2": {"solver": 9, "groups": 0}\n}\n')
+    bad.write_text('{\n  "2d-f32-F3-nx8-ny8-ppc2": {"solver": 9, "groups": 0, "scatter_tile": 0, '
+                   '"inner_rtol": -1, "time_ms": 1}\n}\n')
     with pytest.raises(B.P2MError):
         ctx2.load_plans(bad)
     assert ctx2.plan(d, 3) is None
