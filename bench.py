@@ -197,6 +197,11 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip p2m_tune (the library's default launch choices are timed)")
+    ap.add_argument("--save-plans", default=None, metavar="PATH",
+                    help="write the tuned plans to PATH (JSON)")
+    ap.add_argument("--load-plans", default=None, metavar="PATH",
+                    help="apply the plans in PATH instead of tuning (e.g. for profiler runs, "
+                         "whose timings would perturb the tuner)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy MIB MiB device-to-device three times "
                          "(a kernel of known traffic for scaling memory counters)")
@@ -256,10 +261,17 @@ def main():
             ev[2].record(stream)
 
     plan = None
-    if not args.no_tune:
+    if args.load_plans:
+        ctx.load_plans(args.load_plans)
+        plan = ctx.plan(d, F)
+        assert plan is not None, f"{args.load_plans} holds no plan for this shape"
+        log(f"bench: loaded plan {plan}")
+    elif not args.no_tune:
         plan, _, _ = B.p2m_tune(ctx, d, v, opts)
         torch.cuda.synchronize()
         log(f"bench: tuned plan {plan}")
+    if plan is not None and args.save_plans:
+        ctx.save_plans(args.save_plans)
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
         one_step()

@@ -90,7 +90,7 @@ Layout make_layout(const Mesh& m, int F, size_t tsize, int cg_blocks) {
     };
     const size_t np = (size_t)m.np, nn = (size_t)m.nn;
     const size_t cm = (m.dim == 2) ? 4 : 2;
-    L.key = take(np * sizeof(int32_t));
+    L.key = take(2 * np * sizeof(int32_t));      // cell keys, then in-cell ranks
     L.counts = take(nn * sizeof(int32_t));
     L.cell_start = take((nn + 1) * sizeof(int32_t));
     L.perm = take(np * sizeof(int32_t));
@@ -234,12 +234,13 @@ p2m_status run_bin(const Prepared& pp, const p2m_problem* prob, int32_t* perm, i
     const Mesh& m = pp.m;
     int32_t* key = (int32_t*)(pp.ws + pp.L.key);
     int32_t* counts = (int32_t*)(pp.ws + pp.L.counts);
+    int32_t* rank = key + m.np;
     int32_t* sums = (int32_t*)(pp.ws + pp.L.scan);
     P2M_TRY(launch_fill_i32(counts, 0, (size_t)m.nn, pp.stream));
-    P2M_TRY(launch_locate_count<T>(m, particles_of<T>(prob), key, counts, pp.rep, pp.stream));
+    P2M_TRY(launch_locate_count<T>(m, particles_of<T>(prob), key, rank, counts, pp.rep,
+                                   pp.stream));
     P2M_TRY(launch_exclusive_scan(counts, cs, m.nn, sums, pp.stream));
-    P2M_TRY(launch_fill_i32(counts, 0, (size_t)m.nn, pp.stream));
-    P2M_TRY(launch_place(m, key, cs, counts, perm, pp.stream));
+    P2M_TRY(launch_place(m, key, rank, cs, perm, pp.stream));
     P2M_TRY(launch_segment_sort(m, cs, perm, pp.stream));
     return P2M_OK;
 }
@@ -437,7 +438,7 @@ p2m_status plan_batch(const Context* c, const p2m_problem* probs, int nprob, int
     P.amap_b = align_up(sizeof(int32_t) * P.nat);
     P.rmap_b = align_up(sizeof(int32_t) * P.nrt);
     take(P.inst_b + P.lmap_b + P.amap_b + P.rmap_b);
-    P.o_key = take(sizeof(int32_t) * (size_t)np);
+    P.o_key = take(sizeof(int32_t) * 2 * (size_t)np);      // keys, then in-cell ranks
     P.o_counts = take(sizeof(int32_t) * (size_t)nn);
     P.o_cs = take(sizeof(int32_t) * ((size_t)nn + 1));
     P.o_perm = take(sizeof(int32_t) * (size_t)np);
@@ -468,11 +469,12 @@ hipError_t enqueue_batch(const BatchPlan& P, char* ws, p2m_report* reps, const p
     hipError_t e;
     if ((e = launch_report_clear_n(reps, P.nprob, stream)) != hipSuccess) return e;
     if ((e = launch_fill_i32(counts, 0, (size_t)P.nn, stream)) != hipSuccess) return e;
-    if ((e = launch_locate_count_batch(inst, lmap, P.nlb, key, counts, stream)) != hipSuccess)
+    if ((e = launch_locate_count_batch(inst, lmap, P.nlb, key, key + P.np, counts, stream)) !=
+        hipSuccess)
         return e;
     if ((e = launch_exclusive_scan(counts, cs, (int)P.nn, sums, stream)) != hipSuccess) return e;
-    if ((e = launch_fill_i32(counts, 0, (size_t)P.nn, stream)) != hipSuccess) return e;
-    if ((e = launch_place_flat((int)P.np, key, cs, counts, perm, stream)) != hipSuccess) return e;
+    if ((e = launch_place_flat((int)P.np, key, key + P.np, cs, perm, stream)) != hipSuccess)
+        return e;
     if ((e = launch_segment_sort_flat((int)P.nn, cs, perm, stream)) != hipSuccess) return e;
     if ((e = launch_assemble_batch(P.F, inst, amap, P.nat, perm, cs, b, w, coef, stream)) !=
         hipSuccess)

@@ -1,9 +1,11 @@
 // Binning of particles by cell: a stable counting sort.
 //
 //   locate_count : FP64 locate of every particle, cell key, per-cell counts
-//                  (integer atomics: order-independent, so the counts are exact)
+//                  (integer atomics: order-independent, so the counts are exact);
+//                  the value an atomic returns gives each particle a distinct
+//                  slot of its cell (its rank), in an order that depends on timing
 //   exclusive_scan: cell_start = exclusive prefix sum of the counts
-//   place        : every particle takes a free slot of its cell (unordered)
+//   place        : perm[cell_start[key] + rank] = particle (no atomics)
 //   segment_sort : every cell sorts its slots by original index, which makes the
 //                  permutation exactly the stable (cell, original index) order
 //
@@ -59,12 +61,15 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 }
 
 // Locate of particle i of one problem (lanes with i >= np take part in the wave
-// operations only), its key cell0 + cell or -1, and the count of its cell.  One
-// atomic per distinct cell per wave: particles arrive spatially coherent in
-// typical inputs, so this removes most same-address atomic traffic.
+// operations only), its key cell0 + cell or -1, the count of its cell and its
+// rank in the cell (the slot it takes, 0 .. count - 1).  One atomic per distinct
+// cell per wave: particles arrive spatially coherent in typical inputs, so this
+// removes most same-address atomic traffic; a group's lanes take consecutive
+// slots from the value the atomic returns.
 template <typename T>
 __device__ __forceinline__ void locate_count_one(const Mesh& m, const Particles<T>& P, int i,
                                                  int cell0, int32_t* __restrict__ key,
+                                                 int32_t* __restrict__ rank,
                                                  int32_t* __restrict__ counts,
                                                  p2m_report* __restrict__ rep) {
     const bool in = i < m.np;
@@ -78,29 +83,36 @@ __device__ __forceinline__ void locate_count_one(const Mesh& m, const Particles<
     }
     const int k = ok ? cell0 + cx + m.nx * cy : -1;
     const uint64_t grp = match_any(k, ok);
-    if (ok && (threadIdx.x & 63) == __ffsll((unsigned long long)grp) - 1)
-        atomicAdd(&counts[k], (int)__popcll(grp));
+    const int lane = threadIdx.x & 63;
+    const int leader = ok ? __ffsll((unsigned long long)grp) - 1 : lane;
+    int first = 0;
+    if (ok && lane == leader) first = atomicAdd(&counts[k], (int)__popcll(grp));
+    first = __shfl(first, leader, 64);
     if (in && !ok && rep) {
         const uint32_t f = (fin_x && fin_y) ? P2M_FLAG_RANGE : P2M_FLAG_NONFINITE;
         atomicOr(&rep->flags, f);
         atomicAdd(&rep->n_invalid, 1);
     }
-    if (in) key[i] = k;
+    if (in) {
+        key[i] = k;
+        rank[i] = ok ? first + (int)__popcll(grp & lanemask_lt()) : -1;
+    }
 }
 
 template <typename T>
 __global__ void k_locate_count(Mesh m, Particles<T> P, int32_t* __restrict__ key,
-                               int32_t* __restrict__ counts, p2m_report* __restrict__ rep) {
-    locate_count_one<T>(m, P, blockIdx.x * blockDim.x + threadIdx.x, 0, key, counts, rep);
+                               int32_t* __restrict__ rank, int32_t* __restrict__ counts,
+                               p2m_report* __restrict__ rep) {
+    locate_count_one<T>(m, P, blockIdx.x * blockDim.x + threadIdx.x, 0, key, rank, counts, rep);
 }
 
 // batch: block b covers particles [(b - lb) * kBinBlock, ...) of instance lmap[b]
 __global__ void k_locate_count_batch(const BatchInst* __restrict__ inst,
                                      const int32_t* __restrict__ lmap, int32_t* __restrict__ key,
-                                     int32_t* __restrict__ counts) {
+                                     int32_t* __restrict__ rank, int32_t* __restrict__ counts) {
     const BatchInst& I = inst[lmap[blockIdx.x]];
     locate_count_one<float>(I.m, I.P, (blockIdx.x - I.lb) * kBinBlock + threadIdx.x, I.no,
-                            key + I.po, counts, I.rep);
+                            key + I.po, rank + I.po, counts, I.rep);
 }
 
 __global__ void k_report_clear_n(p2m_report* __restrict__ reps, int n) {
@@ -218,58 +230,58 @@ __global__ void k_scan_apply(const int32_t* __restrict__ in, int n,
     }
 }
 
-// Every particle takes a free slot of its cell: one atomic per distinct cell per
-// wave reserves a run of slots, filled in lane (= original index) order.
-__global__ void k_place(int np, const int32_t* __restrict__ key,
-                        const int32_t* __restrict__ cell_start, int32_t* __restrict__ fill,
-                        int32_t* __restrict__ perm) {
+// Every located particle goes to its slot cell_start[key] + rank.  With
+// ncells >= 0, slots [valid, np) (after every valid particle) are set to -1.
+__global__ void k_place(int np, const int32_t* __restrict__ key, const int32_t* __restrict__ rank,
+                        const int32_t* __restrict__ cell_start, int32_t* __restrict__ perm,
+                        int ncells) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = (i < np) ? key[i] : -1;
-    const bool ok = k >= 0;
-    const uint64_t grp = match_any(k, ok);
-    const int leader = ok ? __ffsll((unsigned long long)grp) - 1 : 0;
-    int base = 0;
-    if (ok && (threadIdx.x & 63) == leader) base = atomicAdd(&fill[k], (int)__popcll(grp));
-    base = __shfl(base, leader, 64);
-    if (ok) perm[cell_start[k] + base + (int)__popcll(grp & lanemask_lt())] = i;
-}
-
-__global__ void k_perm_tail(int np, int ncells, const int32_t* __restrict__ cell_start,
-                            int32_t* __restrict__ perm) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= np) return;
-    if (i >= cell_start[ncells]) perm[i] = -1;
+    if (ncells >= 0 && i >= cell_start[ncells]) perm[i] = -1;
+    const int k = key[i];
+    if (k >= 0) perm[cell_start[k] + rank[i]] = i;
 }
 
-// Insertion sort of every cell's slots by original index.  Segments are short (a
-// few particles per cell) and usually already in order: up to 16 entries are
-// checked from registers and nothing is written when they are sorted; longer or
-// unsorted segments are sorted in place (cost grows with the square of a cell's
-// count).
-__global__ void k_segment_sort(int ncells, const int32_t* __restrict__ cell_start,
-                               int32_t* __restrict__ perm) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+// Every cell's slots sorted by original index, one thread per cell.  A cell of at
+// most kSortReg particles is loaded into registers; when out of order each entry
+// goes to the slot given by the number of smaller entries (the indices are
+// distinct), so no step waits on another.  Larger cells are sorted in place by
+// insertion.  Cells that are already in order are not written.
+constexpr int kSortReg = 16;
+
+__global__ __launch_bounds__(kBlock) void k_segment_sort(int ncells,
+                                                         const int32_t* __restrict__ cell_start,
+                                                         int32_t* __restrict__ perm) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncells) return;
     const int s = cell_start[c], e = cell_start[c + 1];
     const int n = e - s;
     if (n <= 1) return;
-    if (n <= 16) {
-        int v[16];
+    if (n <= kSortReg) {
+        int v[kSortReg];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = (j < n) ? perm[s + j] : 0x7fffffff;
+        for (int j = 0; j < kSortReg; ++j) v[j] = (j < n) ? perm[s + j] : 0x7fffffff;
         bool sorted = true;
 #pragma unroll
-        for (int j = 1; j < 16; ++j) sorted = sorted && (j >= n || v[j - 1] < v[j]);
+        for (int j = 1; j < kSortReg; ++j) sorted = sorted && v[j - 1] <= v[j];
         if (sorted) return;
+#pragma unroll
+        for (int j = 0; j < kSortReg; ++j) {
+            int r = 0;
+#pragma unroll
+            for (int q = 0; q < kSortReg; ++q) r += v[q] < v[j] ? 1 : 0;
+            if (j < n) perm[s + r] = v[j];
+        }
+        return;
     }
     for (int i = s + 1; i < e; ++i) {
-        int v = perm[i];
+        const int x = perm[i];
         int j = i - 1;
-        while (j >= s && perm[j] > v) {
+        while (j >= s && perm[j] > x) {
             perm[j + 1] = perm[j];
             --j;
         }
-        perm[j + 1] = v;
+        perm[j + 1] = x;
     }
 }
 
@@ -292,17 +304,17 @@ hipError_t launch_fill_i32(int32_t* p, int32_t value, size_t n, hipStream_t stre
 }
 
 template <typename T>
-hipError_t launch_locate_count(const Mesh& m, Particles<T> P, int32_t* key, int32_t* counts,
-                               p2m_report* rep, hipStream_t stream) {
+hipError_t launch_locate_count(const Mesh& m, Particles<T> P, int32_t* key, int32_t* rank,
+                               int32_t* counts, p2m_report* rep, hipStream_t stream) {
     if (m.np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_locate_count<T>, dim3(grid_for(m.np, kBlock)), dim3(kBlock), 0, stream,
-                       m, P, key, counts, rep);
+                       m, P, key, rank, counts, rep);
     return hipGetLastError();
 }
 template hipError_t launch_locate_count<float>(const Mesh&, Particles<float>, int32_t*, int32_t*,
-                                               p2m_report*, hipStream_t);
+                                               int32_t*, p2m_report*, hipStream_t);
 template hipError_t launch_locate_count<double>(const Mesh&, Particles<double>, int32_t*,
-                                                int32_t*, p2m_report*, hipStream_t);
+                                                int32_t*, int32_t*, p2m_report*, hipStream_t);
 
 size_t scan_workspace_bytes(int n) {
     size_t nb = (size_t)(n + kScanTile - 1) / kScanTile;
@@ -320,13 +332,11 @@ hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, int
     return hipGetLastError();
 }
 
-hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* cell_start,
-                        int32_t* fill, int32_t* perm, hipStream_t stream) {
+hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* rank,
+                        const int32_t* cell_start, int32_t* perm, hipStream_t stream) {
     if (m.np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_place, dim3(grid_for(m.np, kBlock)), dim3(kBlock), 0, stream, m.np, key,
-                       cell_start, fill, perm);
-    hipLaunchKernelGGL(k_perm_tail, dim3(grid_for(m.np, kBlock)), dim3(kBlock), 0, stream, m.np,
-                       m.nn, cell_start, perm);
+                       rank, cell_start, perm, m.nn);
     return hipGetLastError();
 }
 
@@ -338,18 +348,19 @@ hipError_t launch_report_clear_n(p2m_report* reps, int n, hipStream_t stream) {
 }
 
 hipError_t launch_locate_count_batch(const BatchInst* inst, const int32_t* lmap, int nblocks,
-                                     int32_t* key, int32_t* counts, hipStream_t stream) {
+                                     int32_t* key, int32_t* rank, int32_t* counts,
+                                     hipStream_t stream) {
     if (nblocks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_locate_count_batch, dim3(nblocks), dim3(kBinBlock), 0, stream, inst, lmap,
-                       key, counts);
+                       key, rank, counts);
     return hipGetLastError();
 }
 
-hipError_t launch_place_flat(int np, const int32_t* key, const int32_t* cell_start,
-                             int32_t* fill, int32_t* perm, hipStream_t stream) {
+hipError_t launch_place_flat(int np, const int32_t* key, const int32_t* rank,
+                             const int32_t* cell_start, int32_t* perm, hipStream_t stream) {
     if (np == 0) return hipSuccess;
     hipLaunchKernelGGL(k_place, dim3(grid_for(np, kBlock)), dim3(kBlock), 0, stream, np, key,
-                       cell_start, fill, perm);
+                       rank, cell_start, perm, -1);
     return hipGetLastError();
 }
 

@@ -285,6 +285,9 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                 }
                 x64[o] = x0;
                 sD[o] = 0.f;
+                // the start's boundary values for the first residual (the first
+                // fold, which would add d = 0, is skipped)
+                if (bmask & (1u << j)) std8<kCoherent>(rs_f8(a.pubX, f), kk, x0);
             }
             if (orphan && I.rep) {
                 atomicAdd(&I.rep->n_orphan, 1);
@@ -321,7 +324,8 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
 
     for (int outer = 0; alive; ++outer) {
         // ---- fold the correction into x64, publish the boundary x64 ------------
-        for (int ti = 0; ti < nown; ++ti) {
+        // (outer 0: the start vector, published by the P phase)
+        for (int ti = 0; ti < nown && outer > 0; ++ti) {
             set_tile(ti);
 #pragma unroll
             for (int f = 0; f < F; ++f) {

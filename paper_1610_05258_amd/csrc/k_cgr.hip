@@ -162,6 +162,9 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
             }
             a.x64[o] = x0;
             a.xout[o] = 0.f;  // xout holds the FP32 correction d during the solve
+            // the start's boundary values for the first residual (the first fold,
+            // which would add d = 0, is skipped)
+            if (bmask & (1u << j)) std8<kCoherent>(rs_pubX(f), k, x0);
         }
         if (orphan && a.rep) {
             atomicAdd(&a.rep->n_orphan, 1);
@@ -219,9 +222,10 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
 
     for (int outer = 0; alive; ++outer) {
         // ---- fold the correction into x64, publish the boundary x64 ------------
+        // (outer 0: the start vector, published by the P phase)
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-            if (s_done[f]) continue;
+            if (s_done[f] || outer == 0) continue;
             const rsrc_t rx = rs_x64(f), rpx = rs_pubX(f);
 #pragma unroll
             for (int j = 0; j < RNPT; ++j) {

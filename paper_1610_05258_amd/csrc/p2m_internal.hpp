@@ -111,13 +111,15 @@ hipError_t launch_fill_i32(int32_t* p, int32_t value, size_t n, hipStream_t stre
 
 // binning
 template <typename T>
-hipError_t launch_locate_count(const Mesh& m, Particles<T> P, int32_t* key, int32_t* counts,
-                               p2m_report* rep, hipStream_t stream);
+// key [np] (cell or -1), rank [np] (slot within the cell, -1 when not located),
+// counts [nn] (zeroed by the caller, incremented)
+hipError_t launch_locate_count(const Mesh& m, Particles<T> P, int32_t* key, int32_t* rank,
+                               int32_t* counts, p2m_report* rep, hipStream_t stream);
 size_t scan_workspace_bytes(int n);
 hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, int32_t* block_sums,
                                  hipStream_t stream);
-hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* cell_start,
-                        int32_t* fill, int32_t* perm, hipStream_t stream);
+hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* rank,
+                        const int32_t* cell_start, int32_t* perm, hipStream_t stream);
 hipError_t launch_segment_sort(const Mesh& m, const int32_t* cell_start, int32_t* perm,
                                hipStream_t stream);
 
@@ -183,11 +185,12 @@ hipError_t launch_report_clear_n(p2m_report* reps, int n, hipStream_t stream);
 // locate + count of every particle of the batch; block b belongs to instance
 // lmap[b]; keys are batch cell numbers (or -1)
 hipError_t launch_locate_count_batch(const BatchInst* inst, const int32_t* lmap, int nblocks,
-                                     int32_t* key, int32_t* counts, hipStream_t stream);
+                                     int32_t* key, int32_t* rank, int32_t* counts,
+                                     hipStream_t stream);
 // place / segment sort over the whole batch (keys and cell_start in batch numbering,
 // perm receives batch particle numbers); no tail is written
-hipError_t launch_place_flat(int np, const int32_t* key, const int32_t* cell_start,
-                             int32_t* fill, int32_t* perm, hipStream_t stream);
+hipError_t launch_place_flat(int np, const int32_t* key, const int32_t* rank,
+                             const int32_t* cell_start, int32_t* perm, hipStream_t stream);
 hipError_t launch_segment_sort_flat(int ncells, const int32_t* cell_start, int32_t* perm,
                                     hipStream_t stream);
 // scatter of every instance: tile t belongs to instance amap[t]; b, w, coef hold
