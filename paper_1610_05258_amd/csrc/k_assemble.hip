@@ -51,6 +51,7 @@ __device__ __forceinline__ void assemble2d_tile(const Mesh& m, const Particles<T
     constexpr int NT = (HC + 63) / 64 * 64;     // threads: one per cell
     constexpr int NQ = Q_B + 4 * F;
     constexpr int NS = 5 + F;                   // staged values per slot
+    constexpr int SPT = (CH + NT - 1) / NT;     // staged slots per thread and chunk
     constexpr size_t SLOT_B = (size_t)NS * CH * sizeof(T);
     constexpr size_t PART_B = (size_t)NQ * HC * sizeof(T);
     __shared__ __align__(16) unsigned char smem[SLOT_B > PART_B ? SLOT_B : PART_B];
@@ -106,25 +107,50 @@ __device__ __forceinline__ void assemble2d_tile(const Mesh& m, const Particles<T
         const int a0 = max(my_lo, cb), a1 = min(my_hi, ce);
         for (int sl = a0; sl < a1; ++sl) cmap[sl - cb] = (short)t;
         __syncthreads();
-        // stage: slot-parallel loads and FP64 locate
-        for (int sl = cb + t; sl < ce; sl += NT) {
-            const int hc = cmap[sl - cb];
-            const int i = perm[c_seg[hc] + (sl - c_off[hc])] - po;
-            int cx, cy;
-            double xi, eta;
-            bool fx, fy;
-            locate_axis((double)P.x[i], m.nx, m.inv_hx, cx, xi, fx);
-            locate_axis((double)P.y[i], m.ny, m.inv_hy, cy, eta, fy);
-            T c00, c10, c11, c01;
-            corner_weights<T>(xi, eta, c00, c10, c11, c01);
-            const int o = sl - cb;
-            st[0 * CH + o] = c00;
-            st[1 * CH + o] = c10;
-            st[2 * CH + o] = c11;
-            st[3 * CH + o] = c01;
-            st[4 * CH + o] = P.vol ? P.vol[i] : v_uni;
+        // stage: slot-parallel loads and FP64 locate.  A thread's SPT slots are
+        // loaded together (particle numbers, then every gather) so the chunk costs
+        // two memory round trips, not two per slot.
+        {
+            int pi[SPT];
 #pragma unroll
-            for (int f = 0; f < F; ++f) st[(5 + f) * CH + o] = values[(size_t)f * m.np + i];
+            for (int u = 0; u < SPT; ++u) {
+                const int sl = cb + t + u * NT;
+                pi[u] = -1;
+                if (sl < ce) {
+                    const int hc = cmap[sl - cb];
+                    pi[u] = perm[c_seg[hc] + (sl - c_off[hc])] - po;
+                }
+            }
+            T px[SPT], py[SPT], pv[SPT], pa[SPT][F];
+#pragma unroll
+            for (int u = 0; u < SPT; ++u) {
+                if (pi[u] < 0) continue;
+                const int i = pi[u];
+                px[u] = P.x[i];
+                py[u] = P.y[i];
+                pv[u] = P.vol ? P.vol[i] : v_uni;
+#pragma unroll
+                for (int f = 0; f < F; ++f) pa[u][f] = values[(size_t)f * m.np + i];
+            }
+#pragma unroll
+            for (int u = 0; u < SPT; ++u) {
+                if (pi[u] < 0) continue;
+                int cx, cy;
+                double xi, eta;
+                bool fx, fy;
+                locate_axis((double)px[u], m.nx, m.inv_hx, cx, xi, fx);
+                locate_axis((double)py[u], m.ny, m.inv_hy, cy, eta, fy);
+                T c00, c10, c11, c01;
+                corner_weights<T>(xi, eta, c00, c10, c11, c01);
+                const int o = t + u * NT;
+                st[0 * CH + o] = c00;
+                st[1 * CH + o] = c10;
+                st[2 * CH + o] = c11;
+                st[3 * CH + o] = c01;
+                st[4 * CH + o] = pv[u];
+#pragma unroll
+                for (int f = 0; f < F; ++f) st[(5 + f) * CH + o] = pa[u][f];
+            }
         }
         __syncthreads();
         // accumulate: one thread per cell, its slots in order

@@ -131,47 +131,8 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         if (lc == 0 || lr == 0 || lc == txa - 1 || lr == tya - 1) bmask |= 1u << j;
     }
 
-    // ---- P: coefficients into LDS, orphan regularisation, FP64 start vector ----
-#pragma unroll
-    for (int j = 0; j < RNPT; ++j) {
-        if (!(amask & (1u << j))) continue;
-        const int k = gk(j);
-        const int q = qcj(j);
-        const float wk = a.w[k];
-        const bool orphan = !(wk > 0.f);
-        const float dk = a.coef[k];
-        if (orphan) a.coef[k] = 1.f;
-        cf[q] = orphan ? 1.f : dk;
-        dv[qj(j)] = jacobi_inv(dk, wk);
-        cf[CN + q] = a.coef[(size_t)nn + k];
-        cf[2 * CN + q] = a.coef[(size_t)2 * nn + k];
-        cf[3 * CN + q] = a.coef[(size_t)3 * nn + k];
-#pragma unroll
-        for (int f = 0; f < F; ++f) {
-            const size_t o = (size_t)f * nn + k;
-            double x0;
-            if (orphan) {
-                a.b[o] = 0.f;
-                x0 = 0.0;
-            } else if (a.start == P2M_START_FLIP) {
-                x0 = (double)a.b[o] / (double)wk;
-            } else if (a.start == P2M_START_ZERO) {
-                x0 = 0.0;
-            } else {
-                x0 = (double)a.xout[o];
-            }
-            a.x64[o] = x0;
-            a.xout[o] = 0.f;  // xout holds the FP32 correction d during the solve
-            // the start's boundary values for the first residual (the first fold,
-            // which would add d = 0, is skipped)
-            if (bmask & (1u << j)) std8<kCoherent>(rs_pubX(f), k, x0);
-        }
-        if (orphan && a.rep) {
-            atomicAdd(&a.rep->n_orphan, 1);
-            atomicOr(&a.rep->flags, (uint32_t)P2M_FLAG_ORPHAN);
-        }
-    }
     // left column / bottom row: only their E, N, NE are used, never modified here
+    // (these loads go first: they do not depend on the P phase below)
     for (int h = threadIdx.x; h < txa + 1 + tya; h += RBS) {
         int lc, lr;
         if (h < txa + 1) { lr = -1; lc = h - 1; } else { lc = -1; lr = h - (txa + 1); }
@@ -187,6 +148,65 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         if (!halo_slot(h, txa, tya, lc, lr)) continue;
         const int k = gidx(m, i0, j0, lc, lr);
         dv[lidx(lc, lr)] = jacobi_inv(a.coef[k], a.w[k]);
+    }
+    // ---- P: coefficients into LDS, orphan regularisation, FP64 start vector ----
+    // Every load is issued before the first store: the memory counter covers loads
+    // and stores in issue order, so a load issued after a store would also wait for
+    // the store.
+    {
+        float pw[RNPT], pc[4][RNPT], px[F][RNPT];
+#pragma unroll
+        for (int j = 0; j < RNPT; ++j) {
+            if (!(amask & (1u << j))) continue;
+            const int k = gk(j);
+            pw[j] = a.w[k];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) pc[c][j] = a.coef[(size_t)c * nn + k];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const size_t o = (size_t)f * nn + k;
+                px[f][j] = a.start == P2M_START_USER ? a.xout[o] : a.b[o];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < RNPT; ++j) {
+            if (!(amask & (1u << j))) continue;
+            const int k = gk(j);
+            const int q = qcj(j);
+            const float wk = pw[j];
+            const bool orphan = !(wk > 0.f);
+            const float dk = pc[0][j];
+            if (orphan) a.coef[k] = 1.f;
+            cf[q] = orphan ? 1.f : dk;
+            dv[qj(j)] = jacobi_inv(dk, wk);
+            cf[CN + q] = pc[1][j];
+            cf[2 * CN + q] = pc[2][j];
+            cf[3 * CN + q] = pc[3][j];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const size_t o = (size_t)f * nn + k;
+                double x0;
+                if (orphan) {
+                    a.b[o] = 0.f;
+                    x0 = 0.0;
+                } else if (a.start == P2M_START_FLIP) {
+                    x0 = (double)px[f][j] / (double)wk;
+                } else if (a.start == P2M_START_ZERO) {
+                    x0 = 0.0;
+                } else {
+                    x0 = (double)px[f][j];
+                }
+                a.x64[o] = x0;
+                a.xout[o] = 0.f;  // xout holds the FP32 correction d during the solve
+                // the start's boundary values for the first residual (the first
+                // fold, which would add d = 0, is skipped)
+                if (bmask & (1u << j)) std8<kCoherent>(rs_pubX(f), k, x0);
+            }
+            if (orphan && a.rep) {
+                atomicAdd(&a.rep->n_orphan, 1);
+                atomicOr(&a.rep->flags, (uint32_t)P2M_FLAG_ORPHAN);
+            }
+        }
     }
 #pragma unroll
     for (int f = 0; f < F; ++f)
@@ -321,20 +341,14 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         // ---- CG start: u = r / diag, w = M u, delta = (w, u), gamma = (r, u);
         //      p = s = d = 0 -----------------------------------------------------
         uint32_t imask = inner_mask();
+        // own residuals and the ring's are loaded before d = 0 is stored
 #pragma unroll
         for (int f = 0; f < F; ++f) {
             if (!(imask & (1u << f))) continue;
-            float* L = lf + (size_t)f * LH * LW;
             const rsrc_t rd = rs_d(f);
 #pragma unroll
-            for (int j = 0; j < RNPT; ++j) {
-                vr[f][j] = 0.f;
-                if (amask & (1u << j)) {
-                    vr[f][j] = ldf<kPlain>(rd, gk(j));
-                    stf<kPlain>(rd, gk(j), 0.f);
-                    L[qj(j)] = __fmul_rn(vr[f][j], dv[qj(j)]);
-                }
-            }
+            for (int j = 0; j < RNPT; ++j)
+                if (amask & (1u << j)) vr[f][j] = ldf<kPlain>(rd, gk(j));
         }
         for (int h = threadIdx.x; h < nhalo; h += RBS) {
             int lc, lr;
@@ -347,6 +361,18 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
 #pragma unroll
             for (int f = 0; f < F; ++f)
                 if (imask & (1u << f)) lf[(size_t)f * LH * LW + lidx(lc, lr)] = __fmul_rn(hv[f], dh);
+        }
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            if (!(imask & (1u << f))) continue;
+            float* L = lf + (size_t)f * LH * LW;
+            const rsrc_t rd = rs_d(f);
+#pragma unroll
+            for (int j = 0; j < RNPT; ++j) {
+                if (!(amask & (1u << j))) continue;
+                stf<kPlain>(rd, gk(j), 0.f);
+                L[qj(j)] = __fmul_rn(vr[f][j], dv[qj(j)]);
+            }
         }
         __syncthreads();
         ex ^= 1;
@@ -504,14 +530,18 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     if (!alive && threadIdx.x == 0) s_flags |= P2M_FLAG_BREAKDOWN | P2M_FLAG_NOT_CONVERGED;
     __syncthreads();
     // result: the FP64 solution rounded to FP32 (0 for fields with b == 0)
+    {
+        float res[F][RNPT];
 #pragma unroll
-    for (int f = 0; f < F; ++f) {
-        const rsrc_t rx = rs_x64(f), rd = rs_d(f);
+        for (int f = 0; f < F; ++f)
 #pragma unroll
-        for (int j = 0; j < RNPT; ++j) {
-            if (!(amask & (1u << j))) continue;
-            stf<kPlain>(rd, gk(j), s_zero[f] ? 0.f : (float)ldd<kPlain>(rx, gk(j)));
-        }
+            for (int j = 0; j < RNPT; ++j)
+                if (amask & (1u << j)) res[f][j] = (float)ldd<kPlain>(rs_x64(f), gk(j));
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+#pragma unroll
+            for (int j = 0; j < RNPT; ++j)
+                if (amask & (1u << j)) stf<kPlain>(rs_d(f), gk(j), s_zero[f] ? 0.f : res[f][j]);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.rep) {
         for (int f = 0; f < F; ++f) {
