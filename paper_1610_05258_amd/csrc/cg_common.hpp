@@ -95,21 +95,39 @@ __device__ __forceinline__ void block_sum_to(double (&v)[NV], double* lds /* [RB
 }
 
 // Sum of the partials part[bk * kNV + jv] over bk < nblocks for every jv < nv,
-// written to tot[jv] (device-coherent).  The fixed order that every solve uses:
-// value jv is summed by the 32 lanes of segment jv, lane l over blocks l, l+32,
-// ... in increasing order, then a fixed shuffle tree over the 32 lanes.  Called
-// by all threads of one workgroup.
-__device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int nv,
-                                                double* tot) {
+// handed to out(jv, sum).  The fixed order that every solve uses: value jv is
+// summed by the 32 lanes of segment jv, lane l over blocks l, l+32, ... in
+// increasing order, then a fixed shuffle tree over the 32 lanes.  Called by all
+// threads of one workgroup.  Loads go out kPartBatch at a time before they are
+// added (in the same order), so a lane waits once per batch, not once per block.
+template <typename Out>
+__device__ __forceinline__ void sum_partials(const double* part, int nblocks, int nv, Out out) {
+    constexpr int kPartBatch = 8;
     const int seg = threadIdx.x >> 5, l = threadIdx.x & 31;
     for (int jv = seg; jv < kNV; jv += RBS / 32) {
         double acc = 0.0;
         if (jv < nv)
-            for (int bk = l; bk < nblocks; bk += 32) acc += ld_c(&part[(size_t)bk * kNV + jv]);
+            for (int b0 = l; b0 < nblocks; b0 += 32 * kPartBatch) {
+                double v[kPartBatch];
+#pragma unroll
+                for (int u = 0; u < kPartBatch; ++u) {
+                    const int bk = b0 + 32 * u;
+                    v[u] = bk < nblocks ? ld_c(&part[(size_t)bk * kNV + jv]) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kPartBatch; ++u)
+                    if (b0 + 32 * u < nblocks) acc += v[u];
+            }
 #pragma unroll
         for (int d = 16; d >= 1; d >>= 1) acc += __shfl_down(acc, d, 32);
-        if (jv < nv && l == 0) st_c(&tot[jv], acc);
+        if (jv < nv && l == 0) out(jv, acc);
     }
+}
+
+// The same sum written to tot[jv] (device-coherent).
+__device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int nv,
+                                                double* tot) {
+    sum_partials(part, nblocks, nv, [&](int jv, double v) { st_c(&tot[jv], v); });
 }
 
 // Arrival at the two-level barrier tree (thread 0 only): the group counter of
@@ -147,30 +165,30 @@ __device__ __forceinline__ void tree_release(const RSync& s, unsigned epoch) {
     __hip_atomic_store(s.rel, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Grid barrier that also sums the workgroups' partials vals[0..nv) (FP64).  On
-// return vals[0..nv) holds the totals in every workgroup.  Returns false after
-// an abort.
+// Grid barrier that also sums the workgroups' partials vals[0..nv) (FP64).  Every
+// workgroup stores its partials, arrives, waits for the release and then sums all
+// partials itself in the fixed order of sum_partials, so every workgroup holds
+// the same totals without a second exchange.  The partials are double-buffered
+// by epoch parity: epoch e + 2 overwrites epoch e's buffer only after every
+// workgroup has passed epoch e + 1, i.e. finished reading it.  On return
+// vals[0..nv) holds the totals.  Returns false after an abort.
 __device__ bool sync_reduce(const RSync& s, unsigned epoch, double* vals, int nv, int nblocks) {
-    __shared__ int s_role;
     __shared__ int s_ok;
-    double* part = s.part + (size_t)(epoch & 1) * nblocks * kNV;
-    double* tot = s.tot + (size_t)(epoch & 1) * kNV;
-    if (threadIdx.x < nv) st_c(&part[(size_t)blockIdx.x * kNV + threadIdx.x], vals[threadIdx.x]);
+    const double* part = s.part + (size_t)(epoch & 1) * nblocks * kNV;
+    if (threadIdx.x < nv)
+        st_c(&s.part[(size_t)(epoch & 1) * nblocks * kNV + (size_t)blockIdx.x * kNV + threadIdx.x],
+             vals[threadIdx.x]);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) s_role = tree_arrive(s, epoch, nblocks) ? 1 : 0;
-    __syncthreads();
-    if (s_role) {
-        reduce_partials(part, nblocks, nv, tot);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (threadIdx.x == 0) tree_release(s, epoch);
+    if (threadIdx.x == 0) {
+        if (tree_arrive(s, epoch, nblocks)) tree_release(s, epoch);
+        s_ok = tree_wait(s, epoch) ? 1 : 0;
     }
-    if (threadIdx.x == 0) s_ok = tree_wait(s, epoch) ? 1 : 0;
     __syncthreads();
-    if (threadIdx.x < nv) vals[threadIdx.x] = ld_c(&tot[threadIdx.x]);
+    const bool ok = s_ok != 0;
+    if (ok && nv > 0) sum_partials(part, nblocks, nv, [&](int jv, double v) { vals[jv] = v; });
     __syncthreads();
-    return s_ok != 0;
+    return ok;
 }
 
 // ---------------------------------------------------------------------------

@@ -65,45 +65,88 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // rank in the cell (the slot it takes, 0 .. count - 1).  One atomic per distinct
 // cell per wave: particles arrive spatially coherent in typical inputs, so this
 // removes most same-address atomic traffic; a group's lanes take consecutive
-// slots from the value the atomic returns.
+// slots from the value the atomic returns.  Split in two so that a thread can
+// have several atomics in flight: locate_count_issue locates and issues the
+// atomic, locate_count_finish waits for its value and writes key and rank.
+struct LocState {
+    int k;           // key or -1
+    int first;       // value returned to the group leader (the group's first slot)
+    uint64_t grp;    // lanes of this lane's group
+    bool in;         // i < np
+};
+
+// (px, py: the particle's coordinates, loaded by the caller; py unused in 1D)
 template <typename T>
-__device__ __forceinline__ void locate_count_one(const Mesh& m, const Particles<T>& P, int i,
-                                                 int cell0, int32_t* __restrict__ key,
-                                                 int32_t* __restrict__ rank,
-                                                 int32_t* __restrict__ counts,
-                                                 p2m_report* __restrict__ rep) {
-    const bool in = i < m.np;
+__device__ __forceinline__ LocState locate_count_issue(const Mesh& m, T px, T py, int i,
+                                                       int cell0, int32_t* __restrict__ counts,
+                                                       p2m_report* __restrict__ rep) {
+    LocState st;
+    st.in = i < m.np;
     bool fin_x = true, fin_y = true;
     int cx = 0, cy = 0;
     double xi, eta;
     bool ok = false;
-    if (in) {
-        ok = locate_axis((double)P.x[i], m.nx, m.inv_hx, cx, xi, fin_x);
-        if (m.dim == 2) ok = locate_axis((double)P.y[i], m.ny, m.inv_hy, cy, eta, fin_y) && ok;
+    if (st.in) {
+        ok = locate_axis((double)px, m.nx, m.inv_hx, cx, xi, fin_x);
+        if (m.dim == 2) ok = locate_axis((double)py, m.ny, m.inv_hy, cy, eta, fin_y) && ok;
     }
-    const int k = ok ? cell0 + cx + m.nx * cy : -1;
-    const uint64_t grp = match_any(k, ok);
+    st.k = ok ? cell0 + cx + m.nx * cy : -1;
+    st.grp = match_any(st.k, ok);
     const int lane = threadIdx.x & 63;
-    const int leader = ok ? __ffsll((unsigned long long)grp) - 1 : lane;
-    int first = 0;
-    if (ok && lane == leader) first = atomicAdd(&counts[k], (int)__popcll(grp));
-    first = __shfl(first, leader, 64);
-    if (in && !ok && rep) {
+    st.first = 0;
+    if (ok && lane == __ffsll((unsigned long long)st.grp) - 1)
+        st.first = atomicAdd(&counts[st.k], (int)__popcll(st.grp));
+    if (st.in && !ok && rep) {
         const uint32_t f = (fin_x && fin_y) ? P2M_FLAG_RANGE : P2M_FLAG_NONFINITE;
         atomicOr(&rep->flags, f);
         atomicAdd(&rep->n_invalid, 1);
     }
-    if (in) {
-        key[i] = k;
-        rank[i] = ok ? first + (int)__popcll(grp & lanemask_lt()) : -1;
+    return st;
+}
+
+__device__ __forceinline__ void locate_count_finish(const LocState& st, int i,
+                                                    int32_t* __restrict__ key,
+                                                    int32_t* __restrict__ rank) {
+    const int lane = threadIdx.x & 63;
+    const bool ok = st.k >= 0;
+    const int leader = ok ? __ffsll((unsigned long long)st.grp) - 1 : lane;
+    const int first = __shfl(st.first, leader, 64);
+    if (st.in) {
+        key[i] = st.k;
+        rank[i] = ok ? first + (int)__popcll(st.grp & lanemask_lt()) : -1;
     }
 }
 
+// kLocItems particles per thread: item u of block b covers particles
+// [(b * kLocItems + u) * kBlock, ... + kBlock), so each wave step is 64
+// consecutive particles.  Every coordinate is loaded before the first atomic
+// and all items' atomics are issued before any is awaited (one memory counter
+// covers loads and atomics in issue order).
+constexpr int kLocItems = 4;
+
 template <typename T>
-__global__ void k_locate_count(Mesh m, Particles<T> P, int32_t* __restrict__ key,
-                               int32_t* __restrict__ rank, int32_t* __restrict__ counts,
-                               p2m_report* __restrict__ rep) {
-    locate_count_one<T>(m, P, blockIdx.x * blockDim.x + threadIdx.x, 0, key, rank, counts, rep);
+__global__ __launch_bounds__(kBlock) void k_locate_count(Mesh m, Particles<T> P,
+                                                         int32_t* __restrict__ key,
+                                                         int32_t* __restrict__ rank,
+                                                         int32_t* __restrict__ counts,
+                                                         p2m_report* __restrict__ rep) {
+    const int base = blockIdx.x * (kBlock * kLocItems) + threadIdx.x;
+    T px[kLocItems], py[kLocItems];
+#pragma unroll
+    for (int u = 0; u < kLocItems; ++u) {
+        const int i = base + u * kBlock;
+        px[u] = py[u] = (T)0;
+        if (i < m.np) {
+            px[u] = P.x[i];
+            if (m.dim == 2) py[u] = P.y[i];
+        }
+    }
+    LocState st[kLocItems];
+#pragma unroll
+    for (int u = 0; u < kLocItems; ++u)
+        st[u] = locate_count_issue<T>(m, px[u], py[u], base + u * kBlock, 0, counts, rep);
+#pragma unroll
+    for (int u = 0; u < kLocItems; ++u) locate_count_finish(st[u], base + u * kBlock, key, rank);
 }
 
 // batch: block b covers particles [(b - lb) * kBinBlock, ...) of instance lmap[b]
@@ -111,8 +154,14 @@ __global__ void k_locate_count_batch(const BatchInst* __restrict__ inst,
                                      const int32_t* __restrict__ lmap, int32_t* __restrict__ key,
                                      int32_t* __restrict__ rank, int32_t* __restrict__ counts) {
     const BatchInst& I = inst[lmap[blockIdx.x]];
-    locate_count_one<float>(I.m, I.P, (blockIdx.x - I.lb) * kBinBlock + threadIdx.x, I.no,
-                            key + I.po, rank + I.po, counts, I.rep);
+    const int i = (blockIdx.x - I.lb) * kBinBlock + threadIdx.x;
+    float px = 0.f, py = 0.f;
+    if (i < I.m.np) {
+        px = I.P.x[i];
+        if (I.m.dim == 2) py = I.P.y[i];
+    }
+    const LocState st = locate_count_issue<float>(I.m, px, py, i, I.no, counts, I.rep);
+    locate_count_finish(st, i, key + I.po, rank + I.po);
 }
 
 __global__ void k_report_clear_n(p2m_report* __restrict__ reps, int n) {
@@ -307,8 +356,8 @@ template <typename T>
 hipError_t launch_locate_count(const Mesh& m, Particles<T> P, int32_t* key, int32_t* rank,
                                int32_t* counts, p2m_report* rep, hipStream_t stream) {
     if (m.np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_locate_count<T>, dim3(grid_for(m.np, kBlock)), dim3(kBlock), 0, stream,
-                       m, P, key, rank, counts, rep);
+    hipLaunchKernelGGL(k_locate_count<T>, dim3(grid_for(m.np, kBlock * kLocItems)), dim3(kBlock),
+                       0, stream, m, P, key, rank, counts, rep);
     return hipGetLastError();
 }
 template hipError_t launch_locate_count<float>(const Mesh&, Particles<float>, int32_t*, int32_t*,
