@@ -240,6 +240,24 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         }
     };
 
+    // the boundary's (r, w, s) of every inner-active field into the exchange
+    // planes of parity ex
+    auto publish_rws = [&](uint32_t imask) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            if (!(imask & (1u << f))) continue;
+            const rsrc_t rr = rs_pub(a.pubR, ex, f), rw = rs_pub(a.pubW, ex, f),
+                         rs = rs_pub(a.pubS, ex, f);
+#pragma unroll
+            for (int j = 0; j < RNPT; ++j) {
+                if (!(bmask & (1u << j))) continue;
+                stf<kCoherent>(rr, gk(j), vr[f][j]);
+                stf<kCoherent>(rw, gk(j), vw[f][j]);
+                stf<kCoherent>(rs, gk(j), vs[f][j]);
+            }
+        }
+    };
+
     for (int outer = 0; alive; ++outer) {
         // ---- fold the correction into x64, publish the boundary x64 ------------
         // (outer 0: the start vector, published by the P phase)
@@ -384,8 +402,6 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 if (!(imask & (1u << f))) continue;
-                const rsrc_t rr = rs_pub(a.pubR, ex, f), rw = rs_pub(a.pubW, ex, f),
-                             rs = rs_pub(a.pubS, ex, f);
 #pragma unroll
                 for (int j = 0; j < RNPT; ++j) {
                     vs[f][j] = 0.f;
@@ -395,15 +411,11 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     const float uj = lf[(size_t)f * LH * LW + qj(j)];
                     pd[f] = dot_acc(pd[f], vw[f][j], uj);
                     pd[F + f] = dot_acc(pd[F + f], vr[f][j], uj);
-                    if (bmask & (1u << j)) {
-                        stf<kCoherent>(rr, gk(j), vr[f][j]);
-                        stf<kCoherent>(rw, gk(j), vw[f][j]);
-                        stf<kCoherent>(rs, gk(j), 0.f);
-                    }
                 }
             }
             __syncthreads();
             block_sum_to<2 * F>(pd, red_lds, vals);
+            publish_rws(imask);
         }
         alive = sync_reduce(a.sy, ++epoch, vals, 2 * F, nblocks);
         if (!alive) break;
@@ -476,8 +488,6 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     if (!(imask & (1u << f))) continue;
-                    const rsrc_t rr = rs_pub(a.pubR, ex, f), rw = rs_pub(a.pubW, ex, f),
-                                 rs = rs_pub(a.pubS, ex, f);
 #pragma unroll
                     for (int j = 0; j < RNPT; ++j) {
                         if (!(amask & (1u << j))) continue;
@@ -485,15 +495,13 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                         pg[f] = dot_acc(pg[f], vr[f][j], uj);
                         pg[F + f] = dot_acc(pg[F + f], vw[f][j], uj);
                         pg[2 * F + f] = dot_acc(pg[2 * F + f], vr[f][j], vr[f][j]);
-                        if (bmask & (1u << j)) {
-                            stf<kCoherent>(rr, gk(j), vr[f][j]);
-                            stf<kCoherent>(rw, gk(j), vw[f][j]);
-                            stf<kCoherent>(rs, gk(j), vs[f][j]);
-                        }
                     }
                 }
                 __syncthreads();
                 block_sum_to<3 * F>(pg, red_lds, vals);
+                // the boundary's (r, w, s) go out last: a load issued after a store
+                // waits for it, and the barrier below waits for the stores anyway
+                publish_rws(imask);
             }
             alive = sync_reduce(a.sy, ++epoch, vals, 3 * F, nblocks);
             if (!alive) break;
