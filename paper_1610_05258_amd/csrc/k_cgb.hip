@@ -322,6 +322,35 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
         }
     };
 
+    // the current tile's CG state (p, d, s, r, w) of every inner-active field into
+    // the owner-only arrays, and its boundary (r, w, s) into the exchange planes
+    // of parity ex ^ 1 (r only with_r: at the CG start it is already stored)
+    auto store_state = [&](uint32_t imask, bool with_r) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            if (!(imask & (1u << f))) continue;
+            const rsrc_t rr = rs_pub(a.pubR, ex ^ 1, f), rw = rs_pub(a.pubW, ex ^ 1, f),
+                         rs = rs_pub(a.pubS, ex ^ 1, f);
+            const rsrc_t sP = rs_f4(a.sP, f), sD = rs_f4(a.sD, f), sS = rs_f4(a.sS, f),
+                         sR = rs_f4(a.sR, f), sW = rs_f4(a.sW, f);
+#pragma unroll
+            for (int j = 0; j < RNPT; ++j) {
+                if (!(amask & (1u << j))) continue;
+                const int kk = gk(j);
+                stf<kPlain>(sP, kk, vp[f][j]);
+                stf<kPlain>(sD, kk, vd[f][j]);
+                stf<kPlain>(sS, kk, vs[f][j]);
+                if (with_r) stf<kPlain>(sR, kk, vr[f][j]);
+                stf<kPlain>(sW, kk, vw[f][j]);
+                if (bmask & (1u << j)) {
+                    stf<kCoherent>(rr, kk, vr[f][j]);
+                    stf<kCoherent>(rw, kk, vw[f][j]);
+                    stf<kCoherent>(rs, kk, vs[f][j]);
+                }
+            }
+        }
+    };
+
     for (int outer = 0; alive; ++outer) {
         // ---- fold the correction into x64, publish the boundary x64 ------------
         // (outer 0: the start vector, published by the P phase)
@@ -470,31 +499,19 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 if (!(imask & (1u << f))) continue;
-                const rsrc_t rr = rs_pub(a.pubR, ex ^ 1, f), rw = rs_pub(a.pubW, ex ^ 1, f),
-                             rs = rs_pub(a.pubS, ex ^ 1, f);
-                const rsrc_t sP = rs_f4(a.sP, f), sD = rs_f4(a.sD, f), sS = rs_f4(a.sS, f),
-                             sW = rs_f4(a.sW, f);
 #pragma unroll
                 for (int j = 0; j < RNPT; ++j) {
+                    vp[f][j] = vd[f][j] = vs[f][j] = 0.f;
                     if (!(amask & (1u << j))) continue;
-                    const int kk = gk(j);
                     const float uj = lf[(size_t)f * LH * LW + qj(j)];
                     pd[f] = dot_acc(pd[f], vw[f][j], uj);
                     pd[F + f] = dot_acc(pd[F + f], vr[f][j], uj);
-                    stf<kPlain>(sW, kk, vw[f][j]);
-                    stf<kPlain>(sP, kk, 0.f);
-                    stf<kPlain>(sD, kk, 0.f);
-                    stf<kPlain>(sS, kk, 0.f);
-                    if (bmask & (1u << j)) {
-                        stf<kCoherent>(rr, kk, vr[f][j]);
-                        stf<kCoherent>(rw, kk, vw[f][j]);
-                        stf<kCoherent>(rs, kk, 0.f);
-                    }
                 }
             }
             __syncthreads();
             block_sum_to<2 * F>(pd, red_lds, tv);
             store_partials(ti, epoch + 1, 2 * F);
+            store_state(imask, false);
         }
         ex ^= 1;
         alive = sync_batch(++epoch, 2 * F);
@@ -611,19 +628,11 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                     if (!(imask & (1u << f))) continue;
                     const float al = af[f], be = bf[f];
                     float* L = lf + (size_t)f * LH * LW;
-                    const rsrc_t sP = rs_f4(a.sP, f), sD = rs_f4(a.sD, f), sS = rs_f4(a.sS, f),
-                                 sR = rs_f4(a.sR, f);
 #pragma unroll
                     for (int j = 0; j < RNPT; ++j) {
                         if (!(amask & (1u << j))) continue;
-                        const float un = pcg_update(al, be, jacobi_inv(cD[j], 1.f), vp[f][j],
-                                                    vd[f][j], vs[f][j], vr[f][j], vw[f][j]);
-                        const int kk = gk(j);
-                        stf<kPlain>(sP, kk, vp[f][j]);
-                        stf<kPlain>(sD, kk, vd[f][j]);
-                        stf<kPlain>(sS, kk, vs[f][j]);
-                        stf<kPlain>(sR, kk, vr[f][j]);
-                        L[qj(j)] = un;
+                        L[qj(j)] = pcg_update(al, be, jacobi_inv(cD[j], 1.f), vp[f][j], vd[f][j],
+                                              vs[f][j], vr[f][j], vw[f][j]);
                     }
                 }
                 __syncthreads();
@@ -634,28 +643,21 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     if (!(imask & (1u << f))) continue;
-                    const rsrc_t rr = rs_pub(a.pubR, ex ^ 1, f), rw = rs_pub(a.pubW, ex ^ 1, f),
-                                 rs = rs_pub(a.pubS, ex ^ 1, f);
-                    const rsrc_t sW = rs_f4(a.sW, f);
 #pragma unroll
                     for (int j = 0; j < RNPT; ++j) {
                         if (!(amask & (1u << j))) continue;
-                        const int kk = gk(j);
                         const float uj = lf[(size_t)f * LH * LW + qj(j)];
                         pg[f] = dot_acc(pg[f], vr[f][j], uj);
                         pg[F + f] = dot_acc(pg[F + f], vw[f][j], uj);
                         pg[2 * F + f] = dot_acc(pg[2 * F + f], vr[f][j], vr[f][j]);
-                        stf<kPlain>(sW, kk, vw[f][j]);
-                        if (bmask & (1u << j)) {
-                            stf<kCoherent>(rr, kk, vr[f][j]);
-                            stf<kCoherent>(rw, kk, vw[f][j]);
-                            stf<kCoherent>(rs, kk, vs[f][j]);
-                        }
                     }
                 }
                 __syncthreads();
                 block_sum_to<3 * F>(pg, red_lds, tv);
                 store_partials(ti, epoch + 1, 3 * F);
+                // the tile's state and its published boundary go out last: a load
+                // issued after a store waits for it
+                store_state(imask, true);
             }
             ex ^= 1;
             alive = sync_batch(++epoch, 3 * F);
