@@ -306,7 +306,7 @@ def main():
                               nodes=nn, particles=int(vals.shape[1]), fields=F, tol=args.tol),
                   plan=None if plan is None else dict(solver={1: "streaming (k_cg)", 2: "resident (k_cgr)",
                                                               3: "tile-streaming (k_cgb)"}[plan.solver],
-                                                      groups=plan.groups, scatter_tile=plan.scatter_tile or 16,
+                                                      groups=plan.groups, scatter_tile=plan.scatter_tile or 15,
                                                       inner_rtol=(plan.inner_rtol if plan.inner_rtol >= 0
                                                                   else opts.inner_rtol),
                                                       tuned_ms=plan.time_ms),

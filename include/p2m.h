@@ -337,7 +337,7 @@ p2m_status p2m_learned_train_step(void* ctx, float* params, float* adam_m, float
 typedef struct {
     int32_t solver;        /* P2M_SOLVER_* */
     int32_t groups;        /* workgroups of the tile-streaming solve (0: one per compute unit) */
-    int32_t scatter_tile;  /* 2D scatter node tile: 0 = default (16 x 16 where it fits), 8 = 8 x 8 */
+    int32_t scatter_tile;  /* 2D scatter node tile: 0 = default (15 x 15 where it fits), 8 = 8 x 8 */
     int32_t reserved;      /* 0 */
     double inner_rtol;     /* replaces opts->inner_rtol when >= 0 (the inner / outer schedule;
                               the FP64 stopping test on tol is unchanged); < 0: keep opts */

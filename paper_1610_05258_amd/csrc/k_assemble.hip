@@ -355,7 +355,7 @@ hipError_t assemble2d_ts(const Mesh& m, Particles<T> P, const T* values, const i
     return hipGetLastError();
 }
 
-// tile: 0 = the default node tile (16 x 16 where its parts fit 64 KB of LDS, else
+// tile: 0 = the default node tile (15 x 15 where its parts fit 64 KB of LDS, else
 // 8 x 8), 8 = 8 x 8
 template <typename T, int F>
 hipError_t assemble_f(const Mesh& m, Particles<T> P, const T* values, const int32_t* perm,
@@ -367,7 +367,7 @@ hipError_t assemble_f(const Mesh& m, Particles<T> P, const T* values, const int3
                            perm, cs, b, w, coef);
         return hipGetLastError();
     }
-    // tile 16x16 unless the per-cell parts of its 17x17 cells exceed 64 KB; chunk
+    // tile 15x15 unless the per-cell parts of its 16x16 cells exceed 64 KB; chunk
     // of staged slots sized to keep the staging area within 32 KB
     static_assert(Q_B == 13, "assemble_tile assumes 13 + 4F parts per cell");
     constexpr int TS = assemble_tile(F, (int)sizeof(T));

@@ -37,10 +37,12 @@ constexpr int kBinBlock = 256;       // particles per block of the locate / plac
 constexpr int kSolveTileX = 128;     // node tile of the tile solvers (one workgroup per tile)
 constexpr int kSolveTileY = 32;
 
-// Node tile of the 2D scatter for F fields of element size tsize: 16 x 16 unless
-// the per-cell parts of its 17 x 17 cells exceed 64 KB of LDS, then 8 x 8.
+// Node tile of the 2D scatter for F fields of element size tsize: 15 x 15 (its
+// 16 x 16 cells, one thread each, make a workgroup of exactly four waves, one per
+// SIMD, so four workgroups share a compute unit whatever their wave placement)
+// unless the per-cell parts of those cells exceed 64 KB of LDS, then 8 x 8.
 constexpr int assemble_tile(int F, int tsize) {
-    return (size_t)(13 + 4 * F) * 17 * 17 * tsize <= 65536 ? 16 : 8;
+    return (size_t)(13 + 4 * F) * 16 * 16 * tsize <= 65536 ? 15 : 8;
 }
 
 // One instance of a batch of independent 2D FP32 problems (an entry of the
@@ -87,17 +89,13 @@ __device__ __forceinline__ bool locate_axis(double x, int n, double inv, int& c,
 template <typename T>
 __device__ __forceinline__ void corner_weights(double xi, double eta, T& c00, T& c10, T& c11,
                                                T& c01) {
-    if (xi >= eta) {
-        c00 = (T)__dsub_rn(1.0, xi);
-        c10 = (T)__dsub_rn(xi, eta);
-        c11 = (T)eta;
-        c01 = (T)0;
-    } else {
-        c00 = (T)__dsub_rn(1.0, eta);
-        c11 = (T)xi;
-        c01 = (T)__dsub_rn(eta, xi);
-        c10 = (T)0;
-    }
+    // selects rather than branches: the branchy form was lowered through a local
+    // array in scratch memory
+    const bool lower = xi >= eta;  // lower-right triangle of the "/" split
+    c00 = (T)__dsub_rn(1.0, lower ? xi : eta);
+    c10 = lower ? (T)__dsub_rn(xi, eta) : (T)0;
+    c11 = (T)(lower ? eta : xi);
+    c01 = lower ? (T)0 : (T)__dsub_rn(eta, xi);
 }
 
 // ---------------------------------------------------------------------------
