@@ -291,47 +291,95 @@ __global__ void k_place(int np, const int32_t* __restrict__ key, const int32_t* 
     if (k >= 0) perm[cell_start[k] + rank[i]] = i;
 }
 
-// Every cell's slots sorted by original index, one thread per cell.  A cell of at
-// most kSortReg particles is loaded into registers; when out of order each entry
-// goes to the slot given by the number of smaller entries (the indices are
-// distinct), so no step waits on another.  Larger cells are sorted in place by
-// insertion.  Cells that are already in order are not written.
+// Every cell's slots sorted by original index, one thread per cell.  A cell of
+// at most kSortReg particles is held in registers and, when out of order, sorted
+// by a fixed network (8 or 16 wide).  Larger cells are sorted in place by
+// insertion.  A workgroup's kBlock consecutive cells own one contiguous range of
+// perm: when it fits kSortStage entries it is loaded into LDS and written back
+// with coalesced accesses (only if some cell was out of order); otherwise every
+// thread works on global memory directly.
 constexpr int kSortReg = 16;
+constexpr int kSortStage = 4096;   // perm entries staged per workgroup (16 KB)
+
+// Batcher's odd-even merge sort network on N (a power of two) registers; every
+// bound is a compile-time constant, so the network unrolls to N log^2 N / 4
+// compare-exchanges.
+template <int N>
+__device__ __forceinline__ void sort_network(int (&v)[N]) {
+#pragma unroll
+    for (int p = 1; p < N; p <<= 1)
+#pragma unroll
+        for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+            for (int j = k % p; j + k < N; j += 2 * k)
+#pragma unroll
+                for (int i = 0; i < k; ++i)
+                    if (i + j + k < N && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                        const int a = v[i + j], b = v[i + j + k];
+                        v[i + j] = min(a, b);
+                        v[i + j + k] = max(a, b);
+                    }
+}
+
+// Sorts a segment of n <= N entries (padded with the largest int) in registers;
+// writes it back only when it was out of order.  Returns whether it wrote.
+template <int N>
+__device__ __forceinline__ bool sort_small(int32_t* __restrict__ seg, int n) {
+    int v[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = (j < n) ? seg[j] : 0x7fffffff;
+    bool sorted = true;
+#pragma unroll
+    for (int j = 1; j < N; ++j) sorted = sorted && v[j - 1] <= v[j];
+    if (sorted) return false;
+    sort_network<N>(v);
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if (j < n) seg[j] = v[j];
+    return true;
+}
+
+__device__ __forceinline__ bool rank_sort_small(int32_t* __restrict__ seg, int n) {
+    return n <= 8 ? sort_small<8>(seg, n) : sort_small<kSortReg>(seg, n);
+}
+
+__device__ __forceinline__ bool insertion_sort(int32_t* __restrict__ seg, int n) {
+    bool moved = false;
+    for (int i = 1; i < n; ++i) {
+        const int x = seg[i];
+        int j = i - 1;
+        while (j >= 0 && seg[j] > x) {
+            seg[j + 1] = seg[j];
+            --j;
+            moved = true;
+        }
+        seg[j + 1] = x;
+    }
+    return moved;
+}
 
 __global__ __launch_bounds__(kBlock) void k_segment_sort(int ncells,
                                                          const int32_t* __restrict__ cell_start,
                                                          int32_t* __restrict__ perm) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncells) return;
-    const int s = cell_start[c], e = cell_start[c + 1];
+    __shared__ int32_t st[kSortStage];
+    const int c0 = blockIdx.x * kBlock;
+    const int c1 = min(c0 + kBlock, ncells);
+    const int c = c0 + (int)threadIdx.x;
+    const int lo = cell_start[c0], hi = cell_start[c1];
+    const int s = c < c1 ? cell_start[c] : lo, e = c < c1 ? cell_start[c + 1] : lo;
     const int n = e - s;
-    if (n <= 1) return;
-    if (n <= kSortReg) {
-        int v[kSortReg];
-#pragma unroll
-        for (int j = 0; j < kSortReg; ++j) v[j] = (j < n) ? perm[s + j] : 0x7fffffff;
-        bool sorted = true;
-#pragma unroll
-        for (int j = 1; j < kSortReg; ++j) sorted = sorted && v[j - 1] <= v[j];
-        if (sorted) return;
-#pragma unroll
-        for (int j = 0; j < kSortReg; ++j) {
-            int r = 0;
-#pragma unroll
-            for (int q = 0; q < kSortReg; ++q) r += v[q] < v[j] ? 1 : 0;
-            if (j < n) perm[s + r] = v[j];
-        }
+    if (hi - lo > kSortStage) {  // uniform over the workgroup
+        if (n > kSortReg) insertion_sort(perm + s, n);
+        else if (n > 1) rank_sort_small(perm + s, n);
         return;
     }
-    for (int i = s + 1; i < e; ++i) {
-        const int x = perm[i];
-        int j = i - 1;
-        while (j >= s && perm[j] > x) {
-            perm[j + 1] = perm[j];
-            --j;
-        }
-        perm[j + 1] = x;
-    }
+    for (int t = lo + (int)threadIdx.x; t < hi; t += kBlock) st[t - lo] = perm[t];
+    __syncthreads();
+    bool moved = false;
+    if (n > kSortReg) moved = insertion_sort(st + (s - lo), n);
+    else if (n > 1) moved = rank_sort_small(st + (s - lo), n);
+    if (!__syncthreads_or(moved)) return;
+    for (int t = lo + (int)threadIdx.x; t < hi; t += kBlock) perm[t] = st[t - lo];
 }
 
 inline int grid_for(size_t n, int block) { return (int)((n + block - 1) / block); }
