@@ -186,6 +186,34 @@ def batched_leg(B, ctx, check, reps=10, tol=1e-9):
     return res
 
 
+def m2p_leg(B, ctx, d, nodal, stream, calls=20):
+    """M2P interpolation of the solved fields back to the particles (one p2m_interpolate
+    call: report clear + k_gather2d), event-timed over `calls` calls.  Algorithmic bytes:
+    positions (8 B) and F outputs (4F B) per particle, the nodal arrays (4F B per node)
+    read once."""
+    import torch
+    F, nn = nodal.shape
+    npart = d.n_particles
+    g_out = torch.empty((F, npart), dtype=torch.float32, device="cuda")
+    g_rep = ctx.new_report()
+    for _ in range(3):
+        B.p2m_interpolate(ctx, d, nodal, out=g_out, rep=g_rep)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(calls):
+        B.p2m_interpolate(ctx, d, nodal, out=g_out, rep=g_rep)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / calls
+    nbytes = npart * (8 + 4 * F) + nn * 4 * F
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    log(f"bench: M2P gather {ms * 1e3:.1f} us per call ({gbs:.0f} GB/s algorithmic)")
+    return dict(ms=ms, particles_per_s=npart / (ms * 1e-3), kernel="k_gather2d<float>",
+                bytes_per_call=nbytes, achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=gbs / HBM_PEAK_GBS)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -313,6 +341,7 @@ def main():
                   phases=dict(assemble_ms=asm_ms, solve_ms=cg_ms, cg_iters=r.iters.tolist(),
                               refines=r.refines.tolist(), rel_residual=r.rel_residual.tolist(),
                               flags=r.flags))
+    result["m2p"] = m2p_leg(B, ctx, d, out, stream)
     k_ref = None
     if not args.no_cpu:
         log("bench: FP64 oracle on the full input (accuracy and K_ref)")

@@ -92,9 +92,9 @@ Layout make_layout(const Mesh& m, int F, size_t tsize, int cg_blocks) {
     const size_t cm = (m.dim == 2) ? 4 : 2;
     L.key = take(2 * np * sizeof(int32_t));      // cell keys, then in-cell ranks
     L.counts = take(nn * sizeof(int32_t));
+    L.scan = take(scan_workspace_bytes((int)nn));   // right after counts: one fill clears both
     L.cell_start = take((nn + 1) * sizeof(int32_t));
     L.perm = take(np * sizeof(int32_t));
-    L.scan = take(scan_workspace_bytes((int)nn));
     L.b = take((size_t)F * nn * tsize);
     L.w = take(nn * tsize);
     L.coef = take(cm * nn * tsize);
@@ -235,11 +235,12 @@ p2m_status run_bin(const Prepared& pp, const p2m_problem* prob, int32_t* perm, i
     int32_t* key = (int32_t*)(pp.ws + pp.L.key);
     int32_t* counts = (int32_t*)(pp.ws + pp.L.counts);
     int32_t* rank = key + m.np;
-    int32_t* sums = (int32_t*)(pp.ws + pp.L.scan);
-    P2M_TRY(launch_fill_i32(counts, 0, (size_t)m.nn, pp.stream));
+    void* scan_ws = pp.ws + pp.L.scan;
+    const size_t clear = (pp.L.scan + scan_workspace_bytes(m.nn) - pp.L.counts) / sizeof(int32_t);
+    P2M_TRY(launch_fill_i32(counts, 0, clear, pp.stream));   // counts and the scan's words
     P2M_TRY(launch_locate_count<T>(m, particles_of<T>(prob), key, rank, counts, pp.rep,
                                    pp.stream));
-    P2M_TRY(launch_exclusive_scan(counts, cs, m.nn, sums, pp.stream));
+    P2M_TRY(launch_exclusive_scan(counts, cs, m.nn, scan_ws, pp.stream));
     P2M_TRY(launch_place(m, key, rank, cs, perm, pp.stream));
     P2M_TRY(launch_segment_sort(m, cs, perm, pp.stream));
     return P2M_OK;
@@ -440,9 +441,9 @@ p2m_status plan_batch(const Context* c, const p2m_problem* probs, int nprob, int
     take(P.inst_b + P.lmap_b + P.amap_b + P.rmap_b);
     P.o_key = take(sizeof(int32_t) * 2 * (size_t)np);      // keys, then in-cell ranks
     P.o_counts = take(sizeof(int32_t) * (size_t)nn);
+    P.o_scan = take(scan_workspace_bytes((int)nn));   // right after counts: one fill clears both
     P.o_cs = take(sizeof(int32_t) * ((size_t)nn + 1));
     P.o_perm = take(sizeof(int32_t) * (size_t)np);
-    P.o_scan = take(scan_workspace_bytes((int)nn));
     P.o_b = take(sizeof(float) * (size_t)F * nn);
     P.o_w = take(sizeof(float) * (size_t)nn);
     P.o_coef = take(sizeof(float) * (size_t)4 * nn);
@@ -462,17 +463,18 @@ hipError_t enqueue_batch(const BatchPlan& P, char* ws, p2m_report* reps, const p
     int32_t* counts = (int32_t*)(ws + P.o_counts);
     int32_t* cs = (int32_t*)(ws + P.o_cs);
     int32_t* perm = (int32_t*)(ws + P.o_perm);
-    int32_t* sums = (int32_t*)(ws + P.o_scan);
+    void* scan_ws = ws + P.o_scan;
+    const size_t clear = (P.o_scan + scan_workspace_bytes((int)P.nn) - P.o_counts) / sizeof(int32_t);
     float* b = (float*)(ws + P.o_b);
     float* w = (float*)(ws + P.o_w);
     float* coef = (float*)(ws + P.o_coef);
     hipError_t e;
     if ((e = launch_report_clear_n(reps, P.nprob, stream)) != hipSuccess) return e;
-    if ((e = launch_fill_i32(counts, 0, (size_t)P.nn, stream)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(counts, 0, clear, stream)) != hipSuccess) return e;
     if ((e = launch_locate_count_batch(inst, lmap, P.nlb, key, key + P.np, counts, stream)) !=
         hipSuccess)
         return e;
-    if ((e = launch_exclusive_scan(counts, cs, (int)P.nn, sums, stream)) != hipSuccess) return e;
+    if ((e = launch_exclusive_scan(counts, cs, (int)P.nn, scan_ws, stream)) != hipSuccess) return e;
     if ((e = launch_place_flat((int)P.np, key, key + P.np, cs, perm, stream)) != hipSuccess)
         return e;
     if ((e = launch_segment_sort_flat((int)P.nn, cs, perm, stream)) != hipSuccess) return e;

@@ -219,50 +219,25 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int& total) {
     return off + inc - v;
 }
 
-__global__ void k_scan_block_sums(const int32_t* __restrict__ in, int n,
-                                  int32_t* __restrict__ block_sums) {
-    int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    int s = 0;
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        int idx = base + j;
-        if (idx < n) s += in[idx];
-    }
-    int total;
-    (void)block_exclusive_scan(s, total);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
-}
+// Single-pass exclusive scan with decoupled look-back.  Workgroups take tile
+// numbers in launch order from a counter, so every predecessor of a tile has
+// started; a tile publishes its own sum (AGG), looks back over its predecessors'
+// words (64 at a time, one per lane of wave 0) until it meets an inclusive prefix
+// (PRE), and publishes its own inclusive prefix.  A word holds the flag in bits
+// 62-63 and the value (< 2^31) in bits 0-31; the words and the counter start at
+// zero (the caller clears them with the counts).
+constexpr unsigned long long kScanAgg = 1ull << 62, kScanPre = 2ull << 62;
+constexpr long kScanSpinMax = 1L << 26;
 
-// One block scans the nb block sums in place (exclusive) and writes the grand
-// total to out[n].
-__global__ void k_scan_single(int32_t* __restrict__ sums, int nb, int32_t* __restrict__ out,
-                              int n) {
-    int carry = 0;
-    for (int base = 0; base < nb; base += kScanTile) {
-        int idx0 = base + threadIdx.x * kScanItems;
-        int vals[kScanItems];
-        int s = 0;
-#pragma unroll
-        for (int j = 0; j < kScanItems; ++j) {
-            vals[j] = (idx0 + j < nb) ? sums[idx0 + j] : 0;
-            s += vals[j];
-        }
-        int total;
-        int ex = block_exclusive_scan(s, total) + carry;
-#pragma unroll
-        for (int j = 0; j < kScanItems; ++j) {
-            if (idx0 + j < nb) sums[idx0 + j] = ex;
-            ex += vals[j];
-        }
-        carry += total;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[n] = carry;
-}
-
-__global__ void k_scan_apply(const int32_t* __restrict__ in, int n,
-                             const int32_t* __restrict__ block_off, int32_t* __restrict__ out) {
-    int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+__global__ __launch_bounds__(kBlock) void k_scan_lookback(const int32_t* __restrict__ in, int n,
+                                                          int32_t* __restrict__ out,
+                                                          unsigned long long* status,
+                                                          unsigned* tile_ctr) {
+    __shared__ int s_tile, s_excl;
+    if (threadIdx.x == 0) s_tile = (int)atomicAdd(tile_ctr, 1u);
+    __syncthreads();
+    const int tile = s_tile;
+    const int base = tile * kScanTile + threadIdx.x * kScanItems;
     int vals[kScanItems];
     int s = 0;
 #pragma unroll
@@ -271,12 +246,51 @@ __global__ void k_scan_apply(const int32_t* __restrict__ in, int n,
         s += vals[j];
     }
     int total;
-    int ex = block_exclusive_scan(s, total) + block_off[blockIdx.x];
+    int ex = block_exclusive_scan(s, total);
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        if (lane == 0)
+            __hip_atomic_store(&status[tile], (tile == 0 ? kScanPre : kScanAgg) | (unsigned)total,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int excl = 0;
+        int end = tile;  // predecessors [end - 64, end) are examined in one step
+        long spins = 0;
+        while (end > 0) {
+            const int idx = end - 1 - lane;
+            const unsigned long long w =
+                idx >= 0 ? __hip_atomic_load(&status[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                         : kScanPre;
+            const unsigned flag = (unsigned)(w >> 62);
+            const uint64_t pre = __ballot(flag == 2u), inv = __ballot(flag == 0u);
+            const int first = pre ? __ffsll((unsigned long long)pre) - 1 : 63;
+            const uint64_t upto = first >= 63 ? ~0ull : ((1ull << (first + 1)) - 1);
+            if (inv & upto) {  // a word this step needs is not published yet
+                if (++spins > kScanSpinMax) break;
+                continue;
+            }
+            int v = lane <= first ? (int)(w & 0xffffffffull) : 0;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+            excl += v;
+            if (pre) break;
+            end -= 64;
+        }
+        if (lane == 0) {
+            if (tile > 0)
+                __hip_atomic_store(&status[tile], kScanPre | (unsigned)(excl + total),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_excl = excl;
+        }
+    }
+    __syncthreads();
+    ex += s_excl;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
         if (base + j < n) out[base + j] = ex;
         ex += vals[j];
     }
+    if (tile == (n + kScanTile - 1) / kScanTile - 1 && threadIdx.x == kBlock - 1)
+        out[n] = s_excl + total;  // grand total
 }
 
 // Every located particle goes to its slot cell_start[key] + rank.  With
@@ -413,19 +427,23 @@ template hipError_t launch_locate_count<float>(const Mesh&, Particles<float>, in
 template hipError_t launch_locate_count<double>(const Mesh&, Particles<double>, int32_t*,
                                                 int32_t*, int32_t*, p2m_report*, hipStream_t);
 
+// status words (one per tile) and the tile counter; zero before each scan
 size_t scan_workspace_bytes(int n) {
-    size_t nb = (size_t)(n + kScanTile - 1) / kScanTile;
-    return nb * sizeof(int32_t);
+    const size_t nb = (size_t)(n + kScanTile - 1) / kScanTile;
+    return (nb + 1) * sizeof(unsigned long long);
 }
 
-hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, int32_t* block_sums,
+hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, void* scan_ws,
                                  hipStream_t stream) {
-    int nb = (n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_block_sums, dim3(nb), dim3(kBlock), 0, stream, counts, n,
-                       block_sums);
-    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kBlock), 0, stream, block_sums, nb, out, n);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, stream, counts, n, block_sums,
-                       out);
+    const int nb = (n + kScanTile - 1) / kScanTile;
+    unsigned long long* status = (unsigned long long*)scan_ws;
+    unsigned* ctr = (unsigned*)(status + nb);
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, out, 0, (size_t)1);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_scan_lookback, dim3(nb), dim3(kBlock), 0, stream, counts, n, out, status,
+                       ctr);
     return hipGetLastError();
 }
 

@@ -15,39 +15,76 @@ namespace p2m {
 
 namespace {
 
+constexpr int kGatherGroup = 4;
+
 __device__ __forceinline__ void flag_invalid(p2m_report* rep, bool finite) {
     if (rep) atomicOr(&rep->flags, finite ? (uint32_t)P2M_FLAG_RANGE : (uint32_t)P2M_FLAG_NONFINITE);
 }
 
+// kGatherItems particles per thread (item u of block b: particles
+// [(b * kGatherItems + u) * blockDim, ...), coalesced per item): every position
+// is loaded, then every nodal value, then the outputs are stored, so a thread
+// waits for two memory round trips in all.
+constexpr int kGatherItems = 4;
+
 template <typename T>
 __global__ void k_gather2d(Mesh m, Particles<T> P, const T* __restrict__ nodal, int F,
                            T* __restrict__ out, p2m_report* __restrict__ rep) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m.np) return;
-    int cx, cy;
-    double xi, eta;
-    bool fx, fy;
-    bool ok = locate_axis((double)P.x[i], m.nx, m.inv_hx, cx, xi, fx);
-    ok = locate_axis((double)P.y[i], m.ny, m.inv_hy, cy, eta, fy) && ok;
-    if (!ok) {
-        for (int f = 0; f < F; ++f) out[(size_t)f * m.np + i] = (T)NAN;
-        flag_invalid(rep, fx && fy);
-        return;
+    const int base = blockIdx.x * blockDim.x * kGatherItems + threadIdx.x;
+    T px[kGatherItems], py[kGatherItems];
+#pragma unroll
+    for (int u = 0; u < kGatherItems; ++u) {
+        const int i = base + u * (int)blockDim.x;
+        px[u] = py[u] = (T)0;
+        if (i < m.np) {
+            px[u] = P.x[i];
+            py[u] = P.y[i];
+        }
     }
-    const int i1 = (cx + 1 == m.nx) ? 0 : cx + 1;
-    const int j1 = (cy + 1 == m.ny) ? 0 : cy + 1;
-    const int n0 = cx + m.nx * cy;
-    const bool lower = xi >= eta;
-    const int n1 = lower ? i1 + m.nx * cy : i1 + m.nx * j1;
-    const int n2 = lower ? i1 + m.nx * j1 : cx + m.nx * j1;
-    T c00, c10, c11, c01;
-    corner_weights<T>(xi, eta, c00, c10, c11, c01);
-    const T l0 = c00;
-    const T l1 = lower ? c10 : c11;
-    const T l2 = lower ? c11 : c01;
+    int n0[kGatherItems], n1[kGatherItems], n2[kGatherItems];
+    T l0[kGatherItems], l1[kGatherItems], l2[kGatherItems];
+    bool ok[kGatherItems];
+#pragma unroll
+    for (int u = 0; u < kGatherItems; ++u) {
+        const int i = base + u * (int)blockDim.x;
+        int cx = 0, cy = 0;
+        double xi = 0.0, eta = 0.0;
+        bool fx = true, fy = true;
+        ok[u] = false;
+        if (i < m.np) {
+            ok[u] = locate_axis((double)px[u], m.nx, m.inv_hx, cx, xi, fx);
+            ok[u] = locate_axis((double)py[u], m.ny, m.inv_hy, cy, eta, fy) && ok[u];
+            if (!ok[u]) flag_invalid(rep, fx && fy);
+        }
+        if (!ok[u]) cx = cy = 0, xi = eta = 0.0;
+        const int i1 = (cx + 1 == m.nx) ? 0 : cx + 1;
+        const int j1 = (cy + 1 == m.ny) ? 0 : cy + 1;
+        const bool lower = xi >= eta;
+        n0[u] = cx + m.nx * cy;
+        n1[u] = lower ? i1 + m.nx * cy : i1 + m.nx * j1;
+        n2[u] = lower ? i1 + m.nx * j1 : cx + m.nx * j1;
+        T c00, c10, c11, c01;
+        corner_weights<T>(xi, eta, c00, c10, c11, c01);
+        l0[u] = c00;
+        l1[u] = lower ? c10 : c11;
+        l2[u] = lower ? c11 : c01;
+    }
     for (int f = 0; f < F; ++f) {
         const T* a = nodal + (size_t)f * m.nn;
-        out[(size_t)f * m.np + i] = l0 * a[n0] + l1 * a[n1] + l2 * a[n2];
+        T v[kGatherItems][3];
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) {
+            v[u][0] = a[n0[u]];
+            v[u][1] = a[n1[u]];
+            v[u][2] = a[n2[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) {
+            const int i = base + u * (int)blockDim.x;
+            if (i < m.np)
+                out[(size_t)f * m.np + i] =
+                    ok[u] ? l0[u] * v[u][0] + l1[u] * v[u][1] + l2[u] * v[u][2] : (T)NAN;
+        }
     }
 }
 
@@ -67,9 +104,20 @@ __global__ void k_gather1d(Mesh m, Particles<T> P, const T* __restrict__ nodal, 
     }
     const int n1 = (cx + 1 == m.nx) ? 0 : cx + 1;
     const T l0 = (T)__dsub_rn(1.0, xi), l1 = (T)xi;
-    for (int f = 0; f < F; ++f) {
-        const T* a = nodal + (size_t)f * m.nn;
-        out[(size_t)f * m.np + i] = l0 * a[cx] + l1 * a[n1];
+    for (int f0 = 0; f0 < F; f0 += kGatherGroup) {
+        T v[kGatherGroup][2];
+#pragma unroll
+        for (int g = 0; g < kGatherGroup; ++g) {
+            if (f0 + g >= F) break;
+            const T* a = nodal + (size_t)(f0 + g) * m.nn;
+            v[g][0] = a[cx];
+            v[g][1] = a[n1];
+        }
+#pragma unroll
+        for (int g = 0; g < kGatherGroup; ++g) {
+            if (f0 + g >= F) break;
+            out[(size_t)(f0 + g) * m.np + i] = l0 * v[g][0] + l1 * v[g][1];
+        }
     }
 }
 
@@ -185,11 +233,14 @@ hipError_t launch_gather(const Mesh& m, Particles<T> P, const T* nodal, int F, T
                          p2m_report* rep, hipStream_t stream) {
     if (m.np == 0) return hipSuccess;
     const int block = 256;
-    const int grid = (m.np + block - 1) / block;
-    if (m.dim == 2)
+    if (m.dim == 2) {
+        const int grid = (int)(((size_t)m.np + (size_t)block * kGatherItems - 1) /
+                               ((size_t)block * kGatherItems));
         hipLaunchKernelGGL(k_gather2d<T>, dim3(grid), dim3(block), 0, stream, m, P, nodal, F, out, rep);
-    else
+    } else {
+        const int grid = (m.np + block - 1) / block;
         hipLaunchKernelGGL(k_gather1d<T>, dim3(grid), dim3(block), 0, stream, m, P, nodal, F, out, rep);
+    }
     return hipGetLastError();
 }
 template hipError_t launch_gather<float>(const Mesh&, Particles<float>, const float*, int, float*,

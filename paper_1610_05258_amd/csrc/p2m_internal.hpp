@@ -113,8 +113,10 @@ template <typename T>
 // counts [nn] (zeroed by the caller, incremented)
 hipError_t launch_locate_count(const Mesh& m, Particles<T> P, int32_t* key, int32_t* rank,
                                int32_t* counts, p2m_report* rep, hipStream_t stream);
+// single-pass scan: scan_ws (scan_workspace_bytes(n)) must be zero on entry;
+// out[0..n] receives the exclusive prefix sums and the total
 size_t scan_workspace_bytes(int n);
-hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, int32_t* block_sums,
+hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, void* scan_ws,
                                  hipStream_t stream);
 hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* rank,
                         const int32_t* cell_start, int32_t* perm, hipStream_t stream);
