@@ -186,9 +186,10 @@ def batched_leg(B, ctx, check, reps=10, tol=1e-9):
     return res
 
 
-def m2p_leg(B, ctx, d, nodal, stream, calls=20):
+def m2p_leg(B, ctx, d, nodal, stream, ws, calls=20):
     """M2P interpolation of the solved fields back to the particles (one p2m_interpolate
-    call: report clear + k_gather2d), event-timed over `calls` calls.  Algorithmic bytes:
+    call with a workspace: report clear, node-major copy of the nodal values and
+    k_gather2d_nm), event-timed over `calls` calls.  Algorithmic bytes:
     positions (8 B) and F outputs (4F B) per particle, the nodal arrays (4F B per node)
     read once."""
     import torch
@@ -197,19 +198,19 @@ def m2p_leg(B, ctx, d, nodal, stream, calls=20):
     g_out = torch.empty((F, npart), dtype=torch.float32, device="cuda")
     g_rep = ctx.new_report()
     for _ in range(3):
-        B.p2m_interpolate(ctx, d, nodal, out=g_out, rep=g_rep)
+        B.p2m_interpolate(ctx, d, nodal, out=g_out, rep=g_rep, ws=ws)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(calls):
-        B.p2m_interpolate(ctx, d, nodal, out=g_out, rep=g_rep)
+        B.p2m_interpolate(ctx, d, nodal, out=g_out, rep=g_rep, ws=ws)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / calls
     nbytes = npart * (8 + 4 * F) + nn * 4 * F
     gbs = nbytes / (ms * 1e-3) / 1e9
     log(f"bench: M2P gather {ms * 1e3:.1f} us per call ({gbs:.0f} GB/s algorithmic)")
-    return dict(ms=ms, particles_per_s=npart / (ms * 1e-3), kernel="k_gather2d<float>",
+    return dict(ms=ms, particles_per_s=npart / (ms * 1e-3), kernel=f"k_gather2d_nm<float, {F}>",
                 bytes_per_call=nbytes, achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=gbs / HBM_PEAK_GBS)
 
@@ -304,12 +305,17 @@ def main():
     for _ in range(args.warmup):
         one_step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    # HIP events on every EV_EVERY-th timed step give the phase split and the solve
+    # kernel's duration; an event record adds a queue gap of a few microseconds, so
+    # the other steps run without them
+    EV_EVERY = 4
+    evs = {k: [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+           for k in range(0, args.steps, EV_EVERY)}
     log(f"bench: timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        one_step(evs[k])
+        one_step(evs.get(k))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     if args.calibrate_copy > 0:
@@ -320,8 +326,8 @@ def main():
         torch.cuda.synchronize()
         log(f"bench: copied {args.calibrate_copy} MiB three times (counter calibration)")
         del src, dst
-    asm_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    cg_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    asm_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs.values()]))
+    cg_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs.values()]))
     r = B.read_report(rep_s, F)
     log(f"bench: {wall / args.steps * 1e3:.3f} ms/step (assemble {asm_ms:.3f} ms, solve {cg_ms:.3f} ms), "
         f"iters {r.iters.tolist()}, refines {r.refines.tolist()}, relres {r.rel_residual.tolist()}")
@@ -341,7 +347,7 @@ def main():
                   phases=dict(assemble_ms=asm_ms, solve_ms=cg_ms, cg_iters=r.iters.tolist(),
                               refines=r.refines.tolist(), rel_residual=r.rel_residual.tolist(),
                               flags=r.flags))
-    result["m2p"] = m2p_leg(B, ctx, d, out, stream)
+    result["m2p"] = m2p_leg(B, ctx, d, out, stream, ws)
     k_ref = None
     if not args.no_cpu:
         log("bench: FP64 oracle on the full input (accuracy and K_ref)")

@@ -182,7 +182,11 @@ p2m_status p2m_assign(void* ctx, const p2m_problem* prob, p2m_assign_kind kind, 
 
 /* Mesh->particle interpolation (Sec. 2.2 eq. (10), the M2P of delta, FLIP and
  * mass-delta in Table 1): values_out[f*np + mu] = sum_i nodal[f*nn + i] psi_i(r_mu),
- * in the caller's particle order.  Needs no workspace (ws may be NULL). */
+ * in the caller's particle order.  Needs no workspace (ws may be NULL); with a
+ * workspace of at least nfields * nnodes elements (256-byte aligned device
+ * memory, contents overwritten), 2D problems with 2 to 4 fields first copy the
+ * nodal values node-major into it and read each triangle corner's fields with
+ * one load.  The values are the same either way. */
 p2m_status p2m_interpolate(void* ctx, const p2m_problem* prob, const void* nodal, int32_t nfields,
                            void* values_out, p2m_report* rep, void* ws, size_t ws_bytes, void* stream);
 

@@ -337,8 +337,9 @@ def p2m_assign(ctx: Context, prob: Particles, kind: int, values, stream=None, ws
     return out, rep
 
 
-def p2m_interpolate(ctx: Context, prob: Particles, nodal, stream=None, rep=None, out=None):
-    """Mesh->particle interpolation: (values [F, np], report tensor)."""
+def p2m_interpolate(ctx: Context, prob: Particles, nodal, stream=None, rep=None, out=None, ws=None):
+    """Mesh->particle interpolation: (values [F, np], report tensor).  ws: optional device
+    workspace (uint8 tensor) for the node-major path of 2D, 2-4 field gathers."""
     if nodal.dim() == 1:
         nodal = nodal[None, :]
     if nodal.dtype != prob.dtype or nodal.shape[1] != prob.n_nodes or not nodal.is_cuda:
@@ -350,7 +351,8 @@ def p2m_interpolate(ctx: Context, prob: Particles, nodal, stream=None, rep=None,
     rep = ctx.new_report() if rep is None else rep
     _check(lib().p2m_interpolate(ctx.handle, ctypes.byref(cp), ctypes.c_void_p(nodal.data_ptr()), F,
                                  ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(rep.data_ptr()),
-                                 None, 0, _stream_ptr(stream)), "p2m_interpolate")
+                                 None if ws is None else ctypes.c_void_p(ws.data_ptr()),
+                                 0 if ws is None else ws.numel(), _stream_ptr(stream)), "p2m_interpolate")
     return out, rep
 
 

@@ -211,6 +211,9 @@ struct Prepared {
     char* ws;
     hipStream_t stream;
     p2m_report* rep;
+    // the report still has to be zeroed: the first launch of the call does it
+    // together with its own clearing work (one launch fewer per call)
+    mutable bool clear_rep = false;
 };
 
 p2m_status prepare(void* ctx, const p2m_problem* prob, int F, void* ws, size_t ws_bytes,
@@ -237,7 +240,9 @@ p2m_status run_bin(const Prepared& pp, const p2m_problem* prob, int32_t* perm, i
     int32_t* rank = key + m.np;
     void* scan_ws = pp.ws + pp.L.scan;
     const size_t clear = (pp.L.scan + scan_workspace_bytes(m.nn) - pp.L.counts) / sizeof(int32_t);
-    P2M_TRY(launch_fill_i32(counts, 0, clear, pp.stream));   // counts and the scan's words
+    // counts and the scan's words (and the report, when the call has not cleared it)
+    P2M_TRY(launch_fill_i32(counts, 0, clear, pp.stream, pp.clear_rep ? pp.rep : nullptr));
+    pp.clear_rep = false;
     P2M_TRY(launch_locate_count<T>(m, particles_of<T>(prob), key, rank, counts, pp.rep,
                                    pp.stream));
     P2M_TRY(launch_exclusive_scan(counts, cs, m.nn, scan_ws, pp.stream));
@@ -292,8 +297,14 @@ p2m_status run_solve(const Context* c, const Prepared& pp, int F, T* b, const T*
     if (tiled && (kind == P2M_SOLVER_AUTO || kind == P2M_SOLVER_RESIDENT) &&
         cgr_supported(pp.m, F, c->device)) {
         P2M_TRY(launch_cg_resident(pp.m, F, (float*)coef, (float*)b, (const float*)w, (float*)x,
-                                   start, pp.ws + pp.L.resident, opts, pp.rep, pp.stream));
+                                   start, pp.ws + pp.L.resident, opts, pp.rep, pp.clear_rep,
+                                   pp.stream));
+        pp.clear_rep = false;
         return P2M_OK;
+    }
+    if (pp.clear_rep) {
+        P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+        pp.clear_rep = false;
     }
     if (tiled && kind != P2M_SOLVER_STREAMING && cgt_grid(pp.m, F, ch.groups, c->device) > 0) {
         P2M_TRY(launch_cg_tiles(pp.m, F, (float*)coef, (float*)b, (const float*)w, (float*)x, start,
@@ -590,7 +601,7 @@ p2m_status p2m_bin(void* ctx, const p2m_problem* prob, int32_t* perm, int32_t* c
     if ((pp.m.np > 0 && !perm) || !cell_start) return P2M_ERR_INVALID_ARG;
     DeviceGuard g(((Context*)ctx)->device);
     if (!g.ok) return P2M_ERR_HIP;
-    P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+    pp.clear_rep = true;   // zeroed by the call's first launch
     return prob->dtype == P2M_F64 ? run_bin<double>(pp, prob, perm, cell_start)
                                   : run_bin<float>(pp, prob, perm, cell_start);
 }
@@ -604,7 +615,7 @@ p2m_status p2m_assemble(void* ctx, const p2m_problem* prob, const void* values, 
     if ((pp.m.np > 0 && !values) || !b || !w) return P2M_ERR_INVALID_ARG;
     DeviceGuard g(((Context*)ctx)->device);
     if (!g.ok) return P2M_ERR_HIP;
-    P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+    pp.clear_rep = true;   // zeroed by the call's first launch
     const Choice ch = choose((const Context*)ctx, pp.m, prob->dtype, nfields);
     return prob->dtype == P2M_F64 ? run_assemble<double>(pp, prob, values, nfields, b, w, coef, ch)
                                   : run_assemble<float>(pp, prob, values, nfields, b, w, coef, ch);
@@ -621,7 +632,7 @@ p2m_status p2m_assign(void* ctx, const p2m_problem* prob, p2m_assign_kind kind, 
     if ((pp.m.np > 0 && !values) || !nodal_out) return P2M_ERR_INVALID_ARG;
     DeviceGuard g(((Context*)ctx)->device);
     if (!g.ok) return P2M_ERR_HIP;
-    P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+    pp.clear_rep = true;   // zeroed by the call's first launch
     return prob->dtype == P2M_F64 ? run_assign<double>(pp, prob, kind, values, nfields, nodal_out)
                                   : run_assign<float>(pp, prob, kind, values, nfields, nodal_out);
 }
@@ -629,8 +640,6 @@ p2m_status p2m_assign(void* ctx, const p2m_problem* prob, p2m_assign_kind kind, 
 p2m_status p2m_interpolate(void* ctx, const p2m_problem* prob, const void* nodal, int32_t nfields,
                            void* values_out, p2m_report* rep, void* ws, size_t ws_bytes,
                            void* stream) {
-    (void)ws;
-    (void)ws_bytes;
     if (!ctx) return P2M_ERR_INVALID_ARG;
     if (nfields < 1 || nfields > kMaxFields) return P2M_ERR_INVALID_ARG;
     Mesh m;
@@ -643,9 +652,9 @@ p2m_status p2m_interpolate(void* ctx, const p2m_problem* prob, const void* nodal
     P2M_TRY(launch_report_clear(rep, strm));
     if (prob->dtype == P2M_F64)
         return st(launch_gather<double>(m, particles_of<double>(prob), (const double*)nodal, nfields,
-                                        (double*)values_out, rep, strm));
+                                        (double*)values_out, rep, strm, ws, ws ? ws_bytes : 0));
     return st(launch_gather<float>(m, particles_of<float>(prob), (const float*)nodal, nfields,
-                                   (float*)values_out, rep, strm));
+                                   (float*)values_out, rep, strm, ws, ws ? ws_bytes : 0));
 }
 
 p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
@@ -664,7 +673,7 @@ p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* value
     if ((pp.m.np > 0 && !values) || !nodal_inout) return P2M_ERR_INVALID_ARG;
     DeviceGuard g(((Context*)ctx)->device);
     if (!g.ok) return P2M_ERR_HIP;
-    P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+    pp.clear_rep = true;   // zeroed by the call's first launch
     const Context* c = (const Context*)ctx;
     const Choice ch = choose(c, pp.m, prob->dtype, nfields);
     return prob->dtype == P2M_F64
@@ -686,7 +695,7 @@ p2m_status p2m_mass_solve(void* ctx, const p2m_problem* prob, int32_t nfields, v
     if (!b || !w || !coef || !nodal_inout) return P2M_ERR_INVALID_ARG;
     DeviceGuard g(((Context*)ctx)->device);
     if (!g.ok) return P2M_ERR_HIP;
-    P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+    pp.clear_rep = true;   // zeroed by the call's first launch
     const Context* c = (const Context*)ctx;
     const Choice ch = choose(c, pp.m, prob->dtype, nfields);
     if (prob->dtype == P2M_F64)
@@ -797,7 +806,7 @@ p2m_status p2m_learned_features(void* ctx, const p2m_problem* prob, const void* 
     if ((size_t)nrows * nfields * P2M_LEARNED_NIN >= ((size_t)1 << 40)) return P2M_ERR_UNSUPPORTED;
     DeviceGuard g(((Context*)ctx)->device);
     if (!g.ok) return P2M_ERR_HIP;
-    P2M_TRY(launch_report_clear(pp.rep, pp.stream));
+    pp.clear_rep = true;   // zeroed by the call's first launch
     int32_t* perm = (int32_t*)(pp.ws + pp.L.perm);
     int32_t* cs = (int32_t*)(pp.ws + pp.L.cell_start);
     s = run_bin<float>(pp, prob, perm, cs);

@@ -33,7 +33,23 @@ __global__ void k_report_clear(p2m_report* rep) {
     }
 }
 
-__global__ void k_fill_i32(int32_t* __restrict__ p, int32_t value, size_t n) {
+// Fill of n ints; with rep, block 0 also zeroes that report (one launch for both).
+__global__ void k_fill_i32(int32_t* __restrict__ p, int32_t value, size_t n,
+                           p2m_report* __restrict__ rep) {
+    if (rep && blockIdx.x == 0) {
+        const int t = threadIdx.x;
+        if (t < 8) {
+            rep->iters[t] = 0;
+            rep->refines[t] = 0;
+            rep->rel_residual[t] = 0.0;
+        }
+        if (t == 0) {
+            rep->flags = 0u;
+            rep->n_orphan = 0;
+            rep->n_invalid = 0;
+            rep->reserved = 0;
+        }
+    }
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) p[i] = value;
@@ -406,11 +422,13 @@ hipError_t launch_report_clear(p2m_report* rep, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_fill_i32(int32_t* p, int32_t value, size_t n, hipStream_t stream) {
-    if (n == 0) return hipSuccess;
+hipError_t launch_fill_i32(int32_t* p, int32_t value, size_t n, hipStream_t stream,
+                           p2m_report* rep) {
+    if (n == 0 && !rep) return hipSuccess;
     int grid = (int)((n + kBlock - 1) / kBlock);
     if (grid > 65536) grid = 65536;
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid), dim3(kBlock), 0, stream, p, value, n);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid), dim3(kBlock), 0, stream, p, value, n, rep);
     return hipGetLastError();
 }
 
@@ -439,7 +457,8 @@ hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, voi
     unsigned long long* status = (unsigned long long*)scan_ws;
     unsigned* ctr = (unsigned*)(status + nb);
     if (nb == 0) {
-        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, out, 0, (size_t)1);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, out, 0, (size_t)1,
+                           (p2m_report*)nullptr);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_scan_lookback, dim3(nb), dim3(kBlock), 0, stream, counts, n, out, status,

@@ -561,10 +561,25 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     }
 }
 
-__global__ void k_sync_clear(unsigned* ctr, unsigned* root, unsigned* rel, unsigned* abort_) {
+// barrier counters to zero; with rep, that report too (one launch for both)
+__global__ void k_sync_clear(unsigned* ctr, unsigned* root, unsigned* rel, unsigned* abort_,
+                             p2m_report* rep) {
     const int t = threadIdx.x;
     if (t < kGroups * 32) ctr[t] = 0u;
     if (t < 32) { root[t] = 0u; rel[t] = 0u; abort_[t] = 0u; }
+    if (rep) {
+        if (t < 8) {
+            rep->iters[t] = 0;
+            rep->refines[t] = 0;
+            rep->rel_residual[t] = 0.0;
+        }
+        if (t == 0) {
+            rep->flags = 0u;
+            rep->n_orphan = 0;
+            rep->n_invalid = 0;
+            rep->reserved = 0;
+        }
+    }
 }
 
 const void* cgr_kernel(int F) {
@@ -609,7 +624,7 @@ bool cgr_supported(const Mesh& m, int F, int device) {
 
 hipError_t launch_cg_resident(const Mesh& m, int F, float* coef, float* b, const float* w,
                               float* x, int start, void* ws, const p2m_solve_opts& opts,
-                              p2m_report* rep, hipStream_t stream) {
+                              p2m_report* rep, bool clear_rep, hipStream_t stream) {
     auto al = [](size_t v) { return (v + kAlign - 1) / kAlign * kAlign; };
     const int blocks = cgr_tiles(m);
     char* p = (char*)ws;
@@ -635,13 +650,18 @@ hipError_t launch_cg_resident(const Mesh& m, int F, float* coef, float* b, const
     a.sy.part = (double*)p; p += al((size_t)2 * blocks * kNV * sizeof(double));
     a.sy.tot = (double*)p;
     hipLaunchKernelGGL(k_sync_clear, dim3(1), dim3(kGroups * 32), 0, stream, a.sy.ctr, a.sy.root,
-                       a.sy.rel, a.sy.abort);
+                       a.sy.rel, a.sy.abort, clear_rep ? rep : (p2m_report*)nullptr);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const void* fn = cgr_kernel(F);
     if (!fn) return hipErrorInvalidValue;
     void* args[] = {&a};
-    return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(RBS), args, 0, stream);
+    // An ordinary launch: the stream has finished every earlier kernel, and the
+    // grid (one workgroup per compute unit at most, checked by cgr_supported) is
+    // then resident as a whole.  The barrier is the kernel's own counter tree, not
+    // the cooperative-groups one, and every wait in it is bounded.  (A cooperative
+    // launch added ~30 us of queue gaps around each solve.)
+    return hipLaunchKernel(fn, dim3(blocks), dim3(RBS), args, 0, stream);
 }
 
 }  // namespace p2m

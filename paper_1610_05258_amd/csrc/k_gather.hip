@@ -21,6 +21,43 @@ __device__ __forceinline__ void flag_invalid(p2m_report* rep, bool finite) {
     if (rep) atomicOr(&rep->flags, finite ? (uint32_t)P2M_FLAG_RANGE : (uint32_t)P2M_FLAG_NONFINITE);
 }
 
+// Cell corners and P1 weights of particle i's triangle (the "/" split); ok is
+// false for a particle that cannot be located (flagged, NaN output).
+template <typename T>
+struct GatherGeom {
+    int n0, n1, n2;
+    T l0, l1, l2;
+    bool ok;
+};
+
+template <typename T>
+__device__ __forceinline__ GatherGeom<T> gather_geom(const Mesh& m, T px, T py, bool in,
+                                                     p2m_report* rep) {
+    GatherGeom<T> g;
+    int cx = 0, cy = 0;
+    double xi = 0.0, eta = 0.0;
+    bool fx = true, fy = true;
+    g.ok = false;
+    if (in) {
+        g.ok = locate_axis((double)px, m.nx, m.inv_hx, cx, xi, fx);
+        g.ok = locate_axis((double)py, m.ny, m.inv_hy, cy, eta, fy) && g.ok;
+        if (!g.ok) flag_invalid(rep, fx && fy);
+    }
+    if (!g.ok) cx = cy = 0, xi = eta = 0.0;
+    const int i1 = (cx + 1 == m.nx) ? 0 : cx + 1;
+    const int j1 = (cy + 1 == m.ny) ? 0 : cy + 1;
+    const bool lower = xi >= eta;
+    g.n0 = cx + m.nx * cy;
+    g.n1 = lower ? i1 + m.nx * cy : i1 + m.nx * j1;
+    g.n2 = lower ? i1 + m.nx * j1 : cx + m.nx * j1;
+    T c00, c10, c11, c01;
+    corner_weights<T>(xi, eta, c00, c10, c11, c01);
+    g.l0 = c00;
+    g.l1 = lower ? c10 : c11;
+    g.l2 = lower ? c11 : c01;
+    return g;
+}
+
 // kGatherItems particles per thread (item u of block b: particles
 // [(b * kGatherItems + u) * blockDim, ...), coalesced per item): every position
 // is loaded, then every nodal value, then the outputs are stored, so a thread
@@ -41,51 +78,76 @@ __global__ void k_gather2d(Mesh m, Particles<T> P, const T* __restrict__ nodal, 
             py[u] = P.y[i];
         }
     }
-    int n0[kGatherItems], n1[kGatherItems], n2[kGatherItems];
-    T l0[kGatherItems], l1[kGatherItems], l2[kGatherItems];
-    bool ok[kGatherItems];
+    GatherGeom<T> g[kGatherItems];
 #pragma unroll
-    for (int u = 0; u < kGatherItems; ++u) {
-        const int i = base + u * (int)blockDim.x;
-        int cx = 0, cy = 0;
-        double xi = 0.0, eta = 0.0;
-        bool fx = true, fy = true;
-        ok[u] = false;
-        if (i < m.np) {
-            ok[u] = locate_axis((double)px[u], m.nx, m.inv_hx, cx, xi, fx);
-            ok[u] = locate_axis((double)py[u], m.ny, m.inv_hy, cy, eta, fy) && ok[u];
-            if (!ok[u]) flag_invalid(rep, fx && fy);
-        }
-        if (!ok[u]) cx = cy = 0, xi = eta = 0.0;
-        const int i1 = (cx + 1 == m.nx) ? 0 : cx + 1;
-        const int j1 = (cy + 1 == m.ny) ? 0 : cy + 1;
-        const bool lower = xi >= eta;
-        n0[u] = cx + m.nx * cy;
-        n1[u] = lower ? i1 + m.nx * cy : i1 + m.nx * j1;
-        n2[u] = lower ? i1 + m.nx * j1 : cx + m.nx * j1;
-        T c00, c10, c11, c01;
-        corner_weights<T>(xi, eta, c00, c10, c11, c01);
-        l0[u] = c00;
-        l1[u] = lower ? c10 : c11;
-        l2[u] = lower ? c11 : c01;
-    }
+    for (int u = 0; u < kGatherItems; ++u)
+        g[u] = gather_geom<T>(m, px[u], py[u], base + u * (int)blockDim.x < m.np, rep);
     for (int f = 0; f < F; ++f) {
         const T* a = nodal + (size_t)f * m.nn;
         T v[kGatherItems][3];
 #pragma unroll
         for (int u = 0; u < kGatherItems; ++u) {
-            v[u][0] = a[n0[u]];
-            v[u][1] = a[n1[u]];
-            v[u][2] = a[n2[u]];
+            v[u][0] = a[g[u].n0];
+            v[u][1] = a[g[u].n1];
+            v[u][2] = a[g[u].n2];
         }
 #pragma unroll
         for (int u = 0; u < kGatherItems; ++u) {
             const int i = base + u * (int)blockDim.x;
             if (i < m.np)
                 out[(size_t)f * m.np + i] =
-                    ok[u] ? l0[u] * v[u][0] + l1[u] * v[u][1] + l2[u] * v[u][2] : (T)NAN;
+                    g[u].ok ? g[u].l0 * v[u][0] + g[u].l1 * v[u][1] + g[u].l2 * v[u][2] : (T)NAN;
         }
     }
+}
+
+// The same from a node-major copy nm[k * F + f] of the nodal values: one load of
+// F consecutive values per corner instead of F loads.
+template <typename T, int F>
+__global__ void k_gather2d_nm(Mesh m, Particles<T> P, const T* __restrict__ nm,
+                              T* __restrict__ out, p2m_report* __restrict__ rep) {
+    const int base = blockIdx.x * blockDim.x * kGatherItems + threadIdx.x;
+    T px[kGatherItems], py[kGatherItems];
+#pragma unroll
+    for (int u = 0; u < kGatherItems; ++u) {
+        const int i = base + u * (int)blockDim.x;
+        px[u] = py[u] = (T)0;
+        if (i < m.np) {
+            px[u] = P.x[i];
+            py[u] = P.y[i];
+        }
+    }
+    GatherGeom<T> g[kGatherItems];
+#pragma unroll
+    for (int u = 0; u < kGatherItems; ++u)
+        g[u] = gather_geom<T>(m, px[u], py[u], base + u * (int)blockDim.x < m.np, rep);
+    T v[kGatherItems][3][F];
+#pragma unroll
+    for (int u = 0; u < kGatherItems; ++u)
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+            v[u][0][f] = nm[(size_t)g[u].n0 * F + f];
+            v[u][1][f] = nm[(size_t)g[u].n1 * F + f];
+            v[u][2][f] = nm[(size_t)g[u].n2 * F + f];
+        }
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) {
+            const int i = base + u * (int)blockDim.x;
+            if (i < m.np)
+                out[(size_t)f * m.np + i] =
+                    g[u].ok ? g[u].l0 * v[u][0][f] + g[u].l1 * v[u][1][f] + g[u].l2 * v[u][2][f]
+                            : (T)NAN;
+        }
+}
+
+// nm[k * F + f] = nodal[f * nn + k]
+template <typename T>
+__global__ void k_node_major(const T* __restrict__ nodal, int F, int nn, T* __restrict__ nm) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn) return;
+    for (int f = 0; f < F; ++f) nm[(size_t)k * F + f] = nodal[(size_t)f * nn + k];
 }
 
 template <typename T>
@@ -230,12 +292,31 @@ __global__ void k_delta1d(Mesh m, Particles<T> P, const T* __restrict__ values, 
 
 template <typename T>
 hipError_t launch_gather(const Mesh& m, Particles<T> P, const T* nodal, int F, T* out,
-                         p2m_report* rep, hipStream_t stream) {
+                         p2m_report* rep, hipStream_t stream, void* ws, size_t ws_bytes) {
     if (m.np == 0) return hipSuccess;
     const int block = 256;
     if (m.dim == 2) {
         const int grid = (int)(((size_t)m.np + (size_t)block * kGatherItems - 1) /
                                ((size_t)block * kGatherItems));
+        if (ws && F >= 2 && F <= 4 && ws_bytes >= (size_t)F * m.nn * sizeof(T)) {
+            T* nm = (T*)ws;
+            hipLaunchKernelGGL(k_node_major<T>, dim3((m.nn + block - 1) / block), dim3(block), 0,
+                               stream, nodal, F, m.nn, nm);
+            switch (F) {
+                case 2:
+                    hipLaunchKernelGGL((k_gather2d_nm<T, 2>), dim3(grid), dim3(block), 0, stream, m,
+                                       P, nm, out, rep);
+                    break;
+                case 3:
+                    hipLaunchKernelGGL((k_gather2d_nm<T, 3>), dim3(grid), dim3(block), 0, stream, m,
+                                       P, nm, out, rep);
+                    break;
+                default:
+                    hipLaunchKernelGGL((k_gather2d_nm<T, 4>), dim3(grid), dim3(block), 0, stream, m,
+                                       P, nm, out, rep);
+            }
+            return hipGetLastError();
+        }
         hipLaunchKernelGGL(k_gather2d<T>, dim3(grid), dim3(block), 0, stream, m, P, nodal, F, out, rep);
     } else {
         const int grid = (m.np + block - 1) / block;
@@ -244,9 +325,9 @@ hipError_t launch_gather(const Mesh& m, Particles<T> P, const T* nodal, int F, T
     return hipGetLastError();
 }
 template hipError_t launch_gather<float>(const Mesh&, Particles<float>, const float*, int, float*,
-                                         p2m_report*, hipStream_t);
+                                         p2m_report*, hipStream_t, void*, size_t);
 template hipError_t launch_gather<double>(const Mesh&, Particles<double>, const double*, int,
-                                          double*, p2m_report*, hipStream_t);
+                                          double*, p2m_report*, hipStream_t, void*, size_t);
 
 template <typename T>
 hipError_t launch_delta1d(const Mesh& m, Particles<T> P, const T* values, int F,

@@ -105,7 +105,9 @@ __device__ __forceinline__ void corner_weights(double xi, double eta, T& c00, T&
 
 // report: zero it (a fill kernel, so the call stays capturable into graphs)
 hipError_t launch_report_clear(p2m_report* rep, hipStream_t stream);
-hipError_t launch_fill_i32(int32_t* p, int32_t value, size_t n, hipStream_t stream);
+// fill n ints with value; with rep, the same launch zeroes that report
+hipError_t launch_fill_i32(int32_t* p, int32_t value, size_t n, hipStream_t stream,
+                           p2m_report* rep = nullptr);
 
 // binning
 template <typename T>
@@ -135,10 +137,12 @@ template <typename T>
 hipError_t launch_finalize(const Mesh& m, int F, const T* b, const T* w, int pic, T* out,
                            p2m_report* rep, hipStream_t stream);
 
-// M2P gather in caller order
+// M2P gather in caller order.  ws (optional, >= F * nn elements): 2D gathers of
+// 2-4 fields read a node-major copy built there
 template <typename T>
 hipError_t launch_gather(const Mesh& m, Particles<T> P, const T* nodal, int F, T* out,
-                         p2m_report* rep, hipStream_t stream);
+                         p2m_report* rep, hipStream_t stream, void* ws = nullptr,
+                         size_t ws_bytes = 0);
 
 // 1D delta P2M from the binned particles
 template <typename T>
@@ -174,9 +178,10 @@ constexpr int kResidentMaxFields = 3;
 size_t cgr_workspace_bytes(const Mesh& m, int F, int blocks);
 int cgr_tiles(const Mesh& m);
 bool cgr_supported(const Mesh& m, int F, int device);
+// clear_rep: the report the kernel writes is zeroed first (by the counter clear)
 hipError_t launch_cg_resident(const Mesh& m, int F, float* coef, float* b, const float* w,
                               float* x, int start, void* ws, const p2m_solve_opts& opts,
-                              p2m_report* rep, hipStream_t stream);
+                              p2m_report* rep, bool clear_rep, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // batches (k_bin.hip, k_assemble.hip, k_cgb.hip)
