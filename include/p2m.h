@@ -351,8 +351,9 @@ typedef struct {
 /* Times p2m_mass_assign of this problem under every applicable plan (each solve
  * kernel; the tile-streaming kernel with one and with half a workgroup per
  * compute unit; the default and the 8 x 8 scatter tile; the caller's inner_rtol,
- * 3e-5 and 0), three runs each after a warm-up, on `stream`; keeps the fastest
- * plan whose solve converged for the problem's shape class and returns it.  Synchronises `stream`.  opts->start must
+ * 3e-5, 1e-5, 1e-6 and 0), three runs each after a warm-up, on `stream`; keeps the
+ * fastest plan whose solve converged for the problem's shape class and returns it.
+ * Synchronises `stream`.  opts->start must
  * be FLIP or ZERO; nodal_out and rep receive the chosen plan's result. */
 p2m_status p2m_tune(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
                     const p2m_solve_opts* opts, void* nodal_out, p2m_report* rep, void* ws,

@@ -868,7 +868,7 @@ p2m_status p2m_tune(void* ctx, const p2m_problem* prob, const void* values, int3
     // candidates: every solve kernel that applies, with the default and the 8 x 8
     // scatter tile; the tile-streaming solve with one and with half a workgroup per CU
     std::vector<p2m_plan> cand;
-    const double rtols[3] = {-1.0, 3e-5, 0.0};
+    const double rtols[5] = {-1.0, 3e-5, 1e-5, 1e-6, 0.0};
     auto add = [&](int solver, int groups, int tile) {
         for (double rt : rtols) {
             if (rt >= 0.0 && rt == opts->inner_rtol) continue;
