@@ -56,7 +56,7 @@ __device__ __forceinline__ void assemble2d_tile(const Mesh& m, const Particles<T
     constexpr size_t PART_B = (size_t)NQ * HC * sizeof(T);
     __shared__ __align__(16) unsigned char smem[SLOT_B > PART_B ? SLOT_B : PART_B];
     __shared__ int c_seg[HC], c_off[HC + 1];
-    __shared__ short cmap[CH];                  // slot of the chunk -> its cell
+    __shared__ short cmap[2][CH];               // slot of a chunk -> its cell (2 buffers)
     __shared__ int wsum[NT / 64];
     T* st = (T*)smem;                           // st[q * CH + slot]
     T(*part)[HC] = (T(*)[HC])smem;              // after the chunks: part[q][cell]
@@ -102,58 +102,91 @@ __device__ __forceinline__ void assemble2d_tile(const Mesh& m, const Particles<T
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = (T)0;
 
-    for (int cb = 0; cb < total; cb += CH) {
-        const int ce = min(cb + CH, total);
+    // Chunks of CH slots, pipelined two deep: while chunk c is accumulated, the
+    // particle data of chunk c+1 and the particle numbers of chunk c+2 are in
+    // flight.  cmap (slot of a chunk -> its cell) is double-buffered; every sum
+    // still runs over a cell's slots in binned order.
+    const int nch = (total + CH - 1) / CH;
+    auto fill_cmap = [&](int c) {  // cell threads mark their slots of chunk c
+        const int cb = c * CH, ce = min(cb + CH, total);
         const int a0 = max(my_lo, cb), a1 = min(my_hi, ce);
-        for (int sl = a0; sl < a1; ++sl) cmap[sl - cb] = (short)t;
-        __syncthreads();
-        // stage: slot-parallel loads and FP64 locate.  A thread's SPT slots are
-        // loaded together (particle numbers, then every gather) so the chunk costs
-        // two memory round trips, not two per slot.
-        {
-            int pi[SPT];
+        short* cm = cmap[c & 1];
+        for (int sl = a0; sl < a1; ++sl) cm[sl - cb] = (short)t;
+    };
+    auto load_perm = [&](int c, int (&pi)[SPT]) {  // particle numbers of chunk c
+        const int cb = c * CH, ce = min(cb + CH, total);
+        const short* cm = cmap[c & 1];
 #pragma unroll
-            for (int u = 0; u < SPT; ++u) {
-                const int sl = cb + t + u * NT;
-                pi[u] = -1;
-                if (sl < ce) {
-                    const int hc = cmap[sl - cb];
-                    pi[u] = perm[c_seg[hc] + (sl - c_off[hc])] - po;
-                }
-            }
-            T px[SPT], py[SPT], pv[SPT], pa[SPT][F];
-#pragma unroll
-            for (int u = 0; u < SPT; ++u) {
-                if (pi[u] < 0) continue;
-                const int i = pi[u];
-                px[u] = P.x[i];
-                py[u] = P.y[i];
-                pv[u] = P.vol ? P.vol[i] : v_uni;
-#pragma unroll
-                for (int f = 0; f < F; ++f) pa[u][f] = values[(size_t)f * m.np + i];
-            }
-#pragma unroll
-            for (int u = 0; u < SPT; ++u) {
-                if (pi[u] < 0) continue;
-                int cx, cy;
-                double xi, eta;
-                bool fx, fy;
-                locate_axis((double)px[u], m.nx, m.inv_hx, cx, xi, fx);
-                locate_axis((double)py[u], m.ny, m.inv_hy, cy, eta, fy);
-                T c00, c10, c11, c01;
-                corner_weights<T>(xi, eta, c00, c10, c11, c01);
-                const int o = t + u * NT;
-                st[0 * CH + o] = c00;
-                st[1 * CH + o] = c10;
-                st[2 * CH + o] = c11;
-                st[3 * CH + o] = c01;
-                st[4 * CH + o] = pv[u];
-#pragma unroll
-                for (int f = 0; f < F; ++f) st[(5 + f) * CH + o] = pa[u][f];
+        for (int u = 0; u < SPT; ++u) {
+            const int sl = cb + t + u * NT;
+            pi[u] = -1;
+            if (sl < ce) {
+                const int hc = cm[sl - cb];
+                pi[u] = perm[c_seg[hc] + (sl - c_off[hc])] - po;
             }
         }
+    };
+    auto load_vals = [&](const int (&pi)[SPT], T (&px)[SPT], T (&py)[SPT], T (&pv)[SPT],
+                         T (&pa)[SPT][F]) {
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            if (pi[u] < 0) continue;
+            const int i = pi[u];
+            px[u] = P.x[i];
+            py[u] = P.y[i];
+            pv[u] = P.vol ? P.vol[i] : v_uni;
+#pragma unroll
+            for (int f = 0; f < F; ++f) pa[u][f] = values[(size_t)f * m.np + i];
+        }
+    };
+    int piA[SPT], piB[SPT];
+    T pxA[SPT], pyA[SPT], pvA[SPT], paA[SPT][F];
+    T pxB[SPT], pyB[SPT], pvB[SPT], paB[SPT][F];
+    if (nch > 0) {
+        fill_cmap(0);
+        if (nch > 1) fill_cmap(1);
         __syncthreads();
+        load_perm(0, piA);
+        load_vals(piA, pxA, pyA, pvA, paA);
+        if (nch > 1) load_perm(1, piB);
+        __syncthreads();  // cmap[0] is read above and refilled (chunk 2) in the first pass
+    }
+    for (int c = 0; c < nch; ++c) {
+        const int cb = c * CH, ce = min(cb + CH, total);
+        // stage chunk c: FP64 locate of the loaded positions into LDS
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            if (piA[u] < 0) continue;
+            int cx, cy;
+            double xi, eta;
+            bool fx, fy;
+            locate_axis((double)pxA[u], m.nx, m.inv_hx, cx, xi, fx);
+            locate_axis((double)pyA[u], m.ny, m.inv_hy, cy, eta, fy);
+            T c00, c10, c11, c01;
+            corner_weights<T>(xi, eta, c00, c10, c11, c01);
+            const int o = t + u * NT;
+            st[0 * CH + o] = c00;
+            st[1 * CH + o] = c10;
+            st[2 * CH + o] = c11;
+            st[3 * CH + o] = c01;
+            st[4 * CH + o] = pvA[u];
+#pragma unroll
+            for (int f = 0; f < F; ++f) st[(5 + f) * CH + o] = paA[u][f];
+        }
+        // chunk c's cmap buffer is free (its particle numbers are loaded): chunk c+2's
+        if (c + 2 < nch) fill_cmap(c + 2);
+        __syncthreads();
+        // chunk c+1's particle data, then chunk c+2's particle numbers, in flight
+        // during the accumulation of chunk c
+        int piN[SPT];
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) piN[u] = -1;
+        if (c + 1 < nch) {
+            load_vals(piB, pxB, pyB, pvB, paB);
+            if (c + 2 < nch) load_perm(c + 2, piN);
+        }
         // accumulate: one thread per cell, its slots in order
+        const int a0 = max(my_lo, cb), a1 = min(my_hi, ce);
         for (int sl = a0; sl < a1; ++sl) {
             const int o = sl - cb;
             const T c00 = st[0 * CH + o], c10 = st[1 * CH + o], c11 = st[2 * CH + o],
@@ -174,14 +207,24 @@ __device__ __forceinline__ void assemble2d_tile(const Mesh& m, const Particles<T
             acc[Q_W01] += v01;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
-                const T a = st[(5 + f) * CH + o];
-                acc[Q_B + 4 * f + 0] += v00 * a;
-                acc[Q_B + 4 * f + 1] += v10 * a;
-                acc[Q_B + 4 * f + 2] += v11 * a;
-                acc[Q_B + 4 * f + 3] += v01 * a;
+                const T av = st[(5 + f) * CH + o];
+                acc[Q_B + 4 * f + 0] += v00 * av;
+                acc[Q_B + 4 * f + 1] += v10 * av;
+                acc[Q_B + 4 * f + 2] += v11 * av;
+                acc[Q_B + 4 * f + 3] += v01 * av;
             }
         }
         __syncthreads();
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            piA[u] = piB[u];
+            pxA[u] = pxB[u];
+            pyA[u] = pyB[u];
+            pvA[u] = pvB[u];
+#pragma unroll
+            for (int f = 0; f < F; ++f) paA[u][f] = paB[u][f];
+            piB[u] = piN[u];
+        }
     }
     if (t < HC) {
 #pragma unroll
