@@ -198,26 +198,43 @@ __device__ __forceinline__ int gather_positions(const GatherIn& g, int node, __b
     return n;
 }
 
-// Value part of field f: base, s and the usable flag of the lane's node (the same
-// in its four lanes); writes (A - base) / s into the tile.
-__device__ __forceinline__ void gather_values(const GatherIn& g, int f, int node, int n,
-                                              const int (&pidx)[kSlots], __bf16* x, float& base,
-                                              float& scale, bool& usable) {
-    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+// Value part of field f, loads: the kept particles' values of the lane's slots
+// and the node's b and w (so that several fields' loads can be in flight at once).
+struct ValLoads {
+    float a[kSlots];
+    float bk, wk;
+};
+
+__device__ __forceinline__ void load_values(const GatherIn& g, int f, int node,
+                                            const int (&pidx)[kSlots], ValLoads& vl) {
     const Mesh& m = g.m;
-    float wk = 0.f;
-    base = 0.f;
+    vl.wk = 0.f;
+    vl.bk = 0.f;
     if (node >= 0) {
-        wk = g.w[node];
-        base = wk > 0.f ? g.b[(size_t)f * m.nn + node] / wk : 0.f;
+        vl.wk = g.w[node];
+        vl.bk = g.b[(size_t)f * m.nn + node];
     }
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j)
+        vl.a[j] = pidx[j] >= 0 ? g.values[(size_t)f * m.np + pidx[j]] : 0.f;
+}
+
+// Value part of field f from its loads: base, s and the usable flag of the lane's
+// node (the same in its four lanes); writes (A - base) / s into the tile.
+__device__ __forceinline__ void apply_values(int node, int n, const int (&pidx)[kSlots],
+                                             const ValLoads& vl, __bf16* x, float& base,
+                                             float& scale, bool& usable) {
+    const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+    const float wk = vl.wk;
+    base = 0.f;
+    if (node >= 0) base = wk > 0.f ? vl.bk / wk : 0.f;
     float d[kSlots];
     float ss = 0.f, amax = 0.f;
 #pragma unroll
     for (int j = 0; j < kSlots; ++j) {
         d[j] = 0.f;
         if (pidx[j] >= 0) {
-            const float a = g.values[(size_t)f * m.np + pidx[j]];
+            const float a = vl.a[j];
             d[j] = a - base;
             ss = fmaf(d[j], d[j], ss);
             amax = fmaxf(amax, fabsf(a));
@@ -236,6 +253,15 @@ __device__ __forceinline__ void gather_values(const GatherIn& g, int f, int node
         const int sl = q + 4 * j;
         x[r * XS + 3 * sl + 2] = (__bf16)(s > 0.f && pidx[j] >= 0 ? d[j] / s : 0.f);
     }
+}
+
+// Both parts for one field.
+__device__ __forceinline__ void gather_values(const GatherIn& g, int f, int node, int n,
+                                              const int (&pidx)[kSlots], __bf16* x, float& base,
+                                              float& scale, bool& usable) {
+    ValLoads vl;
+    load_values(g, f, node, pidx, vl);
+    apply_values(node, n, pidx, vl, x, base, scale, usable);
 }
 
 // ---------------------------------------------------------------------------
@@ -301,10 +327,13 @@ __global__ __launch_bounds__(64 * kWaves) void k_learn_forward(const float* __re
 
 // Learned start of every node and field: x0 = base + s y where usable, the FLIP
 // value elsewhere; the per-field usable count goes to used[f].
+// Persistent over node groups (kWaves * 16 nodes each, group grp, grp + gridDim,
+// ...): the weights are converted into LDS once per workgroup.
 __global__ __launch_bounds__(64 * kWaves) void k_learned_start(GatherIn g, int F,
                                                               const float* __restrict__ th,
                                                               float* __restrict__ x0,
-                                                              float* __restrict__ xflip) {
+                                                              float* __restrict__ xflip,
+                                                              int ngroups) {
     __shared__ __align__(16) __bf16 W1[kLH * XS], W2[kLH * HS], W3[kLH * HS];
     __shared__ float b1[kLH], b2[kLH], b3[kLH], W4[kLH];
     __shared__ __align__(16) __bf16 xt[kWaves][16 * XS], h1[kWaves][16 * HS];
@@ -313,33 +342,47 @@ __global__ __launch_bounds__(64 * kWaves) void k_learned_start(GatherIn g, int F
     LWeights w{W1, W2, W3, b1, b2, b3, W4, th[ob4]};
     load_weights(th, w, nullptr, nullptr);
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, q = l >> 4;
-    const int node0 = (blockIdx.x * kWaves + wave) * 16;
-    const int node = node0 + r < g.m.nn ? node0 + r : -1;
-    int pidx[kSlots];
-    const int n = gather_positions(g, node, xt[wave], pidx);
-    for (int f = 0; f < F; ++f) {
-        float base, scale;
-        bool usable;
-        gather_values(g, f, node, n, pidx, xt[wave], base, scale, usable);
-        if (q == 0) {
-            sbase[wave][r] = base;
-            sscale[wave][r] = scale;
-            suse[wave][r] = usable ? 1 : 0;
-        }
-        __syncthreads();
-        float h3[4][4], y[4];
-        forward16(xt[wave], w, h1[wave], h1[wave], h3, y);
-        if (r == 0) {
+    for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+        const int node0 = (grp * kWaves + wave) * 16;
+        const int node = node0 + r < g.m.nn ? node0 + r : -1;
+        int pidx[kSlots];
+        const int n = gather_positions(g, node, xt[wave], pidx);
+        // the values of up to kFieldLoads fields are loaded together
+        constexpr int kFieldLoads = 4;
+        for (int f0 = 0; f0 < F; f0 += kFieldLoads) {
+            ValLoads vl[kFieldLoads];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int rr = 4 * q + i, nd = node0 + rr;
-                if (nd >= g.m.nn) continue;
-                const float bs = sbase[wave][rr];
-                x0[(size_t)f * g.m.nn + nd] = suse[wave][rr] ? fmaf(sscale[wave][rr], y[i], bs) : bs;
-                xflip[(size_t)f * g.m.nn + nd] = bs;
+            for (int e = 0; e < kFieldLoads; ++e)
+                if (f0 + e < F) load_values(g, f0 + e, node, pidx, vl[e]);
+#pragma unroll
+            for (int e = 0; e < kFieldLoads; ++e) {
+                const int f = f0 + e;
+                if (f >= F) break;
+                float base, scale;
+                bool usable;
+                apply_values(node, n, pidx, vl[e], xt[wave], base, scale, usable);
+                if (q == 0) {
+                    sbase[wave][r] = base;
+                    sscale[wave][r] = scale;
+                    suse[wave][r] = usable ? 1 : 0;
+                }
+                __syncthreads();
+                float h3[4][4], y[4];
+                forward16(xt[wave], w, h1[wave], h1[wave], h3, y);
+                if (r == 0) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int rr = 4 * q + i, nd = node0 + rr;
+                        if (nd >= g.m.nn) continue;
+                        const float bs = sbase[wave][rr];
+                        x0[(size_t)f * g.m.nn + nd] =
+                            suse[wave][rr] ? fmaf(sscale[wave][rr], y[i], bs) : bs;
+                        xflip[(size_t)f * g.m.nn + nd] = bs;
+                    }
+                }
+                __syncthreads();
             }
         }
-        __syncthreads();
     }
 }
 
@@ -639,17 +682,34 @@ __global__ __launch_bounds__(kJBlock) void k_start_resid(Mesh m, int F, const fl
     }
 }
 
-// one block: per field, keep the learned start unless its residual exceeds the
-// FLIP start's; a replaced field is flagged
-__global__ void k_start_choose(int F, const double* __restrict__ part, int nblocks,
-                               int* __restrict__ use_flip, p2m_report* __restrict__ rep) {
+// One workgroup of kJBlock threads: per field, keep the learned start unless its
+// residual exceeds the FLIP start's; a replaced field is flagged.  Thread t sums
+// the partials of blocks t, t + kJBlock, ... (all 2F values of a block in one
+// pass), then a fixed tree over the threads: a deterministic order.
+__global__ __launch_bounds__(kJBlock) void k_start_choose(int F, const double* __restrict__ part,
+                                                          int nblocks, int* __restrict__ use_flip,
+                                                          p2m_report* __restrict__ rep) {
+    __shared__ double sh[2 * kMaxFields][kJBlock];
     const int t = threadIdx.x;
-    if (t >= F) return;
-    double rl = 0.0, rf = 0.0;
-    for (int k = 0; k < nblocks; ++k) {
-        rl += part[(size_t)k * 2 * kMaxFields + 2 * t];
-        rf += part[(size_t)k * 2 * kMaxFields + 2 * t + 1];
+    double acc[2 * kMaxFields];
+#pragma unroll
+    for (int v = 0; v < 2 * kMaxFields; ++v) acc[v] = 0.0;
+    for (int k = t; k < nblocks; k += kJBlock) {
+        const double* pk = part + (size_t)k * 2 * kMaxFields;
+#pragma unroll
+        for (int v = 0; v < 2 * kMaxFields; ++v)
+            if (v < 2 * F) acc[v] += pk[v];
     }
+#pragma unroll
+    for (int v = 0; v < 2 * kMaxFields; ++v) sh[v][t] = acc[v];
+    __syncthreads();
+    for (int d = kJBlock / 2; d >= 1; d >>= 1) {
+        if (t < d)
+            for (int v = 0; v < 2 * F; ++v) sh[v][t] += sh[v][t + d];
+        __syncthreads();
+    }
+    if (t >= F) return;
+    const double rl = sh[2 * t][0], rf = sh[2 * t + 1][0];
     const int flip = !(rl <= rf);
     use_flip[t] = flip;
     if (flip && rep) atomicOr(&rep->flags, (uint32_t)P2M_FLAG_LEARNED_FALLBACK);
@@ -740,12 +800,18 @@ hipError_t launch_learned_start(const Mesh& m, Particles<float> P, const float* 
     double* part = (double*)p;
     p += ((size_t)nb * 2 * kMaxFields * sizeof(double) + 255) / 256 * 256;
     int* use_flip = (int*)p;
-    const int grid = (m.nn + 16 * kWaves - 1) / (16 * kWaves);
+    const int ngroups = (m.nn + 16 * kWaves - 1) / (16 * kWaves);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 256;
+    const int grid = ngroups < 2 * cus ? ngroups : 2 * cus;  // two workgroups fit a CU's LDS
     hipLaunchKernelGGL(k_learned_start, dim3(grid), dim3(64 * kWaves), 0, stream,
-                       gather_in(m, P, values, perm, cs, b, w), F, params, x0, xf);
+                       gather_in(m, P, values, perm, cs, b, w), F, params, x0, xf, ngroups);
     hipLaunchKernelGGL(k_start_resid, dim3(nb), dim3(kJBlock), 0, stream, m, F, coef, b, w, x0, xf,
                        part);
-    hipLaunchKernelGGL(k_start_choose, dim3(1), dim3(64), 0, stream, F, part, nb, use_flip, rep);
+    hipLaunchKernelGGL(k_start_choose, dim3(1), dim3(kJBlock), 0, stream, F, part, nb, use_flip, rep);
     const size_t tot = (size_t)m.nn * F;
     hipLaunchKernelGGL(k_start_apply, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, stream, m.nn,
                        F, use_flip, xf, x0);
