@@ -75,10 +75,25 @@ __device__ void load_weights(const float* __restrict__ th, const LWeights& w, __
     }
 }
 
+// Synchronisation of the forward pass: the whole workgroup, or (kWave) only the
+// wave, when every buffer it touches besides the read-only weights is the wave's
+// own (a wave's LDS accesses execute in program order; the fences keep the
+// compiler from moving them across the point).
+template <bool kWave>
+__device__ __forceinline__ void fwd_sync() {
+    if constexpr (kWave) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // One hidden layer for the wave's 16 rows: out[row][n] = bf16(relu(in . W[n] + b[n])),
 // K = 32 * KS.  Lane holds rows 4q .. 4q+3 of columns 16t + r.  Every product is
 // formed before the barrier and written after it, so out may be the input.
-template <int KS>
+template <int KS, bool kWave = false>
 __device__ __forceinline__ void dense_relu_bf16(const __bf16* in, int in_stride, const __bf16* W,
                                                 int w_stride, const float* b, __bf16* out) {
     const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
@@ -91,7 +106,7 @@ __device__ __forceinline__ void dense_relu_bf16(const __bf16* in, int in_stride,
             acc[t] = mfma16(ld8(in + r * in_stride + 32 * s + 8 * q),
                             ld8(W + (16 * t + r) * w_stride + 32 * s + 8 * q), acc[t]);
     }
-    __syncthreads();
+    fwd_sync<kWave>();
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         const float bb = b[16 * t + r];
@@ -105,13 +120,14 @@ __device__ __forceinline__ void dense_relu_bf16(const __bf16* in, int in_stride,
 // this wave (they may be the same buffer).  Returns h3 (FP32, [t][i] = row 4q+i,
 // column 16t+r) and y for rows 4q .. 4q+3 (every lane of a 16-lane group holds
 // its group's four y).
+template <bool kWave = false>
 __device__ __forceinline__ void forward16(const __bf16* x, const LWeights& w, __bf16* h1,
                                           __bf16* h2, float (&h3)[4][4], float (&y)[4]) {
     const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
-    dense_relu_bf16<kLIn / 32>(x, XS, w.W1, XS, w.b1, h1);
-    __syncthreads();
-    dense_relu_bf16<kLH / 32>(h1, HS, w.W2, HS, w.b2, h2);
-    __syncthreads();
+    dense_relu_bf16<kLIn / 32, kWave>(x, XS, w.W1, XS, w.b1, h1);
+    fwd_sync<kWave>();
+    dense_relu_bf16<kLH / 32, kWave>(h1, HS, w.W2, HS, w.b2, h2);
+    fwd_sync<kWave>();
     float yp[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -341,6 +357,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_learned_start(GatherIn g, int F
     __shared__ int suse[kWaves][16];
     LWeights w{W1, W2, W3, b1, b2, b3, W4, th[ob4]};
     load_weights(th, w, nullptr, nullptr);
+    __syncthreads();
+    // from here on a wave touches only its own tiles (and the read-only weights):
+    // wave-level synchronisation, so the waves of a workgroup run independently
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, r = l & 15, q = l >> 4;
     for (int grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
         const int node0 = (grp * kWaves + wave) * 16;
@@ -366,9 +385,9 @@ __global__ __launch_bounds__(64 * kWaves) void k_learned_start(GatherIn g, int F
                     sscale[wave][r] = scale;
                     suse[wave][r] = usable ? 1 : 0;
                 }
-                __syncthreads();
+                fwd_sync<true>();
                 float h3[4][4], y[4];
-                forward16(xt[wave], w, h1[wave], h1[wave], h3, y);
+                forward16<true>(xt[wave], w, h1[wave], h1[wave], h3, y);
                 if (r == 0) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
@@ -380,7 +399,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_learned_start(GatherIn g, int F
                         xflip[(size_t)f * g.m.nn + nd] = bs;
                     }
                 }
-                __syncthreads();
+                fwd_sync<true>();
             }
         }
     }
