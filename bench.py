@@ -121,8 +121,10 @@ def cpu_baseline(prob, vals, min_seconds=10.0):
                        f"{os.cpu_count()} host cores")
 
 
-def batched_leg(B, ctx, check, reps=10, tol=1e-9):
-    """The uneven batch as one graph launch, and as one call per problem."""
+def batched_leg(B, ctx, check, tune, reps=10, tol=1e-9):
+    """The uneven batch as one graph launch, and as one call per problem.  With `tune`
+    the batch's inner_rtol is tuned first (unless a loaded plan covers it); the single
+    calls then run with the inner_rtol the batch ran with, so they give the same bits."""
     import torch
     from paper_1610_05258_amd import workloads as wl
     insts = wl.uneven_batch(seed=3, count=64)
@@ -131,6 +133,12 @@ def batched_leg(B, ctx, check, reps=10, tol=1e-9):
     F = insts[0][1].shape[0]
     opts = B.solve_opts(tol=tol, inner_rtol=1e-4, maxit=2000, max_refine=10)
     bt = B.Batch(ctx, probs, vals, opts)
+    plan = bt.plan()
+    if plan is None and tune:
+        plan = bt.tune()
+        log(f"bench: batch plan {plan}")
+    if plan is not None and plan.inner_rtol >= 0.0:
+        opts = B.solve_opts(tol=tol, inner_rtol=plan.inner_rtol, maxit=2000, max_refine=10)
     for _ in range(2):
         bt.run()
     torch.cuda.synchronize()
@@ -161,7 +169,7 @@ def batched_leg(B, ctx, check, reps=10, tol=1e-9):
                particles=int(sum(p.n_particles for p in probs)),
                value=len(insts) * F / t_batch, unit="projections/s", ms_per_batch=t_batch * 1e3,
                single_calls_ms=t_single * 1e3, speedup_vs_single_calls=t_single / t_batch,
-               bitwise_equal_to_single_calls=bool(bitwise),
+               bitwise_equal_to_single_calls=bool(bitwise), inner_rtol=opts.inner_rtol,
                max_iters=int(max(int(x.iters[:F].max()) for x in r)),
                max_rel_residual=float(max(float(x.rel_residual[:F].max()) for x in r)),
                flags=int(np.bitwise_or.reduce([x.flags for x in r])))
@@ -363,7 +371,9 @@ def main():
         log("bench: CPU baseline (oracle on the full input, one thread)")
         result["cpu_baseline"] = cpu_baseline(prob, vals)
     if not args.no_batch:
-        result["batched"] = batched_leg(B, ctx, check=not args.no_cpu)
+        result["batched"] = batched_leg(B, ctx, check=not args.no_cpu, tune=not args.no_tune)
+        if args.save_plans:
+            ctx.save_plans(args.save_plans)
     if k_ref is not None:
         kk = max(k_ref)
         achieved = cg_algorithmic_bytes(kk, nn, F) / (cg_ms * 1e-3) / 1e9

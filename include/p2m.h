@@ -359,8 +359,29 @@ p2m_status p2m_tune(void* ctx, const p2m_problem* prob, const void* values, int3
                     const p2m_solve_opts* opts, void* nodal_out, p2m_report* rep, void* ws,
                     size_t ws_bytes, void* stream, p2m_plan* best);
 
+/* Batch granularity of the tuner: times p2m_mass_assign_batched of this batch with
+ * the caller's inner_rtol, 3e-5, 1e-5, 1e-6 and 0 (one graph build and three timed
+ * launches each, on `stream`); keeps the fastest plan under which every instance
+ * converged for the batch's shape class (field count, and the instance count, total
+ * nodes and total particles rounded to powers of two) and returns it (solver
+ * P2M_SOLVER_TILES, groups 0, scatter_tile 0: only inner_rtol applies to a batch).
+ * While P2M_OPT_PLANS is 1, p2m_mass_assign_batched takes the inner_rtol of the
+ * stored plan of its batch's class; each instance then equals p2m_mass_assign with
+ * that inner_rtol bit for bit.  Synchronises `stream`.  opts->start must be FLIP or
+ * ZERO; nodal_inout and reps receive the chosen plan's result; P2M_ERR_UNSUPPORTED
+ * when no candidate converged. */
+p2m_status p2m_tune_batched(void* ctx, const p2m_problem* probs, int32_t nprob,
+                            const void* const* values, int32_t nfields, const p2m_solve_opts* opts,
+                            void* const* nodal_inout, p2m_report* reps, void* ws, size_t ws_bytes,
+                            void* stream, p2m_plan* best);
+
 /* The stored plan of this problem's shape class (P2M_ERR_UNSUPPORTED: none). */
 p2m_status p2m_plan_get(void* ctx, const p2m_problem* prob, int32_t nfields, p2m_plan* plan);
+
+/* The stored plan of this batch's shape class (P2M_ERR_UNSUPPORTED: none, or a batch
+ * p2m_mass_assign_batched does not take). */
+p2m_status p2m_plan_get_batched(void* ctx, const p2m_problem* probs, int32_t nprob,
+                                int32_t nfields, p2m_plan* plan);
 
 /* Write every stored plan to `path` (JSON object: shape class -> plan); read
  * plans from such a file into the context (entries of the file replace stored

@@ -37,7 +37,8 @@ EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size
            "p2m_assemble", "p2m_assign", "p2m_interpolate", "p2m_mass_assign", "p2m_mass_solve",
            "p2m_set_option", "p2m_batch_workspace_size", "p2m_mass_assign_batched",
            "p2m_set_learned", "p2m_learned_features", "p2m_learned_forward",
-           "p2m_learned_workspace_size", "p2m_learned_train_step", "p2m_tune", "p2m_plan_get",
+           "p2m_learned_workspace_size", "p2m_learned_train_step", "p2m_tune", "p2m_tune_batched",
+           "p2m_plan_get", "p2m_plan_get_batched",
            "p2m_plan_save", "p2m_plan_load", "p2m_plan_clear")
 LEARNED_KMAX, LEARNED_NIN, LEARNED_HIDDEN, LEARNED_NPARAM = 48, 160, 64, 18689
 
@@ -113,6 +114,9 @@ def lib():
         del fp
         pplan = ctypes.POINTER(CPlan)
         L.p2m_tune.argtypes = [vp, pprob, vp, i32, ctypes.POINTER(CSolveOpts), vp, vp, vp, sz, vp, pplan]
+        L.p2m_plan_get_batched.argtypes = [vp, pprob, i32, i32, pplan]
+        L.p2m_tune_batched.argtypes = [vp, pprob, i32, ctypes.POINTER(vp), i32, ctypes.POINTER(CSolveOpts),
+                                       ctypes.POINTER(vp), vp, vp, sz, vp, pplan]
         L.p2m_plan_get.argtypes = [vp, pprob, i32, pplan]
         L.p2m_plan_save.argtypes = [vp, ctypes.c_char_p]
         L.p2m_plan_load.argtypes = [vp, ctypes.c_char_p]
@@ -444,6 +448,23 @@ class Batch:
             self._optr, ctypes.c_void_p(self.reps.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
             ctypes.c_size_t(self.ws.numel()), _stream_ptr(stream)), "p2m_mass_assign_batched")
         return self.out
+
+    def tune(self, stream=None):
+        """Time the batch under each inner_rtol candidate and keep the fastest plan for
+        its shape class (applied by later run() calls while plans are on)."""
+        plan = CPlan()
+        _check(lib().p2m_tune_batched(
+            self.ctx.handle, self._cprobs, self.n, self._vptr, self.F, ctypes.byref(self.opts),
+            self._optr, ctypes.c_void_p(self.reps.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+            ctypes.c_size_t(self.ws.numel()), _stream_ptr(stream), ctypes.byref(plan)),
+            "p2m_tune_batched")
+        return plan
+
+    def plan(self):
+        """The stored plan of this batch's shape class, or None."""
+        p = CPlan()
+        st = lib().p2m_plan_get_batched(self.ctx.handle, self._cprobs, self.n, self.F, ctypes.byref(p))
+        return p if st == 0 else None
 
     def reports(self):
         raw = self.reps.cpu().numpy()

@@ -158,6 +158,16 @@ Particles<T> particles_of(const p2m_problem* p) {
     return P;
 }
 
+// Shape class of a batch for tuned plans: field count, and the instance count, total
+// nodes and total particles, each rounded to a power of two.
+std::string batch_key(int F, int nprob, int64_t nn, int64_t np) {
+    auto lg = [](double v) { return (int)floor(log2(v > 1.0 ? v : 1.0) + 0.5); };
+    char buf[96];
+    snprintf(buf, sizeof buf, "batch-f32-F%d-n%d-nodes%d-parts%d", F, lg(nprob), lg((double)nn),
+             lg((double)np));
+    return std::string(buf);
+}
+
 // Shape class of a problem for tuned plans: dimension, dtype, field count, the
 // mesh sides and the particles per cell, each rounded to a power of two.
 std::string shape_key(const Mesh& m, int dtype, int F) {
@@ -735,6 +745,18 @@ p2m_status p2m_mass_assign_batched(void* ctx, const p2m_problem* probs, int32_t 
     if (s != P2M_OK) return s;
     if (!ws || ws_bytes < P.total || ((uintptr_t)ws) % kAlign) return P2M_ERR_WORKSPACE;
     hipStream_t strm = (hipStream_t)stream;
+    // the batch's plan (the tuner's candidate, else a stored plan of its shape class)
+    // sets the inner/outer CG schedule
+    p2m_solve_opts o = *opts;
+    {
+        const p2m_plan* plan = c->forced;
+        if (!plan && c->use_plans && c->plans) {
+            auto it = c->plans->plans.find(batch_key(P.F, P.nprob, P.nn, P.np));
+            if (it != c->plans->plans.end()) plan = &it->second;
+        }
+        if (plan && plan->inner_rtol >= 0.0 && plan->inner_rtol < 1.0) o.inner_rtol = plan->inner_rtol;
+    }
+    opts = &o;
     if (!c->batch) {
         c->batch = new (std::nothrow) BatchCache();
         if (!c->batch) return P2M_ERR_HIP;
@@ -940,6 +962,96 @@ p2m_status p2m_tune(void* ctx, const p2m_problem* prob, const void* values, int3
     result = p2m_mass_assign(ctx, prob, values, nfields, opts, nodal_out, rep, ws, ws_bytes, stream);
     c->forced = nullptr;
     return result;
+}
+
+p2m_status p2m_tune_batched(void* ctx, const p2m_problem* probs, int32_t nprob,
+                            const void* const* values, int32_t nfields, const p2m_solve_opts* opts,
+                            void* const* nodal_inout, p2m_report* reps, void* ws, size_t ws_bytes,
+                            void* stream, p2m_plan* best) {
+    if (!ctx || !best || !reps || nprob < 1) return P2M_ERR_INVALID_ARG;
+    p2m_status s = check_opts(opts);
+    if (s != P2M_OK) return s;
+    if (opts->start != P2M_START_FLIP && opts->start != P2M_START_ZERO) return P2M_ERR_UNSUPPORTED;
+    Context* c = (Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    BatchPlan P;
+    s = plan_batch(c, probs, nprob, nfields, values, nodal_inout, reps, P);
+    if (s != P2M_OK) return s;
+    // candidates: the inner/outer CG schedule of the batched solve
+    std::vector<p2m_plan> cand;
+    const double rtols[5] = {-1.0, 3e-5, 1e-5, 1e-6, 0.0};
+    for (double rt : rtols) {
+        if (rt >= 0.0 && rt == opts->inner_rtol) continue;
+        p2m_plan p;
+        memset(&p, 0, sizeof(p));
+        p.solver = P2M_SOLVER_TILES;
+        p.inner_rtol = rt;
+        cand.push_back(p);
+    }
+    hipStream_t strm = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return P2M_ERR_HIP;
+    }
+    std::vector<p2m_report> host(nprob);
+    p2m_status result = P2M_OK;
+    int best_i = -1;
+    for (size_t i = 0; i < cand.size() && result == P2M_OK; ++i) {
+        c->forced = &cand[i];
+        float ms = 0.f;
+        const int runs = 3;
+        for (int r = 0; r <= runs && result == P2M_OK; ++r) {  // run 0 captures the graph
+            if (r == 1 && hipEventRecord(e0, strm) != hipSuccess) result = P2M_ERR_HIP;
+            if (result == P2M_OK)
+                result = p2m_mass_assign_batched(ctx, probs, nprob, values, nfields, opts,
+                                                 nodal_inout, reps, ws, ws_bytes, stream);
+        }
+        if (result == P2M_OK &&
+            (hipEventRecord(e1, strm) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+             hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+             hipMemcpy(host.data(), reps, sizeof(p2m_report) * nprob, hipMemcpyDeviceToHost) !=
+                 hipSuccess))
+            result = P2M_ERR_HIP;
+        if (result != P2M_OK) break;
+        cand[i].time_ms = ms / runs;
+        bool ok = true;
+        for (const p2m_report& r : host)
+            ok = ok && !(r.flags & (P2M_FLAG_NOT_CONVERGED | P2M_FLAG_BREAKDOWN));
+        if (ok && (best_i < 0 || cand[i].time_ms < cand[best_i].time_ms)) best_i = (int)i;
+    }
+    c->forced = nullptr;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != P2M_OK) return result;
+    if (best_i < 0) return P2M_ERR_UNSUPPORTED;   // no candidate converged
+    if (!c->plans) {
+        c->plans = new (std::nothrow) PlanCache();
+        if (!c->plans) return P2M_ERR_HIP;
+    }
+    *best = cand[best_i];
+    c->plans->plans[batch_key(P.F, P.nprob, P.nn, P.np)] = *best;
+    // leave the chosen plan's results in nodal_inout and reps
+    c->forced = best;
+    result = p2m_mass_assign_batched(ctx, probs, nprob, values, nfields, opts, nodal_inout, reps, ws,
+                                     ws_bytes, stream);
+    c->forced = nullptr;
+    return result;
+}
+
+p2m_status p2m_plan_get_batched(void* ctx, const p2m_problem* probs, int32_t nprob,
+                                int32_t nfields, p2m_plan* plan) {
+    if (!ctx || !plan) return P2M_ERR_INVALID_ARG;
+    Context* c = (Context*)ctx;
+    BatchPlan P;
+    p2m_status s = plan_batch(c, probs, nprob, nfields, nullptr, nullptr, nullptr, P);
+    if (s != P2M_OK) return s;
+    if (!c->plans) return P2M_ERR_UNSUPPORTED;
+    auto it = c->plans->plans.find(batch_key(P.F, P.nprob, P.nn, P.np));
+    if (it == c->plans->plans.end()) return P2M_ERR_UNSUPPORTED;
+    *plan = it->second;
+    return P2M_OK;
 }
 
 p2m_status p2m_plan_get(void* ctx, const p2m_problem* prob, int32_t nfields, p2m_plan* plan) {

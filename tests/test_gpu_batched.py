@@ -245,3 +245,68 @@ def test_uneven_batch_64(B, ctx):
             worst_inf = max(worst_inf, metrics.rel_linf(got.numpy()[f].astype(np.float64), x))
             assert e <= 1e-6, (k, f, e)
     say(f"  all 64 bitwise equal to single runs; worst rel_l2 {worst:.2e}, rel_linf {worst_inf:.2e}")
+
+
+def test_batched_tune_plan(B, tmp_path):
+    """p2m_tune_batched times the inner_rtol candidates on a batch, stores the fastest
+    converged plan for the batch's shape class, later runs apply it (the tuned bits
+    again), each instance equals the single-problem call with the plan's inner_rtol
+    bit for bit, and a saved plan reloads into a fresh context."""
+    tctx = B.Context(0)
+    insts = [tg_instance(130 + i, n, m, ppc, 3) for i, (n, m, ppc) in
+             enumerate([(128, 96, 8), (200, 120, 4), (64, 64, 2), (150, 150, 8)])]
+    probs = [B.particles_from(p, dtype=torch.float32) for p, _ in insts]
+    vals = [torch.as_tensor(v).cuda() for _, v in insts]
+    opts = B.solve_opts(tol=1e-8, inner_rtol=1e-4, maxit=1000, max_refine=10)
+    bt = B.Batch(tctx, probs, vals, opts)
+    assert bt.plan() is None
+    plan = bt.tune()
+    tuned = [o.clone() for o in bt.out]
+    torch.cuda.synchronize()
+    say(f"[batched tune] chosen {plan}")
+    assert plan.solver == B.SOLVER_TILES and plan.groups == 0 and plan.scatter_tile == 0
+    assert plan.time_ms > 0.0 and plan.inner_rtol < 1.0
+    got = bt.plan()
+    assert got is not None and got.inner_rtol == plan.inner_rtol
+    reps = bt.reports()
+    for r in reps:
+        assert not (r.flags & (B.FLAG_NOT_CONVERGED | B.FLAG_BREAKDOWN))
+    again = bt.run()
+    torch.cuda.synchronize()
+    for a, b in zip(again, tuned):
+        assert torch.equal(a, b)
+    rt = plan.inner_rtol if plan.inner_rtol >= 0.0 else opts.inner_rtol
+    sopts = B.solve_opts(tol=1e-8, inner_rtol=rt, maxit=1000, max_refine=10)
+    for k, (prob, v) in enumerate(insts):
+        single, rs = run_single(B, tctx, prob, v, sopts)
+        assert torch.equal(tuned[k].cpu(), single), k
+        assert same_report(reps[k], rs), (k, reps[k], rs)
+        ref, _ = p1.mass_assign(f64(prob), v.astype(np.float64), solver="direct")
+        for f in range(3):
+            assert metrics.rel_l2(single.numpy()[f].astype(np.float64), ref[f]) <= 1e-6
+    path = tmp_path / "batch_plans.json"
+    tctx.save_plans(path)
+    text = path.read_text()
+    say("  " + text.strip().replace("\n", " "))
+    assert '"batch-f32-F3-n' in text
+    ctx2 = B.Context(0)
+    ctx2.load_plans(path)
+    bt2 = B.Batch(ctx2, probs, vals, opts)
+    assert bt2.plan().inner_rtol == plan.inner_rtol
+    # another batch (one instance fewer) is another shape class
+    assert B.Batch(ctx2, probs[:3], vals[:3], opts).plan() is None
+    out2 = bt2.run()
+    torch.cuda.synchronize()
+    for a, b in zip(out2, tuned):
+        assert torch.equal(a, b)
+    # plans off: the caller's inner_rtol again
+    ctx2.use_plans(False)
+    out3 = bt2.run()
+    torch.cuda.synchronize()
+    for k, (prob, v) in enumerate(insts):
+        single, _ = run_single(B, ctx2, prob, v, opts)
+        assert torch.equal(out3[k].cpu(), single), k
+    # the tuner needs a start it can repeat
+    bt_user = B.Batch(tctx, probs, vals, B.solve_opts(tol=1e-6, start=B.START_USER))
+    with pytest.raises(B.P2MError):
+        bt_user.tune()
