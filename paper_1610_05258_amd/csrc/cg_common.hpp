@@ -73,16 +73,45 @@ __device__ __forceinline__ void std8(rsrc_t r, int i, double v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, i * 8, 0, AUX);
 }
 
+// Lane moves of a double through the VALU's data-parallel primitives (DPP), both
+// halves; every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const u32x2 u = __builtin_bit_cast(u32x2, v);
+    u32x2 r;
+    r.x = (unsigned)__builtin_amdgcn_mov_dpp((int)u.x, CTRL, 0xF, 0xF, false);
+    r.y = (unsigned)__builtin_amdgcn_mov_dpp((int)u.y, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const u32x2 u = __builtin_bit_cast(u32x2, v);
+    u32x2 r;
+    r.x = (unsigned)__builtin_amdgcn_readlane((int)u.x, lane);
+    r.y = (unsigned)__builtin_amdgcn_readlane((int)u.y, lane);
+    return __builtin_bit_cast(double, r);
+}
+// Sum over each 16-lane row of the wave, exact in the row's first lane: lane pairs,
+// then quads, then quads two apart (row rotation by 4), then the row's halves
+// (rotation by 8).  Register-to-register moves: no LDS round trip per step.
+__device__ __forceinline__ double row_sum16(double s) {
+    s += dpp_d<0xB1>(s);    // quad_perm [1,0,3,2]
+    s += dpp_d<0x4E>(s);    // quad_perm [2,3,0,1]
+    s += dpp_d<0x124>(s);   // row_ror:4
+    s += dpp_d<0x128>(s);   // row_ror:8
+    return s;
+}
+
 // Block sum of NV doubles per thread in a fixed order; totals land in out[0..NV).
+// Per wave: the four row sums (row_sum16) added as (r0 + r1) + (r2 + r3); then the
+// waves' sums in wave order.
 template <int NV>
 __device__ __forceinline__ void block_sum_to(double (&v)[NV], double* lds /* [RBS/64][NV] */,
                                              double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
-        double s = v[j];
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) s += __shfl_down(s, d, 64);
+        const double r = row_sum16(v[j]);
+        const double s = (readlane_d(r, 0) + readlane_d(r, 16)) + (readlane_d(r, 32) + readlane_d(r, 48));
         if (lane == 0) lds[wave * NV + j] = s;
     }
     __syncthreads();
@@ -97,9 +126,12 @@ __device__ __forceinline__ void block_sum_to(double (&v)[NV], double* lds /* [RB
 // Sum of the partials part[bk * kNV + jv] over bk < nblocks for every jv < nv,
 // handed to out(jv, sum).  The fixed order that every solve uses: value jv is
 // summed by the 32 lanes of segment jv, lane l over blocks l, l+32, ... in
-// increasing order, then a fixed shuffle tree over the 32 lanes.  Called by all
-// threads of one workgroup.  Loads go out kPartBatch at a time before they are
+// increasing order, then the two row sums of the segment (row_sum16) added in row
+// order.  Called by all threads of one workgroup (every wave runs the same number
+// of segment steps, so the lane moves see every lane active).  Loads go out kPartBatch at a time before they are
 // added (in the same order), so a lane waits once per batch, not once per block.
+static_assert(kNV % 2 == 0 && (RBS / 32) % 2 == 0 && RBS % 64 == 0,
+              "both segments of a wave take the same number of steps");
 template <typename Out>
 __device__ __forceinline__ void sum_partials(const double* part, int nblocks, int nv, Out out) {
     constexpr int kPartBatch = 8;
@@ -118,9 +150,10 @@ __device__ __forceinline__ void sum_partials(const double* part, int nblocks, in
                 for (int u = 0; u < kPartBatch; ++u)
                     if (b0 + 32 * u < nblocks) acc += v[u];
             }
-#pragma unroll
-        for (int d = 16; d >= 1; d >>= 1) acc += __shfl_down(acc, d, 32);
-        if (jv < nv && l == 0) out(jv, acc);
+        const double r = row_sum16(acc);
+        const double lo = readlane_d(r, 0) + readlane_d(r, 16);
+        const double hi = readlane_d(r, 32) + readlane_d(r, 48);
+        if (jv < nv && l == 0) out(jv, (threadIdx.x & 32) ? hi : lo);
     }
 }
 
