@@ -65,14 +65,16 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
     const int row0 = (RNPT / 2) * wave;
 
     constexpr int CW = RX + 1, CN = (RY + 1) * (RX + 1);
-    constexpr size_t XB = (size_t)F * LH * LW * sizeof(float) > (size_t)LH * LW * sizeof(double)
-                              ? (size_t)F * LH * LW * sizeof(float)
-                              : (size_t)LH * LW * sizeof(double);
+    // xbuf: the F FP32 planes of the CG iterations, or (residual phase) one FP64
+    // plane of x followed by one FP32 plane of b
+    constexpr size_t XB = (size_t)(F > 3 ? F : 3) * LH * LW * sizeof(float);
+    static_assert(2 * (RX + 2) + 2 * RY <= RBS, "one ring slot per thread");
     __shared__ float cf[4 * CN];
     __shared__ float dv[LH * LW];   // Jacobi inverse diagonal of the tile and its ring
     __shared__ __align__(16) unsigned char xbuf[XB];
     float* lf = (float*)xbuf;
     double* ld64 = (double*)xbuf;
+    float* lb = (float*)(ld64 + LH * LW);
     __shared__ double red_lds[(RBS / 64) * kNV];
     __shared__ double tv[kNV];                         // block sums of the current tile
     __shared__ double vals[3 * kBatchMaxPairs];        // instance totals, [k * nv + j]
@@ -360,11 +362,22 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
             for (int f = 0; f < F; ++f) {
                 if (s_done[k * F + f]) continue;
                 const rsrc_t rx = rs_f8(a.x64, f), rpx = rs_f8(a.pubX, f), rd = rs_f4(a.sD, f);
+                // the field's loads go out together, ahead of its stores (a load
+                // issued after a store waits for it); a node outside the mesh reads
+                // element 0
+                double xo[RNPT];
+                float dd[RNPT];
+#pragma unroll
+                for (int j = 0; j < RNPT; ++j) {
+                    const int kk = (amask & (1u << j)) ? gk(j) : 0;
+                    xo[j] = ldd<kPlain>(rx, kk);
+                    dd[j] = ldf<kPlain>(rd, kk);
+                }
 #pragma unroll
                 for (int j = 0; j < RNPT; ++j) {
                     if (!(amask & (1u << j))) continue;
                     const int kk = gk(j);
-                    const double xv = ldd<kPlain>(rx, kk) + (double)ldf<kPlain>(rd, kk);
+                    const double xv = xo[j] + (double)dd[j];
                     std8<kPlain>(rx, kk, xv);
                     if (bmask & (1u << j)) std8<kCoherent>(rpx, kk, xv);
                 }
@@ -390,15 +403,36 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                 const rsrc_t rx = rs_f8(a.x64, f), rpx = rs_f8(a.pubX, f), rb = rs_f4(a.b, f),
                              rr = rs_f4(a.sR, f);
                 const rsrc_t rpr = rs_pub(a.pubR, ex, f);
-#pragma unroll
-                for (int j = 0; j < RNPT; ++j)
-                    if (amask & (1u << j)) ld64[qj(j)] = ldd<kPlain>(rx, gk(j));
-                for (int h = threadIdx.x; h < nhalo; h += RBS) {
+                // every load of the field is issued before the first LDS write: the
+                // ring slot of this thread (at most one), then x and b of the own
+                // nodes (a node outside the mesh reads element 0, never written)
+                int hq = -1;
+                double hx = 0.0;
+                if (threadIdx.x < nhalo) {
                     int lc, lr;
-                    if (!halo_slot(h, txa, tya, lc, lr)) continue;
-                    ld64[lidx(lc, lr)] = ldd<kCoherent>(rpx, ghalo(lc, lr));
+                    if (halo_slot(threadIdx.x, txa, tya, lc, lr)) {
+                        hq = lidx(lc, lr);
+                        hx = ldd<kCoherent>(rpx, ghalo(lc, lr));
+                    }
                 }
+                double xo[RNPT];
+                float bo[RNPT];
+#pragma unroll
+                for (int j = 0; j < RNPT; ++j) {
+                    const int kk = (amask & (1u << j)) ? gk(j) : 0;
+                    xo[j] = ldd<kPlain>(rx, kk);
+                    bo[j] = ldf<kPlain>(rb, kk);
+                }
+#pragma unroll
+                for (int j = 0; j < RNPT; ++j) {
+                    if (!(amask & (1u << j))) continue;
+                    ld64[qj(j)] = xo[j];
+                    lb[qj(j)] = bo[j];
+                }
+                if (hq >= 0) ld64[hq] = hx;
                 __syncthreads();
+                // b was staged in LDS with x: the loop issues no global load that would
+                // wait on its stores
 #pragma unroll 1
                 for (int j = 0; j < RNPT; ++j) {
                     if (!(amask & (1u << j))) continue;
@@ -409,7 +443,7 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                         ld64[q - 1], ld64[q + LW], ld64[q - LW], ld64[q + LW + 1],
                         ld64[q - LW - 1]);
                     const int kk = gk(j);
-                    const double bk = (double)ldf<kPlain>(rb, kk);
+                    const double bk = (double)lb[q];
                     const double r64 = bk - mx;
                     const float rt = (float)r64;
                     stf<kPlain>(rr, kk, rt);

@@ -64,6 +64,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row0 = (RNPT / 2) * wave;
     const int nhalo = 2 * (txa + 2) + 2 * tya;
+    static_assert(2 * (RX + 2) + 2 * RY <= RBS, "one ring slot per thread");
     auto nrow = [&](int j) { return row0 + (j >> 1); };
     auto ncol = [&](int j) { return lane + 64 * (j & 1); };
     auto active = [&](int j) { return nrow(j) < tya && ncol(j) < txa; };
@@ -82,14 +83,15 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     // LDS: stencil coefficients of the tile plus its left column and bottom row,
     // and one exchange area used as F FP32 planes or as one FP64 plane
     constexpr int CW = RX + 1, CN = (RY + 1) * (RX + 1);
-    constexpr size_t XB = (size_t)F * LH * LW * sizeof(float) > (size_t)LH * LW * sizeof(double)
-                              ? (size_t)F * LH * LW * sizeof(float)
-                              : (size_t)LH * LW * sizeof(double);
+    // xbuf: the F FP32 planes of the CG iterations, or (residual phase) one FP64
+    // plane of x followed by one FP32 plane of b
+    constexpr size_t XB = (size_t)(F > 3 ? F : 3) * LH * LW * sizeof(float);
     __shared__ float cf[4 * CN];
     __shared__ float dv[LH * LW];   // Jacobi inverse diagonal of the tile and its ring
     __shared__ __align__(16) unsigned char xbuf[XB];
     float* lf = (float*)xbuf;       // plane f at lf + f * LH * LW
     double* ld64 = (double*)xbuf;
+    float* lb = (float*)(ld64 + LH * LW);
     __shared__ double red_lds[(RBS / 64) * kNV];
     __shared__ double vals[kNV];
     __shared__ double s_bb[F], s_gam[F], s_alpha[F], s_relres[F], s_target[F];
@@ -265,11 +267,16 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         for (int f = 0; f < F; ++f) {
             if (s_done[f] || outer == 0) continue;
             const rsrc_t rx = rs_x64(f), rpx = rs_pubX(f);
+            // the field's loads go out together, ahead of its stores (a load issued
+            // after a store waits for it); a node outside the mesh reads element 0
+            double xo[RNPT];
+#pragma unroll
+            for (int j = 0; j < RNPT; ++j) xo[j] = ldd<kPlain>(rx, (amask & (1u << j)) ? gk(j) : 0);
 #pragma unroll
             for (int j = 0; j < RNPT; ++j) {
                 if (!(amask & (1u << j))) continue;
                 const int kk = gk(j);
-                const double xv = ldd<kPlain>(rx, kk) + (double)vd[f][j];
+                const double xv = xo[j] + (double)vd[f][j];
                 std8<kPlain>(rx, kk, xv);
                 if (bmask & (1u << j)) std8<kCoherent>(rpx, kk, xv);
             }
@@ -290,17 +297,37 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                 if (s_done[f]) continue;
                 const rsrc_t rx = rs_x64(f), rpx = rs_pubX(f), rb = rs_b(f), rd = rs_d(f);
                 const rsrc_t rpr = rs_pub(a.pubR, ex, f);
-#pragma unroll
-                for (int j = 0; j < RNPT; ++j)
-                    if (amask & (1u << j)) ld64[qj(j)] = ldd<kPlain>(rx, gk(j));
-                for (int h = threadIdx.x; h < nhalo; h += RBS) {
+                // every load of the field is issued before the first LDS write: the
+                // ring slot of this thread (at most one), then x and b of the own
+                // nodes (a node outside the mesh reads element 0, never written)
+                int hq = -1;
+                double hx = 0.0;
+                if (threadIdx.x < nhalo) {
                     int lc, lr;
-                    if (!halo_slot(h, txa, tya, lc, lr)) continue;
-                    ld64[lidx(lc, lr)] = ldd<kCoherent>(rpx, gidx(m, i0, j0, lc, lr));
+                    if (halo_slot(threadIdx.x, txa, tya, lc, lr)) {
+                        hq = lidx(lc, lr);
+                        hx = ldd<kCoherent>(rpx, gidx(m, i0, j0, lc, lr));
+                    }
                 }
+                double xo[RNPT];
+                float bo[RNPT];
+#pragma unroll
+                for (int j = 0; j < RNPT; ++j) {
+                    const int kk = (amask & (1u << j)) ? gk(j) : 0;
+                    xo[j] = ldd<kPlain>(rx, kk);
+                    bo[j] = ldf<kPlain>(rb, kk);
+                }
+#pragma unroll
+                for (int j = 0; j < RNPT; ++j) {
+                    if (!(amask & (1u << j))) continue;
+                    ld64[qj(j)] = xo[j];
+                    lb[qj(j)] = bo[j];
+                }
+                if (hq >= 0) ld64[hq] = hx;
                 __syncthreads();
                 // the FP32 residual goes to the (now free) correction array xout and
-                // is loaded into registers after the barrier
+                // is loaded into registers after the barrier; b was staged in LDS with
+                // x, so the loop issues no global load that would wait on its stores
 #pragma unroll 1
                 for (int j = 0; j < RNPT; ++j) {
                     if (!(amask & (1u << j))) continue;
@@ -311,7 +338,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                         ld64[q - 1], ld64[q + LW], ld64[q - LW], ld64[q + LW + 1],
                         ld64[q - LW - 1]);
                     const int kk = gk(j);
-                    const double bk = (double)ldf<kPlain>(rb, kk);
+                    const double bk = (double)lb[q];
                     const double r64 = bk - mx;
                     const float rt = (float)r64;
                     stf<kPlain>(rd, kk, rt);
@@ -533,6 +560,12 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
             __syncthreads();
             if (!s_any) break;
         }
+        // the iteration state is dead until the next CG start sets it: constant
+        // here, it holds no registers through the fold and residual phases
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+#pragma unroll
+            for (int j = 0; j < RNPT; ++j) vp[f][j] = vs[f][j] = vr[f][j] = vw[f][j] = 0.f;
     }
 
     if (!alive && threadIdx.x == 0) s_flags |= P2M_FLAG_BREAKDOWN | P2M_FLAG_NOT_CONVERGED;
