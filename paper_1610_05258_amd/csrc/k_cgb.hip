@@ -162,6 +162,28 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
     auto rs_f8 = [&](double* base, int f) {
         return mkrs(base + (size_t)F * no + (size_t)f * nn, (size_t)nn * 8);
     };
+    // The streamed CG state (p, d, s, r, w) is tile-blocked: tile T's block of
+    // F x kTS floats holds field f at f * kTS, and this thread's nodes j = 0..3 and
+    // j = 4..7 in two runs of four at 4 t and 4 RBS + 4 t, so a thread moves its
+    // eight values of a vector with two 16-byte accesses.  Slots of nodes outside
+    // the mesh are moved too and read as 0.
+    static_assert(RNPT == 8, "two runs of four per thread");
+    constexpr int kTS = RBS * RNPT;
+    auto st_blk = [&](float* base, int ti, int f) {
+        return base + ((size_t)(g + ti * G) * F + f) * kTS + (size_t)threadIdx.x * 4;
+    };
+    auto ld8 = [&](const float* q, float (&v)[RNPT]) {
+        const float4 a0 = *reinterpret_cast<const float4*>(q);
+        const float4 a1 = *reinterpret_cast<const float4*>(q + RBS * 4);
+        const float t8[RNPT] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+        for (int j = 0; j < RNPT; ++j) v[j] = (amask & (1u << j)) ? t8[j] : 0.f;
+    };
+    auto st8 = [&](float* q, const float (&v)[RNPT]) {
+        *reinterpret_cast<float4*>(q) = make_float4(v[0], v[1], v[2], v[3]);
+        *reinterpret_cast<float4*>(q + RBS * 4) = make_float4(v[4], v[5], v[6], v[7]);
+    };
+    auto slot = [](int j) { return (j >> 2) * (RBS * 4) + (j & 3); };
     auto rs_pub = [&](float* base, int par, int f) {
         return mkrs(base + (size_t)2 * F * no + ((size_t)par * F + f) * nn, (size_t)nn * 4);
     };
@@ -177,15 +199,27 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
     auto load_coef = [&](bool with_dinv) {
         const float* c = a.coef + (size_t)4 * no;
         const float* w = a.w + no;
+        // every load before the first LDS write (a node outside the mesh reads
+        // element 0 and is not written)
+        float c0[RNPT], c1[RNPT], c2[RNPT], c3[RNPT], wv[RNPT];
+#pragma unroll
+        for (int j = 0; j < RNPT; ++j) {
+            const int kk = (amask & (1u << j)) ? gk(j) : 0;
+            c0[j] = c[kk];
+            c1[j] = c[(size_t)nn + kk];
+            c2[j] = c[(size_t)2 * nn + kk];
+            c3[j] = c[(size_t)3 * nn + kk];
+            wv[j] = with_dinv ? w[kk] : 0.f;
+        }
 #pragma unroll
         for (int j = 0; j < RNPT; ++j) {
             if (!(amask & (1u << j))) continue;
-            const int kk = gk(j), q = qcj(j);
-            cf[q] = c[kk];
-            if (with_dinv) dv[qj(j)] = jacobi_inv(c[kk], w[kk]);
-            cf[CN + q] = c[(size_t)nn + kk];
-            cf[2 * CN + q] = c[(size_t)2 * nn + kk];
-            cf[3 * CN + q] = c[(size_t)3 * nn + kk];
+            const int q = qcj(j);
+            cf[q] = c0[j];
+            if (with_dinv) dv[qj(j)] = jacobi_inv(c0[j], wv[j]);
+            cf[CN + q] = c1[j];
+            cf[2 * CN + q] = c2[j];
+            cf[3 * CN + q] = c3[j];
         }
         for (int h = threadIdx.x; h < txa + 1 + tya; h += RBS) {
             int lc, lr;
@@ -263,7 +297,6 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
         float* bb = a.b + (size_t)F * no;
         const float* w = a.w + no;
         double* x64 = a.x64 + (size_t)F * no;
-        float* sD = a.sD + (size_t)F * no;
 #pragma unroll
         for (int j = 0; j < RNPT; ++j) {
             if (!(amask & (1u << j))) continue;
@@ -286,7 +319,6 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                     x0 = (double)I.out[o];
                 }
                 x64[o] = x0;
-                sD[o] = 0.f;
                 // the start's boundary values for the first residual (the first
                 // fold, which would add d = 0, is skipped)
                 if (bmask & (1u << j)) std8<kCoherent>(rs_f8(a.pubX, f), kk, x0);
@@ -296,6 +328,10 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                 atomicOr(&I.rep->flags, (uint32_t)P2M_FLAG_ORPHAN);
             }
         }
+        // d = 0 (every slot of the tile's block)
+        const float zero8[RNPT] = {};
+#pragma unroll
+        for (int f = 0; f < F; ++f) st8(st_blk(a.sD, ti, f), zero8);
     }
     __syncthreads();
 
@@ -327,23 +363,21 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
     // the current tile's CG state (p, d, s, r, w) of every inner-active field into
     // the owner-only arrays, and its boundary (r, w, s) into the exchange planes
     // of parity ex ^ 1 (r only with_r: at the CG start it is already stored)
-    auto store_state = [&](uint32_t imask, bool with_r) {
+    auto store_state = [&](int ti, uint32_t imask, bool with_r) {
 #pragma unroll
         for (int f = 0; f < F; ++f) {
             if (!(imask & (1u << f))) continue;
             const rsrc_t rr = rs_pub(a.pubR, ex ^ 1, f), rw = rs_pub(a.pubW, ex ^ 1, f),
                          rs = rs_pub(a.pubS, ex ^ 1, f);
-            const rsrc_t sP = rs_f4(a.sP, f), sD = rs_f4(a.sD, f), sS = rs_f4(a.sS, f),
-                         sR = rs_f4(a.sR, f), sW = rs_f4(a.sW, f);
+            st8(st_blk(a.sP, ti, f), vp[f]);
+            st8(st_blk(a.sD, ti, f), vd[f]);
+            st8(st_blk(a.sS, ti, f), vs[f]);
+            if (with_r) st8(st_blk(a.sR, ti, f), vr[f]);
+            st8(st_blk(a.sW, ti, f), vw[f]);
 #pragma unroll
             for (int j = 0; j < RNPT; ++j) {
                 if (!(amask & (1u << j))) continue;
                 const int kk = gk(j);
-                stf<kPlain>(sP, kk, vp[f][j]);
-                stf<kPlain>(sD, kk, vd[f][j]);
-                stf<kPlain>(sS, kk, vs[f][j]);
-                if (with_r) stf<kPlain>(sR, kk, vr[f][j]);
-                stf<kPlain>(sW, kk, vw[f][j]);
                 if (bmask & (1u << j)) {
                     stf<kCoherent>(rr, kk, vr[f][j]);
                     stf<kCoherent>(rw, kk, vw[f][j]);
@@ -361,18 +395,15 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 if (s_done[k * F + f]) continue;
-                const rsrc_t rx = rs_f8(a.x64, f), rpx = rs_f8(a.pubX, f), rd = rs_f4(a.sD, f);
+                const rsrc_t rx = rs_f8(a.x64, f), rpx = rs_f8(a.pubX, f);
                 // the field's loads go out together, ahead of its stores (a load
                 // issued after a store waits for it); a node outside the mesh reads
                 // element 0
                 double xo[RNPT];
                 float dd[RNPT];
+                ld8(st_blk(a.sD, ti, f), dd);
 #pragma unroll
-                for (int j = 0; j < RNPT; ++j) {
-                    const int kk = (amask & (1u << j)) ? gk(j) : 0;
-                    xo[j] = ldd<kPlain>(rx, kk);
-                    dd[j] = ldf<kPlain>(rd, kk);
-                }
+                for (int j = 0; j < RNPT; ++j) xo[j] = ldd<kPlain>(rx, (amask & (1u << j)) ? gk(j) : 0);
 #pragma unroll
                 for (int j = 0; j < RNPT; ++j) {
                     if (!(amask & (1u << j))) continue;
@@ -400,8 +431,8 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 if (s_done[k * F + f]) continue;
-                const rsrc_t rx = rs_f8(a.x64, f), rpx = rs_f8(a.pubX, f), rb = rs_f4(a.b, f),
-                             rr = rs_f4(a.sR, f);
+                const rsrc_t rx = rs_f8(a.x64, f), rpx = rs_f8(a.pubX, f), rb = rs_f4(a.b, f);
+                float* const rr = st_blk(a.sR, ti, f);
                 const rsrc_t rpr = rs_pub(a.pubR, ex, f);
                 // every load of the field is issued before the first LDS write: the
                 // ring slot of this thread (at most one), then x and b of the own
@@ -446,7 +477,7 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                     const double bk = (double)lb[q];
                     const double r64 = bk - mx;
                     const float rt = (float)r64;
-                    stf<kPlain>(rr, kk, rt);
+                    rr[slot(j)] = rt;
                     pr[f] = sq_acc(pr[f], r64);
                     if (outer == 0) pr[2 * F + f] = sq_acc(pr[2 * F + f], bk);
                     if (bmask & (1u << j)) stf<kCoherent>(rpr, kk, rt);
@@ -502,15 +533,10 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
             for (int f = 0; f < F; ++f) {
                 if (!(imask & (1u << f))) continue;
                 float* L = lf + (size_t)f * LH * LW;
-                const rsrc_t rr = rs_f4(a.sR, f);
+                ld8(st_blk(a.sR, ti, f), vr[f]);
 #pragma unroll
-                for (int j = 0; j < RNPT; ++j) {
-                    vr[f][j] = 0.f;
-                    if (amask & (1u << j)) {
-                        vr[f][j] = ldf<kPlain>(rr, gk(j));
-                        L[qj(j)] = __fmul_rn(vr[f][j], dv[qj(j)]);
-                    }
-                }
+                for (int j = 0; j < RNPT; ++j)
+                    if (amask & (1u << j)) L[qj(j)] = __fmul_rn(vr[f][j], dv[qj(j)]);
             }
             for (int h = threadIdx.x; h < nhalo; h += RBS) {
                 int lc, lr;
@@ -545,7 +571,7 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
             __syncthreads();
             block_sum_to<2 * F>(pd, red_lds, tv);
             store_partials(ti, epoch + 1, 2 * F);
-            store_state(imask, false);
+            store_state(ti, imask, false);
         }
         ex ^= 1;
         alive = sync_batch(++epoch, 2 * F);
@@ -601,19 +627,17 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                 }
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
-                    const rsrc_t sP = rs_f4(a.sP, f), sD = rs_f4(a.sD, f), sS = rs_f4(a.sS, f),
-                                 sR = rs_f4(a.sR, f), sW = rs_f4(a.sW, f);
+                    if (!(imask & (1u << f))) {
 #pragma unroll
-                    for (int j = 0; j < RNPT; ++j) {
-                        vp[f][j] = vd[f][j] = vs[f][j] = vr[f][j] = vw[f][j] = 0.f;
-                        if (!(imask & (1u << f)) || !(amask & (1u << j))) continue;
-                        const int kk = gk(j);
-                        vp[f][j] = ldf<kPlain>(sP, kk);
-                        vd[f][j] = ldf<kPlain>(sD, kk);
-                        vs[f][j] = ldf<kPlain>(sS, kk);
-                        vr[f][j] = ldf<kPlain>(sR, kk);
-                        vw[f][j] = ldf<kPlain>(sW, kk);
+                        for (int j = 0; j < RNPT; ++j)
+                            vp[f][j] = vd[f][j] = vs[f][j] = vr[f][j] = vw[f][j] = 0.f;
+                        continue;
                     }
+                    ld8(st_blk(a.sP, ti, f), vp[f]);
+                    ld8(st_blk(a.sD, ti, f), vd[f]);
+                    ld8(st_blk(a.sS, ti, f), vs[f]);
+                    ld8(st_blk(a.sR, ti, f), vr[f]);
+                    ld8(st_blk(a.sW, ti, f), vw[f]);
                 }
                 {
                     int lc = 0, lr = 0;
@@ -691,7 +715,7 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                 store_partials(ti, epoch + 1, 3 * F);
                 // the tile's state and its published boundary go out last: a load
                 // issued after a store waits for it
-                store_state(imask, true);
+                store_state(ti, imask, true);
             }
             ex ^= 1;
             alive = sync_batch(++epoch, 3 * F);
@@ -814,7 +838,7 @@ int cgb_grid(int F, int ntiles, int device) {
 
 size_t cgb_workspace_bytes(int F, int nprob, int ntiles, size_t nodes) {
     size_t s = 0;
-    s += 5 * al((size_t)F * nodes * sizeof(float));       // p, d, s, r, w
+    s += 5 * al((size_t)F * ntiles * RX * RY * sizeof(float));   // p, d, s, r, w (tile-blocked)
     s += al((size_t)F * nodes * sizeof(double));          // x64
     s += 3 * al((size_t)2 * F * nodes * sizeof(float));   // pubR, pubW, pubS
     s += al((size_t)F * nodes * sizeof(double));          // pubX
@@ -898,7 +922,7 @@ hipError_t launch_cg_batch(int F, const BatchSolveBufs& bb, size_t nodes, int gr
     a.w = bb.w;
     a.start = start;
     a.opts = opts;
-    const size_t f4 = al((size_t)F * nodes * sizeof(float));
+    const size_t f4 = al((size_t)F * bb.ntiles * RX * RY * sizeof(float));
     a.sP = (float*)p; p += f4;
     a.sD = (float*)p; p += f4;
     a.sS = (float*)p; p += f4;
