@@ -373,8 +373,8 @@ struct BatchPlan {
     int nlb = 0, nat = 0, nrt = 0;       // locate blocks, scatter tiles, solver tiles
     int grid = 0;                        // workgroups of the batched solve
     std::vector<BatchInst> inst;
-    std::vector<int32_t> lmap, amap, rmap;
-    size_t inst_b = 0, lmap_b = 0, amap_b = 0, rmap_b = 0;   // upload sections
+    std::vector<int32_t> lmap, amap, rmap, omap;
+    size_t inst_b = 0, lmap_b = 0, amap_b = 0, rmap_b = 0, omap_b = 0;   // upload sections
     size_t o_key = 0, o_counts = 0, o_cs = 0, o_perm = 0, o_scan = 0, o_b = 0, o_w = 0,
            o_coef = 0, o_solve = 0, total = 0;
 };
@@ -447,6 +447,32 @@ p2m_status plan_batch(const Context* c, const p2m_problem* probs, int nprob, int
         for (int t = 0; t < I.atx * ts2; ++t) P.amap[I.at + t] = k;
         for (int t = 0; t < I.nrt; ++t) P.rmap[I.rt + t] = k;
     }
+    // Dealing order of the solver tiles (workgroup g owns the tiles at positions
+    // g, g + grid, ...): instances with fewer particles per node first (they need
+    // the most CG iterations, so their tiles should sit on distinct workgroups), then
+    // instances with more tiles, then by index.  Ownership changes no arithmetic.
+    {
+        std::vector<int> ord(nprob);
+        for (int k = 0; k < nprob; ++k) ord[k] = k;
+        auto before = [&](int x, int y) {
+            const BatchInst& X = P.inst[x];
+            const BatchInst& Y = P.inst[y];
+            const long long lx = (long long)X.m.np * Y.m.nn, ly = (long long)Y.m.np * X.m.nn;
+            if (lx != ly) return lx < ly;
+            if (X.nrt != Y.nrt) return X.nrt > Y.nrt;
+            return x < y;
+        };
+        for (int i = 1; i < nprob; ++i)   // insertion sort: nprob <= 128, stable
+            for (int j = i; j > 0 && before(ord[j], ord[j - 1]); --j) {
+                const int t = ord[j];
+                ord[j] = ord[j - 1];
+                ord[j - 1] = t;
+            }
+        P.omap.clear();
+        P.omap.reserve(P.nrt);
+        for (int k : ord)
+            for (int t = 0; t < P.inst[k].nrt; ++t) P.omap.push_back(P.inst[k].rt + t);
+    }
     P.grid = cgb_grid(F, P.nrt, c->device);
     if (P.grid < 1) return P2M_ERR_UNSUPPORTED;
     size_t off = 0;
@@ -459,7 +485,8 @@ p2m_status plan_batch(const Context* c, const p2m_problem* probs, int nprob, int
     P.lmap_b = align_up(sizeof(int32_t) * P.nlb);
     P.amap_b = align_up(sizeof(int32_t) * P.nat);
     P.rmap_b = align_up(sizeof(int32_t) * P.nrt);
-    take(P.inst_b + P.lmap_b + P.amap_b + P.rmap_b);
+    P.omap_b = align_up(sizeof(int32_t) * P.nrt);
+    take(P.inst_b + P.lmap_b + P.amap_b + P.rmap_b + P.omap_b);
     P.o_key = take(sizeof(int32_t) * 2 * (size_t)np);      // keys, then in-cell ranks
     P.o_counts = take(sizeof(int32_t) * (size_t)nn);
     P.o_scan = take(scan_workspace_bytes((int)nn));   // right after counts: one fill clears both
@@ -480,6 +507,7 @@ hipError_t enqueue_batch(const BatchPlan& P, char* ws, p2m_report* reps, const p
     const int32_t* lmap = (const int32_t*)(ws + P.inst_b);
     const int32_t* amap = (const int32_t*)(ws + P.inst_b + P.lmap_b);
     const int32_t* rmap = (const int32_t*)(ws + P.inst_b + P.lmap_b + P.amap_b);
+    const int32_t* omap = (const int32_t*)(ws + P.inst_b + P.lmap_b + P.amap_b + P.rmap_b);
     int32_t* key = (int32_t*)(ws + P.o_key);
     int32_t* counts = (int32_t*)(ws + P.o_counts);
     int32_t* cs = (int32_t*)(ws + P.o_cs);
@@ -506,6 +534,7 @@ hipError_t enqueue_batch(const BatchPlan& P, char* ws, p2m_report* reps, const p
     bb.inst = inst;
     bb.nprob = P.nprob;
     bb.rmap = rmap;
+    bb.order = omap;
     bb.ntiles = P.nrt;
     bb.coef = coef;
     bb.b = b;
@@ -780,12 +809,14 @@ p2m_status p2m_mass_assign_batched(void* ctx, const p2m_problem* probs, int32_t 
     if (!bc.exec || key != bc.key) {
         bc.release();
         // the instance table and tile maps go to the head of the workspace
-        bc.upload.assign(P.inst_b + P.lmap_b + P.amap_b + P.rmap_b, 0);
+        bc.upload.assign(P.inst_b + P.lmap_b + P.amap_b + P.rmap_b + P.omap_b, 0);
         unsigned char* u = bc.upload.data();
         memcpy(u, P.inst.data(), sizeof(BatchInst) * P.nprob);
         memcpy(u + P.inst_b, P.lmap.data(), sizeof(int32_t) * P.nlb);
         memcpy(u + P.inst_b + P.lmap_b, P.amap.data(), sizeof(int32_t) * P.nat);
         memcpy(u + P.inst_b + P.lmap_b + P.amap_b, P.rmap.data(), sizeof(int32_t) * P.nrt);
+        memcpy(u + P.inst_b + P.lmap_b + P.amap_b + P.rmap_b, P.omap.data(),
+               sizeof(int32_t) * P.nrt);
         P2M_TRY(hipMemcpyAsync(ws, u, bc.upload.size(), hipMemcpyHostToDevice, strm));
         P2M_TRY(hipStreamSynchronize(strm));
         P2M_TRY(hipStreamBeginCapture(bc.capture, hipStreamCaptureModeThreadLocal));

@@ -39,6 +39,7 @@ struct BArgs {
     const BatchInst* inst;
     int nprob;
     const int32_t* rmap;
+    const int32_t* order;   // dealing order of the tiles (null: 0, 1, 2, ...)
     int ntiles;
     float* coef;        // [4][nn] blocks at 4*no (orphan diagonals set to 1 here)
     float* b;           // [F][nn] blocks at F*no (orphan entries set to 0 here)
@@ -85,9 +86,8 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
     __shared__ unsigned char s_done[kBatchMaxPairs], s_inner[kBatchMaxPairs],
         s_zero[kBatchMaxPairs];
     __shared__ uint32_t s_flags[kBatchMaxInstances];
-    // the tiles of this workgroup: instance, origin, mesh size, node offset
-    __shared__ int t_k[kBatchMaxOwn], t_i0[kBatchMaxOwn], t_j0[kBatchMaxOwn],
-        t_nx[kBatchMaxOwn], t_ny[kBatchMaxOwn], t_no[kBatchMaxOwn];
+    // the tiles of this workgroup: instance and tile number inside the instance
+    __shared__ int t_k[kBatchMaxOwn], t_lt[kBatchMaxOwn];
     __shared__ int s_nown, s_ok;
 
     const int nprob = a.nprob;
@@ -103,16 +103,11 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
     // ---- set-up: own tiles, instance runs, per-pair state ---------------------
     if (threadIdx.x == 0) {
         int n = 0;
-        for (int t = g; t < a.ntiles; t += G) {
+        for (int i = g; i < a.ntiles; i += G) {
+            const int t = a.order ? a.order[i] : i;
             const int k = a.rmap[t];
-            const BatchInst& I = a.inst[k];
-            const int lt = t - I.rt;
             t_k[n] = k;
-            t_i0[n] = (lt % I.rtx) * RX;
-            t_j0[n] = (lt / I.rtx) * RY;
-            t_nx[n] = I.m.nx;
-            t_ny[n] = I.m.ny;
-            t_no[n] = I.no;
+            t_lt[n] = t - a.inst[k].rt;
             ++n;
         }
         s_nown = n;
@@ -129,8 +124,17 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
     int k = 0, i0 = 0, j0 = 0, nx = 0, ny = 0, no = 0, nn = 0, txa = 0, tya = 0, nhalo = 0;
     uint32_t amask = 0, bmask = 0;
     int kb = 0;
+    int cur = 0;   // the current tile's number in the batch
     auto set_tile = [&](int ti) {
-        k = t_k[ti]; i0 = t_i0[ti]; j0 = t_j0[ti]; nx = t_nx[ti]; ny = t_ny[ti]; no = t_no[ti];
+        k = t_k[ti];
+        const int lt = t_lt[ti];
+        const BatchInst& I = a.inst[k];
+        i0 = (lt % I.rtx) * RX;
+        j0 = (lt / I.rtx) * RY;
+        nx = I.m.nx;
+        ny = I.m.ny;
+        no = I.no;
+        cur = I.rt + lt;
         nn = nx * ny;
         txa = min(RX, nx - i0);
         tya = min(RY, ny - j0);
@@ -169,8 +173,8 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
     // the mesh are moved too and read as 0.
     static_assert(RNPT == 8, "two runs of four per thread");
     constexpr int kTS = RBS * RNPT;
-    auto st_blk = [&](float* base, int ti, int f) {
-        return base + ((size_t)(g + ti * G) * F + f) * kTS + (size_t)threadIdx.x * 4;
+    auto st_blk = [&](float* base, int f) {
+        return base + ((size_t)cur * F + f) * kTS + (size_t)threadIdx.x * 4;
     };
     auto ld8 = [&](const float* q, float (&v)[RNPT]) {
         const float4 a0 = *reinterpret_cast<const float4*>(q);
@@ -239,10 +243,9 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
             }
     };
     // store the current tile's block sums tv[0..nv) as its partials
-    auto store_partials = [&](int ti, unsigned epoch, int nv) {
-        const int tile = g + ti * G;
+    auto store_partials = [&](unsigned epoch, int nv) {
         double* part = a.sy.part + (size_t)(epoch & 1) * a.ntiles * kNV;
-        if (threadIdx.x < nv) st_c(&part[(size_t)tile * kNV + threadIdx.x], tv[threadIdx.x]);
+        if (threadIdx.x < nv) st_c(&part[(size_t)cur * kNV + threadIdx.x], tv[threadIdx.x]);
     };
 
     // Synchronisation `epoch` with nv values per instance: barrier (partials
@@ -331,7 +334,7 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
         // d = 0 (every slot of the tile's block)
         const float zero8[RNPT] = {};
 #pragma unroll
-        for (int f = 0; f < F; ++f) st8(st_blk(a.sD, ti, f), zero8);
+        for (int f = 0; f < F; ++f) st8(st_blk(a.sD, f), zero8);
     }
     __syncthreads();
 
@@ -363,17 +366,17 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
     // the current tile's CG state (p, d, s, r, w) of every inner-active field into
     // the owner-only arrays, and its boundary (r, w, s) into the exchange planes
     // of parity ex ^ 1 (r only with_r: at the CG start it is already stored)
-    auto store_state = [&](int ti, uint32_t imask, bool with_r) {
+    auto store_state = [&](uint32_t imask, bool with_r) {
 #pragma unroll
         for (int f = 0; f < F; ++f) {
             if (!(imask & (1u << f))) continue;
             const rsrc_t rr = rs_pub(a.pubR, ex ^ 1, f), rw = rs_pub(a.pubW, ex ^ 1, f),
                          rs = rs_pub(a.pubS, ex ^ 1, f);
-            st8(st_blk(a.sP, ti, f), vp[f]);
-            st8(st_blk(a.sD, ti, f), vd[f]);
-            st8(st_blk(a.sS, ti, f), vs[f]);
-            if (with_r) st8(st_blk(a.sR, ti, f), vr[f]);
-            st8(st_blk(a.sW, ti, f), vw[f]);
+            st8(st_blk(a.sP, f), vp[f]);
+            st8(st_blk(a.sD, f), vd[f]);
+            st8(st_blk(a.sS, f), vs[f]);
+            if (with_r) st8(st_blk(a.sR, f), vr[f]);
+            st8(st_blk(a.sW, f), vw[f]);
 #pragma unroll
             for (int j = 0; j < RNPT; ++j) {
                 if (!(amask & (1u << j))) continue;
@@ -401,7 +404,7 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                 // element 0
                 double xo[RNPT];
                 float dd[RNPT];
-                ld8(st_blk(a.sD, ti, f), dd);
+                ld8(st_blk(a.sD, f), dd);
 #pragma unroll
                 for (int j = 0; j < RNPT; ++j) xo[j] = ldd<kPlain>(rx, (amask & (1u << j)) ? gk(j) : 0);
 #pragma unroll
@@ -432,7 +435,7 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
             for (int f = 0; f < F; ++f) {
                 if (s_done[k * F + f]) continue;
                 const rsrc_t rx = rs_f8(a.x64, f), rpx = rs_f8(a.pubX, f), rb = rs_f4(a.b, f);
-                float* const rr = st_blk(a.sR, ti, f);
+                float* const rr = st_blk(a.sR, f);
                 const rsrc_t rpr = rs_pub(a.pubR, ex, f);
                 // every load of the field is issued before the first LDS write: the
                 // ring slot of this thread (at most one), then x and b of the own
@@ -485,7 +488,7 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                 __syncthreads();
             }
             block_sum_to<3 * F>(pr, red_lds, tv);
-            store_partials(ti, epoch + 1, 3 * F);
+            store_partials(epoch + 1, 3 * F);
         }
         alive = sync_batch(++epoch, 3 * F);
         if (!alive) break;
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
             for (int f = 0; f < F; ++f) {
                 if (!(imask & (1u << f))) continue;
                 float* L = lf + (size_t)f * LH * LW;
-                ld8(st_blk(a.sR, ti, f), vr[f]);
+                ld8(st_blk(a.sR, f), vr[f]);
 #pragma unroll
                 for (int j = 0; j < RNPT; ++j)
                     if (amask & (1u << j)) L[qj(j)] = __fmul_rn(vr[f][j], dv[qj(j)]);
@@ -570,8 +573,8 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
             }
             __syncthreads();
             block_sum_to<2 * F>(pd, red_lds, tv);
-            store_partials(ti, epoch + 1, 2 * F);
-            store_state(ti, imask, false);
+            store_partials(epoch + 1, 2 * F);
+            store_state(imask, false);
         }
         ex ^= 1;
         alive = sync_batch(++epoch, 2 * F);
@@ -633,11 +636,11 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                             vp[f][j] = vd[f][j] = vs[f][j] = vr[f][j] = vw[f][j] = 0.f;
                         continue;
                     }
-                    ld8(st_blk(a.sP, ti, f), vp[f]);
-                    ld8(st_blk(a.sD, ti, f), vd[f]);
-                    ld8(st_blk(a.sS, ti, f), vs[f]);
-                    ld8(st_blk(a.sR, ti, f), vr[f]);
-                    ld8(st_blk(a.sW, ti, f), vw[f]);
+                    ld8(st_blk(a.sP, f), vp[f]);
+                    ld8(st_blk(a.sD, f), vd[f]);
+                    ld8(st_blk(a.sS, f), vs[f]);
+                    ld8(st_blk(a.sR, f), vr[f]);
+                    ld8(st_blk(a.sW, f), vw[f]);
                 }
                 {
                     int lc = 0, lr = 0;
@@ -712,10 +715,10 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                 }
                 __syncthreads();
                 block_sum_to<3 * F>(pg, red_lds, tv);
-                store_partials(ti, epoch + 1, 3 * F);
+                store_partials(epoch + 1, 3 * F);
                 // the tile's state and its published boundary go out last: a load
                 // issued after a store waits for it
-                store_state(ti, imask, true);
+                store_state(imask, true);
             }
             ex ^= 1;
             alive = sync_batch(++epoch, 3 * F);
@@ -896,6 +899,7 @@ hipError_t launch_cg_tiles(const Mesh& m, int F, float* coef, float* b, const fl
     bb.inst = tbl;
     bb.nprob = 1;
     bb.rmap = rmap;
+    bb.order = nullptr;
     bb.ntiles = nt;
     bb.coef = coef;
     bb.b = b;
@@ -916,6 +920,7 @@ hipError_t launch_cg_batch(int F, const BatchSolveBufs& bb, size_t nodes, int gr
     a.inst = bb.inst;
     a.nprob = bb.nprob;
     a.rmap = bb.rmap;
+    a.order = bb.order;
     a.ntiles = bb.ntiles;
     a.coef = bb.coef;
     a.b = bb.b;

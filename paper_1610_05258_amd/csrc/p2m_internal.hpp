@@ -213,6 +213,7 @@ struct BatchSolveBufs {
     const BatchInst* inst;
     int nprob;
     const int32_t* rmap;   // solver tile -> instance
+    const int32_t* order = nullptr;  // dealing order of the solver tiles (null: 0, 1, 2, ...)
     int ntiles;
     float* coef;           // instance blocks [4][nn] at 4*no
     float* b;              // [F][nn] at F*no
