@@ -39,15 +39,40 @@ struct RArgs {
     const float* w;    // [nn]
     float* xout;       // [F][nn]  start (USER) on entry, result on exit
     double* x64;       // [F][nn]  FP64 solution, owner-only
-    float* pubR;       // [2][F][nn] published boundary values
+    float* pubR;       // [2][F][nn] published values of the boundary rows
     float* pubW;
     float* pubS;
+    float* pubC;       // [2][nn][rec_floats(F)] published records of the boundary columns
     double* pubX;      // [F][nn]
     RSync sy;
     int start;
     p2m_solve_opts opts;
     p2m_report* rep;
 };
+
+// A boundary column's (r, w, s) are published as one record per node (r at f, w at
+// F + f, s at 2F + f, padded to whole 16-byte units): a neighbour reads a ring
+// column slot with dwordx4 loads from one place instead of 3F scattered words.  The
+// boundary rows stay in field planes, where a wave's accesses are contiguous.
+constexpr int rec_floats(int F) { return (3 * F + 3) / 4 * 4; }
+struct F4 {
+    float v[4];
+};
+// 16 bytes at byte offset vo + so (so uniform, kept out of the per-lane address); the
+// result is read through a bit cast to a plain struct (element access on the
+// builtin's vector result is lowered to a single-dword load by this compiler)
+template <int AUX>
+__device__ __forceinline__ void ld4f(rsrc_t r, int vo, int so, float* o) {
+    const F4 q = __builtin_bit_cast(F4, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, AUX));
+    o[0] = q.v[0];
+    o[1] = q.v[1];
+    o[2] = q.v[2];
+    o[3] = q.v[3];
+}
+template <int AUX>
+__device__ __forceinline__ void st1f(rsrc_t r, int vo, int so, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, AUX);
+}
 
 template <int F>
 __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
@@ -78,6 +103,10 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     auto rs_pubX = [&](int f) { return mkrs(a.pubX + (size_t)f * nn, fb8); };
     auto rs_pub = [&](float* base, int par, int f) {
         return mkrs(base + ((size_t)par * F + f) * nn, fb4);
+    };
+    constexpr int RS = rec_floats(F);
+    auto rs_col = [&](int par) {
+        return mkrs(a.pubC + (size_t)par * nn * RS, (size_t)nn * RS * 4);
     };
 
     // LDS: stencil coefficients of the tile plus its left column and bottom row,
@@ -124,14 +153,17 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     }
     if (threadIdx.x == 0) s_flags = 0u;
 
-    uint32_t amask = 0, bmask = 0;  // active nodes; active nodes on the tile boundary
+    // active nodes; those on the tile boundary; on a boundary row; on a boundary column
+    uint32_t amask = 0, bmask = 0, rmask = 0, cmask = 0;
 #pragma unroll
     for (int j = 0; j < RNPT; ++j) {
         if (!active(j)) continue;
         amask |= 1u << j;
         const int lc = ncol(j), lr = nrow(j);
-        if (lc == 0 || lr == 0 || lc == txa - 1 || lr == tya - 1) bmask |= 1u << j;
+        if (lr == 0 || lr == tya - 1) rmask |= 1u << j;
+        if (lc == 0 || lc == txa - 1) cmask |= 1u << j;
     }
+    bmask = rmask | cmask;
 
     // left column / bottom row: only their E, N, NE are used, never modified here
     // (these loads go first: they do not depend on the P phase below)
@@ -249,13 +281,20 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         for (int f = 0; f < F; ++f) {
             if (!(imask & (1u << f))) continue;
             const rsrc_t rr = rs_pub(a.pubR, ex, f), rw = rs_pub(a.pubW, ex, f),
-                         rs = rs_pub(a.pubS, ex, f);
+                         rs = rs_pub(a.pubS, ex, f), rc = rs_col(ex);
 #pragma unroll
             for (int j = 0; j < RNPT; ++j) {
-                if (!(bmask & (1u << j))) continue;
-                stf<kCoherent>(rr, gk(j), vr[f][j]);
-                stf<kCoherent>(rw, gk(j), vw[f][j]);
-                stf<kCoherent>(rs, gk(j), vs[f][j]);
+                if (rmask & (1u << j)) {
+                    stf<kCoherent>(rr, gk(j), vr[f][j]);
+                    stf<kCoherent>(rw, gk(j), vw[f][j]);
+                    stf<kCoherent>(rs, gk(j), vs[f][j]);
+                }
+                if (cmask & (1u << j)) {
+                    const int vo = gk(j) * (RS * 4);
+                    st1f<kCoherent>(rc, vo, 4 * f, vr[f][j]);
+                    st1f<kCoherent>(rc, vo, 4 * (F + f), vw[f][j]);
+                    st1f<kCoherent>(rc, vo, 4 * (2 * F + f), vs[f][j]);
+                }
             }
         }
     };
@@ -296,7 +335,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
             for (int f = 0; f < F; ++f) {
                 if (s_done[f]) continue;
                 const rsrc_t rx = rs_x64(f), rpx = rs_pubX(f), rb = rs_b(f), rd = rs_d(f);
-                const rsrc_t rpr = rs_pub(a.pubR, ex, f);
+                const rsrc_t rpr = rs_pub(a.pubR, ex, f), rpc = rs_col(ex);
                 // every load of the field is issued before the first LDS write: the
                 // ring slot of this thread (at most one), then x and b of the own
                 // nodes (a node outside the mesh reads element 0, never written)
@@ -344,7 +383,8 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     stf<kPlain>(rd, kk, rt);
                     pr[f] = sq_acc(pr[f], r64);
                     if (outer == 0) pr[2 * F + f] = sq_acc(pr[2 * F + f], bk);
-                    if (bmask & (1u << j)) stf<kCoherent>(rpr, kk, rt);
+                    if (rmask & (1u << j)) stf<kCoherent>(rpr, kk, rt);
+                    if (cmask & (1u << j)) st1f<kCoherent>(rpc, kk * (RS * 4), 4 * f, rt);
                 }
                 __syncthreads();
             }
@@ -400,8 +440,15 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
             if (!halo_slot(h, txa, tya, lc, lr)) continue;
             const int gh = gidx(m, i0, j0, lc, lr);
             float hv[F];
+            if (lr >= 0 && lr < tya) {   // a column slot: the neighbour's record
+                float rec[4];
+                ld4f<kCoherent>(rs_col(ex), gh * (RS * 4), 0, rec);
 #pragma unroll
-            for (int f = 0; f < F; ++f) hv[f] = ldf<kCoherent>(rs_pub(a.pubR, ex, f), gh);
+                for (int f = 0; f < F; ++f) hv[f] = rec[f];
+            } else {
+#pragma unroll
+                for (int f = 0; f < F; ++f) hv[f] = ldf<kCoherent>(rs_pub(a.pubR, ex, f), gh);
+            }
             const float dh = dv[lidx(lc, lr)];
 #pragma unroll
             for (int f = 0; f < F; ++f)
@@ -479,11 +526,24 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                 if (!halo_slot(h, txa, tya, lc, lr)) continue;
                 const int gh = gidx(m, i0, j0, lc, lr);
                 float ro[F], wo[F], so[F];
+                if (lr >= 0 && lr < tya) {   // a column slot: the neighbour's record
+                    float rec[RS];
+                    const rsrc_t rc = rs_col(ex);
 #pragma unroll
-                for (int f = 0; f < F; ++f) {
-                    ro[f] = ldf<kCoherent>(rs_pub(a.pubR, ex, f), gh);
-                    wo[f] = ldf<kCoherent>(rs_pub(a.pubW, ex, f), gh);
-                    so[f] = ldf<kCoherent>(rs_pub(a.pubS, ex, f), gh);
+                    for (int c = 0; c < RS / 4; ++c) ld4f<kCoherent>(rc, gh * (RS * 4), 16 * c, rec + 4 * c);
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        ro[f] = rec[f];
+                        wo[f] = rec[F + f];
+                        so[f] = rec[2 * F + f];
+                    }
+                } else {
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        ro[f] = ldf<kCoherent>(rs_pub(a.pubR, ex, f), gh);
+                        wo[f] = ldf<kCoherent>(rs_pub(a.pubW, ex, f), gh);
+                        so[f] = ldf<kCoherent>(rs_pub(a.pubS, ex, f), gh);
+                    }
                 }
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
@@ -632,6 +692,7 @@ size_t cgr_workspace_bytes(const Mesh& m, int F, int blocks) {
     size_t s = 0;
     s += al((size_t)F * m.nn * sizeof(double));           // x64
     s += 3 * al((size_t)2 * F * m.nn * sizeof(float));    // pubR, pubW, pubS
+    s += al((size_t)2 * m.nn * rec_floats(F) * sizeof(float));   // pubC
     s += al((size_t)F * m.nn * sizeof(double));           // pubX
     s += al((size_t)kGroups * 32 * sizeof(unsigned));     // ctr
     s += 3 * al(32 * sizeof(unsigned));                   // root, rel, abort
@@ -675,6 +736,7 @@ hipError_t launch_cg_resident(const Mesh& m, int F, float* coef, float* b, const
     a.pubR = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubW = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubS = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
+    a.pubC = (float*)p; p += al((size_t)2 * m.nn * rec_floats(F) * sizeof(float));
     a.pubX = (double*)p; p += al((size_t)F * m.nn * sizeof(double));
     a.sy.ctr = (unsigned*)p; p += al((size_t)kGroups * 32 * sizeof(unsigned));
     a.sy.root = (unsigned*)p; p += al(32 * sizeof(unsigned));
