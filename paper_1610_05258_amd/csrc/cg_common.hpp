@@ -101,6 +101,30 @@ __device__ __forceinline__ double row_sum16(double s) {
     return s;
 }
 
+// A boundary column's (r, w, s) are published as one record per node (r at f, w at
+// F + f, s at 2F + f, padded to whole 16-byte units): a neighbour reads a ring
+// column slot with dwordx4 loads from one place instead of 3F scattered words.  The
+// boundary rows stay in field planes, where a wave's accesses are contiguous.
+constexpr int rec_floats(int F) { return (3 * F + 3) / 4 * 4; }
+struct F4 {
+    float v[4];
+};
+// 16 bytes at byte offset vo + so (so uniform, kept out of the per-lane address); the
+// result is read through a bit cast to a plain struct (element access on the
+// builtin's vector result is lowered to a single-dword load by this compiler)
+template <int AUX>
+__device__ __forceinline__ void ld4f(rsrc_t r, int vo, int so, float* o) {
+    const F4 q = __builtin_bit_cast(F4, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, AUX));
+    o[0] = q.v[0];
+    o[1] = q.v[1];
+    o[2] = q.v[2];
+    o[3] = q.v[3];
+}
+template <int AUX>
+__device__ __forceinline__ void st1f(rsrc_t r, int vo, int so, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, AUX);
+}
+
 // Block sum of NV doubles per thread in a fixed order; totals land in out[0..NV).
 // Per wave: the four row sums (row_sum16) added as (r0 + r1) + (r2 + r3); then the
 // waves' sums in wave order.

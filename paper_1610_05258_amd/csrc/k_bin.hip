@@ -62,7 +62,7 @@ __device__ __forceinline__ uint64_t match_any(int key, bool active) {
     uint64_t mine = 0;
     while (remaining) {
         const int leader = __ffsll((unsigned long long)remaining) - 1;
-        const int lkey = __shfl(key, leader, 64);
+        const int lkey = __builtin_amdgcn_readlane(key, leader);   // leader is wave-uniform
         const bool same = active && key == lkey;
         const uint64_t grp = __ballot(same);
         if (same) mine = grp;

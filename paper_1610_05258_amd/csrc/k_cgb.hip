@@ -50,9 +50,10 @@ struct BArgs {
     float* sR;
     float* sW;
     double* x64;        // [F][nn] blocks at F*no, owner-only
-    float* pubR;        // [2][F][nn] blocks at 2*F*no, published boundary values
+    float* pubR;        // [2][F][nn] blocks at 2*F*no, published boundary-row values
     float* pubW;
     float* pubS;
+    float* pubC;        // [2][nn][rec_floats(F)] blocks at 2*rec_floats(F)*no, boundary-column records
     double* pubX;       // [F][nn] blocks at F*no
     RSync sy;           // part: [2][ntiles][kNV]; tot: [2][nprob][kNV]
     int start;
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
 
     // per-tile geometry and masks of this thread
     int k = 0, i0 = 0, j0 = 0, nx = 0, ny = 0, no = 0, nn = 0, txa = 0, tya = 0, nhalo = 0;
-    uint32_t amask = 0, bmask = 0;
+    uint32_t amask = 0, bmask = 0, rmask = 0, cmask = 0;   // active; boundary; boundary row; column
     int kb = 0;
     int cur = 0;   // the current tile's number in the batch
     auto set_tile = [&](int ti) {
@@ -140,14 +141,17 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
         tya = min(RY, ny - j0);
         nhalo = 2 * (txa + 2) + 2 * tya;
         amask = 0;
-        bmask = 0;
+        rmask = 0;
+        cmask = 0;
 #pragma unroll
         for (int j = 0; j < RNPT; ++j) {
             const int lc = ncol(j), lr = nrow(j);
             if (!(lr < tya && lc < txa)) continue;
             amask |= 1u << j;
-            if (lc == 0 || lr == 0 || lc == txa - 1 || lr == tya - 1) bmask |= 1u << j;
+            if (lr == 0 || lr == tya - 1) rmask |= 1u << j;
+            if (lc == 0 || lc == txa - 1) cmask |= 1u << j;
         }
+        bmask = rmask | cmask;
         kb = (j0 + row0) * nx + i0 + lane;
     };
     auto gk = [&](int j) { return kb + (j >> 1) * nx + 64 * (j & 1); };
@@ -190,6 +194,10 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
     auto slot = [](int j) { return (j >> 2) * (RBS * 4) + (j & 3); };
     auto rs_pub = [&](float* base, int par, int f) {
         return mkrs(base + (size_t)2 * F * no + ((size_t)par * F + f) * nn, (size_t)nn * 4);
+    };
+    constexpr int RS = rec_floats(F);
+    auto rs_col = [&](int par) {
+        return mkrs(a.pubC + (size_t)2 * RS * no + (size_t)par * nn * RS, (size_t)nn * RS * 4);
     };
     auto inner_mask = [&]() {
         uint32_t mk = 0;
@@ -371,7 +379,7 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
         for (int f = 0; f < F; ++f) {
             if (!(imask & (1u << f))) continue;
             const rsrc_t rr = rs_pub(a.pubR, ex ^ 1, f), rw = rs_pub(a.pubW, ex ^ 1, f),
-                         rs = rs_pub(a.pubS, ex ^ 1, f);
+                         rs = rs_pub(a.pubS, ex ^ 1, f), rc = rs_col(ex ^ 1);
             st8(st_blk(a.sP, f), vp[f]);
             st8(st_blk(a.sD, f), vd[f]);
             st8(st_blk(a.sS, f), vs[f]);
@@ -381,10 +389,16 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
             for (int j = 0; j < RNPT; ++j) {
                 if (!(amask & (1u << j))) continue;
                 const int kk = gk(j);
-                if (bmask & (1u << j)) {
+                if (rmask & (1u << j)) {
                     stf<kCoherent>(rr, kk, vr[f][j]);
                     stf<kCoherent>(rw, kk, vw[f][j]);
                     stf<kCoherent>(rs, kk, vs[f][j]);
+                }
+                if (cmask & (1u << j)) {
+                    const int vo = kk * (RS * 4);
+                    st1f<kCoherent>(rc, vo, 4 * f, vr[f][j]);
+                    st1f<kCoherent>(rc, vo, 4 * (F + f), vw[f][j]);
+                    st1f<kCoherent>(rc, vo, 4 * (2 * F + f), vs[f][j]);
                 }
             }
         }
@@ -436,7 +450,7 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                 if (s_done[k * F + f]) continue;
                 const rsrc_t rx = rs_f8(a.x64, f), rpx = rs_f8(a.pubX, f), rb = rs_f4(a.b, f);
                 float* const rr = st_blk(a.sR, f);
-                const rsrc_t rpr = rs_pub(a.pubR, ex, f);
+                const rsrc_t rpr = rs_pub(a.pubR, ex, f), rpc = rs_col(ex);
                 // every load of the field is issued before the first LDS write: the
                 // ring slot of this thread (at most one), then x and b of the own
                 // nodes (a node outside the mesh reads element 0, never written)
@@ -483,7 +497,8 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                     rr[slot(j)] = rt;
                     pr[f] = sq_acc(pr[f], r64);
                     if (outer == 0) pr[2 * F + f] = sq_acc(pr[2 * F + f], bk);
-                    if (bmask & (1u << j)) stf<kCoherent>(rpr, kk, rt);
+                    if (rmask & (1u << j)) stf<kCoherent>(rpr, kk, rt);
+                    if (cmask & (1u << j)) st1f<kCoherent>(rpc, kk * (RS * 4), 4 * f, rt);
                 }
                 __syncthreads();
             }
@@ -546,8 +561,15 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                 if (!halo_slot(h, txa, tya, lc, lr)) continue;
                 const int gh = ghalo(lc, lr);
                 float hv[F];
+                if (lr >= 0 && lr < tya) {   // a column slot: the neighbour's record
+                    float rec[4];
+                    ld4f<kCoherent>(rs_col(ex), gh * (RS * 4), 0, rec);
 #pragma unroll
-                for (int f = 0; f < F; ++f) hv[f] = ldf<kCoherent>(rs_pub(a.pubR, ex, f), gh);
+                    for (int f = 0; f < F; ++f) hv[f] = rec[f];
+                } else {
+#pragma unroll
+                    for (int f = 0; f < F; ++f) hv[f] = ldf<kCoherent>(rs_pub(a.pubR, ex, f), gh);
+                }
                 const float dh = dv[lidx(lc, lr)];
 #pragma unroll
                 for (int f = 0; f < F; ++f)
@@ -650,11 +672,25 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
                         // fix in this launch: the orphan test reads w, never rewritten
                         const float dh = jacobi_inv(c[gh], w[gh]);
                         float ro[F], wo[F], so[F];
+                        if (lr >= 0 && lr < tya) {   // a column slot: the neighbour's record
+                            float rec[RS];
+                            const rsrc_t rc = rs_col(ex);
 #pragma unroll
-                        for (int f = 0; f < F; ++f) {
-                            ro[f] = ldf<kCoherent>(rs_pub(a.pubR, ex, f), gh);
-                            wo[f] = ldf<kCoherent>(rs_pub(a.pubW, ex, f), gh);
-                            so[f] = ldf<kCoherent>(rs_pub(a.pubS, ex, f), gh);
+                            for (int c4 = 0; c4 < RS / 4; ++c4)
+                                ld4f<kCoherent>(rc, gh * (RS * 4), 16 * c4, rec + 4 * c4);
+#pragma unroll
+                            for (int f = 0; f < F; ++f) {
+                                ro[f] = rec[f];
+                                wo[f] = rec[F + f];
+                                so[f] = rec[2 * F + f];
+                            }
+                        } else {
+#pragma unroll
+                            for (int f = 0; f < F; ++f) {
+                                ro[f] = ldf<kCoherent>(rs_pub(a.pubR, ex, f), gh);
+                                wo[f] = ldf<kCoherent>(rs_pub(a.pubW, ex, f), gh);
+                                so[f] = ldf<kCoherent>(rs_pub(a.pubS, ex, f), gh);
+                            }
                         }
                         // edge coefficients: bottom row lc in [-1, txa), left column
                         // lr in [0, tya) (the only ring slots the stencil reads)
@@ -844,6 +880,7 @@ size_t cgb_workspace_bytes(int F, int nprob, int ntiles, size_t nodes) {
     s += 5 * al((size_t)F * ntiles * RX * RY * sizeof(float));   // p, d, s, r, w (tile-blocked)
     s += al((size_t)F * nodes * sizeof(double));          // x64
     s += 3 * al((size_t)2 * F * nodes * sizeof(float));   // pubR, pubW, pubS
+    s += al((size_t)2 * nodes * rec_floats(F) * sizeof(float));   // pubC
     s += al((size_t)F * nodes * sizeof(double));          // pubX
     s += al((size_t)kGroups * 32 * sizeof(unsigned));     // ctr
     s += 3 * al(32 * sizeof(unsigned));                   // root, rel, abort
@@ -937,6 +974,7 @@ hipError_t launch_cg_batch(int F, const BatchSolveBufs& bb, size_t nodes, int gr
     a.pubR = (float*)p; p += al((size_t)2 * F * nodes * sizeof(float));
     a.pubW = (float*)p; p += al((size_t)2 * F * nodes * sizeof(float));
     a.pubS = (float*)p; p += al((size_t)2 * F * nodes * sizeof(float));
+    a.pubC = (float*)p; p += al((size_t)2 * nodes * rec_floats(F) * sizeof(float));
     a.pubX = (double*)p; p += al((size_t)F * nodes * sizeof(double));
     a.sy.ctr = (unsigned*)p; p += al((size_t)kGroups * 32 * sizeof(unsigned));
     a.sy.root = (unsigned*)p; p += al(32 * sizeof(unsigned));
