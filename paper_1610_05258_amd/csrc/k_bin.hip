@@ -403,7 +403,21 @@ __global__ __launch_bounds__(kBlock) void k_segment_sort(int ncells,
         else if (n > 1) rank_sort_small(perm + s, n);
         return;
     }
-    for (int t = lo + (int)threadIdx.x; t < hi; t += kBlock) st[t - lo] = perm[t];
+    // every load of the stage goes out before the first LDS write (a loop that
+    // stores each load to LDS would wait for each load in turn)
+    constexpr int kStageIt = kSortStage / kBlock;
+    static_assert(kSortStage % kBlock == 0, "whole staging rounds");
+    int32_t tmp[kStageIt];
+#pragma unroll
+    for (int u = 0; u < kStageIt; ++u) {
+        const int t = lo + (int)threadIdx.x + u * kBlock;
+        tmp[u] = t < hi ? perm[t] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStageIt; ++u) {
+        const int t = lo + (int)threadIdx.x + u * kBlock;
+        if (t < hi) st[t - lo] = tmp[u];
+    }
     __syncthreads();
     bool moved = false;
     if (n > kSortReg) moved = insertion_sort(st + (s - lo), n);
