@@ -208,7 +208,6 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     x0 = (double)px[f][j];
                 }
                 a.x64[o] = x0;
-                a.xout[o] = 0.f;  // xout holds the FP32 correction d during the solve
                 // the start's boundary values for the first residual (the first
                 // fold, which would add d = 0, is skipped)
                 if (bmask & (1u << j)) std8<kCoherent>(rs_pubX(f), k, x0);
@@ -341,8 +340,8 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                 }
                 if (hq >= 0) ld64[hq] = hx;
                 __syncthreads();
-                // the FP32 residual goes to the (now free) correction array xout and
-                // is loaded into registers after the barrier; b was staged in LDS with
+                // the FP32 residual goes to the output array xout (unused until the
+                // result phase) and is loaded into registers after the barrier; b was staged in LDS with
                 // x, so the loop issues no global load that would wait on its stores
 #pragma unroll 1
                 for (int j = 0; j < RNPT; ++j) {
@@ -435,13 +434,9 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         for (int f = 0; f < F; ++f) {
             if (!(imask & (1u << f))) continue;
             float* L = lf + (size_t)f * LH * LW;
-            const rsrc_t rd = rs_d(f);
 #pragma unroll
-            for (int j = 0; j < RNPT; ++j) {
-                if (!(amask & (1u << j))) continue;
-                stf<kPlain>(rd, gk(j), 0.f);
-                L[qj(j)] = __fmul_rn(vr[f][j], dv[qj(j)]);
-            }
+            for (int j = 0; j < RNPT; ++j)
+                if (amask & (1u << j)) L[qj(j)] = __fmul_rn(vr[f][j], dv[qj(j)]);
         }
         __syncthreads();
         ex ^= 1;
