@@ -244,8 +244,8 @@ def main():
                          "(a kernel of known traffic for scaling memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design, not measured", file=sys.stderr)
+        print(f"bench.py: the path runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding across GPUs is designed, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
