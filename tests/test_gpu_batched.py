@@ -310,3 +310,31 @@ def test_batched_tune_plan(B, tmp_path):
     bt_user = B.Batch(tctx, probs, vals, B.solve_opts(tol=1e-6, start=B.START_USER))
     with pytest.raises(B.P2MError):
         bt_user.tune()
+
+
+def test_batched_at_capacity(B, ctx):
+    """128 instances x 2 fields = 256 (instance, field) pairs, the batch limits: every
+    instance equals its single-problem run bit for bit; a few against the oracle."""
+    g = np.random.Generator(np.random.PCG64(404))
+    sides = g.integers(12, 48, size=(128, 2))
+    ppcs = g.integers(2, 6, size=128)
+    insts = [tg_instance(500 + i, int(nx), int(ny), int(pc), 2)
+             for i, ((nx, ny), pc) in enumerate(zip(sides, ppcs))]
+    say(f"[batched capacity] 128 instances, sides {int(sides.min())}..{int(sides.max())}")
+    probs = [B.particles_from(p, dtype=torch.float32) for p, _ in insts]
+    vals = [torch.as_tensor(v).cuda() for _, v in insts]
+    opts = B.solve_opts(tol=1e-8, maxit=1000, max_refine=10)
+    outs, bt = B.p2m_mass_assign_batched(ctx, probs, vals, opts)
+    torch.cuda.synchronize()
+    reps = bt.reports()
+    for k, (prob, v) in enumerate(insts):
+        assert not (reps[k].flags & (B.FLAG_NOT_CONVERGED | B.FLAG_BREAKDOWN)), (k, reps[k])
+        single, rs = run_single(B, ctx, prob, v, opts)
+        assert torch.equal(outs[k].cpu(), single), k
+        assert same_report(reps[k], rs), (k, reps[k], rs)
+    for k in (0, 63, 127):
+        prob, v = insts[k]
+        ref, _ = p1.mass_assign(f64(prob), v.astype(np.float64), solver="direct")
+        for f in range(2):
+            assert metrics.rel_l2(outs[k].cpu().numpy()[f].astype(np.float64), ref[f]) <= 1e-6
+    say("  bitwise equal to single-problem runs")
