@@ -142,23 +142,37 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     }
     bmask = rmask | cmask;
 
-    // left column / bottom row: only their E, N, NE are used, never modified here
-    // (these loads go first: they do not depend on the P phase below)
-    for (int h = threadIdx.x; h < txa + 1 + tya; h += RBS) {
+    // left column / bottom row (only their E, N, NE are used, never modified here)
+    // and the ring's inverse diagonals (an orphan's is 1 whatever its stored
+    // diagonal): at most one slot of each per thread, both slots' loads issued
+    // before either LDS write
+    static_assert(RX + 1 + RY <= RBS, "one left-column or bottom-row slot per thread");
+    {
+        const int h = threadIdx.x;
+        int eq = -1, dq = -1;
+        float e1 = 0.f, e2 = 0.f, e3 = 0.f, dc = 0.f, dw = 0.f;
+        if (h < txa + 1 + tya) {
+            int lc, lr;
+            if (h < txa + 1) { lr = -1; lc = h - 1; } else { lc = -1; lr = h - (txa + 1); }
+            const int k = gidx(m, i0, j0, lc, lr);
+            eq = cidx(lc, lr);
+            e1 = a.coef[(size_t)nn + k];
+            e2 = a.coef[(size_t)2 * nn + k];
+            e3 = a.coef[(size_t)3 * nn + k];
+        }
         int lc, lr;
-        if (h < txa + 1) { lr = -1; lc = h - 1; } else { lc = -1; lr = h - (txa + 1); }
-        const int k = gidx(m, i0, j0, lc, lr);
-        const int q = cidx(lc, lr);
-        cf[CN + q] = a.coef[(size_t)nn + k];
-        cf[2 * CN + q] = a.coef[(size_t)2 * nn + k];
-        cf[3 * CN + q] = a.coef[(size_t)3 * nn + k];
-    }
-    // the ring's inverse diagonals (an orphan's is 1 whatever its stored diagonal)
-    for (int h = threadIdx.x; h < nhalo; h += RBS) {
-        int lc, lr;
-        if (!halo_slot(h, txa, tya, lc, lr)) continue;
-        const int k = gidx(m, i0, j0, lc, lr);
-        dv[lidx(lc, lr)] = jacobi_inv(a.coef[k], a.w[k]);
+        if (h < nhalo && halo_slot(h, txa, tya, lc, lr)) {
+            const int k = gidx(m, i0, j0, lc, lr);
+            dq = lidx(lc, lr);
+            dc = a.coef[k];
+            dw = a.w[k];
+        }
+        if (eq >= 0) {
+            cf[CN + eq] = e1;
+            cf[2 * CN + eq] = e2;
+            cf[3 * CN + eq] = e3;
+        }
+        if (dq >= 0) dv[dq] = jacobi_inv(dc, dw);
     }
     // ---- P: coefficients into LDS, orphan regularisation, FP64 start vector ----
     // Every load is issued before the first store: the memory counter covers loads
