@@ -147,17 +147,22 @@ __device__ __forceinline__ void block_sum_to(double (&v)[NV], double* lds /* [RB
     __syncthreads();
 }
 
-// Sum of the partials part[bk * kNV + jv] over bk < nblocks for every jv < nv,
-// handed to out(jv, sum).  The fixed order that every solve uses: value jv is
-// summed by the 32 lanes of segment jv, lane l over blocks l, l+32, ... in
-// increasing order, then the two row sums of the segment (row_sum16) added in row
-// order.  Called by all threads of one workgroup (every wave runs the same number
-// of segment steps, so the lane moves see every lane active).  Loads go out kPartBatch at a time before they are
-// added (in the same order), so a lane waits once per batch, not once per block.
+// Sum of the partials (bk, jv) over bk < nblocks for every jv < nv, handed to
+// out(jv, sum).  The fixed order that every solve uses: value jv is summed by the
+// 32 lanes of segment jv, lane l over blocks l, l+32, ... in increasing order, then
+// the two row sums of the segment (row_sum16) added in row order.  Called by all
+// threads of one workgroup (every wave runs the same number of segment steps, so
+// the lane moves see every lane active).  Loads go out kPartBatch at a time before
+// they are added (in the same order), so a lane waits once per batch, not once per
+// block.
 static_assert(kNV % 2 == 0 && (RBS / 32) % 2 == 0 && RBS % 64 == 0,
               "both segments of a wave take the same number of steps");
+// Partial (bk, jv) is part[bk * sb + jv * sv]: block-major (sb = kNV, sv = 1) or
+// value-major (sb = 1, sv = the block count), where a segment's lanes read
+// consecutive words.  The layout changes addresses only, never the order.
 template <typename Out>
-__device__ __forceinline__ void sum_partials(const double* part, int nblocks, int nv, Out out) {
+__device__ __forceinline__ void sum_partials(const double* part, int nblocks, int nv, size_t sb,
+                                             size_t sv, Out out) {
     constexpr int kPartBatch = 8;
     const int seg = threadIdx.x >> 5, l = threadIdx.x & 31;
     for (int jv = seg; jv < kNV; jv += RBS / 32) {
@@ -168,7 +173,7 @@ __device__ __forceinline__ void sum_partials(const double* part, int nblocks, in
 #pragma unroll
                 for (int u = 0; u < kPartBatch; ++u) {
                     const int bk = b0 + 32 * u;
-                    v[u] = bk < nblocks ? ld_c(&part[(size_t)bk * kNV + jv]) : 0.0;
+                    v[u] = bk < nblocks ? ld_c(&part[(size_t)bk * sb + (size_t)jv * sv]) : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < kPartBatch; ++u)
@@ -184,7 +189,7 @@ __device__ __forceinline__ void sum_partials(const double* part, int nblocks, in
 // The same sum written to tot[jv] (device-coherent).
 __device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int nv,
                                                 double* tot) {
-    sum_partials(part, nblocks, nv, [&](int jv, double v) { st_c(&tot[jv], v); });
+    sum_partials(part, nblocks, nv, kNV, 1, [&](int jv, double v) { st_c(&tot[jv], v); });
 }
 
 // Arrival at the two-level barrier tree (thread 0 only): the group counter of
@@ -232,8 +237,9 @@ __device__ __forceinline__ void tree_release(const RSync& s, unsigned epoch) {
 __device__ bool sync_reduce(const RSync& s, unsigned epoch, double* vals, int nv, int nblocks) {
     __shared__ int s_ok;
     const double* part = s.part + (size_t)(epoch & 1) * nblocks * kNV;
+    // value-major partials: the readers' lanes of one value read consecutive words
     if (threadIdx.x < nv)
-        st_c(&s.part[(size_t)(epoch & 1) * nblocks * kNV + (size_t)blockIdx.x * kNV + threadIdx.x],
+        st_c(&s.part[(size_t)(epoch & 1) * nblocks * kNV + (size_t)threadIdx.x * nblocks + blockIdx.x],
              vals[threadIdx.x]);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -243,7 +249,8 @@ __device__ bool sync_reduce(const RSync& s, unsigned epoch, double* vals, int nv
     }
     __syncthreads();
     const bool ok = s_ok != 0;
-    if (ok && nv > 0) sum_partials(part, nblocks, nv, [&](int jv, double v) { vals[jv] = v; });
+    if (ok && nv > 0)
+        sum_partials(part, nblocks, nv, 1, (size_t)nblocks, [&](int jv, double v) { vals[jv] = v; });
     __syncthreads();
     return ok;
 }
