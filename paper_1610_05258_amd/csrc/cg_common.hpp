@@ -186,12 +186,6 @@ __device__ __forceinline__ void sum_partials(const double* part, int nblocks, in
     }
 }
 
-// The same sum written to tot[jv] (device-coherent).
-__device__ __forceinline__ void reduce_partials(const double* part, int nblocks, int nv,
-                                                double* tot) {
-    sum_partials(part, nblocks, nv, kNV, 1, [&](int jv, double v) { st_c(&tot[jv], v); });
-}
-
 // Arrival at the two-level barrier tree (thread 0 only): the group counter of
 // this workgroup, then, for the last of its group, the root counter.  Counters
 // only grow; epoch e is complete when they reach e times their fan-in.  Returns

@@ -253,7 +253,8 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
     // store the current tile's block sums tv[0..nv) as its partials
     auto store_partials = [&](unsigned epoch, int nv) {
         double* part = a.sy.part + (size_t)(epoch & 1) * a.ntiles * kNV;
-        if (threadIdx.x < nv) st_c(&part[(size_t)cur * kNV + threadIdx.x], tv[threadIdx.x]);
+        // value-major: the lanes summing one value read consecutive words
+        if (threadIdx.x < nv) st_c(&part[(size_t)threadIdx.x * a.ntiles + cur], tv[threadIdx.x]);
     };
 
     // Synchronisation `epoch` with nv values per instance: barrier (partials
@@ -279,7 +280,9 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
         if (g < nprob) {
             for (int kk = g; kk < nprob; kk += G) {
                 const BatchInst& I = a.inst[kk];
-                reduce_partials(part + (size_t)I.rt * kNV, I.nrt, nv, tot + (size_t)kk * kNV);
+                double* tk = tot + (size_t)kk * kNV;
+                sum_partials(part + I.rt, I.nrt, nv, 1, (size_t)a.ntiles,
+                             [&](int jv, double v) { st_c(&tk[jv], v); });
             }
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
