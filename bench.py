@@ -389,6 +389,10 @@ def main():
                                            if solver == 2 else None), k_ref=kk,
                                   bytes_per_launch=cg_algorithmic_bytes(kk, nn, F))
     print(json.dumps(result), flush=True)
+    # release the library context (and the batch graph it caches) while the HIP
+    # runtime is fully alive, rather than from a finaliser at interpreter exit
+    torch.cuda.synchronize()
+    ctx.close()
 
 
 if __name__ == "__main__":

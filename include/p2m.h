@@ -64,7 +64,11 @@ enum {
     P2M_FLAG_BREAKDOWN = 1u << 2,        /* CG met p.Mp <= 0 or a non-finite scalar */
     P2M_FLAG_RANGE = 1u << 3,            /* some position outside [0, L + h) */
     P2M_FLAG_NONFINITE = 1u << 4,        /* some position is NaN or infinite */
-    P2M_FLAG_LEARNED_FALLBACK = 1u << 5  /* learned start was worse than FLIP and was replaced */
+    P2M_FLAG_LEARNED_FALLBACK = 1u << 5, /* learned start was worse than FLIP and was replaced */
+    P2M_FLAG_BIN_TIMEOUT = 1u << 6       /* the binning scan's bounded wait for another workgroup
+                                            ended: the binning is discarded (every cell empty:
+                                            cell_start all 0, perm all -1), so P2M results are 0
+                                            (orphans) and M2P is unaffected; retry the call */
 };
 
 typedef enum { P2M_F32 = 0, P2M_F64 = 1 } p2m_dtype;
@@ -142,10 +146,15 @@ p2m_status p2m_destroy(void* ctx);
 enum { P2M_SOLVER_AUTO = 0, P2M_SOLVER_STREAMING = 1, P2M_SOLVER_RESIDENT = 2, P2M_SOLVER_TILES = 3 };
 
 /* Context options (p2m_set_option).
- *   P2M_OPT_SOLVER  a P2M_SOLVER_* value (default AUTO); anything but AUTO forces
- *                   that kernel where it applies, tuned plans notwithstanding
- *   P2M_OPT_PLANS   1 (default): apply tuned plans; 0: ignore them */
-enum { P2M_OPT_SOLVER = 0, P2M_OPT_PLANS = 1 };
+ *   P2M_OPT_SOLVER     a P2M_SOLVER_* value (default AUTO); anything but AUTO forces
+ *                      that kernel where it applies, tuned plans notwithstanding
+ *   P2M_OPT_PLANS      1 (default): apply tuned plans; 0: ignore them
+ *   P2M_OPT_SCAN_SPIN  bound on the polls of the binning scan's wait for a
+ *                      preceding workgroup's prefix (0: the default, 2^26); a
+ *                      negative value ends every such wait at once, which
+ *                      raises P2M_FLAG_BIN_TIMEOUT on any mesh of more than 2048
+ *                      cells (for testing the timeout handling) */
+enum { P2M_OPT_SOLVER = 0, P2M_OPT_PLANS = 1, P2M_OPT_SCAN_SPIN = 2 };
 p2m_status p2m_set_option(void* ctx, int32_t option, int32_t value);
 
 /* Bytes of workspace that every call below needs for this problem and field count

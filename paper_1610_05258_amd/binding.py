@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -28,10 +29,11 @@ FLAG_BREAKDOWN = 1 << 2
 FLAG_RANGE = 1 << 3
 FLAG_NONFINITE = 1 << 4
 FLAG_LEARNED_FALLBACK = 1 << 5
+FLAG_BIN_TIMEOUT = 1 << 6
 REPORT_BYTES = 144
 MAX_FIELDS = 8
 SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT, SOLVER_TILES = 0, 1, 2, 3
-OPT_SOLVER, OPT_PLANS = 0, 1
+OPT_SOLVER, OPT_PLANS, OPT_SCAN_SPIN = 0, 1, 2
 
 EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size", "p2m_bin",
            "p2m_assemble", "p2m_assign", "p2m_interpolate", "p2m_mass_assign", "p2m_mass_solve",
@@ -229,7 +231,17 @@ class Context:
             lib().p2m_destroy(self.handle)
             self.handle = None
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        # no HIP call while the interpreter shuts down: the runtime (or a profiler
+        # attached to it) may already be finalised; the process exit releases it
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -241,6 +253,10 @@ class Context:
 
     def use_plans(self, on: bool):
         _check(lib().p2m_set_option(self.handle, OPT_PLANS, 1 if on else 0), "p2m_set_option")
+
+    def set_scan_spin(self, value: int):
+        """Bound of the binning scan's wait (0: default; < 0: end every wait at once)."""
+        _check(lib().p2m_set_option(self.handle, OPT_SCAN_SPIN, int(value)), "p2m_set_option")
 
     def plan(self, prob, nfields):
         """The stored plan of the problem's shape class, or None."""

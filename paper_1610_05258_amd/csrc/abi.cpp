@@ -42,7 +42,7 @@ struct BatchCache {
 
 // Tuned plans by shape class (see shape_key).
 struct PlanCache {
-    std::map<std::string, p2m_plan> plans;
+    std::map<std::string, p2m_plan, std::less<>> plans;   // transparent: found by char key
 };
 
 struct Context {
@@ -51,6 +51,7 @@ struct Context {
     int cg_blocks_f64;
     int solver_mode;        // P2M_SOLVER_*: AUTO or a forced solve kernel
     int use_plans;          // 1: apply tuned plans of the problem's shape class
+    long scan_spin;         // bound of the binning scan's look-back wait (< 0: test hook)
     BatchCache* batch;      // created on the first batched call
     const float* learned;   // parameters of the learned start (device), or null
     PlanCache* plans;       // created on the first tuned or loaded plan
@@ -73,6 +74,7 @@ struct DeviceGuard {
 };
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
 
 // Workspace carve-up.  Offsets are fixed functions of (problem, F, cg blocks).
 struct Layout {
@@ -160,23 +162,28 @@ Particles<T> particles_of(const p2m_problem* p) {
 
 // Shape class of a batch for tuned plans: field count, and the instance count, total
 // nodes and total particles, each rounded to a power of two.
-std::string batch_key(int F, int nprob, int64_t nn, int64_t np) {
+// A shape-class key in a fixed buffer (looking a plan up allocates nothing).
+struct Key {
+    char s[96];
+};
+
+Key batch_key(int F, int nprob, int64_t nn, int64_t np) {
     auto lg = [](double v) { return (int)floor(log2(v > 1.0 ? v : 1.0) + 0.5); };
-    char buf[96];
-    snprintf(buf, sizeof buf, "batch-f32-F%d-n%d-nodes%d-parts%d", F, lg(nprob), lg((double)nn),
+    Key k;
+    snprintf(k.s, sizeof k.s, "batch-f32-F%d-n%d-nodes%d-parts%d", F, lg(nprob), lg((double)nn),
              lg((double)np));
-    return std::string(buf);
+    return k;
 }
 
 // Shape class of a problem for tuned plans: dimension, dtype, field count, the
 // mesh sides and the particles per cell, each rounded to a power of two.
-std::string shape_key(const Mesh& m, int dtype, int F) {
+Key shape_key(const Mesh& m, int dtype, int F) {
     auto lg = [](double v) { return (int)floor(log2(v) + 0.5); };
     const double ppc = m.np > 0 ? (double)m.np / (double)m.nn : 0.125;
-    char buf[96];
-    snprintf(buf, sizeof buf, "%dd-%s-F%d-nx%d-ny%d-ppc%d", m.dim, dtype == P2M_F64 ? "f64" : "f32", F,
+    Key k;
+    snprintf(k.s, sizeof k.s, "%dd-%s-F%d-nx%d-ny%d-ppc%d", m.dim, dtype == P2M_F64 ? "f64" : "f32", F,
              lg(m.nx), lg(m.ny), lg(ppc < 0.125 ? 0.125 : ppc));
-    return std::string(buf);
+    return k;
 }
 
 struct Choice {
@@ -196,7 +203,7 @@ Choice choose(const Context* c, const Mesh& m, int dtype, int F) {
         return ch;
     }
     if (c->use_plans && c->plans) {
-        auto it = c->plans->plans.find(shape_key(m, dtype, F));
+        auto it = c->plans->plans.find(shape_key(m, dtype, F).s);
         if (it != c->plans->plans.end()) {
             ch.solver = it->second.solver;
             ch.groups = it->second.groups;
@@ -221,6 +228,7 @@ struct Prepared {
     char* ws;
     hipStream_t stream;
     p2m_report* rep;
+    long scan_spin;
     // the report still has to be zeroed: the first launch of the call does it
     // together with its own clearing work (one launch fewer per call)
     mutable bool clear_rep = false;
@@ -239,6 +247,7 @@ p2m_status prepare(void* ctx, const p2m_problem* prob, int F, void* ws, size_t w
     out.ws = (char*)ws;
     out.stream = (hipStream_t)stream;
     out.rep = rep ? rep : (p2m_report*)(out.ws + out.L.report);
+    out.scan_spin = c->scan_spin;
     return P2M_OK;
 }
 
@@ -255,8 +264,8 @@ p2m_status run_bin(const Prepared& pp, const p2m_problem* prob, int32_t* perm, i
     pp.clear_rep = false;
     P2M_TRY(launch_locate_count<T>(m, particles_of<T>(prob), key, rank, counts, pp.rep,
                                    pp.stream));
-    P2M_TRY(launch_exclusive_scan(counts, cs, m.nn, scan_ws, pp.stream));
-    P2M_TRY(launch_place(m, key, rank, cs, perm, pp.stream));
+    P2M_TRY(launch_exclusive_scan(counts, cs, m.nn, scan_ws, pp.scan_spin, pp.rep, 1, pp.stream));
+    P2M_TRY(launch_place(m, key, rank, cs, perm, scan_ws, pp.stream));
     P2M_TRY(launch_segment_sort(m, cs, perm, pp.stream));
     return P2M_OK;
 }
@@ -502,7 +511,7 @@ p2m_status plan_batch(const Context* c, const p2m_problem* probs, int nprob, int
 
 // The launch sequence of a batch on `stream` (captured into the batch graph).
 hipError_t enqueue_batch(const BatchPlan& P, char* ws, p2m_report* reps, const p2m_solve_opts& opts,
-                         hipStream_t stream) {
+                         long scan_spin, hipStream_t stream) {
     const BatchInst* inst = (const BatchInst*)ws;
     const int32_t* lmap = (const int32_t*)(ws + P.inst_b);
     const int32_t* amap = (const int32_t*)(ws + P.inst_b + P.lmap_b);
@@ -523,8 +532,11 @@ hipError_t enqueue_batch(const BatchPlan& P, char* ws, p2m_report* reps, const p
     if ((e = launch_locate_count_batch(inst, lmap, P.nlb, key, key + P.np, counts, stream)) !=
         hipSuccess)
         return e;
-    if ((e = launch_exclusive_scan(counts, cs, (int)P.nn, scan_ws, stream)) != hipSuccess) return e;
-    if ((e = launch_place_flat((int)P.np, key, key + P.np, cs, perm, stream)) != hipSuccess)
+    if ((e = launch_exclusive_scan(counts, cs, (int)P.nn, scan_ws, scan_spin, reps, P.nprob,
+                                   stream)) != hipSuccess)
+        return e;
+    if ((e = launch_place_flat((int)P.np, (int)P.nn, key, key + P.np, cs, perm, scan_ws, stream)) !=
+        hipSuccess)
         return e;
     if ((e = launch_segment_sort_flat((int)P.nn, cs, perm, stream)) != hipSuccess) return e;
     if ((e = launch_assemble_batch(P.F, inst, amap, P.nat, perm, cs, b, w, coef, stream)) !=
@@ -584,6 +596,7 @@ p2m_status p2m_create(void** ctx, int device) {
     c->cg_blocks_f64 = cg_max_blocks<double>(device);
     c->solver_mode = P2M_SOLVER_AUTO;
     c->use_plans = 1;
+    c->scan_spin = kScanSpinDefault;
     if (c->cg_blocks_f32 <= 0 || c->cg_blocks_f64 <= 0) {
         free(c);
         return P2M_ERR_HIP;
@@ -603,6 +616,10 @@ p2m_status p2m_set_option(void* ctx, int32_t option, int32_t value) {
     if (option == P2M_OPT_PLANS) {
         if (value != 0 && value != 1) return P2M_ERR_INVALID_ARG;
         c->use_plans = value;
+        return P2M_OK;
+    }
+    if (option == P2M_OPT_SCAN_SPIN) {
+        c->scan_spin = value == 0 ? kScanSpinDefault : (long)value;
         return P2M_OK;
     }
     return P2M_ERR_INVALID_ARG;
@@ -780,7 +797,7 @@ p2m_status p2m_mass_assign_batched(void* ctx, const p2m_problem* probs, int32_t 
     {
         const p2m_plan* plan = c->forced;
         if (!plan && c->use_plans && c->plans) {
-            auto it = c->plans->plans.find(batch_key(P.F, P.nprob, P.nn, P.np));
+            auto it = c->plans->plans.find(batch_key(P.F, P.nprob, P.nn, P.np).s);
             if (it != c->plans->plans.end()) plan = &it->second;
         }
         if (plan && plan->inner_rtol >= 0.0 && plan->inner_rtol < 1.0) o.inner_rtol = plan->inner_rtol;
@@ -806,6 +823,7 @@ p2m_status p2m_mass_assign_batched(void* ctx, const p2m_problem* probs, int32_t 
     put(opts, sizeof(*opts));
     put(&ws, sizeof(ws));
     put(&reps, sizeof(reps));
+    put(&c->scan_spin, sizeof(c->scan_spin));
     if (!bc.exec || key != bc.key) {
         bc.release();
         // the instance table and tile maps go to the head of the workspace
@@ -820,7 +838,7 @@ p2m_status p2m_mass_assign_batched(void* ctx, const p2m_problem* probs, int32_t 
         P2M_TRY(hipMemcpyAsync(ws, u, bc.upload.size(), hipMemcpyHostToDevice, strm));
         P2M_TRY(hipStreamSynchronize(strm));
         P2M_TRY(hipStreamBeginCapture(bc.capture, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_batch(P, (char*)ws, reps, *opts, bc.capture);
+        hipError_t e = enqueue_batch(P, (char*)ws, reps, *opts, c->scan_spin, bc.capture);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(bc.capture, &graph);
         if (e != hipSuccess || e2 != hipSuccess || !graph) {
@@ -987,7 +1005,7 @@ p2m_status p2m_tune(void* ctx, const p2m_problem* prob, const void* values, int3
         if (!c->plans) return P2M_ERR_HIP;
     }
     *best = cand[best_i];
-    c->plans->plans[shape_key(pp.m, prob->dtype, nfields)] = *best;
+    c->plans->plans[std::string(shape_key(pp.m, prob->dtype, nfields).s)] = *best;
     // leave the chosen plan's result in nodal_out and rep
     c->forced = best;
     result = p2m_mass_assign(ctx, prob, values, nfields, opts, nodal_out, rep, ws, ws_bytes, stream);
@@ -1062,7 +1080,7 @@ p2m_status p2m_tune_batched(void* ctx, const p2m_problem* probs, int32_t nprob,
         if (!c->plans) return P2M_ERR_HIP;
     }
     *best = cand[best_i];
-    c->plans->plans[batch_key(P.F, P.nprob, P.nn, P.np)] = *best;
+    c->plans->plans[std::string(batch_key(P.F, P.nprob, P.nn, P.np).s)] = *best;
     // leave the chosen plan's results in nodal_inout and reps
     c->forced = best;
     result = p2m_mass_assign_batched(ctx, probs, nprob, values, nfields, opts, nodal_inout, reps, ws,
@@ -1079,7 +1097,7 @@ p2m_status p2m_plan_get_batched(void* ctx, const p2m_problem* probs, int32_t npr
     p2m_status s = plan_batch(c, probs, nprob, nfields, nullptr, nullptr, nullptr, P);
     if (s != P2M_OK) return s;
     if (!c->plans) return P2M_ERR_UNSUPPORTED;
-    auto it = c->plans->plans.find(batch_key(P.F, P.nprob, P.nn, P.np));
+    auto it = c->plans->plans.find(batch_key(P.F, P.nprob, P.nn, P.np).s);
     if (it == c->plans->plans.end()) return P2M_ERR_UNSUPPORTED;
     *plan = it->second;
     return P2M_OK;
@@ -1092,7 +1110,7 @@ p2m_status p2m_plan_get(void* ctx, const p2m_problem* prob, int32_t nfields, p2m
     if (s != P2M_OK) return s;
     const Context* c = (const Context*)ctx;
     if (!c->plans) return P2M_ERR_UNSUPPORTED;
-    auto it = c->plans->plans.find(shape_key(m, prob->dtype, nfields));
+    auto it = c->plans->plans.find(shape_key(m, prob->dtype, nfields).s);
     if (it == c->plans->plans.end()) return P2M_ERR_UNSUPPORTED;
     *plan = it->second;
     return P2M_OK;

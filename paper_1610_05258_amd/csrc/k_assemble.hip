@@ -16,6 +16,8 @@
 // (c00-c10) and top edge (c01-c11) entries of E; the left edge (c00-c01) and
 // right edge (c10-c11) entries of N; the diagonal edge (c00-c11) entry of NE;
 // w_c and b_f,c for each corner.
+#include <type_traits>
+
 #include "p2m_internal.hpp"
 
 namespace p2m {
@@ -29,6 +31,58 @@ enum : int {
     Q_W00, Q_W10, Q_W11, Q_W01,
     Q_B = 13   // then 4 per field: b00, b10, b11, b01
 };
+
+// A cell's sums run over its particles one after the other.  Plain FP32 sums
+// lose about sqrt(n) units of rounding over n terms: harmless at the usual few
+// particles per cell, not for crowded cells.  Cells of more than
+// kCompensateAbove particles are therefore summed apart, by the whole
+// workgroup: every thread sums a strided share of the cell's particles with
+// Kahan's compensation, and the shares are added in thread order, again
+// compensated (FP32 arithmetic throughout, error about two roundings whatever
+// the count).  Which cells take that path depends on the data only, so results
+// stay deterministic.
+constexpr int kCompensateAbove = 32;
+
+template <bool KAHAN, typename T>
+__device__ __forceinline__ void acc_add(T& s, T& c, T x) {
+    if (KAHAN) {
+        const T y = x - c;
+        const T t = s + y;
+        c = (t - s) - y;
+        s = t;
+    } else {
+        s += x;
+    }
+}
+
+// One particle (corner weights, volume, values av[f] = av[f * stride]) added
+// to a cell's parts acc (and their compensations cmp when KAHAN).
+template <bool KAHAN, typename T, int F, int NQ>
+__device__ __forceinline__ void acc_particle(T (&acc)[NQ], T (&cmp)[NQ], T c00, T c10, T c11,
+                                             T c01, T v, const T* av, int stride) {
+    const T v00 = v * c00, v10 = v * c10, v11 = v * c11, v01 = v * c01;
+    acc_add<KAHAN>(acc[Q_D00], cmp[Q_D00], v00 * c00);
+    acc_add<KAHAN>(acc[Q_D10], cmp[Q_D10], v10 * c10);
+    acc_add<KAHAN>(acc[Q_D11], cmp[Q_D11], v11 * c11);
+    acc_add<KAHAN>(acc[Q_D01], cmp[Q_D01], v01 * c01);
+    acc_add<KAHAN>(acc[Q_EB], cmp[Q_EB], v00 * c10);
+    acc_add<KAHAN>(acc[Q_ET], cmp[Q_ET], v01 * c11);
+    acc_add<KAHAN>(acc[Q_NL], cmp[Q_NL], v00 * c01);
+    acc_add<KAHAN>(acc[Q_NR], cmp[Q_NR], v10 * c11);
+    acc_add<KAHAN>(acc[Q_NE], cmp[Q_NE], v00 * c11);
+    acc_add<KAHAN>(acc[Q_W00], cmp[Q_W00], v00);
+    acc_add<KAHAN>(acc[Q_W10], cmp[Q_W10], v10);
+    acc_add<KAHAN>(acc[Q_W11], cmp[Q_W11], v11);
+    acc_add<KAHAN>(acc[Q_W01], cmp[Q_W01], v01);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        const T a = av[f * stride];
+        acc_add<KAHAN>(acc[Q_B + 4 * f + 0], cmp[Q_B + 4 * f + 0], v00 * a);
+        acc_add<KAHAN>(acc[Q_B + 4 * f + 1], cmp[Q_B + 4 * f + 1], v10 * a);
+        acc_add<KAHAN>(acc[Q_B + 4 * f + 2], cmp[Q_B + 4 * f + 2], v11 * a);
+        acc_add<KAHAN>(acc[Q_B + 4 * f + 3], cmp[Q_B + 4 * f + 3], v01 * a);
+    }
+}
 
 // Staged 2D scatter.  A workgroup owns a TS x TS node tile and the (TS+1)^2 cells
 // around it.  The particles of those cells (their perm segments) are processed in
@@ -54,8 +108,14 @@ __device__ __forceinline__ void assemble2d_tile(const Mesh& m, const Particles<T
     constexpr int SPT = (CH + NT - 1) / NT;     // staged slots per thread and chunk
     constexpr size_t SLOT_B = (size_t)NS * CH * sizeof(T);
     constexpr size_t PART_B = (size_t)NQ * HC * sizeof(T);
-    __shared__ __align__(16) unsigned char smem[SLOT_B > PART_B ? SLOT_B : PART_B];
+    constexpr size_t RED_B = (size_t)NQ * (NT + 1) * sizeof(T);   // crowded-cell shares
+    constexpr size_t SMEM_B = SLOT_B > PART_B ? (SLOT_B > RED_B ? SLOT_B : RED_B)
+                                              : (PART_B > RED_B ? PART_B : RED_B);
+    static_assert(NQ <= NT, "one thread per quantity in the crowded-cell sums");
+    __shared__ __align__(16) unsigned char smem[SMEM_B];
     __shared__ int c_seg[HC], c_off[HC + 1];
+    __shared__ short big_cell[HC];              // crowded cells of the tile
+    __shared__ int n_big;
     __shared__ short cmap[2][CH];               // slot of a chunk -> its cell (2 buffers)
     __shared__ int wsum[NT / 64];
     T* st = (T*)smem;                           // st[q * CH + slot]
@@ -67,7 +127,9 @@ __device__ __forceinline__ void assemble2d_tile(const Mesh& m, const Particles<T
     const int t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6;
 
-    // cell segments and their exclusive prefix (cells beyond the mesh: empty)
+    // cell segments and their exclusive prefix (cells beyond the mesh: empty;
+    // crowded cells are listed and left out of the staged chunks)
+    if (t == 0) n_big = 0;
     int cnt = 0;
     if (t < HC) {
         const int hx = t % HS, hy = t / HS;
@@ -81,6 +143,11 @@ __device__ __forceinline__ void assemble2d_tile(const Mesh& m, const Particles<T
             cnt = cell_start[c + 1] - s0;
         }
         c_seg[t] = s0;
+    }
+    __syncthreads();
+    if (cnt > kCompensateAbove) {
+        big_cell[atomicAdd(&n_big, 1)] = (short)t;   // any order: cells are independent
+        cnt = 0;
     }
     int inc = cnt;
 #pragma unroll
@@ -98,9 +165,9 @@ __device__ __forceinline__ void assemble2d_tile(const Mesh& m, const Particles<T
     const int total = c_off[HC];
     const int my_lo = (t < HC) ? c_off[t] : 0, my_hi = (t < HC) ? c_off[t + 1] : 0;
 
-    T acc[NQ];
+    T acc[NQ], cmp[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = (T)0;
+    for (int q = 0; q < NQ; ++q) acc[q] = cmp[q] = (T)0;
 
     // Chunks of CH slots, pipelined two deep: while chunk c is accumulated, the
     // particle data of chunk c+1 and the particle numbers of chunk c+2 are in
@@ -189,30 +256,8 @@ __device__ __forceinline__ void assemble2d_tile(const Mesh& m, const Particles<T
         const int a0 = max(my_lo, cb), a1 = min(my_hi, ce);
         for (int sl = a0; sl < a1; ++sl) {
             const int o = sl - cb;
-            const T c00 = st[0 * CH + o], c10 = st[1 * CH + o], c11 = st[2 * CH + o],
-                    c01 = st[3 * CH + o], v = st[4 * CH + o];
-            const T v00 = v * c00, v10 = v * c10, v11 = v * c11, v01 = v * c01;
-            acc[Q_D00] += v00 * c00;
-            acc[Q_D10] += v10 * c10;
-            acc[Q_D11] += v11 * c11;
-            acc[Q_D01] += v01 * c01;
-            acc[Q_EB] += v00 * c10;
-            acc[Q_ET] += v01 * c11;
-            acc[Q_NL] += v00 * c01;
-            acc[Q_NR] += v10 * c11;
-            acc[Q_NE] += v00 * c11;
-            acc[Q_W00] += v00;
-            acc[Q_W10] += v10;
-            acc[Q_W11] += v11;
-            acc[Q_W01] += v01;
-#pragma unroll
-            for (int f = 0; f < F; ++f) {
-                const T av = st[(5 + f) * CH + o];
-                acc[Q_B + 4 * f + 0] += v00 * av;
-                acc[Q_B + 4 * f + 1] += v10 * av;
-                acc[Q_B + 4 * f + 2] += v11 * av;
-                acc[Q_B + 4 * f + 3] += v01 * av;
-            }
+            acc_particle<false, T, F>(acc, cmp, st[0 * CH + o], st[1 * CH + o], st[2 * CH + o],
+                                      st[3 * CH + o], st[4 * CH + o], st + 5 * CH + o, CH);
         }
         __syncthreads();
 #pragma unroll
@@ -226,6 +271,50 @@ __device__ __forceinline__ void assemble2d_tile(const Mesh& m, const Particles<T
             piB[u] = piN[u];
         }
     }
+    // crowded cells, one after the other: thread t sums slots t, t + NT, ... of
+    // the cell with compensation; then thread q adds quantity q's NT shares in
+    // thread order, compensated; the cell's own thread takes the totals
+    const int nbig = n_big;
+    T* red = (T*)smem;                          // red[q * NT + thread], totals at NQ * NT
+    for (int kb = 0; kb < nbig; ++kb) {
+        const int hc = big_cell[kb];
+        const int hx = hc % HS, hy = hc / HS;
+        int gi = i0 - 1 + hx, gj = j0 - 1 + hy;
+        if (gi < 0) gi += m.nx;
+        if (gj < 0) gj += m.ny;
+        const int c = gi + m.nx * gj;
+        const int s0 = c_seg[hc], n = cell_start[c + 1] - s0;
+        T sa[NQ], sc[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sa[q] = sc[q] = (T)0;
+        for (int sl = t; sl < n; sl += NT) {
+            const int i = perm[s0 + sl] - po;
+            int cx, cy;
+            double xi, eta;
+            bool fx, fy;
+            locate_axis((double)P.x[i], m.nx, m.inv_hx, cx, xi, fx);
+            locate_axis((double)P.y[i], m.ny, m.inv_hy, cy, eta, fy);
+            T c00, c10, c11, c01;
+            corner_weights<T>(xi, eta, c00, c10, c11, c01);
+            const T v = P.vol ? P.vol[i] : v_uni;
+            acc_particle<true, T, F>(sa, sc, c00, c10, c11, c01, v, values + i, m.np);
+        }
+        __syncthreads();     // the staging area is free (previous cell's totals read)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) red[q * NT + t] = sa[q] - sc[q];
+        __syncthreads();
+        if (t < NQ) {
+            T s1 = (T)0, c1 = (T)0;
+            for (int u = 0; u < NT; ++u) acc_add<true>(s1, c1, red[t * NT + u]);
+            red[NQ * NT + t] = s1 - c1;
+        }
+        __syncthreads();
+        if (t == hc) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) acc[q] = red[NQ * NT + q];
+        }
+    }
+    if (nbig > 0) __syncthreads();
     if (t < HC) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) part[q][t] = acc[q];
@@ -294,14 +383,10 @@ __global__ __launch_bounds__(TS) void k_assemble1d(Mesh m, Particles<T> P,
     __shared__ T part[NQ][HC];
     const int i0 = blockIdx.x * TS;
     const T v_uni = (T)m.v_uniform;
-    for (int hc = threadIdx.x; hc < HC; hc += TS) {
-        int gi = i0 - 1 + hc;
-        if (gi >= m.nx) continue;
-        if (gi < 0) gi += m.nx;
-        T acc[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] = (T)0;
-        const int s = cell_start[gi], e = cell_start[gi + 1];
+    // one cell per thread, its particles in binned order; a cell of more than
+    // kCompensateAbove particles is summed with Kahan's compensation
+    auto cell_sums = [&](auto kahan, int s, int e, T (&acc)[NQ], T (&cmp)[NQ]) {
+        constexpr bool K = decltype(kahan)::value;
         for (int kk = s; kk < e; ++kk) {
             const int i = perm[kk];
             int cx;
@@ -311,20 +396,32 @@ __global__ __launch_bounds__(TS) void k_assemble1d(Mesh m, Particles<T> P,
             const T cl = (T)__dsub_rn(1.0, xi), cr = (T)xi;
             const T v = P.vol ? P.vol[i] : v_uni;
             const T vl = v * cl, vr = v * cr;
-            acc[0] += vl * cl;
-            acc[1] += vr * cr;
-            acc[2] += vl * cr;
-            acc[3] += vl;
-            acc[4] += vr;
+            acc_add<K>(acc[0], cmp[0], vl * cl);
+            acc_add<K>(acc[1], cmp[1], vr * cr);
+            acc_add<K>(acc[2], cmp[2], vl * cr);
+            acc_add<K>(acc[3], cmp[3], vl);
+            acc_add<K>(acc[4], cmp[4], vr);
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 const T a = values[(size_t)f * m.np + i];
-                acc[5 + 2 * f] += vl * a;
-                acc[6 + 2 * f] += vr * a;
+                acc_add<K>(acc[5 + 2 * f], cmp[5 + 2 * f], vl * a);
+                acc_add<K>(acc[6 + 2 * f], cmp[6 + 2 * f], vr * a);
             }
         }
+    };
+    for (int hc = threadIdx.x; hc < HC; hc += TS) {
+        int gi = i0 - 1 + hc;
+        if (gi >= m.nx) continue;
+        if (gi < 0) gi += m.nx;
+        T acc[NQ], cmp[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) part[q][hc] = acc[q];
+        for (int q = 0; q < NQ; ++q) acc[q] = cmp[q] = (T)0;
+        const int s = cell_start[gi], e = cell_start[gi + 1];
+        const bool crowded = e - s > kCompensateAbove;
+        if (crowded) cell_sums(std::true_type{}, s, e, acc, cmp);
+        else cell_sums(std::false_type{}, s, e, acc, cmp);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) part[q][hc] = crowded ? acc[q] - cmp[q] : acc[q];
     }
     __syncthreads();
     const int gi = i0 + threadIdx.x;

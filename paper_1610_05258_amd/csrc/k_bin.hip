@@ -4,12 +4,18 @@
 //                  (integer atomics: order-independent, so the counts are exact);
 //                  the value an atomic returns gives each particle a distinct
 //                  slot of its cell (its rank), in an order that depends on timing
-//   exclusive_scan: cell_start = exclusive prefix sum of the counts
+//   exclusive_scan: cell_start = exclusive prefix sum of the counts (one kernel,
+//                  decoupled look-back over the predecessor tiles)
 //   place        : perm[cell_start[key] + rank] = particle (no atomics)
 //   segment_sort : every cell sorts its slots by original index, which makes the
 //                  permutation exactly the stable (cell, original index) order
 //
 // The result does not depend on the order in which the atomics were served.
+//
+// Every wait is bounded.  If the scan's look-back gives up on a predecessor, it
+// raises P2M_FLAG_BIN_TIMEOUT and an abort word; place then leaves every cell
+// empty (cell_start all 0, perm all -1), so whatever reads the binning stays in
+// bounds and the caller sees the flag.
 #include "p2m_internal.hpp"
 
 namespace p2m {
@@ -199,8 +205,8 @@ __global__ void k_report_clear_n(p2m_report* __restrict__ reps, int n) {
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan of int32 counts (three phases: block sums, scan of the block
-// sums by one block, per-block scan plus offset)
+// exclusive scan of int32 counts: one kernel, each workgroup scans a tile of
+// kScanTile counts and adds the prefix of its predecessors found by look-back
 // ---------------------------------------------------------------------------
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
@@ -240,15 +246,23 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int& total) {
 // started; a tile publishes its own sum (AGG), looks back over its predecessors'
 // words (64 at a time, one per lane of wave 0) until it meets an inclusive prefix
 // (PRE), and publishes its own inclusive prefix.  A word holds the flag in bits
-// 62-63 and the value (< 2^31) in bits 0-31; the words and the counter start at
-// zero (the caller clears them with the counts).
+// 62-63 and the value (< 2^31) in bits 0-31; the words, the counter and the abort
+// word start at zero (the caller clears them with the counts).
+//
+// The wait for an unpublished word is bounded by spin_max polls (spin_max < 0:
+// no poll at all, the first unpublished word ends the wait; a test hook for the
+// timeout path).  A tile that gives up still publishes a (wrong) PRE so that its
+// successors finish, sets the abort word and raises P2M_FLAG_BIN_TIMEOUT in the
+// nrep reports; k_place then discards the whole scan.
 constexpr unsigned long long kScanAgg = 1ull << 62, kScanPre = 2ull << 62;
-constexpr long kScanSpinMax = 1L << 26;
 
 __global__ __launch_bounds__(kBlock) void k_scan_lookback(const int32_t* __restrict__ in, int n,
                                                           int32_t* __restrict__ out,
                                                           unsigned long long* status,
-                                                          unsigned* tile_ctr) {
+                                                          unsigned* tile_ctr, unsigned* abort_word,
+                                                          long spin_max,
+                                                          p2m_report* __restrict__ reps,
+                                                          int nrep) {
     __shared__ int s_tile, s_excl;
     if (threadIdx.x == 0) s_tile = (int)atomicAdd(tile_ctr, 1u);
     __syncthreads();
@@ -271,17 +285,22 @@ __global__ __launch_bounds__(kBlock) void k_scan_lookback(const int32_t* __restr
         int excl = 0;
         int end = tile;  // predecessors [end - 64, end) are examined in one step
         long spins = 0;
+        bool gave_up = false;
         while (end > 0) {
             const int idx = end - 1 - lane;
             const unsigned long long w =
-                idx >= 0 ? __hip_atomic_load(&status[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                         : kScanPre;
+                (idx >= 0 && spin_max >= 0)
+                    ? __hip_atomic_load(&status[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                    : (idx >= 0 ? 0ull : kScanPre);
             const unsigned flag = (unsigned)(w >> 62);
             const uint64_t pre = __ballot(flag == 2u), inv = __ballot(flag == 0u);
             const int first = pre ? __ffsll((unsigned long long)pre) - 1 : 63;
             const uint64_t upto = first >= 63 ? ~0ull : ((1ull << (first + 1)) - 1);
             if (inv & upto) {  // a word this step needs is not published yet
-                if (++spins > kScanSpinMax) break;
+                if (++spins > spin_max) {
+                    gave_up = true;
+                    break;
+                }
                 continue;
             }
             int v = lane <= first ? (int)(w & 0xffffffffull) : 0;
@@ -296,6 +315,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_lookback(const int32_t* __restr
                 __hip_atomic_store(&status[tile], kScanPre | (unsigned)(excl + total),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s_excl = excl;
+            if (gave_up) {
+                __hip_atomic_store(abort_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int r = 0; r < nrep; ++r) atomicOr(&reps[r].flags, (uint32_t)P2M_FLAG_BIN_TIMEOUT);
+            }
         }
     }
     __syncthreads();
@@ -310,24 +333,33 @@ __global__ __launch_bounds__(kBlock) void k_scan_lookback(const int32_t* __restr
 }
 
 // Every located particle goes to its slot cell_start[key] + rank.  With
-// ncells >= 0, slots [valid, np) (after every valid particle) are set to -1.
+// fill_tail, slots [valid, np) (after every valid particle) are set to -1.
+// When the scan has aborted (abort word set), the binning is discarded instead:
+// cell_start[0..ncells] = 0 and perm[0..np) = -1, so every cell is empty.  The
+// grid covers max(np, ncells + 1) threads.
 __global__ void k_place(int np, const int32_t* __restrict__ key, const int32_t* __restrict__ rank,
-                        const int32_t* __restrict__ cell_start, int32_t* __restrict__ perm,
-                        int ncells) {
+                        int32_t* __restrict__ cell_start, int32_t* __restrict__ perm, int ncells,
+                        int fill_tail, const unsigned* __restrict__ abort_word) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        if (i < np) perm[i] = -1;
+        if (i <= ncells) cell_start[i] = 0;
+        return;
+    }
     if (i >= np) return;
-    if (ncells >= 0 && i >= cell_start[ncells]) perm[i] = -1;
+    if (fill_tail && i >= cell_start[ncells]) perm[i] = -1;
     const int k = key[i];
     if (k >= 0) perm[cell_start[k] + rank[i]] = i;
 }
 
-// Every cell's slots sorted by original index, one thread per cell.  A cell of
-// at most kSortReg particles is held in registers and, when out of order, sorted
-// by a fixed network (8 or 16 wide).  Larger cells are sorted in place by
-// insertion.  A workgroup's kBlock consecutive cells own one contiguous range of
-// perm: when it fits kSortStage entries it is loaded into LDS and written back
-// with coalesced accesses (only if some cell was out of order); otherwise every
-// thread works on global memory directly.
+// Every cell's slots sorted by original index.  A workgroup owns kBlock
+// consecutive cells, which own one contiguous range of perm; when that range
+// fits kSortStage entries it is loaded into LDS and written back with coalesced
+// accesses (only if some cell was out of order), otherwise the sort works on
+// global memory in place.  A cell of at most kSortReg particles is sorted by its
+// own thread in registers with a fixed network (8 or 16 wide).  Larger cells
+// are sorted one after the other by the whole workgroup with a merge network of
+// n log^2 n / 4 compare-exchanges (bounded work whatever the crowding).
 constexpr int kSortReg = 16;
 constexpr int kSortStage = 4096;   // perm entries staged per workgroup (16 KB)
 
@@ -373,55 +405,116 @@ __device__ __forceinline__ bool rank_sort_small(int32_t* __restrict__ seg, int n
     return n <= 8 ? sort_small<8>(seg, n) : sort_small<kSortReg>(seg, n);
 }
 
-__device__ __forceinline__ bool insertion_sort(int32_t* __restrict__ seg, int n) {
-    bool moved = false;
-    for (int i = 1; i < n; ++i) {
-        const int x = seg[i];
-        int j = i - 1;
-        while (j >= 0 && seg[j] > x) {
-            seg[j + 1] = seg[j];
-            --j;
-            moved = true;
+// One segment of n entries sorted ascending by all kBlock threads of the
+// workgroup (every thread calls it; seg is LDS or global memory private to the
+// workgroup).  Bitonic sort in the form whose comparators all put the smaller
+// value at the lower index: each merge of two sorted halves of a block of k
+// first compares i with its mirror k - 1 - i, then half-cleans at distances
+// k/4, ..., 1.  The segment is padded to the next power of two P with virtual
+// +infinity entries; a comparator whose upper index is >= n would leave both
+// entries in place, so it is skipped and the padding is never stored.  The
+// values are distinct particle numbers.  Returns (to every thread) whether any
+// entry moved.
+__device__ __forceinline__ bool block_sort_segment(int32_t* seg, int n, int* moved_flag) {
+    int P = 1;
+    while (P < n) P <<= 1;
+    if (threadIdx.x == 0) *moved_flag = 0;
+    __syncthreads();
+    int moved = 0;
+    for (int k = 2; k <= P; k <<= 1) {
+        const int half = k >> 1;
+        for (int q = threadIdx.x; q < P / 2; q += kBlock) {
+            const int blk = q / half, off = q - blk * half;
+            const int i = blk * k + off, j = blk * k + k - 1 - off;
+            if (j < n) {
+                const int a = seg[i], b = seg[j];
+                if (a > b) {
+                    seg[i] = b;
+                    seg[j] = a;
+                    moved = 1;
+                }
+            }
         }
-        seg[j + 1] = x;
+        __syncthreads();
+        for (int d = k >> 2; d >= 1; d >>= 1) {
+            for (int q = threadIdx.x; q < P / 2; q += kBlock) {
+                const int blk = q / d;
+                const int i = blk * 2 * d + (q - blk * d), j = i + d;
+                if (j < n) {
+                    const int a = seg[i], b = seg[j];
+                    if (a > b) {
+                        seg[i] = b;
+                        seg[j] = a;
+                        moved = 1;
+                    }
+                }
+            }
+            __syncthreads();
+        }
     }
-    return moved;
+    if (moved) *moved_flag = 1;
+    __syncthreads();
+    const int any = *moved_flag;
+    __syncthreads();
+    return any != 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_segment_sort(int ncells,
                                                          const int32_t* __restrict__ cell_start,
                                                          int32_t* __restrict__ perm) {
     __shared__ int32_t st[kSortStage];
+    __shared__ int big[kBlock];
+    __shared__ int n_big, s_flag;
     const int c0 = blockIdx.x * kBlock;
     const int c1 = min(c0 + kBlock, ncells);
     const int c = c0 + (int)threadIdx.x;
     const int lo = cell_start[c0], hi = cell_start[c1];
     const int s = c < c1 ? cell_start[c] : lo, e = c < c1 ? cell_start[c + 1] : lo;
     const int n = e - s;
-    if (hi - lo > kSortStage) {  // uniform over the workgroup
-        if (n > kSortReg) insertion_sort(perm + s, n);
-        else if (n > 1) rank_sort_small(perm + s, n);
-        return;
-    }
-    // every load of the stage goes out before the first LDS write (a loop that
-    // stores each load to LDS would wait for each load in turn)
-    constexpr int kStageIt = kSortStage / kBlock;
-    static_assert(kSortStage % kBlock == 0, "whole staging rounds");
-    int32_t tmp[kStageIt];
+    if (threadIdx.x == 0) n_big = 0;
+    const bool staged = hi - lo <= kSortStage;   // uniform over the workgroup
+    if (staged) {
+        // every load of the stage goes out before the first LDS write (a loop that
+        // stores each load to LDS would wait for each load in turn)
+        constexpr int kStageIt = kSortStage / kBlock;
+        static_assert(kSortStage % kBlock == 0, "whole staging rounds");
+        int32_t tmp[kStageIt];
 #pragma unroll
-    for (int u = 0; u < kStageIt; ++u) {
-        const int t = lo + (int)threadIdx.x + u * kBlock;
-        tmp[u] = t < hi ? perm[t] : 0;
-    }
+        for (int u = 0; u < kStageIt; ++u) {
+            const int t = lo + (int)threadIdx.x + u * kBlock;
+            tmp[u] = t < hi ? perm[t] : 0;
+        }
 #pragma unroll
-    for (int u = 0; u < kStageIt; ++u) {
-        const int t = lo + (int)threadIdx.x + u * kBlock;
-        if (t < hi) st[t - lo] = tmp[u];
+        for (int u = 0; u < kStageIt; ++u) {
+            const int t = lo + (int)threadIdx.x + u * kBlock;
+            if (t < hi) st[t - lo] = tmp[u];
+        }
     }
     __syncthreads();
+    // large cells are listed (in any order: cells are independent) and sorted
+    // after the small ones; the LDS and global forms are written out separately
+    // so that each compiles to its own memory instructions
+    if (n > kSortReg) big[atomicAdd(&n_big, 1)] = (int)threadIdx.x;
+    if (!staged) {
+        if (n > 1 && n <= kSortReg) rank_sort_small(perm + s, n);
+        __syncthreads();
+        const int nb = n_big;
+        for (int k = 0; k < nb; ++k) {
+            const int cc = c0 + big[k];
+            const int bs = cell_start[cc];
+            block_sort_segment(perm + bs, cell_start[cc + 1] - bs, &s_flag);
+        }
+        return;
+    }
     bool moved = false;
-    if (n > kSortReg) moved = insertion_sort(st + (s - lo), n);
-    else if (n > 1) moved = rank_sort_small(st + (s - lo), n);
+    if (n > 1 && n <= kSortReg) moved = rank_sort_small(st + (s - lo), n);
+    __syncthreads();
+    const int nb = n_big;
+    for (int k = 0; k < nb; ++k) {
+        const int cc = c0 + big[k];
+        const int bs = cell_start[cc];
+        moved = block_sort_segment(st + (bs - lo), cell_start[cc + 1] - bs, &s_flag) || moved;
+    }
     if (!__syncthreads_or(moved)) return;
     for (int t = lo + (int)threadIdx.x; t < hi; t += kBlock) perm[t] = st[t - lo];
 }
@@ -465,26 +558,33 @@ size_t scan_workspace_bytes(int n) {
     return (nb + 1) * sizeof(unsigned long long);
 }
 
+// words of the scan workspace: status[nb], then the tile counter and the abort word
+static unsigned* scan_ctr(void* scan_ws, int n) {
+    return (unsigned*)((unsigned long long*)scan_ws + (n + kScanTile - 1) / kScanTile);
+}
+
 hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, void* scan_ws,
-                                 hipStream_t stream) {
+                                 long spin_max, p2m_report* reps, int nrep, hipStream_t stream) {
     const int nb = (n + kScanTile - 1) / kScanTile;
     unsigned long long* status = (unsigned long long*)scan_ws;
-    unsigned* ctr = (unsigned*)(status + nb);
+    unsigned* ctr = scan_ctr(scan_ws, n);
     if (nb == 0) {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, stream, out, 0, (size_t)1,
                            (p2m_report*)nullptr);
         return hipGetLastError();
     }
+    if (!reps) nrep = 0;
     hipLaunchKernelGGL(k_scan_lookback, dim3(nb), dim3(kBlock), 0, stream, counts, n, out, status,
-                       ctr);
+                       ctr, ctr + 1, spin_max, reps, nrep);
     return hipGetLastError();
 }
 
-hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* rank,
-                        const int32_t* cell_start, int32_t* perm, hipStream_t stream) {
+hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* rank, int32_t* cell_start,
+                        int32_t* perm, const void* scan_ws, hipStream_t stream) {
     if (m.np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_place, dim3(grid_for(m.np, kBlock)), dim3(kBlock), 0, stream, m.np, key,
-                       rank, cell_start, perm, m.nn);
+    const int nthreads = m.np > m.nn + 1 ? m.np : m.nn + 1;
+    hipLaunchKernelGGL(k_place, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, stream, m.np,
+                       key, rank, cell_start, perm, m.nn, 1, scan_ctr((void*)scan_ws, m.nn) + 1);
     return hipGetLastError();
 }
 
@@ -504,11 +604,13 @@ hipError_t launch_locate_count_batch(const BatchInst* inst, const int32_t* lmap,
     return hipGetLastError();
 }
 
-hipError_t launch_place_flat(int np, const int32_t* key, const int32_t* rank,
-                             const int32_t* cell_start, int32_t* perm, hipStream_t stream) {
+hipError_t launch_place_flat(int np, int ncells, const int32_t* key, const int32_t* rank,
+                             int32_t* cell_start, int32_t* perm, const void* scan_ws,
+                             hipStream_t stream) {
     if (np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_place, dim3(grid_for(np, kBlock)), dim3(kBlock), 0, stream, np, key,
-                       rank, cell_start, perm, -1);
+    const int nthreads = np > ncells + 1 ? np : ncells + 1;
+    hipLaunchKernelGGL(k_place, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, stream, np, key,
+                       rank, cell_start, perm, ncells, 0, scan_ctr((void*)scan_ws, ncells) + 1);
     return hipGetLastError();
 }
 

@@ -116,12 +116,19 @@ template <typename T>
 hipError_t launch_locate_count(const Mesh& m, Particles<T> P, int32_t* key, int32_t* rank,
                                int32_t* counts, p2m_report* rep, hipStream_t stream);
 // single-pass scan: scan_ws (scan_workspace_bytes(n)) must be zero on entry;
-// out[0..n] receives the exclusive prefix sums and the total
+// out[0..n] receives the exclusive prefix sums and the total.  spin_max bounds
+// the wait for a predecessor tile (< 0: no wait, a test hook); a scan that gives
+// up raises P2M_FLAG_BIN_TIMEOUT in reps[0..nrep) and sets an abort word in
+// scan_ws that the place kernels read
+constexpr long kScanSpinDefault = 1L << 26;
 size_t scan_workspace_bytes(int n);
 hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, void* scan_ws,
-                                 hipStream_t stream);
-hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* rank,
-                        const int32_t* cell_start, int32_t* perm, hipStream_t stream);
+                                 long spin_max, p2m_report* reps, int nrep, hipStream_t stream);
+// perm[cell_start[key] + rank] = particle; slots after the valid particles -1.
+// After an aborted scan (scan_ws as given to the scan): every cell empty
+// (cell_start[0..nn] = 0, perm = -1)
+hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* rank, int32_t* cell_start,
+                        int32_t* perm, const void* scan_ws, hipStream_t stream);
 hipError_t launch_segment_sort(const Mesh& m, const int32_t* cell_start, int32_t* perm,
                                hipStream_t stream);
 
@@ -194,8 +201,9 @@ hipError_t launch_locate_count_batch(const BatchInst* inst, const int32_t* lmap,
                                      hipStream_t stream);
 // place / segment sort over the whole batch (keys and cell_start in batch numbering,
 // perm receives batch particle numbers); no tail is written
-hipError_t launch_place_flat(int np, const int32_t* key, const int32_t* rank,
-                             const int32_t* cell_start, int32_t* perm, hipStream_t stream);
+hipError_t launch_place_flat(int np, int ncells, const int32_t* key, const int32_t* rank,
+                             int32_t* cell_start, int32_t* perm, const void* scan_ws,
+                             hipStream_t stream);
 hipError_t launch_segment_sort_flat(int ncells, const int32_t* cell_start, int32_t* perm,
                                     hipStream_t stream);
 // scatter of every instance: tile t belongs to instance amap[t]; b, w, coef hold

@@ -440,3 +440,23 @@ def test_stencil_assembly_matches_sparse_assembly(dim):
     assert np.allclose(st["w"], a["w"], atol=1e-15) and np.allclose(st["b"], a["b"], atol=1e-15)
     M2 = p1.stencil_matrix(prob, st)
     assert abs(M2 - a["M"]).max() < 1e-15
+
+
+def test_relative_residual_by_hand():
+    """R13's stopping measure ||b - M x|| / ||b|| with the orphan row of R7 replaced
+    by the identity.  M = [[2, 1, 0], [1, 2, 0], [0, 0, 0]], node 2 an orphan
+    (w = 0); b = (1, 2, 0), x = (0.5, 0.25, 7): the regularised M x is
+    (1.25, 1, 7), r = (-0.25, 1, -7), so the value is sqrt(50.0625 / 5).  An
+    unregularised M would give sqrt(1.0625 / 5), an unnormalised one
+    sqrt(50.0625)."""
+    import scipy.sparse as sp
+    M = sp.csr_matrix(np.array([[2.0, 1.0, 0.0], [1.0, 2.0, 0.0], [0.0, 0.0, 0.0]]))
+    w = np.array([3.0, 3.0, 0.0])
+    b = np.array([[1.0, 2.0, 0.0], [0.0, 0.0, 0.0]])
+    x = np.array([[0.5, 0.25, 7.0], [0.0, 0.0, 0.0]])
+    got = p1.relative_residual(M, w, b, x)
+    assert abs(got[0] - math.sqrt(50.0625 / 5.0)) < 1e-15
+    assert got[1] == 0.0                       # b = 0 and x = 0
+    # b = 0 with x != 0: the absolute residual norm
+    got0 = p1.relative_residual(M, w, np.zeros(3), np.array([1.0, 0.0, 0.0]))
+    assert abs(got0[0] - math.sqrt(5.0)) < 1e-15

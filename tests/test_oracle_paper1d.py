@@ -156,3 +156,75 @@ def test_lumped_rows_conserve():
     out = px.round_trip("lumped", x, A, 50, quad="exact")
     assert abs((v * out).sum() - (v * A).sum()) < 1e-13
     assert (v * out ** 2).sum() <= (v * A ** 2).sum()
+
+
+# ----------------------------------------------------------------------------
+# single P2M / M2P operators of Table 1 against hand values and dense hats
+# ----------------------------------------------------------------------------
+def test_delta_operators_by_hand():
+    """eq. (9): the particle interpolant at the nodes; eq. (10): the mesh
+    interpolant at the particles.  Two particles at 0.1 (A = 1) and 0.6 (A = 3) on
+    [0, 1) with nodes 0, 0.25, 0.5, 0.75: the interpolant rises by 2 over 0.5 and
+    falls back over the wrap-around gap, so Abar = (1.4, 1.6, 2.6, 2.4).  Nodal
+    values 0, 1, 2, 3 read at 0.125 and 0.9 give 0.5 and 3 - 3 * 0.6 = 1.2."""
+    got = px.p2m_delta(np.array([0.6, 0.1]), np.array([3.0, 1.0]), 4)
+    assert np.allclose(got, [1.4, 1.6, 2.6, 2.4], rtol=0, atol=1e-15)
+    back = px.m2p_delta(np.array([0.125, 0.9]), np.array([0.0, 1.0, 2.0, 3.0]), 4)
+    assert np.allclose(back, [0.5, 1.2], rtol=0, atol=1e-15)
+
+
+def test_pic_and_flip_against_dense_hats():
+    """eq. (11) with the mesh volume of eq. (5) (PIC: divide by h) and with the
+    FLIP volume of eq. (12) (divide by sum v psi_i), built from a dense matrix of
+    the mesh hats at the particles."""
+    g = np.random.default_rng(11)
+    n, N = 9, 23
+    xp = g.uniform(0, 1, N)
+    A = g.normal(size=N)
+    v = px.particle_volumes(xp)
+    H = np.zeros((n, N))                     # psi_i(x_mu) from the hat's closed form
+    for i in range(n):
+        for s in (-1, 0, 1):
+            H[i] += np.maximum(0.0, 1.0 - np.abs(xp * n - i - s * n))
+    b = H @ (v * A)
+    assert np.allclose(px.p2m_pic(xp, A, n), b * n, rtol=1e-13, atol=1e-15)
+    assert np.allclose(px.p2m_flip(xp, A, n), b / (H @ v), rtol=1e-13, atol=1e-15)
+    # PIC conserves against the mesh volumes h, FLIP against the FLIP volumes
+    assert abs(px.p2m_pic(xp, A, n).sum() / n - (v * A).sum()) < 1e-14
+    assert abs(((H @ v) * px.p2m_flip(xp, A, n)).sum() - (v * A).sum()) < 1e-14
+
+
+@pytest.mark.parametrize("quad", ["exact", "appB"])
+def test_lumped_rows_on_regular_particles_closed_form(quad):
+    """Particles on the nodes: the particle and mesh hats coincide, the overlap
+    integrals are m A with m the consistent mass matrix (2h/3, h/6), and the
+    Appendix-B rule is exact (no particle inside an element).  So the lumped P2M
+    and the lumped M2P of Table 1 are each the (1, 4, 1)/6 average (eq. (17) with
+    v = h), mass P2M returns A (preservation, eq. (18)), and the round trips are
+    mass-lumped: (1,4,1)/6 once; lumped: twice."""
+    n = 12
+    x = np.arange(n) / n
+    A = np.random.default_rng(7).normal(size=n)
+    avg = (np.roll(A, 1) + 4.0 * A + np.roll(A, -1)) / 6.0
+    assert np.allclose(px.p2m_lumped(x, A, n, quad=quad), avg, rtol=0, atol=1e-14)
+    assert np.allclose(px.m2p_lumped(x, A, n, quad=quad), avg, rtol=0, atol=1e-14)
+    assert np.allclose(px.p2m_mass(x, A, n, quad=quad), A, rtol=0, atol=1e-13)
+    assert np.allclose(px.round_trip("mass_lumped", x, A, n, quad=quad), avg, rtol=0, atol=1e-13)
+    avg2 = (np.roll(avg, 1) + 4.0 * avg + np.roll(avg, -1)) / 6.0
+    assert np.allclose(px.round_trip("lumped", x, A, n, quad=quad), avg2, rtol=0, atol=1e-13)
+
+
+def test_mass_lumped_round_trip_conserves_and_is_stable():
+    """Sec. 2.4: the mass-lumped pair conserves (exact integrals: the mass P2M keeps
+    int A, the lumped M2P keeps int Abar) and is stable: sum v Abarbar^2 <=
+    int Abar^2 <= int A^2 = A^T m_part A (Cauchy-Schwarz with weight psi_mu, then
+    the L2 projection)."""
+    x = px.tophat_positions(60, distort=0.35, seed=8)
+    n = 40
+    A = ((x > 0.25) & (x < 0.75)).astype(float) + 0.3 * np.sin(2 * np.pi * x)
+    v = px.particle_volumes(x)
+    out = px.round_trip("mass_lumped", x, A, n, quad="exact")
+    assert abs((v * out).sum() - (v * A).sum()) < 1e-14
+    assert (v * out ** 2).sum() <= A @ px.particle_mass(x) @ A * (1 + 1e-14)
+    # and it differs from mass-delta (the M2P differs)
+    assert not np.allclose(out, px.round_trip("mass_delta", x, A, n, quad="exact"), atol=1e-6)
