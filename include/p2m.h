@@ -52,7 +52,9 @@ typedef enum {
     P2M_ERR_WORKSPACE = 3,     /* ws NULL or ws_bytes smaller than p2m_workspace_size */
     P2M_ERR_RANGE = 4,         /* lx, ly not > 0, or tol not > 0 */
     P2M_ERR_NONFINITE = 5,     /* lx, ly or tol not finite */
-    P2M_ERR_HIP = 6            /* a HIP runtime call or kernel launch failed */
+    P2M_ERR_HIP = 6,           /* a HIP runtime call or kernel launch failed */
+    P2M_ERR_SCRATCH = 7        /* p2m_mass_assign_noalloc: the problem needs more workspace
+                                  than the static scratch holds (P2M_SCRATCH_BYTES) */
 } p2m_status;
 
 /* Report flags (p2m_report.flags).  Output contents are defined for every flag:
@@ -211,6 +213,27 @@ p2m_status p2m_interpolate(void* ctx, const p2m_problem* prob, const void* nodal
 p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* values, int32_t nfields,
                            const p2m_solve_opts* opts, void* nodal_inout, p2m_report* rep,
                            void* ws, size_t ws_bytes, void* stream);
+
+/* Mass assignment that allocates nothing, for callers that cannot allocate
+ * device memory or pass a workspace (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  The same computation and
+ * the same kernels as p2m_mass_assign, bit for bit, with the workspace taken
+ * from a static device array of P2M_SCRATCH_BYTES (64 MiB) that the library
+ * holds on every device it runs on until the process ends; its device address
+ * is looked up once per device when a context is created.  The caller still
+ * passes values, nodal_inout and rep (device memory, as for p2m_mass_assign).
+ * Returns P2M_ERR_SCRATCH, launching nothing, when p2m_workspace_size of the
+ * problem exceeds P2M_SCRATCH_BYTES (for example 2D meshes of about 256 x 256
+ * nodes at 8 particles per cell and F = 3 fit; 1024 x 1024 does not), and
+ * P2M_ERR_HIP if the scratch's address could not be looked up.  Every call on
+ * one device shares that device's scratch and leaves its contents behind (each
+ * call clears what it needs cleared itself): calls that overlap on one device,
+ * on different streams or from different host threads, race and must not be
+ * issued. */
+enum { P2M_SCRATCH_BYTES = 64 << 20 };
+p2m_status p2m_mass_assign_noalloc(void* ctx, const p2m_problem* prob, const void* values,
+                                   int32_t nfields, const p2m_solve_opts* opts, void* nodal_inout,
+                                   p2m_report* rep, void* stream);
 
 /* The solve step of p2m_mass_assign alone, for a system assembled by
  * p2m_assemble with the same problem and field count (b [F][nn], w [nn], coef

@@ -41,7 +41,9 @@ EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size
            "p2m_set_learned", "p2m_learned_features", "p2m_learned_forward",
            "p2m_learned_workspace_size", "p2m_learned_train_step", "p2m_tune", "p2m_tune_batched",
            "p2m_plan_get", "p2m_plan_get_batched",
-           "p2m_plan_save", "p2m_plan_load", "p2m_plan_clear")
+           "p2m_plan_save", "p2m_plan_load", "p2m_plan_clear", "p2m_mass_assign_noalloc")
+ERR_SCRATCH = 7
+SCRATCH_BYTES = 64 << 20
 LEARNED_KMAX, LEARNED_NIN, LEARNED_HIDDEN, LEARNED_NPARAM = 48, 160, 64, 18689
 
 
@@ -102,6 +104,7 @@ def lib():
                                       sz, vp]
         L.p2m_mass_solve.argtypes = [vp, pprob, i32, vp, vp, vp, ctypes.POINTER(CSolveOpts), vp, vp,
                                      vp, sz, vp]
+        L.p2m_mass_assign_noalloc.argtypes = [vp, pprob, vp, i32, ctypes.POINTER(CSolveOpts), vp, vp, vp]
         L.p2m_batch_workspace_size.argtypes = [vp, pprob, i32, i32, ctypes.POINTER(sz)]
         L.p2m_mass_assign_batched.argtypes = [vp, pprob, i32, ctypes.POINTER(vp), i32,
                                               ctypes.POINTER(CSolveOpts), ctypes.POINTER(vp), vp, vp,
@@ -398,6 +401,27 @@ def p2m_mass_assign(ctx: Context, prob: Particles, values, opts: CSolveOpts | No
                                  ctypes.byref(opts), ctypes.c_void_p(out.data_ptr()),
                                  ctypes.c_void_p(rep.data_ptr()), wp, wn, _stream_ptr(stream)),
            "p2m_mass_assign")
+    return out, rep
+
+
+def p2m_mass_assign_noalloc(ctx: Context, prob: Particles, values, opts: CSolveOpts | None = None,
+                            x0=None, stream=None, rep=None, out=None):
+    """Mass assignment on the library's static device scratch (no workspace argument):
+    (nodal [F, nn], report tensor).  Raises P2MError with ERR_SCRATCH when the problem
+    needs more than SCRATCH_BYTES of workspace."""
+    values, F = _values_tensor(values, prob)
+    cp = prob.cstruct()
+    opts = opts if opts is not None else solve_opts(fp64=prob.dtype == torch.float64)
+    if out is None:
+        out = torch.empty((F, prob.n_nodes), dtype=prob.dtype, device=prob.x.device)
+    if x0 is not None:
+        out.copy_(x0)
+    rep = ctx.new_report() if rep is None else rep
+    _check(lib().p2m_mass_assign_noalloc(ctx.handle, ctypes.byref(cp),
+                                         ctypes.c_void_p(values.data_ptr()), F, ctypes.byref(opts),
+                                         ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(rep.data_ptr()), _stream_ptr(stream)),
+           "p2m_mass_assign_noalloc")
     return out, rep
 
 

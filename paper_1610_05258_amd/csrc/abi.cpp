@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -56,6 +57,7 @@ struct Context {
     const float* learned;   // parameters of the learned start (device), or null
     PlanCache* plans;       // created on the first tuned or loaded plan
     const p2m_plan* forced; // the candidate being timed by p2m_tune
+    void* scratch;          // device address of this device's static scratch, or null
 };
 
 // Makes the context's device current for the duration of a call and restores
@@ -75,6 +77,31 @@ struct DeviceGuard {
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// ---------------------------------------------------------------------------
+// Static scratch of p2m_mass_assign_noalloc: the workspace of that entry point is
+// this file-scope device array (one copy per device, held by the loaded code
+// object until the process ends).  Host code never uses the array's name as an
+// address: p2m_create looks the device address up once per device with
+// hipGetSymbolAddress, and every use goes through that pointer.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)P2M_SCRATCH_BYTES;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kScratchDevices];   // device address per device (null: not looked up)
+
+// The device address of `scratch` on `device`, which must be current; null when
+// the lookup fails (the no-allocation entry point then reports P2M_ERR_HIP).
+void* scratch_address(int device) {
+    if (device < 0 || device >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p) g_scratch_dev[device] = p;
+        else (void)hipGetLastError();   // leave no sticky error for the caller's next call
+    }
+    return g_scratch_dev[device];
+}
 
 // Workspace carve-up.  Offsets are fixed functions of (problem, F, cg blocks).
 struct Layout {
@@ -577,6 +604,7 @@ const char* p2m_status_string(p2m_status s) {
         case P2M_ERR_RANGE: return "P2M_ERR_RANGE";
         case P2M_ERR_NONFINITE: return "P2M_ERR_NONFINITE";
         case P2M_ERR_HIP: return "P2M_ERR_HIP";
+        case P2M_ERR_SCRATCH: return "P2M_ERR_SCRATCH";
     }
     return "P2M_UNKNOWN_STATUS";
 }
@@ -597,6 +625,7 @@ p2m_status p2m_create(void** ctx, int device) {
     c->solver_mode = P2M_SOLVER_AUTO;
     c->use_plans = 1;
     c->scan_spin = kScanSpinDefault;
+    c->scratch = scratch_address(device);
     if (c->cg_blocks_f32 <= 0 || c->cg_blocks_f64 <= 0) {
         free(c);
         return P2M_ERR_HIP;
@@ -735,6 +764,20 @@ p2m_status p2m_mass_assign(void* ctx, const p2m_problem* prob, const void* value
     return prob->dtype == P2M_F64
                ? run_mass<double>(c, pp, prob, values, nfields, *opts, nodal_inout, ch)
                : run_mass<float>(c, pp, prob, values, nfields, *opts, nodal_inout, ch);
+}
+
+p2m_status p2m_mass_assign_noalloc(void* ctx, const p2m_problem* prob, const void* values,
+                                   int32_t nfields, const p2m_solve_opts* opts, void* nodal_inout,
+                                   p2m_report* rep, void* stream) {
+    if (!ctx) return P2M_ERR_INVALID_ARG;
+    size_t need = 0;
+    p2m_status s = p2m_workspace_size(ctx, prob, nfields, &need);
+    if (s != P2M_OK) return s;
+    if (need > kScratchBytes) return P2M_ERR_SCRATCH;
+    void* ws = ((const Context*)ctx)->scratch;
+    if (!ws) return P2M_ERR_HIP;
+    return p2m_mass_assign(ctx, prob, values, nfields, opts, nodal_inout, rep, ws, kScratchBytes,
+                           stream);
 }
 
 p2m_status p2m_mass_solve(void* ctx, const p2m_problem* prob, int32_t nfields, void* b, const void* w,
