@@ -144,8 +144,16 @@ p2m_status p2m_destroy(void* ctx);
  *                         (p2m_tune) overrides this choice
  *   P2M_SOLVER_STREAMING  grid-synchronised streaming kernel (any problem)
  *   P2M_SOLVER_RESIDENT   register-resident kernel where it applies (as AUTO)
- *   P2M_SOLVER_TILES      tile-streaming kernel where it applies */
-enum { P2M_SOLVER_AUTO = 0, P2M_SOLVER_STREAMING = 1, P2M_SOLVER_RESIDENT = 2, P2M_SOLVER_TILES = 3 };
+ *   P2M_SOLVER_TILES      tile-streaming kernel where it applies
+ *   P2M_SOLVER_RESIDENT_CHEB
+ *                         the register-resident kernel with a degree-2 Chebyshev
+ *                         polynomial preconditioner, u = (c0 + c1 D^-1 M) D^-1 r,
+ *                         instead of the diagonal one (D = diag M): the same system
+ *                         and tolerance in fewer iterations, one grid barrier each;
+ *                         where it does not apply, as AUTO.  The tuner tries it;
+ *                         AUTO itself keeps the diagonal preconditioner. */
+enum { P2M_SOLVER_AUTO = 0, P2M_SOLVER_STREAMING = 1, P2M_SOLVER_RESIDENT = 2, P2M_SOLVER_TILES = 3,
+       P2M_SOLVER_RESIDENT_CHEB = 4 };
 
 /* Context options (p2m_set_option).
  *   P2M_OPT_SOLVER     a P2M_SOLVER_* value (default AUTO); anything but AUTO forces
@@ -245,6 +253,54 @@ p2m_status p2m_mass_assign_noalloc(void* ctx, const p2m_problem* prob, const voi
 p2m_status p2m_mass_solve(void* ctx, const p2m_problem* prob, int32_t nfields, void* b,
                           const void* w, void* coef, const p2m_solve_opts* opts, void* nodal_inout,
                           p2m_report* rep, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Paper-exact 1D assignment (Table 1 with the particle hats of Sec. 2: in 1D the
+ * particle "triangulation" is the order of the particles along the periodic
+ * segment; Sec. 3.1).  FP64 1D problems only (dtype P2M_F64, dim 1; prob->vol is
+ * ignored: the particle volumes are those of eq. (4), v_mu = (x_{mu+1} -
+ * x_{mu-1}) / 2 on the sorted particles).  Particles are ordered by wrapped
+ * position, ties by particle number.  The integrals int A psi_j (P2M, mesh hats
+ * psi_j, A the particle interpolant of eq. (1)) and int Abar psi_mu (M2P,
+ * particle hats, Abar the mesh interpolant of eq. (3)) are evaluated either
+ * exactly (P2M_QUAD_EXACT: breakpoints of both interpolants merged, Simpson's
+ * rule exact on every piece) or with the Appendix-B rule (P2M_QUAD_APPB: on
+ * every gap of the target hats, the parabola through the source interpolant at
+ * both ends and the midpoint, integrated exactly).  Mass systems use the
+ * consistent mass matrices (mesh: 2h/3 and h/6; particles: (g_{mu-1} + g_mu)/3
+ * and g_mu/6 with g_mu = x_{mu+1} - x_mu) and are solved by the FP64 streaming
+ * CG to opts->tol.  Each call synchronises `stream` once, after binning (to
+ * size the particle-order arrays).  Particles that cannot be located are left
+ * out (P2M) and get NaN (M2P); at least one located particle is needed for the
+ * mass and lumped kinds and for delta.
+ * --------------------------------------------------------------------------- */
+typedef enum { P2M_QUAD_EXACT = 0, P2M_QUAD_APPB = 1 } p2m_quad;
+typedef enum {
+    P2M_X1D_DELTA = 0,   /* P2M: Abar_i = A(x_i), eq. (9);  M2P: Abar(x_mu), eq. (10) */
+    P2M_X1D_FLIP = 1,    /* P2M only: eqs. (11)-(12) with the volumes of eq. (4) */
+    P2M_X1D_PIC = 2,     /* P2M only: eq. (11) with v_i = h, eq. (5) */
+    P2M_X1D_MASS = 3,    /* P2M: m^-1 int A psi_j (mass-delta and full mass, Table 1);
+                            M2P: m_part^-1 int Abar psi_mu, eq. (20) (full mass) */
+    P2M_X1D_LUMPED = 4   /* P2M: (1/h) int A psi_i;  M2P: (1/v_mu) int Abar psi_mu, eq. (17) */
+} p2m_x1d_kind;
+
+/* Workspace bytes of the three calls below for this problem and field count. */
+p2m_status p2m_x1d_workspace_size(void* ctx, const p2m_problem* prob, int32_t nfields,
+                                  size_t* bytes);
+/* Particle -> mesh: nodal_out [F][nx] (device).  opts is used by P2M_X1D_MASS (NULL:
+ * tol 1e-14); rep (device, required) receives the solve's report. */
+p2m_status p2m_x1d_assign(void* ctx, const p2m_problem* prob, int32_t kind, int32_t quad,
+                          const void* values, int32_t nfields, const p2m_solve_opts* opts,
+                          void* nodal_out, p2m_report* rep, void* ws, size_t ws_bytes,
+                          void* stream);
+/* Mesh -> particle (kind DELTA, MASS or LUMPED): values_out [F][np] in caller order. */
+p2m_status p2m_x1d_interpolate(void* ctx, const p2m_problem* prob, int32_t kind, int32_t quad,
+                               const void* nodal, int32_t nfields, const p2m_solve_opts* opts,
+                               void* values_out, p2m_report* rep, void* ws, size_t ws_bytes,
+                               void* stream);
+/* The particle volumes of eq. (4), vol_out [np] in caller order (NaN: not located). */
+p2m_status p2m_x1d_volumes(void* ctx, const p2m_problem* prob, void* vol_out, p2m_report* rep,
+                           void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent problems in one launch.

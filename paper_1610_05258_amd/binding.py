@@ -32,7 +32,7 @@ FLAG_LEARNED_FALLBACK = 1 << 5
 FLAG_BIN_TIMEOUT = 1 << 6
 REPORT_BYTES = 144
 MAX_FIELDS = 8
-SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT, SOLVER_TILES = 0, 1, 2, 3
+SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT, SOLVER_TILES, SOLVER_RESIDENT_CHEB = 0, 1, 2, 3, 4
 OPT_SOLVER, OPT_PLANS, OPT_SCAN_SPIN = 0, 1, 2
 
 EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size", "p2m_bin",
@@ -41,7 +41,10 @@ EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size
            "p2m_set_learned", "p2m_learned_features", "p2m_learned_forward",
            "p2m_learned_workspace_size", "p2m_learned_train_step", "p2m_tune", "p2m_tune_batched",
            "p2m_plan_get", "p2m_plan_get_batched",
-           "p2m_plan_save", "p2m_plan_load", "p2m_plan_clear", "p2m_mass_assign_noalloc")
+           "p2m_plan_save", "p2m_plan_load", "p2m_plan_clear", "p2m_mass_assign_noalloc",
+           "p2m_x1d_workspace_size", "p2m_x1d_assign", "p2m_x1d_interpolate", "p2m_x1d_volumes")
+QUAD_EXACT, QUAD_APPB = 0, 1
+X1D_DELTA, X1D_FLIP, X1D_PIC, X1D_MASS, X1D_LUMPED = 0, 1, 2, 3, 4
 ERR_SCRATCH = 7
 SCRATCH_BYTES = 64 << 20
 LEARNED_KMAX, LEARNED_NIN, LEARNED_HIDDEN, LEARNED_NPARAM = 48, 160, 64, 18689
@@ -105,6 +108,12 @@ def lib():
         L.p2m_mass_solve.argtypes = [vp, pprob, i32, vp, vp, vp, ctypes.POINTER(CSolveOpts), vp, vp,
                                      vp, sz, vp]
         L.p2m_mass_assign_noalloc.argtypes = [vp, pprob, vp, i32, ctypes.POINTER(CSolveOpts), vp, vp, vp]
+        L.p2m_x1d_workspace_size.argtypes = [vp, pprob, i32, ctypes.POINTER(sz)]
+        L.p2m_x1d_assign.argtypes = [vp, pprob, i32, i32, vp, i32, ctypes.POINTER(CSolveOpts), vp, vp,
+                                     vp, sz, vp]
+        L.p2m_x1d_interpolate.argtypes = [vp, pprob, i32, i32, vp, i32, ctypes.POINTER(CSolveOpts), vp,
+                                          vp, vp, sz, vp]
+        L.p2m_x1d_volumes.argtypes = [vp, pprob, vp, vp, vp, sz, vp]
         L.p2m_batch_workspace_size.argtypes = [vp, pprob, i32, i32, ctypes.POINTER(sz)]
         L.p2m_mass_assign_batched.argtypes = [vp, pprob, i32, ctypes.POINTER(vp), i32,
                                               ctypes.POINTER(CSolveOpts), ctypes.POINTER(vp), vp, vp,
@@ -240,10 +249,11 @@ class Context:
     def __exit__(self, *exc):
         self.close()
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP call while the interpreter shuts down: the runtime (or a profiler
         # attached to it) may already be finalised; the process exit releases it
-        if sys.is_finalizing():
+        # (the check is bound at definition: module globals may be gone by then)
+        if _finalizing():
             return
         try:
             self.close()
@@ -251,7 +261,7 @@ class Context:
             pass
 
     def set_solver(self, kind: int):
-        """SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT or SOLVER_TILES."""
+        """SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT, SOLVER_TILES or SOLVER_RESIDENT_CHEB."""
         _check(lib().p2m_set_option(self.handle, OPT_SOLVER, int(kind)), "p2m_set_option")
 
     def use_plans(self, on: bool):
@@ -423,6 +433,74 @@ def p2m_mass_assign_noalloc(ctx: Context, prob: Particles, values, opts: CSolveO
                                          ctypes.c_void_p(rep.data_ptr()), _stream_ptr(stream)),
            "p2m_mass_assign_noalloc")
     return out, rep
+
+
+# ----------------------------------------------------------------------------
+# paper-exact 1D (FP64 1D problems; particle volumes from the sorted particles)
+# ----------------------------------------------------------------------------
+def x1d_workspace_size(ctx, prob, F):
+    n = ctypes.c_size_t()
+    cp = prob.cstruct()
+    _check(lib().p2m_x1d_workspace_size(ctx.handle, ctypes.byref(cp), int(F), ctypes.byref(n)),
+           "p2m_x1d_workspace_size")
+    return int(n.value)
+
+
+def _x1d_ws(ctx, prob, F, ws):
+    if ws is None:
+        ws = ctx.workspace(x1d_workspace_size(ctx, prob, F))
+    return ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel())
+
+
+def _opts_ptr(opts):
+    return ctypes.byref(opts) if opts is not None else None
+
+
+def p2m_x1d_assign(ctx: Context, prob: Particles, kind: int, quad: int, values, opts=None,
+                   stream=None, ws=None, rep=None, out=None):
+    """Paper-exact 1D particle->mesh of kind X1D_* with QUAD_EXACT / QUAD_APPB integrals:
+    (nodal [F, nx] FP64, report tensor)."""
+    values, F = _values_tensor(values, prob)
+    cp = prob.cstruct()
+    if out is None:
+        out = torch.empty((F, prob.n_nodes), dtype=torch.float64, device=prob.x.device)
+    rep = ctx.new_report() if rep is None else rep
+    wp, wn = _x1d_ws(ctx, prob, F, ws)
+    _check(lib().p2m_x1d_assign(ctx.handle, ctypes.byref(cp), int(kind), int(quad),
+                                ctypes.c_void_p(values.data_ptr()), F, _opts_ptr(opts),
+                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(rep.data_ptr()),
+                                wp, wn, _stream_ptr(stream)), "p2m_x1d_assign")
+    return out, rep
+
+
+def p2m_x1d_interpolate(ctx: Context, prob: Particles, kind: int, quad: int, nodal, opts=None,
+                        stream=None, ws=None, rep=None, out=None):
+    """Paper-exact 1D mesh->particle of kind X1D_DELTA / X1D_MASS / X1D_LUMPED:
+    (values [F, np] FP64 in caller order, report tensor)."""
+    nodal = nodal.contiguous()
+    F = int(nodal.shape[0])
+    cp = prob.cstruct()
+    if out is None:
+        out = torch.empty((F, prob.n_particles), dtype=torch.float64, device=prob.x.device)
+    rep = ctx.new_report() if rep is None else rep
+    wp, wn = _x1d_ws(ctx, prob, F, ws)
+    _check(lib().p2m_x1d_interpolate(ctx.handle, ctypes.byref(cp), int(kind), int(quad),
+                                     ctypes.c_void_p(nodal.data_ptr()), F, _opts_ptr(opts),
+                                     ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(rep.data_ptr()),
+                                     wp, wn, _stream_ptr(stream)), "p2m_x1d_interpolate")
+    return out, rep
+
+
+def p2m_x1d_volumes(ctx: Context, prob: Particles, stream=None, ws=None, rep=None):
+    """Particle volumes of eq. (4) in caller order (FP64)."""
+    cp = prob.cstruct()
+    out = torch.empty(prob.n_particles, dtype=torch.float64, device=prob.x.device)
+    rep = ctx.new_report() if rep is None else rep
+    wp, wn = _x1d_ws(ctx, prob, 1, ws)
+    _check(lib().p2m_x1d_volumes(ctx.handle, ctypes.byref(cp), ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(rep.data_ptr()), wp, wn, _stream_ptr(stream)),
+           "p2m_x1d_volumes")
+    return out
 
 
 def p2m_mass_solve(ctx: Context, prob: Particles, b, w, coef, opts: CSolveOpts | None = None,

@@ -340,7 +340,15 @@ p2m_status run_solve(const Context* c, const Prepared& pp, int F, T* b, const T*
     if (ch.inner_rtol >= 0.0 && ch.inner_rtol < 1.0) opts.inner_rtol = ch.inner_rtol;
     const bool tiled = sizeof(T) == 4 && pp.m.dim == 2 && F <= kResidentMaxFields;
     const int kind = ch.solver;
-    if (tiled && (kind == P2M_SOLVER_AUTO || kind == P2M_SOLVER_RESIDENT) &&
+    if (tiled && kind == P2M_SOLVER_RESIDENT_CHEB && cgrc_supported(pp.m, F, c->device)) {
+        P2M_TRY(launch_cg_resident_cheb(pp.m, F, (float*)coef, (float*)b, (const float*)w,
+                                        (float*)x, start, pp.ws + pp.L.resident, opts, pp.rep,
+                                        pp.clear_rep, pp.stream));
+        pp.clear_rep = false;
+        return P2M_OK;
+    }
+    if (tiled && (kind == P2M_SOLVER_AUTO || kind == P2M_SOLVER_RESIDENT ||
+                  kind == P2M_SOLVER_RESIDENT_CHEB) &&
         cgr_supported(pp.m, F, c->device)) {
         P2M_TRY(launch_cg_resident(pp.m, F, (float*)coef, (float*)b, (const float*)w, (float*)x,
                                    start, pp.ws + pp.L.resident, opts, pp.rep, pp.clear_rep,
@@ -582,6 +590,125 @@ hipError_t enqueue_batch(const BatchPlan& P, char* ws, p2m_report* reps, const p
     return launch_cg_batch(P.F, bb, (size_t)P.nn, P.grid, opts.start, opts, stream);
 }
 
+// ---------------------------------------------------------------------------
+// paper-exact 1D (k_exact1d.hip)
+// ---------------------------------------------------------------------------
+struct X1DLayout {
+    size_t key, counts, scan, cell_start, perm;          // binning (as in Layout)
+    size_t skey, sidx, gap, vols, volc, As, fa, fb, tlo, thi, c, coef, w, x, b, bw;
+    size_t r, p0, p1, q, x64, dinv, part, report, total;
+    int blocks;
+};
+
+X1DLayout make_x1d_layout(const Context* c, const Mesh& m, int F) {
+    X1DLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const size_t np = (size_t)m.np, n = (size_t)m.nn, K = np > n ? np : n, d8 = sizeof(double);
+    Mesh mk = m;
+    mk.nn = (int)K;
+    L.blocks = cg_blocks_for(c, mk, P2M_F64);
+    L.key = take(2 * np * sizeof(int32_t));
+    L.counts = take(n * sizeof(int32_t));
+    L.scan = take(scan_workspace_bytes((int)n));   // right after counts: one fill clears both
+    L.cell_start = take((n + 1) * sizeof(int32_t));
+    L.perm = take(np * sizeof(int32_t));
+    L.skey = take(np * d8);
+    L.sidx = take(np * sizeof(int32_t));
+    L.gap = take(np * d8);
+    L.vols = take(np * d8);
+    L.volc = take(np * d8);
+    L.As = take((size_t)F * np * d8);
+    L.fa = take((size_t)F * K * d8);
+    L.fb = take((size_t)F * K * d8);
+    L.tlo = take((size_t)F * K * d8);
+    L.thi = take((size_t)F * K * d8);
+    L.c = take((size_t)F * K * d8);
+    L.coef = take(2 * K * d8);
+    L.w = take(K * d8);
+    L.x = take((size_t)F * K * d8);
+    L.b = take((size_t)F * n * d8);
+    L.bw = take(n * d8);
+    L.r = take((size_t)F * K * d8);
+    L.p0 = take((size_t)F * K * d8);
+    L.p1 = take((size_t)F * K * d8);
+    L.q = take((size_t)F * K * d8);
+    L.x64 = take((size_t)2 * F * K * d8);
+    L.dinv = take(K * d8);
+    L.part = take(cg_partials_bytes(L.blocks));
+    L.report = take(sizeof(p2m_report));
+    L.total = off;
+    return L;
+}
+
+// Validation, layout, binning and the located count N (one stream synchronisation).
+p2m_status x1d_begin(void* ctx, const p2m_problem* prob, int F, void* ws, size_t ws_bytes,
+                     void* stream, p2m_report* rep, Prepared& pp, X1DLayout& X, int& N) {
+    if (!ctx || F < 1 || F > kMaxFields) return P2M_ERR_INVALID_ARG;
+    Mesh m;
+    p2m_status s = check_problem(prob, m);
+    if (s != P2M_OK) return s;
+    if (m.dim != 1 || prob->dtype != P2M_F64) return P2M_ERR_UNSUPPORTED;
+    const Context* c = (const Context*)ctx;
+    X = make_x1d_layout(c, m, F);
+    if (!ws || ws_bytes < X.total || ((uintptr_t)ws) % kAlign) return P2M_ERR_WORKSPACE;
+    pp.m = m;
+    memset(&pp.L, 0, sizeof(pp.L));
+    pp.L.key = X.key;
+    pp.L.counts = X.counts;
+    pp.L.scan = X.scan;
+    pp.L.cell_start = X.cell_start;
+    pp.L.perm = X.perm;
+    pp.ws = (char*)ws;
+    pp.stream = (hipStream_t)stream;
+    pp.rep = rep ? rep : (p2m_report*)(pp.ws + X.report);
+    pp.scan_spin = c->scan_spin;
+    pp.clear_rep = true;
+    int32_t* perm = (int32_t*)(pp.ws + X.perm);
+    int32_t* cs = (int32_t*)(pp.ws + X.cell_start);
+    s = run_bin<double>(pp, prob, perm, cs);
+    if (s != P2M_OK) return s;
+    int32_t located = 0;
+    P2M_TRY(hipMemcpyAsync(&located, cs + m.nn, sizeof(int32_t), hipMemcpyDeviceToHost, pp.stream));
+    P2M_TRY(hipStreamSynchronize(pp.stream));
+    N = located;
+    P2M_TRY(x1d_sort(m, N, (const double*)prob->x, perm, cs, (double*)(pp.ws + X.skey),
+                     (int32_t*)(pp.ws + X.sidx), pp.stream));
+    return P2M_OK;
+}
+
+CgWorkspace x1d_cg_ws(const Prepared& pp, const X1DLayout& X, const Context* c, const Mesh& ms) {
+    CgWorkspace cw;
+    cw.r = pp.ws + X.r;
+    cw.p0 = pp.ws + X.p0;
+    cw.p1 = pp.ws + X.p1;
+    cw.q = pp.ws + X.q;
+    cw.x64 = (double*)(pp.ws + X.x64);
+    cw.partials = (double*)(pp.ws + X.part);
+    cw.dinv = pp.ws + X.dinv;
+    cw.blocks = cg_blocks_for(c, ms, P2M_F64);
+    return cw;
+}
+
+p2m_solve_opts x1d_opts(const p2m_solve_opts* o, int n) {
+    p2m_solve_opts r;
+    if (o) {
+        r = *o;
+    } else {
+        r.tol = 1e-14;
+        r.maxit = 20 * n + 200;
+        r.max_refine = 20;
+    }
+    r.inner_rtol = 0.0;
+    r.start = P2M_START_FLIP;
+    r.reserved = 0;
+    return r;
+}
+
 p2m_status check_opts(const p2m_solve_opts* opts) {
     if (!opts) return P2M_ERR_INVALID_ARG;
     if (!isfinite(opts->tol) || !isfinite(opts->inner_rtol)) return P2M_ERR_NONFINITE;
@@ -638,7 +765,7 @@ p2m_status p2m_set_option(void* ctx, int32_t option, int32_t value) {
     if (!ctx) return P2M_ERR_INVALID_ARG;
     Context* c = (Context*)ctx;
     if (option == P2M_OPT_SOLVER) {
-        if (value < P2M_SOLVER_AUTO || value > P2M_SOLVER_TILES) return P2M_ERR_INVALID_ARG;
+        if (value < P2M_SOLVER_AUTO || value > P2M_SOLVER_RESIDENT_CHEB) return P2M_ERR_INVALID_ARG;
         c->solver_mode = value;
         return P2M_OK;
     }
@@ -778,6 +905,172 @@ p2m_status p2m_mass_assign_noalloc(void* ctx, const p2m_problem* prob, const voi
     if (!ws) return P2M_ERR_HIP;
     return p2m_mass_assign(ctx, prob, values, nfields, opts, nodal_inout, rep, ws, kScratchBytes,
                            stream);
+}
+
+p2m_status p2m_x1d_workspace_size(void* ctx, const p2m_problem* prob, int32_t nfields,
+                                  size_t* bytes) {
+    if (!ctx || !bytes || nfields < 1 || nfields > kMaxFields) return P2M_ERR_INVALID_ARG;
+    Mesh m;
+    p2m_status s = check_problem(prob, m);
+    if (s != P2M_OK) return s;
+    if (m.dim != 1 || prob->dtype != P2M_F64) return P2M_ERR_UNSUPPORTED;
+    *bytes = make_x1d_layout((const Context*)ctx, m, nfields).total;
+    return P2M_OK;
+}
+
+p2m_status p2m_x1d_assign(void* ctx, const p2m_problem* prob, int32_t kind, int32_t quad,
+                          const void* values, int32_t nfields, const p2m_solve_opts* opts,
+                          void* nodal_out, p2m_report* rep, void* ws, size_t ws_bytes,
+                          void* stream) {
+    if (!rep || !nodal_out) return P2M_ERR_INVALID_ARG;
+    if (kind < P2M_X1D_DELTA || kind > P2M_X1D_LUMPED) return P2M_ERR_INVALID_ARG;
+    if (quad != P2M_QUAD_EXACT && quad != P2M_QUAD_APPB) return P2M_ERR_INVALID_ARG;
+    if (opts && kind == P2M_X1D_MASS) {
+        p2m_status so = check_opts(opts);
+        if (so != P2M_OK) return so;
+    }
+    if (!prob || (prob->np > 0 && !values)) return P2M_ERR_INVALID_ARG;
+    if (!ctx) return P2M_ERR_INVALID_ARG;
+    const Context* c = (const Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    Prepared pp;
+    X1DLayout X;
+    int N = 0;
+    p2m_status s = x1d_begin(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp, X, N);
+    if (s != P2M_OK) return s;
+    const Mesh& m = pp.m;
+    const int F = nfields, n = m.nx;
+    const double h = m.cell_measure, L = h * n;
+    char* w8 = pp.ws;
+    double* out = (double*)nodal_out;
+    const double* key = (const double*)(w8 + X.skey);
+    const int32_t* idx = (const int32_t*)(w8 + X.sidx);
+    double* volc = (double*)(w8 + X.volc);
+    P2M_TRY(x1d_setup(N, L, key, idx, (const double*)values, F, m.np, (double*)(w8 + X.gap),
+                      (double*)(w8 + X.vols), volc, (double*)(w8 + X.As), pp.stream));
+    if (kind == P2M_X1D_FLIP || kind == P2M_X1D_PIC) {
+        Particles<double> P = particles_of<double>(prob);
+        P.vol = volc;
+        double* b = (double*)(w8 + X.b);
+        double* bw = (double*)(w8 + X.bw);
+        P2M_TRY(launch_assemble<double>(m, P, (const double*)values, F,
+                                        (const int32_t*)(w8 + X.perm),
+                                        (const int32_t*)(w8 + X.cell_start), b, bw, nullptr,
+                                        pp.stream));
+        P2M_TRY(launch_finalize<double>(m, F, b, bw, kind == P2M_X1D_PIC ? 1 : 0, out, pp.rep,
+                                        pp.stream));
+        return P2M_OK;
+    }
+    const double* As = (const double*)(w8 + X.As);
+    double* cvec = (double*)(w8 + X.c);
+    // the particle interpolant at the nodes (the delta P2M) goes to nodal_out or fa
+    double* fn = kind == P2M_X1D_DELTA ? out : (double*)(w8 + X.fa);
+    P2M_TRY(x1d_p2m_overlap(m, N, key, As, F, kind == P2M_X1D_DELTA ? P2M_QUAD_APPB : quad, fn,
+                            (double*)(w8 + X.fb), (double*)(w8 + X.tlo), (double*)(w8 + X.thi),
+                            cvec, pp.stream));
+    if (kind == P2M_X1D_DELTA) return P2M_OK;
+    if (kind == P2M_X1D_LUMPED) {
+        P2M_TRY(x1d_div(n, F, cvec, nullptr, h, out, pp.stream));
+        return P2M_OK;
+    }
+    double* coef = (double*)(w8 + X.coef);
+    double* wv = (double*)(w8 + X.w);
+    P2M_TRY(x1d_mass_mesh(n, L, coef, wv, pp.stream));
+    const p2m_solve_opts o = x1d_opts(opts, n);
+    P2M_TRY(launch_cg<double>(m, F, coef, cvec, wv, out, P2M_START_FLIP, x1d_cg_ws(pp, X, c, m), o,
+                              pp.rep, pp.stream));
+    return P2M_OK;
+}
+
+p2m_status p2m_x1d_interpolate(void* ctx, const p2m_problem* prob, int32_t kind, int32_t quad,
+                               const void* nodal, int32_t nfields, const p2m_solve_opts* opts,
+                               void* values_out, p2m_report* rep, void* ws, size_t ws_bytes,
+                               void* stream) {
+    if (!rep || !nodal || !values_out || !ctx) return P2M_ERR_INVALID_ARG;
+    if (kind != P2M_X1D_DELTA && kind != P2M_X1D_MASS && kind != P2M_X1D_LUMPED)
+        return P2M_ERR_INVALID_ARG;
+    if (quad != P2M_QUAD_EXACT && quad != P2M_QUAD_APPB) return P2M_ERR_INVALID_ARG;
+    if (opts && kind == P2M_X1D_MASS) {
+        p2m_status so = check_opts(opts);
+        if (so != P2M_OK) return so;
+    }
+    const Context* c = (const Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    if (kind == P2M_X1D_DELTA) {
+        Prepared pp;
+        p2m_status s = prepare(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp);
+        if (s != P2M_OK && s != P2M_ERR_WORKSPACE) return s;
+        if (s == P2M_ERR_WORKSPACE) {   // the gather needs none
+            s = check_problem(prob, pp.m);
+            if (s != P2M_OK) return s;
+        }
+        if (pp.m.dim != 1 || prob->dtype != P2M_F64) return P2M_ERR_UNSUPPORTED;
+        P2M_TRY(launch_report_clear(rep, (hipStream_t)stream));
+        P2M_TRY(launch_gather<double>(pp.m, particles_of<double>(prob), (const double*)nodal,
+                                      nfields, (double*)values_out, rep, (hipStream_t)stream));
+        return P2M_OK;
+    }
+    Prepared pp;
+    X1DLayout X;
+    int N = 0;
+    p2m_status s = x1d_begin(ctx, prob, nfields, ws, ws_bytes, stream, rep, pp, X, N);
+    if (s != P2M_OK) return s;
+    const Mesh& m = pp.m;
+    const int F = nfields, n = m.nx;
+    const double h = m.cell_measure, L = h * n;
+    char* w8 = pp.ws;
+    const double* key = (const double*)(w8 + X.skey);
+    const int32_t* idx = (const int32_t*)(w8 + X.sidx);
+    const double* gap = (const double*)(w8 + X.gap);
+    double* vols = (double*)(w8 + X.vols);
+    P2M_TRY(x1d_setup(N, L, key, idx, nullptr, 0, m.np, (double*)gap, vols, (double*)(w8 + X.volc),
+                      nullptr, pp.stream));
+    double* cvec = (double*)(w8 + X.c);
+    double* xs = (double*)(w8 + X.x);
+    P2M_TRY(x1d_m2p_overlap(m, N, key, gap, (const double*)nodal, F, quad, (double*)(w8 + X.fa),
+                            (double*)(w8 + X.fb), (double*)(w8 + X.tlo), (double*)(w8 + X.thi),
+                            cvec, pp.stream));
+    if (kind == P2M_X1D_LUMPED) {
+        P2M_TRY(x1d_div(N, F, cvec, vols, 0.0, xs, pp.stream));
+    } else if (N > 0) {
+        double* coef = (double*)(w8 + X.coef);
+        P2M_TRY(x1d_mass_part(N, gap, coef, pp.stream));
+        Mesh mp;
+        memset(&mp, 0, sizeof(mp));
+        mp.dim = 1;
+        mp.nx = N;
+        mp.ny = 1;
+        mp.nn = N;
+        mp.inv_hx = mp.inv_hy = 1.0;
+        mp.cell_measure = 1.0;
+        const p2m_solve_opts o = x1d_opts(opts, N);
+        P2M_TRY(launch_cg<double>(mp, F, coef, cvec, vols, xs, P2M_START_FLIP,
+                                  x1d_cg_ws(pp, X, c, mp), o, pp.rep, pp.stream));
+    }
+    P2M_TRY(x1d_scatter(N, F, m.np, idx, xs, (double*)values_out, pp.stream));
+    return P2M_OK;
+}
+
+p2m_status p2m_x1d_volumes(void* ctx, const p2m_problem* prob, void* vol_out, p2m_report* rep,
+                           void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !vol_out) return P2M_ERR_INVALID_ARG;
+    const Context* c = (const Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    Prepared pp;
+    X1DLayout X;
+    int N = 0;
+    p2m_status s = x1d_begin(ctx, prob, 1, ws, ws_bytes, stream, rep, pp, X, N);
+    if (s != P2M_OK) return s;
+    const double L = pp.m.cell_measure * pp.m.nx;
+    char* w8 = pp.ws;
+    P2M_TRY(x1d_scatter(0, 1, pp.m.np, nullptr, nullptr, (double*)vol_out, pp.stream));   // NaN
+    P2M_TRY(x1d_setup(N, L, (const double*)(w8 + X.skey), (const int32_t*)(w8 + X.sidx), nullptr, 0,
+                      pp.m.np, (double*)(w8 + X.gap), (double*)(w8 + X.vols), (double*)vol_out,
+                      nullptr, pp.stream));
+    return P2M_OK;
 }
 
 p2m_status p2m_mass_solve(void* ctx, const p2m_problem* prob, int32_t nfields, void* b, const void* w,
@@ -1000,6 +1293,8 @@ p2m_status p2m_tune(void* ctx, const p2m_problem* prob, const void* values, int3
     for (int ti = 0; ti < (pp.m.dim == 2 ? 2 : 1); ++ti) {
         const int tile = tiles[ti];
         if (tiled && cgr_supported(pp.m, nfields, c->device)) add(P2M_SOLVER_RESIDENT, 0, tile);
+        if (tiled && cgrc_supported(pp.m, nfields, c->device))
+            add(P2M_SOLVER_RESIDENT_CHEB, 0, tile);
         if (tiled) {
             const int cap = cgt_grid(pp.m, nfields, 0, c->device);
             if (cap > 0) add(P2M_SOLVER_TILES, cap, tile);
@@ -1197,7 +1492,7 @@ p2m_status p2m_plan_load(void* ctx, const char* path) {
                    "\"%127[^\"]\": {\"solver\": %d, \"groups\": %d, \"scatter_tile\": %d, "
                    "\"inner_rtol\": %lf, \"time_ms\": %lf}",
                    key, &p.solver, &p.groups, &p.scatter_tile, &p.inner_rtol, &p.time_ms) != 6 ||
-            p.solver < P2M_SOLVER_AUTO || p.solver > P2M_SOLVER_TILES || p.groups < 0 ||
+            p.solver < P2M_SOLVER_AUTO || p.solver > P2M_SOLVER_RESIDENT_CHEB || p.groups < 0 ||
             (p.scatter_tile != 0 && p.scatter_tile != 8) || !(p.inner_rtol < 1.0) ||
             !isfinite(p.inner_rtol)) {
             s = P2M_ERR_INVALID_ARG;

@@ -157,6 +157,33 @@ hipError_t launch_delta1d(const Mesh& m, Particles<T> P, const T* values, int F,
                           const int32_t* perm, const int32_t* cell_start, T* out,
                           hipStream_t stream);
 
+// paper-exact 1D (k_exact1d.hip), FP64.  N = located particles (binned order in
+// perm[0..N)); key / idx [N] receive the positions and particle numbers in
+// position order; gap, vol_s [N] sorted order, vol_c [np] caller order, As [F][N]
+hipError_t x1d_sort(const Mesh& m, int N, const double* x, const int32_t* perm,
+                    const int32_t* cs, double* key, int32_t* idx, hipStream_t stream);
+hipError_t x1d_setup(int N, double L, const double* key, const int32_t* idx, const double* values,
+                     int F, int np, double* gap, double* vol_s, double* vol_c, double* As,
+                     hipStream_t stream);
+// c [F][n] = int A psi_j over the mesh hats (quad: P2M_QUAD_*); fn [F][n] receives the
+// particle interpolant at the nodes (the delta P2M), fm [F][n] at the element
+// midpoints; t_lo, t_hi [F][n] scratch
+hipError_t x1d_p2m_overlap(const Mesh& m, int N, const double* key, const double* As, int F,
+                           int quad, double* fn, double* fm, double* t_lo, double* t_hi,
+                           double* c, hipStream_t stream);
+// c [F][N] = int Abar psi_mu over the particle hats (sorted order); fk, fmid, t_lo,
+// t_hi [F][N] scratch
+hipError_t x1d_m2p_overlap(const Mesh& m, int N, const double* key, const double* gap,
+                           const double* nodal, int F, int quad, double* fk, double* fmid,
+                           double* t_lo, double* t_hi, double* c, hipStream_t stream);
+hipError_t x1d_mass_mesh(int n, double L, double* coef, double* w, hipStream_t stream);
+hipError_t x1d_mass_part(int N, const double* gap, double* coef, hipStream_t stream);
+hipError_t x1d_div(int K, int F, const double* c, const double* d, double s, double* out,
+                   hipStream_t stream);
+// out [F][np] caller order: NaN, then xs [F][N] (sorted order) at idx
+hipError_t x1d_scatter(int N, int F, int np, const int32_t* idx, const double* xs, double* out,
+                       hipStream_t stream);
+
 // mass solve
 struct CgWorkspace {
     void* r;          // [F][nn] T
@@ -189,6 +216,13 @@ bool cgr_supported(const Mesh& m, int F, int device);
 hipError_t launch_cg_resident(const Mesh& m, int F, float* coef, float* b, const float* w,
                               float* x, int start, void* ws, const p2m_solve_opts& opts,
                               p2m_report* rep, bool clear_rep, hipStream_t stream);
+
+// the register-resident solve with the degree-2 Chebyshev polynomial preconditioner
+// (k_cgrc.hip): same workspace as the Jacobi one (cgr_workspace_bytes)
+bool cgrc_supported(const Mesh& m, int F, int device);
+hipError_t launch_cg_resident_cheb(const Mesh& m, int F, float* coef, float* b, const float* w,
+                                   float* x, int start, void* ws, const p2m_solve_opts& opts,
+                                   p2m_report* rep, bool clear_rep, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // batches (k_bin.hip, k_assemble.hip, k_cgb.hip)
