@@ -327,17 +327,18 @@ __device__ __forceinline__ int gidx(const Mesh& m, int i0, int j0, int lc, int l
     return gc + m.nx * gr;
 }
 
-// halo slot h -> local (lc, lr) on the ring around a TXa x TYa tile
+// halo slot h -> local (lc, lr) on the ring around a TXa x TYa tile: the row below,
+// the row above (txa + 2 each, corners included), the left column, the right
+// column (tya each).  Written with selects: assignments through the references in
+// branches were lowered through a stack slot in scratch memory.
 __device__ __forceinline__ bool halo_slot(int h, int txa, int tya, int& lc, int& lr) {
     const int row = txa + 2;
-    if (h < row) { lr = -1; lc = h - 1; return true; }
-    h -= row;
-    if (h < row) { lr = tya; lc = h - 1; return true; }
-    h -= row;
-    if (h < tya) { lc = -1; lr = h; return true; }
-    h -= tya;
-    if (h < tya) { lc = txa; lr = h; return true; }
-    return false;
+    const bool below = h < row, above = !below && h < 2 * row;
+    const int hc = h - 2 * row;                 // column part: left, then right
+    const bool left = hc < tya;
+    lc = below ? h - 1 : (above ? h - row - 1 : (left ? -1 : txa));
+    lr = below ? -1 : (above ? tya : (left ? hc : hc - tya));
+    return h < 2 * row + 2 * tya;
 }
 
 __device__ __forceinline__ bool on_boundary(int lc, int lr, int txa, int tya) {

@@ -19,10 +19,14 @@
 //    barrier.  The new u' = (r - alpha (w + beta s)) / diag M of a neighbour
 //    tile's boundary node is recomputed from its published (r, w, s) with the
 //    same FP32 operations its owner uses, so the halo is bit-identical;
-//  * the grid barrier is a two-level arrival tree on counters (no single
-//    serialised atomic); the last arriving workgroup reduces the per-workgroup
-//    FP64 partials in a fixed order and publishes the totals, so every workgroup
-//    takes identical decisions and the result is deterministic.
+//  * each workgroup also keeps the ring's copies of p and d (the same FP32
+//    operations on the same values as their owners), so the correction of an
+//    inner solve is folded into x inside the next residual phase: the ring's new
+//    x is its owner's published x plus the ring copy of d, and no barrier
+//    separates the fold from the residual;
+//  * the grid barrier adds one to a counter and polls it; after it every
+//    workgroup sums the per-workgroup FP64 partials in the same fixed order, so
+//    every workgroup takes identical decisions and the result is deterministic.
 //  Every wait is bounded: a timed-out wait raises an abort flag that ends the
 //  solve in every workgroup.
 #include "cg_common.hpp"
@@ -39,17 +43,29 @@ struct RArgs {
     const float* w;    // [nn]
     float* xout;       // [F][nn]  start (USER) on entry, result on exit
     double* x64;       // [F][nn]  FP64 solution, owner-only
+    float* res;        // [F][nn]  FP32 residual of the last residual phase, owner-only
     float* pubR;       // [2][F][nn] published values of the boundary rows
     float* pubW;
     float* pubS;
     float* pubC;       // [2][nn][rec_floats(F)] published records of the boundary columns
-    double* pubX;      // [F][nn]
+    double* pubX;      // [2][F][nn] published boundary x64, by refinement parity
     RSync sy;
     int start;
     p2m_solve_opts opts;
     p2m_report* rep;
 };
 
+constexpr int NH = 2 * (RX + 2) + 2 * RY;   // ring slots of a full tile
+
+// the start x0 of node k of field f as the P phase computes it (0 at an orphan,
+// w == 0); the ring's start in the first residual phase
+__device__ __forceinline__ double start_value(const RArgs& a, int f, int k) {
+    if (a.start == P2M_START_ZERO) return 0.0;
+    const float wk = a.w[k];
+    if (!(wk > 0.f)) return 0.0;
+    const size_t o = (size_t)f * a.m.nn + k;
+    return a.start == P2M_START_FLIP ? (double)a.b[o] / (double)wk : (double)a.xout[o];
+}
 
 template <int F>
 __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
@@ -66,7 +82,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int row0 = (RNPT / 2) * wave;
     const int nhalo = 2 * (txa + 2) + 2 * tya;
-    static_assert(2 * (RX + 2) + 2 * RY <= RBS, "one ring slot per thread");
+    static_assert(NH <= RBS, "one ring slot per thread");
     auto nrow = [&](int j) { return row0 + (j >> 1); };
     auto ncol = [&](int j) { return lane + 64 * (j & 1); };
     auto active = [&](int j) { return nrow(j) < tya && ncol(j) < txa; };
@@ -77,7 +93,8 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     auto rs_x64 = [&](int f) { return mkrs(a.x64 + (size_t)f * nn, fb8); };
     auto rs_d = [&](int f) { return mkrs(a.xout + (size_t)f * nn, fb4); };
     auto rs_b = [&](int f) { return mkrs(a.b + (size_t)f * nn, fb4); };
-    auto rs_pubX = [&](int f) { return mkrs(a.pubX + (size_t)f * nn, fb8); };
+    auto rs_res = [&](int f) { return mkrs(a.res + (size_t)f * nn, fb4); };
+    auto rs_pubX = [&](int par, int f) { return mkrs(a.pubX + ((size_t)par * F + f) * nn, fb8); };
     auto rs_pub = [&](float* base, int par, int f) {
         return mkrs(base + ((size_t)par * F + f) * nn, fb4);
     };
@@ -98,11 +115,14 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     float* lf = (float*)xbuf;       // plane f at lf + f * LH * LW
     double* ld64 = (double*)xbuf;
     float* lb = (float*)(ld64 + LH * LW);
+    // the ring's copies of p (field f at f * NH) and d (at (F + f) * NH), slot h
+    // held by thread h
+    __shared__ float rpd[2 * F * NH];
     __shared__ double red_lds[(RBS / 64) * kNV];
     __shared__ double vals[kNV];
     __shared__ double s_bb[F], s_gam[F], s_alpha[F], s_relres[F], s_target[F];
     __shared__ float s_af[F], s_bf[F];
-    __shared__ int s_iters[F], s_refines[F], s_done[F], s_inner[F], s_zero[F];
+    __shared__ int s_iters[F], s_refines[F], s_done[F], s_inner[F], s_zero[F], s_res[F];
     __shared__ uint32_t s_flags;
     __shared__ int s_any;
 
@@ -126,7 +146,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     if (threadIdx.x < F) {
         const int f = threadIdx.x;
         s_iters[f] = 0; s_refines[f] = 0; s_done[f] = 0; s_inner[f] = 0; s_zero[f] = 0;
-        s_relres[f] = 0.0; s_bb[f] = 0.0;
+        s_res[f] = 0; s_relres[f] = 0.0; s_bb[f] = 0.0;
     }
     if (threadIdx.x == 0) s_flags = 0u;
 
@@ -222,9 +242,9 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     x0 = (double)px[f][j];
                 }
                 a.x64[o] = x0;
-                // the start's boundary values for the first residual (the first
-                // fold, which would add d = 0, is skipped)
-                if (bmask & (1u << j)) std8<kCoherent>(rs_pubX(f), k, x0);
+                // the start's boundary values, read by the second residual phase
+                // (the first computes the ring's start itself)
+                if (bmask & (1u << j)) std8<kCoherent>(rs_pubX(0, f), k, x0);
             }
             if (orphan && a.rep) {
                 atomicAdd(&a.rep->n_orphan, 1);
@@ -290,53 +310,37 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     };
 
     for (int outer = 0; alive; ++outer) {
-        // ---- fold the correction into x64, publish the boundary x64 ------------
-        // (outer 0: the start vector, published by the P phase)
-#pragma unroll
-        for (int f = 0; f < F; ++f) {
-            if (s_done[f] || outer == 0) continue;
-            const rsrc_t rx = rs_x64(f), rpx = rs_pubX(f);
-            // the field's loads go out together, ahead of its stores (a load issued
-            // after a store waits for it); a node outside the mesh reads element 0
-            double xo[RNPT];
-#pragma unroll
-            for (int j = 0; j < RNPT; ++j) xo[j] = ldd<kPlain>(rx, (amask & (1u << j)) ? gk(j) : 0);
-#pragma unroll
-            for (int j = 0; j < RNPT; ++j) {
-                if (!(amask & (1u << j))) continue;
-                const int kk = gk(j);
-                const double xv = xo[j] + (double)vd[f][j];
-                std8<kPlain>(rx, kk, xv);
-                if (bmask & (1u << j)) std8<kCoherent>(rpx, kk, xv);
-            }
-#pragma unroll
-            for (int j = 0; j < RNPT; ++j) vd[f][j] = 0.f;
-        }
-        __syncthreads();
-        alive = sync_reduce(a.sy, ++epoch, vals, 0, nblocks);
-        if (!alive) break;
-
-        // ---- R: r = b - M x64 in FP64; r_T = (float) r -------------------------
+        // ---- R: x += d (outer > 0: the correction of the last inner solve), then
+        //      r = b - M x in FP64 and r_T = (float) r.  The ring's x is its owner's
+        //      published x plus the ring copy of d, or (outer 0) the start computed
+        //      from the inputs the owner computes it from, so no barrier separates
+        //      the fold (or the start) from the residual.  With outer > 0, x rounded
+        //      to FP32 is stored as the result: final if this residual ends the
+        //      field's solve, overwritten by the next residual phase otherwise.
         {
+            const int pin = (outer + 1) & 1, pout = outer & 1;   // pubX parity read / written
             double pr[3 * F];
 #pragma unroll
             for (int q = 0; q < 3 * F; ++q) pr[q] = 0.0;
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 if (s_done[f]) continue;
-                const rsrc_t rx = rs_x64(f), rpx = rs_pubX(f), rb = rs_b(f), rd = rs_d(f);
+                const rsrc_t rx = rs_x64(f), rb = rs_b(f), rr = rs_res(f);
                 const rsrc_t rpr = rs_pub(a.pubR, ex, f), rpc = rs_col(ex);
-                // every load of the field is issued before the first LDS write: the
-                // ring slot of this thread (at most one), then x and b of the own
-                // nodes (a node outside the mesh reads element 0, never written)
+                // every load of the field is issued before the first LDS write or
+                // global store: the ring slot of this thread (at most one), then x and
+                // b of the own nodes (a node outside the mesh reads element 0, never
+                // written)
                 int hq = -1;
                 double hx = 0.0;
                 if (threadIdx.x < nhalo) {
                     int lc, lr;
-                    if (halo_slot(threadIdx.x, txa, tya, lc, lr)) {
-                        hq = lidx(lc, lr);
-                        hx = ldd<kCoherent>(rpx, gidx(m, i0, j0, lc, lr));
-                    }
+                    halo_slot(threadIdx.x, txa, tya, lc, lr);
+                    hq = lidx(lc, lr);
+                    const int gh = gidx(m, i0, j0, lc, lr);
+                    hx = outer > 0 ? ldd<kCoherent>(rs_pubX(pin, f), gh) +
+                                         (double)rpd[(F + f) * NH + threadIdx.x]
+                                   : start_value(a, f, gh);
                 }
                 double xo[RNPT];
                 float bo[RNPT];
@@ -346,6 +350,10 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     xo[j] = ldd<kPlain>(rx, kk);
                     bo[j] = ldf<kPlain>(rb, kk);
                 }
+                if (outer > 0) {
+#pragma unroll
+                    for (int j = 0; j < RNPT; ++j) xo[j] += (double)vd[f][j];
+                }
 #pragma unroll
                 for (int j = 0; j < RNPT; ++j) {
                     if (!(amask & (1u << j))) continue;
@@ -353,10 +361,21 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     lb[qj(j)] = bo[j];
                 }
                 if (hq >= 0) ld64[hq] = hx;
+                if (outer > 0) {
+                    const rsrc_t ro = rs_d(f), rpx = rs_pubX(pout, f);
+#pragma unroll
+                    for (int j = 0; j < RNPT; ++j) {
+                        if (!(amask & (1u << j))) continue;
+                        const int kk = gk(j);
+                        std8<kPlain>(rx, kk, xo[j]);
+                        stf<kPlain>(ro, kk, (float)xo[j]);
+                        if (bmask & (1u << j)) std8<kCoherent>(rpx, kk, xo[j]);
+                    }
+                }
                 __syncthreads();
-                // the FP32 residual goes to the output array xout (unused until the
-                // result phase) and is loaded into registers after the barrier; b was staged in LDS with
-                // x, so the loop issues no global load that would wait on its stores
+                // the FP32 residual goes to the owner-only array res and is loaded
+                // into registers by the CG start; b was staged in LDS with x, so the
+                // loop issues no global load that would wait on its stores
 #pragma unroll 1
                 for (int j = 0; j < RNPT; ++j) {
                     if (!(amask & (1u << j))) continue;
@@ -370,7 +389,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     const double bk = (double)lb[q];
                     const double r64 = bk - mx;
                     const float rt = (float)r64;
-                    stf<kPlain>(rd, kk, rt);
+                    stf<kPlain>(rr, kk, rt);
                     pr[f] = sq_acc(pr[f], r64);
                     if (outer == 0) pr[2 * F + f] = sq_acc(pr[2 * F + f], bk);
                     if (rmask & (1u << j)) stf<kCoherent>(rpr, kk, rt);
@@ -382,52 +401,48 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         }
         alive = sync_reduce(a.sy, ++epoch, vals, 3 * F, nblocks);
         if (!alive) break;
-        if (threadIdx.x == 0) {
-            int any = 0;
-            for (int f = 0; f < F; ++f) {
-                if (s_done[f]) continue;
-                s_refines[f] += 1;
-                if (outer == 0) s_bb[f] = vals[2 * F + f];
-                const double bb = s_bb[f];
-                if (bb == 0.0) {
-                    s_zero[f] = 1; s_done[f] = 1; s_relres[f] = 0.0;
-                    continue;
-                }
-                const double rr = vals[f];
-                const double relres = sqrt(rr / bb);
-                s_relres[f] = relres;
-                if (relres <= a.opts.tol || outer >= a.opts.max_refine ||
-                    s_iters[f] >= a.opts.maxit || !(relres == relres)) {
-                    s_done[f] = 1;
-                    if (!(relres <= a.opts.tol)) s_flags |= P2M_FLAG_NOT_CONVERGED;
-                    continue;
-                }
+        // refinement decision, one thread per field
+        if (threadIdx.x < F && !s_done[threadIdx.x]) {
+            const int f = threadIdx.x;
+            s_refines[f] += 1;
+            s_res[f] = outer > 0;
+            if (outer == 0) s_bb[f] = vals[2 * F + f];
+            const double bb = s_bb[f];
+            const double rr = vals[f];
+            const double relres = bb == 0.0 ? 0.0 : sqrt(rr / bb);
+            s_relres[f] = relres;
+            if (bb == 0.0) {
+                s_zero[f] = 1;
+                s_done[f] = 1;
+            } else if (relres <= a.opts.tol || outer >= a.opts.max_refine ||
+                       s_iters[f] >= a.opts.maxit || !(relres == relres)) {
+                s_done[f] = 1;
+                if (!(relres <= a.opts.tol)) atomicOr(&s_flags, (uint32_t)P2M_FLAG_NOT_CONVERGED);
+            } else {
                 const double goal = 0.25 * a.opts.tol * a.opts.tol * bb;
                 const double rel = a.opts.inner_rtol * a.opts.inner_rtol * rr;
                 s_target[f] = goal > rel ? goal : rel;
                 s_inner[f] = 1;
-                any = 1;
             }
-            s_any = any;
         }
         __syncthreads();
-        if (!s_any) break;
+        uint32_t imask = inner_mask();
+        if (!imask) break;
 
         // ---- CG start: u = r / diag, w = M u, delta = (w, u), gamma = (r, u);
-        //      p = s = d = 0 -----------------------------------------------------
-        uint32_t imask = inner_mask();
-        // own residuals and the ring's are loaded before d = 0 is stored
+        //      p = s = d = 0, and the ring copies of p and d ------------------------
 #pragma unroll
         for (int f = 0; f < F; ++f) {
             if (!(imask & (1u << f))) continue;
-            const rsrc_t rd = rs_d(f);
+            const rsrc_t rr = rs_res(f);
 #pragma unroll
             for (int j = 0; j < RNPT; ++j)
-                if (amask & (1u << j)) vr[f][j] = ldf<kPlain>(rd, gk(j));
+                if (amask & (1u << j)) vr[f][j] = ldf<kPlain>(rr, gk(j));
         }
-        for (int h = threadIdx.x; h < nhalo; h += RBS) {
+        if (threadIdx.x < nhalo) {
+            const int h = threadIdx.x;
             int lc, lr;
-            if (!halo_slot(h, txa, tya, lc, lr)) continue;
+            halo_slot(h, txa, tya, lc, lr);
             const int gh = gidx(m, i0, j0, lc, lr);
             float hv[F];
             if (lr >= 0 && lr < tya) {   // a column slot: the neighbour's record
@@ -441,8 +456,12 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
             }
             const float dh = dv[lidx(lc, lr)];
 #pragma unroll
-            for (int f = 0; f < F; ++f)
-                if (imask & (1u << f)) lf[(size_t)f * LH * LW + lidx(lc, lr)] = __fmul_rn(hv[f], dh);
+            for (int f = 0; f < F; ++f) {
+                if (!(imask & (1u << f))) continue;
+                lf[(size_t)f * LH * LW + lidx(lc, lr)] = __fmul_rn(hv[f], dh);
+                rpd[f * NH + h] = 0.f;
+                rpd[(F + f) * NH + h] = 0.f;
+            }
         }
 #pragma unroll
         for (int f = 0; f < F; ++f) {
@@ -456,6 +475,10 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         ex ^= 1;
         {
             spmv_all(imask);
+            // the boundary's (r, w, s) go out as soon as w is known, so their
+            // latency overlaps the dot products; nothing loads from global memory
+            // between them and the barrier, which waits for them
+            publish_rws(imask);
             double pd[2 * F];
 #pragma unroll
             for (int f = 0; f < 2 * F; ++f) pd[f] = 0.0;
@@ -475,19 +498,17 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
             }
             __syncthreads();
             block_sum_to<2 * F>(pd, red_lds, vals);
-            publish_rws(imask);
         }
         alive = sync_reduce(a.sy, ++epoch, vals, 2 * F, nblocks);
         if (!alive) break;
-        if (threadIdx.x == 0) {
-            for (int f = 0; f < F; ++f) {
-                if (!s_inner[f]) continue;
-                const double del = vals[f], gam = vals[F + f];
-                if (!(del > 0.0) || !(gam > 0.0)) {
-                    s_inner[f] = 0; s_done[f] = 1;
-                    s_flags |= P2M_FLAG_BREAKDOWN | P2M_FLAG_NOT_CONVERGED;
-                    continue;
-                }
+        if (threadIdx.x < F && s_inner[threadIdx.x]) {
+            const int f = threadIdx.x;
+            const double del = vals[f], gam = vals[F + f];
+            if (!(del > 0.0) || !(gam > 0.0)) {
+                s_inner[f] = 0;
+                s_done[f] = 1;
+                atomicOr(&s_flags, (uint32_t)(P2M_FLAG_BREAKDOWN | P2M_FLAG_NOT_CONVERGED));
+            } else {
                 s_gam[f] = gam;
                 s_alpha[f] = gam / del;
                 s_af[f] = (float)s_alpha[f];
@@ -506,10 +527,12 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                 bf[f] = s_bf[f];
             }
             // halo first (its loads are the longest latency): the neighbours' new
-            // residual from their published state, all fields' loads in flight
-            for (int h = threadIdx.x; h < nhalo; h += RBS) {
+            // residual from their published state, all fields' loads in flight; the
+            // ring copies of p and d advance with the u they held
+            if (threadIdx.x < nhalo) {
+                const int h = threadIdx.x;
                 int lc, lr;
-                if (!halo_slot(h, txa, tya, lc, lr)) continue;
+                halo_slot(h, txa, tya, lc, lr);
                 const int gh = gidx(m, i0, j0, lc, lr);
                 float ro[F], wo[F], so[F];
                 if (lr >= 0 && lr < tya) {   // a column slot: the neighbour's record
@@ -531,11 +554,16 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                         so[f] = ldf<kCoherent>(rs_pub(a.pubS, ex, f), gh);
                     }
                 }
+                const int q = lidx(lc, lr);
+                const float dh = dv[q];
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     if (!(imask & (1u << f))) continue;
-                    lf[(size_t)f * LH * LW + lidx(lc, lr)] =
-                        halo_u(af[f], bf[f], dv[lidx(lc, lr)], ro[f], wo[f], so[f]);
+                    float* L = lf + (size_t)f * LH * LW;
+                    const float pn = fmaf(bf[f], rpd[f * NH + h], L[q]);
+                    rpd[f * NH + h] = pn;
+                    rpd[(F + f) * NH + h] = fmaf(af[f], pn, rpd[(F + f) * NH + h]);
+                    L[q] = halo_u(af[f], bf[f], dh, ro[f], wo[f], so[f]);
                 }
             }
             // local updates and the new residual into LDS
@@ -555,6 +583,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
             ex ^= 1;
             {
                 spmv_all(imask);
+                publish_rws(imask);
                 double pg[3 * F];
 #pragma unroll
                 for (int q = 0; q < 3 * F; ++q) pg[q] = 0.0;
@@ -572,42 +601,36 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                 }
                 __syncthreads();
                 block_sum_to<3 * F>(pg, red_lds, vals);
-                // the boundary's (r, w, s) go out last: a load issued after a store
-                // waits for it, and the barrier below waits for the stores anyway
-                publish_rws(imask);
             }
             alive = sync_reduce(a.sy, ++epoch, vals, 3 * F, nblocks);
             if (!alive) break;
-            if (threadIdx.x == 0) {
-                int any = 0;
-                for (int f = 0; f < F; ++f) {
-                    if (!s_inner[f]) continue;
-                    const double gam = vals[f], del = vals[F + f], rho = vals[2 * F + f];
-                    s_iters[f] += 1;
-                    if (!(rho > s_target[f]) || s_iters[f] >= a.opts.maxit) {
-                        s_inner[f] = 0;
-                        continue;
-                    }
+            // CG step decision, one thread per field
+            if (threadIdx.x < F && s_inner[threadIdx.x]) {
+                const int f = threadIdx.x;
+                const double gam = vals[f], del = vals[F + f], rho = vals[2 * F + f];
+                s_iters[f] += 1;
+                if (!(rho > s_target[f]) || s_iters[f] >= a.opts.maxit) {
+                    s_inner[f] = 0;
+                } else {
                     const double beta = gam / s_gam[f];
                     const double den = del - beta * gam / s_alpha[f];
                     if (!(den > 0.0) || !(gam > 0.0)) {
                         s_inner[f] = 0;
-                        s_flags |= P2M_FLAG_BREAKDOWN;
-                        continue;
+                        atomicOr(&s_flags, (uint32_t)P2M_FLAG_BREAKDOWN);
+                    } else {
+                        s_alpha[f] = gam / den;
+                        s_gam[f] = gam;
+                        s_af[f] = (float)s_alpha[f];
+                        s_bf[f] = (float)beta;
                     }
-                    s_alpha[f] = gam / den;
-                    s_gam[f] = gam;
-                    s_af[f] = (float)s_alpha[f];
-                    s_bf[f] = (float)beta;
-                    any = 1;
                 }
-                s_any = any;
             }
             __syncthreads();
-            if (!s_any) break;
+            if (!inner_mask()) break;
         }
         // the iteration state is dead until the next CG start sets it: constant
-        // here, it holds no registers through the fold and residual phases
+        // here, it holds no registers through the residual phase (d does: the
+        // residual phase folds it into x)
 #pragma unroll
         for (int f = 0; f < F; ++f)
 #pragma unroll
@@ -616,19 +639,25 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
 
     if (!alive && threadIdx.x == 0) s_flags |= P2M_FLAG_BREAKDOWN | P2M_FLAG_NOT_CONVERGED;
     __syncthreads();
-    // result: the FP64 solution rounded to FP32 (0 for fields with b == 0)
+    // result of the fields that no residual phase with outer > 0 ended (solved by
+    // the start, b == 0, or an aborted solve): the FP64 solution rounded to FP32, 0
+    // for fields with b == 0
     {
         float res[F][RNPT];
 #pragma unroll
-        for (int f = 0; f < F; ++f)
+        for (int f = 0; f < F; ++f) {
+            if (alive && s_res[f] && !s_zero[f]) continue;
 #pragma unroll
             for (int j = 0; j < RNPT; ++j)
                 if (amask & (1u << j)) res[f][j] = (float)ldd<kPlain>(rs_x64(f), gk(j));
+        }
 #pragma unroll
-        for (int f = 0; f < F; ++f)
+        for (int f = 0; f < F; ++f) {
+            if (alive && s_res[f] && !s_zero[f]) continue;
 #pragma unroll
             for (int j = 0; j < RNPT; ++j)
                 if (amask & (1u << j)) stf<kPlain>(rs_d(f), gk(j), s_zero[f] ? 0.f : res[f][j]);
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.rep) {
         for (int f = 0; f < F; ++f) {
@@ -677,9 +706,10 @@ size_t cgr_workspace_bytes(const Mesh& m, int F, int blocks) {
     auto al = [](size_t v) { return (v + kAlign - 1) / kAlign * kAlign; };
     size_t s = 0;
     s += al((size_t)F * m.nn * sizeof(double));           // x64
+    s += al((size_t)F * m.nn * sizeof(float));            // res
     s += 3 * al((size_t)2 * F * m.nn * sizeof(float));    // pubR, pubW, pubS
     s += al((size_t)2 * m.nn * rec_floats(F) * sizeof(float));   // pubC
-    s += al((size_t)F * m.nn * sizeof(double));           // pubX
+    s += al((size_t)2 * F * m.nn * sizeof(double));       // pubX
     s += al((size_t)kGroups * 32 * sizeof(unsigned));     // ctr
     s += 3 * al(32 * sizeof(unsigned));                   // root, rel, abort
     s += al((size_t)2 * blocks * kNV * sizeof(double));   // part
@@ -719,11 +749,12 @@ hipError_t launch_cg_resident(const Mesh& m, int F, float* coef, float* b, const
     a.opts = opts;
     a.rep = rep;
     a.x64 = (double*)p; p += al((size_t)F * m.nn * sizeof(double));
+    a.res = (float*)p; p += al((size_t)F * m.nn * sizeof(float));
     a.pubR = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubW = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubS = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubC = (float*)p; p += al((size_t)2 * m.nn * rec_floats(F) * sizeof(float));
-    a.pubX = (double*)p; p += al((size_t)F * m.nn * sizeof(double));
+    a.pubX = (double*)p; p += al((size_t)2 * F * m.nn * sizeof(double));
     a.sy.ctr = (unsigned*)p; p += al((size_t)kGroups * 32 * sizeof(unsigned));
     a.sy.root = (unsigned*)p; p += al(32 * sizeof(unsigned));
     a.sy.rel = (unsigned*)p; p += al(32 * sizeof(unsigned));

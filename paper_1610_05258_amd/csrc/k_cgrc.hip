@@ -59,23 +59,23 @@ struct CArgs {
 };
 
 // ring slot h (0 <= h < 2 G2 (txa + 2 G2) + 2 G2 tya) -> local (lc, lr): first the
-// 2 G2 full rows below and above the tile, then the side columns
+// 2 G2 full rows below and above the tile, then the side columns.  Written with
+// selects: assignments through the references in branches were lowered through
+// a stack slot in scratch memory.
 __device__ __forceinline__ bool ring2_slot(int h, int txa, int tya, int& lc, int& lr) {
     const int row = txa + 2 * G2;
-    if (h < 2 * G2 * row) {
-        const int rr = h / row;
-        lc = h - rr * row - G2;
-        lr = rr < G2 ? rr - G2 : tya + (rr - G2);
-        return true;
-    }
-    h -= 2 * G2 * row;
-    if (h < 2 * G2 * tya) {
-        const int cc = h / tya;
-        lr = h - cc * tya;
-        lc = cc < G2 ? cc - G2 : txa + (cc - G2);
-        return true;
-    }
-    return false;
+    const int nrows = 2 * G2 * row;
+    const bool in_rows = h < nrows;
+    const int rr = h / row;
+    const int hc = in_rows ? 0 : h - nrows;
+    const int cc = hc / tya;
+    const int lc_r = h - rr * row - G2;
+    const int lr_r = rr < G2 ? rr - G2 : tya + (rr - G2);
+    const int lr_c = hc - cc * tya;
+    const int lc_c = cc < G2 ? cc - G2 : txa + (cc - G2);
+    lc = in_rows ? lc_r : lc_c;
+    lr = in_rows ? lr_r : lr_c;
+    return h < nrows + 2 * G2 * tya;
 }
 
 // Jacobi-preconditioned CG update of one node with the previous preconditioned
@@ -304,33 +304,51 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
                          L[q - LW2 - 1]);
     };
 
-    // The planes hold y = D^-1 r on the tile and the two-deep ring: replace them,
-    // field by field, with u = c0 y + c1 D^-1 (M y) on the tile and the one-deep
-    // ring (the values a tile's own stencil product reads).  The new values wait in
+    // The planes hold y = D^-1 r on the tile and the two-deep ring: replace them
+    // with u = c0 y + c1 D^-1 (M y) on the tile and the one-deep ring (the values a
+    // tile's own stencil product reads).  Node by node, as the stencil product
+    // below: a node's seven coefficients serve every field.  The new values wait in
     // vw (dead here: the update has consumed w, the stencil product after this
-    // recomputes it) until every thread has read the plane.
+    // recomputes it) until every thread has read the planes.
     auto precondition = [&](uint32_t imask) {
+#pragma unroll
+        for (int j = 0; j < RNPT; ++j) {
+            const int qc = qcj(j), q = qj(j);
+            const float cD = cf[qc], cE = cf[CN2 + qc], cEw = cf[CN2 + qc - 1];
+            const float cN = cf[2 * CN2 + qc], cNs = cf[2 * CN2 + qc - CW2];
+            const float cNE = cf[3 * CN2 + qc], cNEsw = cf[3 * CN2 + qc - CW2 - 1];
+            const float di = dv[q];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                if (!(imask & (1u << f))) continue;
+                const float* L = lf + (size_t)f * LH2 * LW2;
+                const float t = stencil32(cD, cE, cEw, cN, cNs, cNE, cNEsw, L[q], L[q + 1], L[q - 1],
+                                          L[q + LW2], L[q - LW2], L[q + LW2 + 1], L[q - LW2 - 1]);
+                vw[f][j] = fmaf(c1, __fmul_rn(di, t), __fmul_rn(c0, L[q]));
+            }
+        }
+        float ur[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) ur[f] = 0.f;
+        if (has_r1) {
+            const int q = lidx(r1c, r1r), qc = cidx(r1c, r1r);
+            const float di = dv[q];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                if (!(imask & (1u << f))) continue;
+                const float* L = lf + (size_t)f * LH2 * LW2;
+                ur[f] = fmaf(c1, __fmul_rn(di, stencil_at(L, q, qc)), __fmul_rn(c0, L[q]));
+            }
+        }
+        __syncthreads();
 #pragma unroll
         for (int f = 0; f < F; ++f) {
             if (!(imask & (1u << f))) continue;
             float* L = lf + (size_t)f * LH2 * LW2;
-            float ur = 0.f;
-#pragma unroll
-            for (int j = 0; j < RNPT; ++j) {
-                const int q = qj(j);
-                const float t = stencil_at(L, q, qcj(j));
-                vw[f][j] = fmaf(c1, __fmul_rn(dv[q], t), __fmul_rn(c0, L[q]));
-            }
-            if (has_r1) {
-                const int q = lidx(r1c, r1r);
-                const float t = stencil_at(L, q, cidx(r1c, r1r));
-                ur = fmaf(c1, __fmul_rn(dv[q], t), __fmul_rn(c0, L[q]));
-            }
-            __syncthreads();
 #pragma unroll
             for (int j = 0; j < RNPT; ++j)
                 if (amask & (1u << j)) L[qj(j)] = vw[f][j];
-            if (has_r1) L[lidx(r1c, r1r)] = ur;
+            if (has_r1) L[lidx(r1c, r1r)] = ur[f];
         }
         __syncthreads();
     };
@@ -790,7 +808,8 @@ hipError_t launch_cg_resident_cheb(const Mesh& m, int F, float* coef, float* b, 
     a.opts = opts;
     a.rep = rep;
     cgrc_coefficients(a.c0, a.c1);
-    // the same workspace carve-up as the Jacobi resident solve (cgr_workspace_bytes)
+    // a carve-up that fits the Jacobi resident solve's workspace (cgr_workspace_bytes,
+    // which also holds that solve's residual array and second x exchange plane)
     a.x64 = (double*)p; p += al((size_t)F * m.nn * sizeof(double));
     a.pubR = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubW = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
