@@ -25,7 +25,7 @@ constexpr long kSpinMax = 1L << 22;
 struct RSync {
     unsigned* ctr;    // [kGroups * 32] group arrival counters (128-byte apart)
     unsigned* root;   // root arrival counter
-    unsigned* rel;    // release epoch
+    unsigned* rel;    // [kGroups * 32] release epoch, one copy per group (128-byte apart)
     unsigned* abort;  // set on a timed-out wait
     double* part;     // [2][nblocks][kNV] per-workgroup partials
     double* tot;      // [2][kNV] totals
@@ -208,7 +208,8 @@ __device__ __forceinline__ bool tree_arrive(const RSync& s, unsigned epoch, int 
 // out, or that sees the abort flag, raises the abort flag and returns false.
 __device__ __forceinline__ bool tree_wait(const RSync& s, unsigned epoch) {
     long spins = 0;
-    while (ld_c(s.rel) < epoch) {
+    const unsigned* rel = s.rel + (blockIdx.x % kGroups) * 32;
+    while (ld_c(rel) < epoch) {
         if (ld_c(s.abort) != 0u || ++spins > kSpinMax) {
             __hip_atomic_store(s.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
@@ -217,8 +218,12 @@ __device__ __forceinline__ bool tree_wait(const RSync& s, unsigned epoch) {
     return true;
 }
 
+// The release goes to every group's copy, so each copy is polled by one group's
+// workgroups only.
 __device__ __forceinline__ void tree_release(const RSync& s, unsigned epoch) {
-    __hip_atomic_store(s.rel, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int g = 0; g < kGroups; ++g)
+        __hip_atomic_store(s.rel + g * 32, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Grid barrier that also sums the workgroups' partials vals[0..nv) (FP64).  Every

@@ -829,10 +829,12 @@ __global__ __launch_bounds__(RBS) void k_cgb(BArgs a) {
 }
 
 __global__ void k_sync_clear_b(unsigned* ctr, unsigned* root, unsigned* rel, unsigned* abort_) {
-    for (int t = threadIdx.x; t < kGroups * 32; t += blockDim.x) ctr[t] = 0u;
+    for (int t = threadIdx.x; t < kGroups * 32; t += blockDim.x) {
+        ctr[t] = 0u;
+        rel[t] = 0u;
+    }
     for (int t = threadIdx.x; t < 32; t += blockDim.x) {
         root[t] = 0u;
-        rel[t] = 0u;
         abort_[t] = 0u;
     }
 }
@@ -886,7 +888,8 @@ size_t cgb_workspace_bytes(int F, int nprob, int ntiles, size_t nodes) {
     s += al((size_t)2 * nodes * rec_floats(F) * sizeof(float));   // pubC
     s += al((size_t)F * nodes * sizeof(double));          // pubX
     s += al((size_t)kGroups * 32 * sizeof(unsigned));     // ctr
-    s += 3 * al(32 * sizeof(unsigned));                   // root, rel, abort
+    s += al((size_t)kGroups * 32 * sizeof(unsigned));     // rel
+    s += 2 * al(32 * sizeof(unsigned));                   // root, abort
     s += al((size_t)2 * ntiles * kNV * sizeof(double));   // part
     s += al((size_t)2 * nprob * kNV * sizeof(double));    // tot
     return s;
@@ -981,7 +984,7 @@ hipError_t launch_cg_batch(int F, const BatchSolveBufs& bb, size_t nodes, int gr
     a.pubX = (double*)p; p += al((size_t)F * nodes * sizeof(double));
     a.sy.ctr = (unsigned*)p; p += al((size_t)kGroups * 32 * sizeof(unsigned));
     a.sy.root = (unsigned*)p; p += al(32 * sizeof(unsigned));
-    a.sy.rel = (unsigned*)p; p += al(32 * sizeof(unsigned));
+    a.sy.rel = (unsigned*)p; p += al((size_t)kGroups * 32 * sizeof(unsigned));
     a.sy.abort = (unsigned*)p; p += al(32 * sizeof(unsigned));
     a.sy.part = (double*)p; p += al((size_t)2 * bb.ntiles * kNV * sizeof(double));
     a.sy.tot = (double*)p;

@@ -673,8 +673,8 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
 __global__ void k_sync_clear(unsigned* ctr, unsigned* root, unsigned* rel, unsigned* abort_,
                              p2m_report* rep) {
     const int t = threadIdx.x;
-    if (t < kGroups * 32) ctr[t] = 0u;
-    if (t < 32) { root[t] = 0u; rel[t] = 0u; abort_[t] = 0u; }
+    if (t < kGroups * 32) { ctr[t] = 0u; rel[t] = 0u; }
+    if (t < 32) { root[t] = 0u; abort_[t] = 0u; }
     if (rep) {
         if (t < 8) {
             rep->iters[t] = 0;
@@ -711,7 +711,8 @@ size_t cgr_workspace_bytes(const Mesh& m, int F, int blocks) {
     s += al((size_t)2 * m.nn * rec_floats(F) * sizeof(float));   // pubC
     s += al((size_t)2 * F * m.nn * sizeof(double));       // pubX
     s += al((size_t)kGroups * 32 * sizeof(unsigned));     // ctr
-    s += 3 * al(32 * sizeof(unsigned));                   // root, rel, abort
+    s += al((size_t)kGroups * 32 * sizeof(unsigned));     // rel
+    s += 2 * al(32 * sizeof(unsigned));                   // root, abort
     s += al((size_t)2 * blocks * kNV * sizeof(double));   // part
     s += al((size_t)2 * kNV * sizeof(double));            // tot
     return s;
@@ -757,7 +758,7 @@ hipError_t launch_cg_resident(const Mesh& m, int F, float* coef, float* b, const
     a.pubX = (double*)p; p += al((size_t)2 * F * m.nn * sizeof(double));
     a.sy.ctr = (unsigned*)p; p += al((size_t)kGroups * 32 * sizeof(unsigned));
     a.sy.root = (unsigned*)p; p += al(32 * sizeof(unsigned));
-    a.sy.rel = (unsigned*)p; p += al(32 * sizeof(unsigned));
+    a.sy.rel = (unsigned*)p; p += al((size_t)kGroups * 32 * sizeof(unsigned));
     a.sy.abort = (unsigned*)p; p += al(32 * sizeof(unsigned));
     a.sy.part = (double*)p; p += al((size_t)2 * blocks * kNV * sizeof(double));
     a.sy.tot = (double*)p;

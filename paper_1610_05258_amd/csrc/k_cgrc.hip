@@ -737,8 +737,8 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
 __global__ void k_sync_clear_c(unsigned* ctr, unsigned* root, unsigned* rel, unsigned* abort_,
                                p2m_report* rep) {
     const int t = threadIdx.x;
-    if (t < kGroups * 32) ctr[t] = 0u;
-    if (t < 32) { root[t] = 0u; rel[t] = 0u; abort_[t] = 0u; }
+    if (t < kGroups * 32) { ctr[t] = 0u; rel[t] = 0u; }
+    if (t < 32) { root[t] = 0u; abort_[t] = 0u; }
     if (rep) {
         if (t < 8) {
             rep->iters[t] = 0;
@@ -818,7 +818,7 @@ hipError_t launch_cg_resident_cheb(const Mesh& m, int F, float* coef, float* b, 
     a.pubX = (double*)p; p += al((size_t)F * m.nn * sizeof(double));
     a.sy.ctr = (unsigned*)p; p += al((size_t)kGroups * 32 * sizeof(unsigned));
     a.sy.root = (unsigned*)p; p += al(32 * sizeof(unsigned));
-    a.sy.rel = (unsigned*)p; p += al(32 * sizeof(unsigned));
+    a.sy.rel = (unsigned*)p; p += al((size_t)kGroups * 32 * sizeof(unsigned));
     a.sy.abort = (unsigned*)p; p += al(32 * sizeof(unsigned));
     a.sy.part = (double*)p; p += al((size_t)2 * blocks * kNV * sizeof(double));
     a.sy.tot = (double*)p;
