@@ -62,29 +62,45 @@ def mass_assign_algorithmic_bytes(n_part, nn, F, k_ref, d=2, c_m=4, with_vol=Fal
                  k_ref * nn * (4 * c_m + 24 * F))
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "counters_k_cgr3_tg1024.md")
-SOLVER_SOURCES = ("k_cgr.hip", "cg_common.hpp", "p2m_internal.hpp")
+# committed memory-counter summaries of the resident solve kernels on this workload,
+# and the sources each one was taken from
+COUNTERS = {2: (os.path.join(ROOT, "profiles", "counters_k_cgr3_tg1024.md"),
+                ("k_cgr.hip", "cg_common.hpp", "p2m_internal.hpp")),
+            4: (os.path.join(ROOT, "profiles", "counters_k_cgrc3_tg1024.md"),
+                ("k_cgrc.hip", "cg_common.hpp", "p2m_internal.hpp"))}
 
 
-def measured_traffic(inner_rtol):
-    """HBM bytes per k_cgr<3> launch from the committed counter summary (FETCH_SIZE
-    and WRITE_SIZE runs scaled by a copy of known size), or None when the solver
-    sources or the solve schedule (inner_rtol) differ from those of the counted run."""
+def measured_traffic(solver, inner_rtol):
+    """HBM bytes per launch of the resident solve kernel from its committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs scaled by a copy of known size), or None
+    when there is none for this solver, or the kernel's sources or the solve schedule
+    (inner_rtol) differ from those of the counted run."""
     import hashlib
     import re
-    if not os.path.exists(COUNTERS):
+    if solver not in COUNTERS or not os.path.exists(COUNTERS[solver][0]):
         return None
-    text = open(COUNTERS).read()
+    path, sources = COUNTERS[solver]
+    text = open(path).read()
     m_t = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
     m_h = re.search(r"^source_sha256: ([0-9a-f]{64})", text, re.M)
     m_r = re.search(r"^inner_rtol: (\S+)", text, re.M)
     if not (m_t and m_h and m_r) or float(m_r.group(1)) != float(inner_rtol):
         return None
     h = hashlib.sha256()
-    for f in SOLVER_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_1610_05258_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return float(m_t.group(1)) if h.hexdigest() == m_h.group(1) else None
+
+
+def solver_sources_sha256(solver):
+    """sha256 of the sources of a resident solve kernel (recorded in its counter summary)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in COUNTERS[solver][1]:
+        with open(os.path.join(ROOT, "paper_1610_05258_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def oracle_reference(prob, vals, tol):
@@ -651,8 +667,8 @@ def main():
                   2: f"k_cgr<{F}> (register-resident mass solve)",
                   3: f"k_cgb<{F}> (tile-streaming mass solve)",
                   4: f"k_cgrc<{F}> (register-resident mass solve, Chebyshev preconditioner)"}[solver]
-        traffic = (measured_traffic(result["plan"]["inner_rtol"] if plan is not None else opts.inner_rtol)
-                   if solver == 2 else None)
+        traffic = measured_traffic(solver, result["plan"]["inner_rtol"] if plan is not None
+                                   else opts.inner_rtol)
         result["roofline"] = dict(bound="hbm", kernel=kernel,
                                   achieved=achieved,
                                   peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,

@@ -120,6 +120,16 @@ __device__ __forceinline__ void ld4f(rsrc_t r, int vo, int so, float* o) {
     o[2] = q.v[2];
     o[3] = q.v[3];
 }
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <int AUX>
+__device__ __forceinline__ void st4f(rsrc_t r, int vo, int so, const float* v) {
+    u32x4 q;
+    q.x = __builtin_bit_cast(unsigned, v[0]);
+    q.y = __builtin_bit_cast(unsigned, v[1]);
+    q.z = __builtin_bit_cast(unsigned, v[2]);
+    q.w = __builtin_bit_cast(unsigned, v[3]);
+    __builtin_amdgcn_raw_buffer_store_b128(q, r, vo, so, AUX);
+}
 template <int AUX>
 __device__ __forceinline__ void st1f(rsrc_t r, int vo, int so, float v) {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, AUX);

@@ -208,8 +208,11 @@ __global__ void k_report_clear_n(p2m_report* __restrict__ reps, int n) {
 // exclusive scan of int32 counts: one kernel, each workgroup scans a tile of
 // kScanTile counts and adds the prefix of its predecessors found by look-back
 // ---------------------------------------------------------------------------
-constexpr int kScanItems = 8;
+// 32 counts per thread (read and written as 16-byte vectors): a tile of 8192 keeps
+// the look-back chain short (128 tiles for 2^20 cells)
+constexpr int kScanItems = 32;
 constexpr int kScanTile = kBlock * kScanItems;
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int wave_inclusive_scan(int v) {
     const int lane = threadIdx.x & 63;
@@ -268,13 +271,25 @@ __global__ __launch_bounds__(kBlock) void k_scan_lookback(const int32_t* __restr
     __syncthreads();
     const int tile = s_tile;
     const int base = tile * kScanTile + threadIdx.x * kScanItems;
+    // a full run of 16-byte aligned arrays: vector accesses
+    const bool whole = base + kScanItems <= n && (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
     int vals[kScanItems];
+    if (whole) {
+#pragma unroll
+        for (int j = 0; j < kScanItems; j += 4) {
+            const i32x4 q = *(const i32x4*)(in + base + j);
+            vals[j] = q.x;
+            vals[j + 1] = q.y;
+            vals[j + 2] = q.z;
+            vals[j + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) vals[j] = (base + j < n) ? in[base + j] : 0;
+    }
     int s = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        vals[j] = (base + j < n) ? in[base + j] : 0;
-        s += vals[j];
-    }
+    for (int j = 0; j < kScanItems; ++j) s += vals[j];
     int total;
     int ex = block_exclusive_scan(s, total);
     if (threadIdx.x < 64) {
@@ -323,10 +338,23 @@ __global__ __launch_bounds__(kBlock) void k_scan_lookback(const int32_t* __restr
     }
     __syncthreads();
     ex += s_excl;
+    if (whole) {
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        if (base + j < n) out[base + j] = ex;
-        ex += vals[j];
+        for (int j = 0; j < kScanItems; j += 4) {
+            i32x4 q;
+            q.x = ex;
+            q.y = q.x + vals[j];
+            q.z = q.y + vals[j + 1];
+            q.w = q.z + vals[j + 2];
+            ex = q.w + vals[j + 3];
+            *(i32x4*)(out + base + j) = q;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < kScanItems; ++j) {
+            if (base + j < n) out[base + j] = ex;
+            ex += vals[j];
+        }
     }
     if (tile == (n + kScanTile - 1) / kScanTile - 1 && threadIdx.x == kBlock - 1)
         out[n] = s_excl + total;  // grand total

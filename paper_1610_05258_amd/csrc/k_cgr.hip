@@ -124,7 +124,6 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     __shared__ float s_af[F], s_bf[F];
     __shared__ int s_iters[F], s_refines[F], s_done[F], s_inner[F], s_zero[F], s_res[F];
     __shared__ uint32_t s_flags;
-    __shared__ int s_any;
 
     auto lidx = [&](int lc, int lr) { return (lr + 1) * LW + (lc + 1); };
     // per-field flags read once into a register after each decision point
@@ -291,7 +290,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         for (int f = 0; f < F; ++f) {
             if (!(imask & (1u << f))) continue;
             const rsrc_t rr = rs_pub(a.pubR, ex, f), rw = rs_pub(a.pubW, ex, f),
-                         rs = rs_pub(a.pubS, ex, f), rc = rs_col(ex);
+                         rs = rs_pub(a.pubS, ex, f);
 #pragma unroll
             for (int j = 0; j < RNPT; ++j) {
                 if (rmask & (1u << j)) {
@@ -299,13 +298,25 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     stf<kCoherent>(rw, gk(j), vw[f][j]);
                     stf<kCoherent>(rs, gk(j), vs[f][j]);
                 }
-                if (cmask & (1u << j)) {
-                    const int vo = gk(j) * (RS * 4);
-                    st1f<kCoherent>(rc, vo, 4 * f, vr[f][j]);
-                    st1f<kCoherent>(rc, vo, 4 * (F + f), vw[f][j]);
-                    st1f<kCoherent>(rc, vo, 4 * (2 * F + f), vs[f][j]);
-                }
             }
+        }
+        // boundary columns: whole records, 16 bytes a store (an idle field's slots
+        // carry its frozen values, which no reader uses)
+        const rsrc_t rc = rs_col(ex);
+#pragma unroll
+        for (int j = 0; j < RNPT; ++j) {
+            if (!(cmask & (1u << j))) continue;
+            float rec[RS];
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                rec[f] = vr[f][j];
+                rec[F + f] = vw[f][j];
+                rec[2 * F + f] = vs[f][j];
+            }
+#pragma unroll
+            for (int c = 3 * F; c < RS; ++c) rec[c] = 0.f;
+#pragma unroll
+            for (int c = 0; c < RS / 4; ++c) st4f<kCoherent>(rc, gk(j) * (RS * 4), 16 * c, rec + 4 * c);
         }
     };
 
