@@ -21,6 +21,9 @@ Modules
              of Sec. 3.3.
 ``mlp``      FP64 forward/backward of the per-cell warm-start network (not in the
              paper; parity target for the GPU training kernels).
+``ns``       the particle fluid solver of Sec. 3.3 (Taylor-Green vortex sheet): P1
+             stiffness and gradient operators, a fractional step on the mesh, and the
+             P2M / M2P / mid-point advection loop around it.
 
 Every function cites the passage of the paper it follows.  Readings where the paper
 is silent or garbled are stated where they are used.
