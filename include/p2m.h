@@ -303,6 +303,51 @@ p2m_status p2m_x1d_volumes(void* ctx, const p2m_problem* prob, void* vol_out, p2
                            void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Particle fluid solver: the Taylor-Green vortex sheet computation of Sec. 3.3
+ * (incompressible Navier-Stokes, particles carrying the velocity, space derivatives
+ * on the mesh).  The paper names only a standard splitting approach with mid-point
+ * time integration; the step below is that reading, for equal-order P1 velocity
+ * and pressure on the problem's periodic mesh (2D, FP32, square cells lx/nx ==
+ * ly/ny):
+ *   1. P2M of the particle velocities vel [2][np] (u then v) with FLIP
+ *      (P2M_NS_FLIP, Sec. 2.3) or the mass assignment (P2M_NS_MASS, Sec. 2.4):
+ *      nodal Ubar;
+ *   2. implicit viscous step (M_L + dt nu K) U* = M_L Ubar, K the P1 stiffness
+ *      matrix (the five-point Laplacian on this mesh), M_L = h^2 the lumped P1 mesh
+ *      mass;
+ *   3. pressure K p = -(1/dt) D U*, (D U)_i = int psi_i div U_h, with node 0 held at
+ *      p = 0 (the system is singular in the constants);
+ *   4. projection U^{n+1} = U* - dt M_L^-1 G p, (G p)_i = int psi_i grad p_h;
+ *   5. M2P: vel <- U^{n+1} interpolated at the particles (Sec. 2.2 eq. (10));
+ *   6. mid-point advection r* = r + (dt/2) vel, r <- r + dt U^{n+1}(r*), each
+ *      coordinate wrapped into [0, L) in FP64 and rounded once.
+ * The three linear systems are solved by the mass-matrix solver (FP32 CG, FP64
+ * residuals and refinement) to opts->tol; the pressure solve's iteration cap is at
+ * least 64 per mesh side.  opts->start must be P2M_START_FLIP or P2M_START_ZERO
+ * (the start of step 1's mass solve; steps 2 and 3 start from b / diag).
+ * --------------------------------------------------------------------------- */
+typedef enum { P2M_NS_FLIP = 0, P2M_NS_MASS = 1 } p2m_ns_assign;
+
+/* Workspace bytes of p2m_ns_step for this problem (the F = 2 assignment workspace
+ * plus 20 floats per node). */
+p2m_status p2m_ns_workspace_size(void* ctx, const p2m_problem* prob, size_t* bytes);
+/* One time step dt with kinematic viscosity nu (dt > 0, nu >= 0, finite).
+ *   vel       [2][np] FP32, in: the particle velocities at prob->x, prob->y;
+ *             out: the new ones (step 5)
+ *   x_out, y_out [np] FP32: the advected positions; may be prob->x, prob->y
+ *   mesh_vel  [2][nn] FP32 out: U^{n+1}, or NULL (then kept in the workspace)
+ *   reps      [3] device reports: 0 = binning, step 1 (its solve for P2M_NS_MASS),
+ *             M2P and advection (invalid particles: flags, NaN outputs); 1 = the
+ *             viscous solve; 2 = the pressure solve (iterations, refinements,
+ *             relative residual per component, NOT_CONVERGED / BREAKDOWN)
+ * Errors: P2M_ERR_INVALID_ARG (NULL ctx / reps / arrays, bad assign),
+ * P2M_ERR_NONFINITE / P2M_ERR_RANGE (dt, nu, opts), P2M_ERR_UNSUPPORTED (not 2D
+ * FP32 with square cells, another start), P2M_ERR_WORKSPACE, P2M_ERR_HIP. */
+p2m_status p2m_ns_step(void* ctx, const p2m_problem* prob, int32_t assign, double dt, double nu,
+                       const p2m_solve_opts* opts, void* vel, void* x_out, void* y_out,
+                       void* mesh_vel, p2m_report* reps, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Batches: many independent problems in one launch.
  *
  * A batch is nprob independent 2D FP32 problems (each its own mesh size, box,

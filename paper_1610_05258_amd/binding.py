@@ -42,9 +42,11 @@ EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size
            "p2m_learned_workspace_size", "p2m_learned_train_step", "p2m_tune", "p2m_tune_batched",
            "p2m_plan_get", "p2m_plan_get_batched",
            "p2m_plan_save", "p2m_plan_load", "p2m_plan_clear", "p2m_mass_assign_noalloc",
-           "p2m_x1d_workspace_size", "p2m_x1d_assign", "p2m_x1d_interpolate", "p2m_x1d_volumes")
+           "p2m_x1d_workspace_size", "p2m_x1d_assign", "p2m_x1d_interpolate", "p2m_x1d_volumes",
+           "p2m_ns_workspace_size", "p2m_ns_step")
 QUAD_EXACT, QUAD_APPB = 0, 1
 X1D_DELTA, X1D_FLIP, X1D_PIC, X1D_MASS, X1D_LUMPED = 0, 1, 2, 3, 4
+NS_FLIP, NS_MASS = 0, 1
 ERR_SCRATCH = 7
 SCRATCH_BYTES = 64 << 20
 LEARNED_KMAX, LEARNED_NIN, LEARNED_HIDDEN, LEARNED_NPARAM = 48, 160, 64, 18689
@@ -114,6 +116,9 @@ def lib():
         L.p2m_x1d_interpolate.argtypes = [vp, pprob, i32, i32, vp, i32, ctypes.POINTER(CSolveOpts), vp,
                                           vp, vp, sz, vp]
         L.p2m_x1d_volumes.argtypes = [vp, pprob, vp, vp, vp, sz, vp]
+        L.p2m_ns_workspace_size.argtypes = [vp, pprob, ctypes.POINTER(sz)]
+        L.p2m_ns_step.argtypes = [vp, pprob, i32, ctypes.c_double, ctypes.c_double,
+                                  ctypes.POINTER(CSolveOpts), vp, vp, vp, vp, vp, vp, sz, vp]
         L.p2m_batch_workspace_size.argtypes = [vp, pprob, i32, i32, ctypes.POINTER(sz)]
         L.p2m_mass_assign_batched.argtypes = [vp, pprob, i32, ctypes.POINTER(vp), i32,
                                               ctypes.POINTER(CSolveOpts), ctypes.POINTER(vp), vp, vp,
@@ -501,6 +506,37 @@ def p2m_x1d_volumes(ctx: Context, prob: Particles, stream=None, ws=None, rep=Non
                                  ctypes.c_void_p(rep.data_ptr()), wp, wn, _stream_ptr(stream)),
            "p2m_x1d_volumes")
     return out
+
+
+def ns_workspace_size(ctx: Context, prob: Particles) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().p2m_ns_workspace_size(ctx.handle, ctypes.byref(prob.cstruct()), ctypes.byref(n)),
+           "p2m_ns_workspace_size")
+    return int(n.value)
+
+
+def p2m_ns_step(ctx: Context, prob: Particles, vel, assign: int, dt: float, nu: float,
+                opts: CSolveOpts | None = None, x_out=None, y_out=None, mesh_vel=None, reps=None,
+                stream=None, ws=None):
+    """One step of the particle fluid solver (p2m_ns_step).  vel [2, np] (FP32, device) is
+    updated in place; the advected positions go to x_out, y_out (default: prob.x, prob.y,
+    in place).  Returns (mesh velocity [2, nn] or None, reports [3, REPORT_BYTES])."""
+    if vel.dtype != torch.float32 or not vel.is_cuda or not vel.is_contiguous():
+        raise TypeError("vel must be a contiguous FP32 device tensor [2, np]")
+    cp = prob.cstruct()
+    opts = opts if opts is not None else solve_opts()
+    x_out = prob.x if x_out is None else x_out
+    y_out = prob.y if y_out is None else y_out
+    reps = torch.zeros((3, REPORT_BYTES), dtype=torch.uint8, device=vel.device) if reps is None else reps
+    if ws is None:
+        ws = ctx.workspace(ns_workspace_size(ctx, prob))
+    mv = ctypes.c_void_p(mesh_vel.data_ptr()) if mesh_vel is not None else None
+    _check(lib().p2m_ns_step(ctx.handle, ctypes.byref(cp), int(assign), float(dt), float(nu),
+                             ctypes.byref(opts), ctypes.c_void_p(vel.data_ptr()),
+                             ctypes.c_void_p(x_out.data_ptr()), ctypes.c_void_p(y_out.data_ptr()), mv,
+                             ctypes.c_void_p(reps.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                             ctypes.c_size_t(ws.numel()), _stream_ptr(stream)), "p2m_ns_step")
+    return mesh_vel, reps
 
 
 def p2m_mass_solve(ctx: Context, prob: Particles, b, w, coef, opts: CSolveOpts | None = None,

@@ -907,6 +907,136 @@ p2m_status p2m_mass_assign_noalloc(void* ctx, const p2m_problem* prob, const voi
                            stream);
 }
 
+// ---------------------------------------------------------------------------
+// particle fluid solver (Sec. 3.3): one time step
+// ---------------------------------------------------------------------------
+// The step's arrays after the F = 2 layout of the problem: Ubar, U*, U^{n+1} [2][nn],
+// the viscous and pressure stencils [4][nn] with their diagonals [nn], the pressure
+// right-hand side and the pressure [nn].
+struct NsLayout {
+    size_t ubar, ustar, unew, cv, wv, cp, wp, rhs, p, total;
+};
+
+NsLayout make_ns_layout(size_t base, const Mesh& m) {
+    NsLayout N;
+    size_t off = base;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const size_t nn = (size_t)m.nn;
+    N.ubar = take(2 * nn * sizeof(float));
+    N.ustar = take(2 * nn * sizeof(float));
+    N.unew = take(2 * nn * sizeof(float));
+    N.cv = take(4 * nn * sizeof(float));
+    N.wv = take(nn * sizeof(float));
+    N.cp = take(4 * nn * sizeof(float));
+    N.wp = take(nn * sizeof(float));
+    N.rhs = take(nn * sizeof(float));
+    N.p = take(nn * sizeof(float));
+    N.total = off;
+    return N;
+}
+
+p2m_status check_ns_problem(const p2m_problem* prob, Mesh& m) {
+    p2m_status s = check_problem(prob, m);
+    if (s != P2M_OK) return s;
+    if (m.dim != 2 || prob->dtype != P2M_F32) return P2M_ERR_UNSUPPORTED;
+    const double hx = prob->lx / prob->nx, hy = prob->ly / prob->ny;
+    if (fabs(hx - hy) > 1e-12 * hx) return P2M_ERR_UNSUPPORTED;   // square cells only
+    return P2M_OK;
+}
+
+p2m_status p2m_ns_workspace_size(void* ctx, const p2m_problem* prob, size_t* bytes) {
+    if (!ctx || !bytes) return P2M_ERR_INVALID_ARG;
+    Mesh m;
+    p2m_status s = check_ns_problem(prob, m);
+    if (s != P2M_OK) return s;
+    const Context* c = (const Context*)ctx;
+    const Layout L = make_layout(m, 2, sizeof(float), cg_blocks_for(c, m, P2M_F32));
+    *bytes = make_ns_layout(L.total, m).total;
+    return P2M_OK;
+}
+
+p2m_status p2m_ns_step(void* ctx, const p2m_problem* prob, int32_t assign, double dt, double nu,
+                       const p2m_solve_opts* opts, void* vel, void* x_out, void* y_out,
+                       void* mesh_vel, p2m_report* reps, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !reps) return P2M_ERR_INVALID_ARG;
+    if (assign != P2M_NS_FLIP && assign != P2M_NS_MASS) return P2M_ERR_INVALID_ARG;
+    if (!isfinite(dt) || !isfinite(nu)) return P2M_ERR_NONFINITE;
+    if (!(dt > 0.0) || !(nu >= 0.0)) return P2M_ERR_RANGE;
+    p2m_status s = check_opts(opts);
+    if (s != P2M_OK) return s;
+    if (opts->start != P2M_START_FLIP && opts->start != P2M_START_ZERO) return P2M_ERR_UNSUPPORTED;
+    Mesh m;
+    s = check_ns_problem(prob, m);
+    if (s != P2M_OK) return s;
+    if (m.np > 0 && (!vel || !x_out || !y_out)) return P2M_ERR_INVALID_ARG;
+    size_t need = 0;
+    s = p2m_ns_workspace_size(ctx, prob, &need);
+    if (s != P2M_OK) return s;
+    if (!ws || ws_bytes < need) return P2M_ERR_WORKSPACE;
+    Prepared pp;
+    s = prepare(ctx, prob, 2, ws, ws_bytes, stream, &reps[0], pp);
+    if (s != P2M_OK) return s;
+    const NsLayout N = make_ns_layout(pp.L.total, m);
+    DeviceGuard g(((Context*)ctx)->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    const Context* c = (const Context*)ctx;
+    char* w = pp.ws;
+    float* ubar = (float*)(w + N.ubar);
+    float* ustar = (float*)(w + N.ustar);
+    float* unew = mesh_vel ? (float*)mesh_vel : (float*)(w + N.unew);
+    float* cv = (float*)(w + N.cv);
+    float* wv = (float*)(w + N.wv);
+    float* cpr = (float*)(w + N.cp);
+    float* wpr = (float*)(w + N.wp);
+    float* rhs = (float*)(w + N.rhs);
+    float* pr = (float*)(w + N.p);
+    const double h = prob->lx / prob->nx;
+    // 1. P2M of the particle velocities (report 0: binning, assignment and its solve)
+    pp.clear_rep = true;
+    if (assign == P2M_NS_FLIP) {
+        s = run_assign<float>(pp, prob, P2M_FLIP, vel, 2, ubar);
+    } else {
+        p2m_solve_opts o = *opts;
+        s = run_mass<float>(c, pp, prob, vel, 2, o, ubar, choose(c, m, P2M_F32, 2));
+    }
+    if (s != P2M_OK) return s;
+    // 2. viscous step (I + s K) U* = Ubar (report 1)
+    P2M_TRY(launch_ns_coef(m, (float)(dt * nu / (h * h)), cv, wv, cpr, wpr, pp.stream));
+    Prepared pv = pp;
+    pv.rep = &reps[1];
+    pv.clear_rep = true;
+    p2m_solve_opts ov = *opts;
+    ov.start = P2M_START_FLIP;
+    s = run_solve<float>(c, pv, 2, ubar, wv, cv, P2M_START_FLIP, ov, ustar, choose(c, m, P2M_F32, 2));
+    if (s != P2M_OK) return s;
+    // 3. pressure K p = -(1/dt) D U*, node 0 held at 0 (report 2); a Poisson system
+    //    needs O(n) CG iterations, so the cap is at least 64 per mesh side
+    P2M_TRY(launch_ns_div(m, -(h / 6.0) / dt, ustar, rhs, pp.stream));
+    Prepared pq = pp;
+    pq.rep = &reps[2];
+    pq.clear_rep = true;
+    p2m_solve_opts op = *opts;
+    op.start = P2M_START_FLIP;
+    const int64_t cap = 64 * (int64_t)(m.nx > m.ny ? m.nx : m.ny);
+    if (op.maxit < cap) op.maxit = (int32_t)(cap < INT32_MAX ? cap : INT32_MAX);
+    s = run_solve<float>(c, pq, 1, rhs, wpr, cpr, P2M_START_FLIP, op, pr, choose(c, m, P2M_F32, 1));
+    if (s != P2M_OK) return s;
+    // 4. projection U^{n+1} = U* - dt M_L^-1 G p
+    P2M_TRY(launch_ns_correct(m, dt / (6.0 * h), ustar, pr, unew, pp.stream));
+    // 5. M2P: the particles' new velocities (invalid particles flagged in report 0)
+    P2M_TRY(launch_gather<float>(m, particles_of<float>(prob), unew, 2, (float*)vel, &reps[0],
+                                 pp.stream, nullptr, 0));
+    // 6. mid-point advection
+    P2M_TRY(launch_ns_advect(m, prob->lx, prob->ly, dt, (const float*)prob->x,
+                             (const float*)prob->y, (const float*)vel, unew, (float*)x_out,
+                             (float*)y_out, &reps[0], pp.stream));
+    return P2M_OK;
+}
+
 p2m_status p2m_x1d_workspace_size(void* ctx, const p2m_problem* prob, int32_t nfields,
                                   size_t* bytes) {
     if (!ctx || !bytes || nfields < 1 || nfields > kMaxFields) return P2M_ERR_INVALID_ARG;

@@ -1,0 +1,205 @@
+// The mesh half of the particle fluid solver of Sec. 3.3 (Taylor-Green vortex
+// sheet) on the periodic "/"-split P1 mesh with square cells of side h:
+//
+//   coef    : stencil arrays of the two symmetric systems the mass-matrix solver
+//             takes (D, E, N, NE per node, and the diagonal as w):
+//               viscous  I + s K, s = dt nu / h^2, K the P1 stiffness matrix, which
+//                        on right isosceles triangles is the five-point Laplacian;
+//               pressure K with node 0 held at 0 (its row and column replaced by
+//                        the identity, which changes p by a constant only);
+//   div     : right-hand side of the pressure system, -(1/dt) (D U*)_k with
+//             (D U)_k = int psi_k div U_h;
+//   correct : the projection U^{n+1} = U* - dt M_L^{-1} G p, (G p)_k = int psi_k
+//             grad p_h, M_L = h^2 (row sums of the P1 mesh mass matrix);
+//   advect  : mid-point advection of the particles, r* = r + (dt/2) a with a the
+//             interpolated U^{n+1}, r <- r + dt U^{n+1}(r*), wrapped into [0, L).
+//
+// Every node sees the six triangles around it: of cell (i, j) both triangles
+// (the node is their corner n00), of cell (i-1, j) the lower one (corner n10), of
+// cell (i-1, j-1) both (corner n11) and of cell (i, j-1) the upper one (corner
+// n01).  On a triangle the P1 derivatives are node differences over h; the
+// integral of a hat over a triangle is h^2/6.  The node sums are formed in FP64
+// and rounded once.
+#include "p2m_internal.hpp"
+
+namespace p2m {
+
+namespace {
+
+struct Nbr {
+    int i, j, im, jm, ip, jp;
+};
+
+__device__ __forceinline__ Nbr nbr(int k, int nx, int ny) {
+    Nbr q;
+    q.i = k % nx;
+    q.j = k / nx;
+    q.im = q.i == 0 ? nx - 1 : q.i - 1;
+    q.jm = q.j == 0 ? ny - 1 : q.j - 1;
+    q.ip = q.i + 1 == nx ? 0 : q.i + 1;
+    q.jp = q.j + 1 == ny ? 0 : q.j + 1;
+    return q;
+}
+
+__global__ void k_ns_coef(int nx, int ny, float s, float* __restrict__ cv, float* __restrict__ wv,
+                          float* __restrict__ cp, float* __restrict__ wp) {
+    const int nn = nx * ny;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn) return;
+    const float dv = (float)(1.0 + 4.0 * (double)s);
+    cv[k] = dv;
+    cv[nn + k] = -s;
+    cv[2 * nn + k] = -s;
+    cv[3 * nn + k] = 0.f;
+    wv[k] = dv;
+    // node 0's couplings: its own E and N, the E of (nx-1, 0) and the N of (0, ny-1)
+    const int i = k % nx, j = k / nx;
+    const bool pin = k == 0;
+    const bool e0 = pin || (i == nx - 1 && j == 0);
+    const bool n0 = pin || (i == 0 && j == ny - 1);
+    const float dp = pin ? 1.f : 4.f;
+    cp[k] = dp;
+    cp[nn + k] = e0 ? 0.f : -1.f;
+    cp[2 * nn + k] = n0 ? 0.f : -1.f;
+    cp[3 * nn + k] = 0.f;
+    wp[k] = dp;
+}
+
+// rhs_k = scale * sum of the six triangles' divergence differences (lower triangle
+// of cell c: u10 - u00 + v11 - v10; upper: u11 - u01 + v01 - v00), scale =
+// -(h/6)/dt; 0 at the held node 0
+__global__ void k_ns_div(int nx, int ny, double scale, const float* __restrict__ U,
+                         float* __restrict__ rhs) {
+    const int nn = nx * ny;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn) return;
+    const Nbr q = nbr(k, nx, ny);
+    const float* u = U;
+    const float* v = U + nn;
+    auto at = [&](const float* a, int ii, int jj) { return (double)a[ii + nx * jj]; };
+    // cell (ci, cj) with upper-right corner (ci1, cj1)
+    auto dl = [&](int ci, int cj, int ci1, int cj1) {
+        return (at(u, ci1, cj) - at(u, ci, cj)) + (at(v, ci1, cj1) - at(v, ci1, cj));
+    };
+    auto du = [&](int ci, int cj, int ci1, int cj1) {
+        return (at(u, ci1, cj1) - at(u, ci, cj1)) + (at(v, ci, cj1) - at(v, ci, cj));
+    };
+    const double sum = dl(q.i, q.j, q.ip, q.jp) + du(q.i, q.j, q.ip, q.jp) +
+                       dl(q.im, q.j, q.i, q.jp) + dl(q.im, q.jm, q.i, q.j) +
+                       du(q.im, q.jm, q.i, q.j) + du(q.i, q.jm, q.ip, q.j);
+    rhs[k] = k == 0 ? 0.f : (float)(scale * sum);
+}
+
+// U^{n+1}_k = U*_k - factor * (sum of the six triangles' gradient differences),
+// lower triangle of cell c: (p10 - p00, p11 - p10); upper: (p11 - p01, p01 - p00);
+// factor = dt / (6 h)
+__global__ void k_ns_correct(int nx, int ny, double factor, const float* __restrict__ Us,
+                             const float* __restrict__ p, float* __restrict__ Un) {
+    const int nn = nx * ny;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn) return;
+    const Nbr q = nbr(k, nx, ny);
+    auto at = [&](int ii, int jj) { return (double)p[ii + nx * jj]; };
+    double gx = 0.0, gy = 0.0;
+    auto gl = [&](int ci, int cj, int ci1, int cj1) {
+        gx += at(ci1, cj) - at(ci, cj);
+        gy += at(ci1, cj1) - at(ci1, cj);
+    };
+    auto gu = [&](int ci, int cj, int ci1, int cj1) {
+        gx += at(ci1, cj1) - at(ci, cj1);
+        gy += at(ci, cj1) - at(ci, cj);
+    };
+    gl(q.i, q.j, q.ip, q.jp);
+    gu(q.i, q.j, q.ip, q.jp);
+    gl(q.im, q.j, q.i, q.jp);
+    gl(q.im, q.jm, q.i, q.j);
+    gu(q.im, q.jm, q.i, q.j);
+    gu(q.i, q.jm, q.ip, q.j);
+    Un[k] = (float)((double)Us[k] - factor * gx);
+    Un[nn + k] = (float)((double)Us[nn + k] - factor * gy);
+}
+
+__device__ __forceinline__ double wrap(double x, double len) {
+    return __dsub_rn(x, len * floor(x / len));
+}
+
+// U at an FP64 position (its triangle's three nodes, FP64 weights); false when the
+// position cannot be located
+__device__ __forceinline__ bool interp2(const Mesh& m, const float* __restrict__ U, double x,
+                                        double y, double& ux, double& uy, bool& finite) {
+    int cx = 0, cy = 0;
+    double xi = 0.0, eta = 0.0;
+    bool fx = true, fy = true;
+    bool ok = locate_axis(x, m.nx, m.inv_hx, cx, xi, fx);
+    ok = locate_axis(y, m.ny, m.inv_hy, cy, eta, fy) && ok;
+    finite = fx && fy;
+    if (!ok) return false;
+    const int i1 = cx + 1 == m.nx ? 0 : cx + 1;
+    const int j1 = cy + 1 == m.ny ? 0 : cy + 1;
+    double c00, c10, c11, c01;
+    corner_weights<double>(xi, eta, c00, c10, c11, c01);
+    const int k00 = cx + m.nx * cy, k10 = i1 + m.nx * cy, k11 = i1 + m.nx * j1, k01 = cx + m.nx * j1;
+    const float* v = U + m.nn;
+    ux = c00 * U[k00] + c10 * U[k10] + c11 * U[k11] + c01 * U[k01];
+    uy = c00 * v[k00] + c10 * v[k10] + c11 * v[k11] + c01 * v[k01];
+    return true;
+}
+
+// x, y and xo, yo may be the same arrays (each thread reads its particle before
+// writing it)
+__global__ void k_ns_advect(Mesh m, double lx, double ly, double dt, const float* x,
+                            const float* y, const float* __restrict__ a,
+                            const float* __restrict__ U, float* xo, float* yo,
+                            p2m_report* __restrict__ rep) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m.np) return;
+    const double x0 = x[i], y0 = y[i];
+    const double xm = wrap(x0 + 0.5 * dt * (double)a[i], lx);
+    const double ym = wrap(y0 + 0.5 * dt * (double)a[m.np + i], ly);
+    double ux = 0.0, uy = 0.0;
+    bool finite = true;
+    if (!interp2(m, U, xm, ym, ux, uy, finite)) {
+        if (rep) atomicOr(&rep->flags, finite ? (uint32_t)P2M_FLAG_RANGE : (uint32_t)P2M_FLAG_NONFINITE);
+        xo[i] = NAN;
+        yo[i] = NAN;
+        return;
+    }
+    xo[i] = (float)wrap(x0 + dt * ux, lx);
+    yo[i] = (float)wrap(y0 + dt * uy, ly);
+}
+
+inline int grid_of(int n, int b) { return (n + b - 1) / b; }
+
+}  // namespace
+
+hipError_t launch_ns_coef(const Mesh& m, float s, float* cv, float* wv, float* cp, float* wp,
+                          hipStream_t stream) {
+    hipLaunchKernelGGL(k_ns_coef, dim3(grid_of(m.nn, 256)), dim3(256), 0, stream, m.nx, m.ny, s,
+                       cv, wv, cp, wp);
+    return hipGetLastError();
+}
+
+hipError_t launch_ns_div(const Mesh& m, double scale, const float* U, float* rhs,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(k_ns_div, dim3(grid_of(m.nn, 256)), dim3(256), 0, stream, m.nx, m.ny, scale,
+                       U, rhs);
+    return hipGetLastError();
+}
+
+hipError_t launch_ns_correct(const Mesh& m, double factor, const float* Us, const float* p,
+                             float* Un, hipStream_t stream) {
+    hipLaunchKernelGGL(k_ns_correct, dim3(grid_of(m.nn, 256)), dim3(256), 0, stream, m.nx, m.ny,
+                       factor, Us, p, Un);
+    return hipGetLastError();
+}
+
+hipError_t launch_ns_advect(const Mesh& m, double lx, double ly, double dt, const float* x,
+                            const float* y, const float* a, const float* U, float* xo, float* yo,
+                            p2m_report* rep, hipStream_t stream) {
+    if (m.np == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ns_advect, dim3(grid_of(m.np, 256)), dim3(256), 0, stream, m, lx, ly, dt,
+                       x, y, a, U, xo, yo, rep);
+    return hipGetLastError();
+}
+
+}  // namespace p2m

@@ -294,4 +294,17 @@ hipError_t launch_learned_start(const Mesh& m, Particles<float> P, const float* 
                                 const float* w, const float* coef, const float* params, float* x0,
                                 void* ws, p2m_report* rep, hipStream_t stream);
 
+// particle fluid solver (k_ns.hip): stencil arrays of the viscous system I + s K and of
+// the pressure system K (node 0 held), the pressure right-hand side -(1/dt) D U*, the
+// projection U* - dt M_L^-1 G p, and the mid-point advection of the particles
+hipError_t launch_ns_coef(const Mesh& m, float s, float* cv, float* wv, float* cp, float* wp,
+                          hipStream_t stream);
+hipError_t launch_ns_div(const Mesh& m, double scale, const float* U, float* rhs,
+                         hipStream_t stream);
+hipError_t launch_ns_correct(const Mesh& m, double factor, const float* Us, const float* p,
+                             float* Un, hipStream_t stream);
+hipError_t launch_ns_advect(const Mesh& m, double lx, double ly, double dt, const float* x,
+                            const float* y, const float* a, const float* U, float* xo, float* yo,
+                            p2m_report* rep, hipStream_t stream);
+
 }  // namespace p2m
