@@ -349,6 +349,58 @@ def zalesak_leg(B, ctx, steps=100, tol=1e-8):
     return out
 
 
+def ns_leg(B, ctx, n=256, ppc=4, t_end=0.25, tol=1e-8):
+    """The particle fluid solver (Sec. 3.3): Taylor-Green vortex sheet, Re = 200, on an
+    n x n mesh with ppc particles per cell, Courant number 0.5 (dt = h / 2), to
+    t_end; FLIP and mass assignment.  Timed: the whole run of steps on the device;
+    reported with the velocity error of eq. (29) (uniform volumes) against the exact
+    solution at t_end."""
+    import torch
+    from paper_1610_05258_amd import workloads as wl
+    nu = 0.005
+    dt = 0.5 / n
+    steps = int(round(t_end / dt))
+    opts = B.solve_opts(tol=tol, maxit=4000, max_refine=20)
+    out = dict(workload=f"taylor-green vortex sheet, unit periodic box {n}x{n} P1, {ppc} stratified ppc "
+                        f"(seed 4), Re=200, Courant 0.5 (dt={dt:g}), {steps} steps to t={t_end:g}, FP32, "
+                        f"tol={tol:g}")
+    for name, code in (("flip", B.NS_FLIP), ("mass", B.NS_MASS)):
+        prob, vel0 = wl.tg_fluid_2d(seed=4, n=n, ppc=ppc)
+        X0, Y0 = torch.as_tensor(prob["x"]).cuda(), torch.as_tensor(prob["y"]).cuda()
+        d = B.particles_from(prob, dtype=torch.float32)
+        V0 = torch.as_tensor(vel0).cuda()
+        vel = V0.clone()
+        mv = torch.empty((2, n * n), dtype=torch.float32, device="cuda")
+        reps = torch.zeros((3, B.REPORT_BYTES), dtype=torch.uint8, device="cuda")
+        ws = ctx.workspace(B.ns_workspace_size(ctx, d))
+
+        def run(k):
+            d.x.copy_(X0)
+            d.y.copy_(Y0)
+            vel.copy_(V0)
+            for _ in range(k):
+                B.p2m_ns_step(ctx, d, vel, code, dt, nu, opts, mesh_vel=mv, reps=reps, ws=ws)
+        run(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        x, y, v = d.x.cpu().numpy().astype(np.float64), d.y.cpu().numpy().astype(np.float64), \
+            vel.cpu().numpy().astype(np.float64)
+        ex = wl.tg_fluid_exact(x, y, steps * dt, nu)
+        err = float(np.sqrt(((ex - v) ** 2).sum() / (ex ** 2).sum()))
+        r = [B.read_report(reps[k], 2) for k in range(3)]
+        out[name] = dict(steps_per_s=steps / wall, ms_per_step=wall / steps * 1e3, l2_error=err,
+                         last_step_iters=dict(p2m=r[0].iters[:2].tolist(), viscous=r[1].iters[:2].tolist(),
+                                              pressure=int(r[2].iters[0])),
+                         flags=[int(q.flags) for q in r])
+        log(f"bench: fluid {name}: {out[name]['ms_per_step']:.3f} ms/step, L2 error at t={t_end:g} {err:.3e}, "
+            f"last step iterations {out[name]['last_step_iters']}")
+    out["mass_over_flip_error"] = out["mass"]["l2_error"] / out["flip"]["l2_error"]
+    return out
+
+
 def learned_leg(B, ctx, reps=5, tol=1e-6):
     """The learned-start workload (1024^2, 8 ppc, TG fields with random phase and
     amplitude disordered by 200 RK2 steps, held-out seed 20000): iterations and
@@ -647,6 +699,7 @@ def main():
         result["learned"] = learned_leg(B, ctx)
         result["tophat_1d"] = tophat_1d_leg(B, ctx)
         result["zalesak"] = zalesak_leg(B, ctx)
+        result["fluid"] = ns_leg(B, ctx)
     if k_ref is not None:
         kk = max(k_ref)
         b_e2e = mass_assign_algorithmic_bytes(int(vals.shape[1]), nn, F, kk)

@@ -176,6 +176,25 @@ def taylor_green_2d(seed=2, n=1024, ppc=8, steps=50, dt=1e-3, noise=1e-3, fields
     return prob, vals.astype(np.float32)
 
 
+def tg_fluid_2d(seed=4, n=256, ppc=4):
+    """The Taylor-Green vortex sheet set-up of Sec. 3.3: unit periodic box, u0 = 1,
+    ``ppc`` stratified particles per cell of an n x n mesh, carrying the exact
+    velocity at t = 0 (no noise).  FP32 positions and velocities [2, np]."""
+    x, y = stratified_2d(seed, n, n, ppc, 1.0, 1.0)
+    vel = tg_fluid_exact(x, y, 0.0)
+    prob = dict(dim=2, nx=n, ny=n, lx=1.0, ly=1.0, x=to_f32_positions(x, 1.0),
+                y=to_f32_positions(y, 1.0), vol=None)
+    return prob, vel.astype(np.float32)
+
+
+def tg_fluid_exact(x, y, t, nu=0.005):
+    """Exact Taylor-Green velocity on the unit box at time t (Sec. 3.3): f(t) (sin 2pi x
+    cos 2pi y, -cos 2pi x sin 2pi y), f = exp(-8 pi^2 nu t) (u0 = 1, L = 1)."""
+    k = TWO_PI
+    f = math.exp(-2.0 * nu * k * k * t)
+    return np.stack([f * np.sin(k * x) * np.cos(k * y), -f * np.cos(k * x) * np.sin(k * y)])
+
+
 def tg_disordered(seed, n=1024, ppc=8, steps=200, dt=1e-3, noise=1e-3, fields=3, random_phase=True,
                   device="cpu"):
     """TG-like fields on particles disordered by the flow: ``ppc`` stratified particles
