@@ -321,15 +321,19 @@ p2m_status p2m_x1d_volumes(void* ctx, const p2m_problem* prob, void* vol_out, p2
  *   5. M2P: vel <- U^{n+1} interpolated at the particles (Sec. 2.2 eq. (10));
  *   6. mid-point advection r* = r + (dt/2) vel, r <- r + dt U^{n+1}(r*), each
  *      coordinate wrapped into [0, L) in FP64 and rounded once.
- * The three linear systems are solved by the mass-matrix solver (FP32 CG, FP64
- * residuals and refinement) to opts->tol; the pressure solve's iteration cap is at
- * least 64 per mesh side.  opts->start must be P2M_START_FLIP or P2M_START_ZERO
- * (the start of step 1's mass solve; steps 2 and 3 start from b / diag).
+ * Step 1's mass system is solved by the mass-matrix solver (FP32 CG, FP64
+ * residuals and refinement) to opts->tol from opts->start, which must be
+ * P2M_START_FLIP or P2M_START_ZERO.  The systems of steps 2 and 3 are circulant:
+ * when nx and ny are powers of two (at most 2048) they are solved exactly by 2D FFT
+ * in FP64 (zero-mean pressure instead of the held node; reports 1 and 2 then show
+ * no iteration), otherwise by the same solver from b / diag, the pressure solve with
+ * an iteration cap of at least 64 per mesh side.
  * --------------------------------------------------------------------------- */
 typedef enum { P2M_NS_FLIP = 0, P2M_NS_MASS = 1 } p2m_ns_assign;
 
 /* Workspace bytes of p2m_ns_step for this problem (the F = 2 assignment workspace
- * plus 20 floats per node). */
+ * plus 20 floats per node, and 64 bytes per node of transform buffers when both
+ * sides are powers of two). */
 p2m_status p2m_ns_workspace_size(void* ctx, const p2m_problem* prob, size_t* bytes);
 /* One time step dt with kinematic viscosity nu (dt > 0, nu >= 0, finite).
  *   vel       [2][np] FP32, in: the particle velocities at prob->x, prob->y;

@@ -912,9 +912,10 @@ p2m_status p2m_mass_assign_noalloc(void* ctx, const p2m_problem* prob, const voi
 // ---------------------------------------------------------------------------
 // The step's arrays after the F = 2 layout of the problem: Ubar, U*, U^{n+1} [2][nn],
 // the viscous and pressure stencils [4][nn] with their diagonals [nn], the pressure
-// right-hand side and the pressure [nn].
+// right-hand side and the pressure [nn], and (power-of-two sides) the transform
+// buffers of the direct solves.
 struct NsLayout {
-    size_t ubar, ustar, unew, cv, wv, cp, wp, rhs, p, total;
+    size_t ubar, ustar, unew, cv, wv, cp, wp, rhs, p, fft, total;
 };
 
 NsLayout make_ns_layout(size_t base, const Mesh& m) {
@@ -935,6 +936,7 @@ NsLayout make_ns_layout(size_t base, const Mesh& m) {
     N.wp = take(nn * sizeof(float));
     N.rhs = take(nn * sizeof(float));
     N.p = take(nn * sizeof(float));
+    N.fft = take(ns_fft_supported(m) ? ns_fft_workspace_bytes(m) : 0);
     N.total = off;
     return N;
 }
@@ -1004,27 +1006,40 @@ p2m_status p2m_ns_step(void* ctx, const p2m_problem* prob, int32_t assign, doubl
         s = run_mass<float>(c, pp, prob, vel, 2, o, ubar, choose(c, m, P2M_F32, 2));
     }
     if (s != P2M_OK) return s;
-    // 2. viscous step (I + s K) U* = Ubar (report 1)
-    P2M_TRY(launch_ns_coef(m, (float)(dt * nu / (h * h)), cv, wv, cpr, wpr, pp.stream));
-    Prepared pv = pp;
-    pv.rep = &reps[1];
-    pv.clear_rep = true;
-    p2m_solve_opts ov = *opts;
-    ov.start = P2M_START_FLIP;
-    s = run_solve<float>(c, pv, 2, ubar, wv, cv, P2M_START_FLIP, ov, ustar, choose(c, m, P2M_F32, 2));
-    if (s != P2M_OK) return s;
-    // 3. pressure K p = -(1/dt) D U*, node 0 held at 0 (report 2); a Poisson system
-    //    needs O(n) CG iterations, so the cap is at least 64 per mesh side
-    P2M_TRY(launch_ns_div(m, -(h / 6.0) / dt, ustar, rhs, pp.stream));
-    Prepared pq = pp;
-    pq.rep = &reps[2];
-    pq.clear_rep = true;
-    p2m_solve_opts op = *opts;
-    op.start = P2M_START_FLIP;
-    const int64_t cap = 64 * (int64_t)(m.nx > m.ny ? m.nx : m.ny);
-    if (op.maxit < cap) op.maxit = (int32_t)(cap < INT32_MAX ? cap : INT32_MAX);
-    s = run_solve<float>(c, pq, 1, rhs, wpr, cpr, P2M_START_FLIP, op, pr, choose(c, m, P2M_F32, 1));
-    if (s != P2M_OK) return s;
+    // 2. viscous step (I + s K) U* = Ubar (report 1); 3. pressure K p = -(1/dt) D U*
+    //    (report 2).  Power-of-two sides: both by 2D FFT, exactly (zero-mean pressure;
+    //    the reports show no iteration).  Otherwise by the mass-matrix solver, node 0
+    //    holding the pressure at 0; a Poisson system needs O(n) CG iterations, so the
+    //    pressure solve's cap is at least 64 per mesh side.
+    const double sv = dt * nu / (h * h);
+    if (ns_fft_supported(m)) {
+        P2M_TRY(launch_report_clear(&reps[1], pp.stream));
+        P2M_TRY(launch_report_clear(&reps[2], pp.stream));
+        P2M_TRY(launch_ns_fft_solve(m, 2, sv, 0, ubar, ustar, w + N.fft, pp.stream));
+        P2M_TRY(launch_ns_div(m, -(h / 6.0) / dt, 0, ustar, rhs, pp.stream));
+        P2M_TRY(launch_ns_fft_solve(m, 1, 0.0, 1, rhs, pr, w + N.fft, pp.stream));
+    } else {
+        P2M_TRY(launch_ns_coef(m, (float)sv, cv, wv, cpr, wpr, pp.stream));
+        Prepared pv = pp;
+        pv.rep = &reps[1];
+        pv.clear_rep = true;
+        p2m_solve_opts ov = *opts;
+        ov.start = P2M_START_FLIP;
+        s = run_solve<float>(c, pv, 2, ubar, wv, cv, P2M_START_FLIP, ov, ustar,
+                             choose(c, m, P2M_F32, 2));
+        if (s != P2M_OK) return s;
+        P2M_TRY(launch_ns_div(m, -(h / 6.0) / dt, 1, ustar, rhs, pp.stream));
+        Prepared pq = pp;
+        pq.rep = &reps[2];
+        pq.clear_rep = true;
+        p2m_solve_opts op = *opts;
+        op.start = P2M_START_FLIP;
+        const int64_t cap = 64 * (int64_t)(m.nx > m.ny ? m.nx : m.ny);
+        if (op.maxit < cap) op.maxit = (int32_t)(cap < INT32_MAX ? cap : INT32_MAX);
+        s = run_solve<float>(c, pq, 1, rhs, wpr, cpr, P2M_START_FLIP, op, pr,
+                             choose(c, m, P2M_F32, 1));
+        if (s != P2M_OK) return s;
+    }
     // 4. projection U^{n+1} = U* - dt M_L^-1 G p
     P2M_TRY(launch_ns_correct(m, dt / (6.0 * h), ustar, pr, unew, pp.stream));
     // 5. M2P: the particles' new velocities (invalid particles flagged in report 0)

@@ -67,8 +67,8 @@ __global__ void k_ns_coef(int nx, int ny, float s, float* __restrict__ cv, float
 
 // rhs_k = scale * sum of the six triangles' divergence differences (lower triangle
 // of cell c: u10 - u00 + v11 - v10; upper: u11 - u01 + v01 - v00), scale =
-// -(h/6)/dt; 0 at the held node 0
-__global__ void k_ns_div(int nx, int ny, double scale, const float* __restrict__ U,
+// -(h/6)/dt; with pin, 0 at the held node 0
+__global__ void k_ns_div(int nx, int ny, double scale, int pin, const float* __restrict__ U,
                          float* __restrict__ rhs) {
     const int nn = nx * ny;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -87,7 +87,7 @@ __global__ void k_ns_div(int nx, int ny, double scale, const float* __restrict__
     const double sum = dl(q.i, q.j, q.ip, q.jp) + du(q.i, q.j, q.ip, q.jp) +
                        dl(q.im, q.j, q.i, q.jp) + dl(q.im, q.jm, q.i, q.j) +
                        du(q.im, q.jm, q.i, q.j) + du(q.i, q.jm, q.ip, q.j);
-    rhs[k] = k == 0 ? 0.f : (float)(scale * sum);
+    rhs[k] = (pin && k == 0) ? 0.f : (float)(scale * sum);
 }
 
 // U^{n+1}_k = U*_k - factor * (sum of the six triangles' gradient differences),
@@ -168,9 +168,152 @@ __global__ void k_ns_advect(Mesh m, double lx, double ly, double dt, const float
     yo[i] = (float)wrap(y0 + dt * uy, ly);
 }
 
+// ---------------------------------------------------------------------------
+// Direct solves of the two mesh systems when both mesh sides are powers of two:
+// I + s K and K are circulant on the periodic mesh, diagonal in the 2D discrete
+// Fourier basis with eigenvalues 1 + s lam and lam, lam(kx, ky) = 4 - 2 cos(2 pi
+// kx / nx) - 2 cos(2 pi ky / ny) (the five-point symbol); K's zero mode is the
+// constant, left at 0 (zero-mean pressure).  Transforms in FP64: row transforms
+// of one length per workgroup (radix-2 Stockham in LDS, natural order in and out),
+// a tiled transpose between the two directions.
+// ---------------------------------------------------------------------------
+constexpr int kFftMaxN = 2048;   // 2n complex doubles of LDS = 64 KB
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// rows of length n = 2^logn, one per workgroup; sign -1 forward, +1 inverse
+// (unnormalised); REAL_IN reads floats (imaginary part 0), REAL_OUT writes the
+// real part times scale as floats
+template <bool REAL_IN, bool REAL_OUT>
+__global__ void k_fft_rows(const void* __restrict__ in, void* __restrict__ out, int n, int logn,
+                           double sign, double scale) {
+    extern __shared__ double2 fsh[];
+    double2* x = fsh;
+    double2* y = fsh + n;
+    const size_t base = (size_t)blockIdx.x * n;
+    for (int t = threadIdx.x; t < n; t += blockDim.x)
+        x[t] = REAL_IN ? make_double2((double)((const float*)in)[base + t], 0.0)
+                       : ((const double2*)in)[base + t];
+    __syncthreads();
+    const int half = n >> 1;
+    for (int ls = 0; ls < logn; ++ls) {
+        const int ns = 1 << ls;
+        for (int j = threadIdx.x; j < half; j += blockDim.x) {
+            const int k = j & (ns - 1);
+            const double2 a = x[j], b0 = x[j + half];
+            double sn, cs;
+            sincospi(sign * (double)k / (double)ns, &sn, &cs);
+            const double2 b = make_double2(b0.x * cs - b0.y * sn, b0.x * sn + b0.y * cs);
+            const int d = ((j >> ls) << (ls + 1)) + k;
+            y[d] = cadd(a, b);
+            y[d + ns] = csub(a, b);
+        }
+        __syncthreads();
+        double2* t = x;
+        x = y;
+        y = t;
+    }
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        if (REAL_OUT)
+            ((float*)out)[base + t] = (float)(x[t].x * scale);
+        else
+            ((double2*)out)[base + t] = x[t];
+    }
+}
+
+// out[b][c][r] = in[b][r][c] for nb matrices of R x C, 32 x 32 tiles through LDS
+__global__ void k_transpose_c(const double2* __restrict__ in, double2* __restrict__ out, int R, int C) {
+    __shared__ double2 tile[32][33];
+    const size_t mb = (size_t)blockIdx.z * R * C;
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    for (int dy = threadIdx.y; dy < 32; dy += blockDim.y) {
+        const int r = r0 + dy, c = c0 + threadIdx.x;
+        if (r < R && c < C) tile[dy][threadIdx.x] = in[mb + (size_t)r * C + c];
+    }
+    __syncthreads();
+    for (int dy = threadIdx.y; dy < 32; dy += blockDim.y) {
+        const int c = c0 + dy, r = r0 + threadIdx.x;
+        if (r < R && c < C) out[mb + (size_t)c * R + r] = tile[threadIdx.x][dy];
+    }
+}
+
+// spectrum [nb][nx][ny] (row kx, column ky) divided by the system's eigenvalue:
+// 1 + s lam (viscous) or lam (pressure; the zero mode set to 0)
+__global__ void k_fft_divide(double2* __restrict__ a, int nx, int ny, int nb, double s, int pressure) {
+    const size_t nn = (size_t)nx * ny;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nn * nb) return;
+    const size_t e = t % nn;
+    const int kx = (int)(e / ny), ky = (int)(e % ny);
+    const double lam = 4.0 - 2.0 * cospi(2.0 * kx / nx) - 2.0 * cospi(2.0 * ky / ny);
+    double2 v = a[t];
+    if (pressure) {
+        if (kx == 0 && ky == 0) v = make_double2(0.0, 0.0);
+        else v = make_double2(v.x / lam, v.y / lam);
+    } else {
+        const double d = 1.0 + s * lam;
+        v = make_double2(v.x / d, v.y / d);
+    }
+    a[t] = v;
+}
+
 inline int grid_of(int n, int b) { return (n + b - 1) / b; }
 
+inline int ilog2(int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return l;
+}
+
 }  // namespace
+
+bool ns_fft_supported(const Mesh& m) {
+    auto pow2 = [](int n) { return n >= 2 && (n & (n - 1)) == 0; };
+    return m.dim == 2 && pow2(m.nx) && pow2(m.ny) && m.nx <= kFftMaxN && m.ny <= kFftMaxN;
+}
+
+size_t ns_fft_workspace_bytes(const Mesh& m) { return (size_t)2 * 2 * m.nn * sizeof(double2); }
+
+hipError_t launch_ns_fft_solve(const Mesh& m, int nb, double s, int pressure, const float* rhs,
+                               float* x, void* ws, hipStream_t stream) {
+    double2* fa = (double2*)ws;
+    double2* fb = fa + (size_t)2 * m.nn;
+    const int nx = m.nx, ny = m.ny, lx = ilog2(nx), ly = ilog2(ny);
+    auto rows = [&](int n, int nrows, const void* in, void* out, double sign, double scale,
+                    bool real_in, bool real_out) {
+        const int threads = n / 2 < 256 ? (n / 2 < 64 ? 64 : n / 2) : 256;
+        const size_t shm = (size_t)2 * n * sizeof(double2);
+        const int lg = ilog2(n);
+        if (real_in)
+            hipLaunchKernelGGL((k_fft_rows<true, false>), dim3(nrows), dim3(threads), shm, stream, in, out, n,
+                               lg, sign, scale);
+        else if (real_out)
+            hipLaunchKernelGGL((k_fft_rows<false, true>), dim3(nrows), dim3(threads), shm, stream, in, out, n,
+                               lg, sign, scale);
+        else
+            hipLaunchKernelGGL((k_fft_rows<false, false>), dim3(nrows), dim3(threads), shm, stream, in, out,
+                               n, lg, sign, scale);
+        return hipGetLastError();
+    };
+    auto transpose = [&](const double2* in, double2* out, int R, int C) {
+        hipLaunchKernelGGL(k_transpose_c, dim3(grid_of(C, 32), grid_of(R, 32), nb), dim3(32, 8), 0, stream,
+                           in, out, R, C);
+        return hipGetLastError();
+    };
+    (void)lx;
+    (void)ly;
+    hipError_t e;
+    if ((e = rows(nx, nb * ny, rhs, fa, -1.0, 1.0, true, false)) != hipSuccess) return e;
+    if ((e = transpose(fa, fb, ny, nx)) != hipSuccess) return e;
+    if ((e = rows(ny, nb * nx, fb, fa, -1.0, 1.0, false, false)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fft_divide, dim3(grid_of(nb * m.nn, 256)), dim3(256), 0, stream, fa, nx, ny, nb,
+                       s, pressure);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = rows(ny, nb * nx, fa, fb, 1.0, 1.0, false, false)) != hipSuccess) return e;
+    if ((e = transpose(fb, fa, nx, ny)) != hipSuccess) return e;
+    return rows(nx, nb * ny, fa, x, 1.0, 1.0 / ((double)nx * ny), false, true);
+}
 
 hipError_t launch_ns_coef(const Mesh& m, float s, float* cv, float* wv, float* cp, float* wp,
                           hipStream_t stream) {
@@ -179,10 +322,10 @@ hipError_t launch_ns_coef(const Mesh& m, float s, float* cv, float* wv, float* c
     return hipGetLastError();
 }
 
-hipError_t launch_ns_div(const Mesh& m, double scale, const float* U, float* rhs,
+hipError_t launch_ns_div(const Mesh& m, double scale, int pin, const float* U, float* rhs,
                          hipStream_t stream) {
     hipLaunchKernelGGL(k_ns_div, dim3(grid_of(m.nn, 256)), dim3(256), 0, stream, m.nx, m.ny, scale,
-                       U, rhs);
+                       pin, U, rhs);
     return hipGetLastError();
 }
 

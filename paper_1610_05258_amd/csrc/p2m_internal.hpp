@@ -299,8 +299,14 @@ hipError_t launch_learned_start(const Mesh& m, Particles<float> P, const float* 
 // projection U* - dt M_L^-1 G p, and the mid-point advection of the particles
 hipError_t launch_ns_coef(const Mesh& m, float s, float* cv, float* wv, float* cp, float* wp,
                           hipStream_t stream);
-hipError_t launch_ns_div(const Mesh& m, double scale, const float* U, float* rhs,
+hipError_t launch_ns_div(const Mesh& m, double scale, int pin, const float* U, float* rhs,
                          hipStream_t stream);
+// direct solve of nb right-hand sides of the viscous (I + s K, pressure = 0) or the
+// pressure system (K, zero-mean solution) by 2D FFT; power-of-two sides <= 2048
+bool ns_fft_supported(const Mesh& m);
+size_t ns_fft_workspace_bytes(const Mesh& m);   // for nb <= 2
+hipError_t launch_ns_fft_solve(const Mesh& m, int nb, double s, int pressure, const float* rhs,
+                               float* x, void* ws, hipStream_t stream);
 hipError_t launch_ns_correct(const Mesh& m, double factor, const float* Us, const float* p,
                              float* Un, hipStream_t stream);
 hipError_t launch_ns_advect(const Mesh& m, double lx, double ly, double dt, const float* x,

@@ -71,8 +71,10 @@ def gpu_steps(B, ctx, prob, a, method, dt, steps, tol=1e-8):
 
 
 @pytest.mark.parametrize("method", ns.ASSIGN)
-@pytest.mark.parametrize("n", [32, 256])
+@pytest.mark.parametrize("n", [32, 48, 256])
 def test_one_step_against_the_oracle(B, method, n):
+    """Power-of-two sides solve the two mesh systems by FFT (no iteration), 48 x 48
+    by the mass-matrix solver (node 0 holding the pressure)."""
     prob, a = tg_problem(n, 2, seed=7)
     dt = 0.5 / n
     say(f"[ns one step] {method} {n}x{n}, {prob['x'].size} particles")
@@ -84,7 +86,8 @@ def test_one_step_against_the_oracle(B, method, n):
     for k, r in enumerate(reps):
         say(f"  report {k}: iters {r.iters[:2].tolist()} refines {r.refines[:2].tolist()} flags {r.flags}")
         assert not (r.flags & (B.FLAG_NOT_CONVERGED | B.FLAG_BREAKDOWN | B.FLAG_RANGE | B.FLAG_NONFINITE))
-    assert reps[2].iters[0] > 0
+    pow2 = (n & (n - 1)) == 0
+    assert (reps[2].iters[0] == 0) if pow2 else (reps[2].iters[0] > 0)
     new, a_ref, U_ref = ns.step(f64(prob), a.astype(np.float64), method, dt, NU)
     eU, ea = rel_l2(mv, U_ref), rel_l2(vel, a_ref)
     ex = max(torus_dist(x, new["x"]).max(), torus_dist(y, new["y"]).max())
