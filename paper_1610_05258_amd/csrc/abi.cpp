@@ -144,31 +144,6 @@ Layout make_layout(const Mesh& m, int F, size_t tsize, int cg_blocks) {
     return L;
 }
 
-p2m_status check_problem(const p2m_problem* p, Mesh& m) {
-    if (!p) return P2M_ERR_INVALID_ARG;
-    if (p->dim != 1 && p->dim != 2) return P2M_ERR_INVALID_ARG;
-    if (p->dtype != P2M_F32 && p->dtype != P2M_F64) return P2M_ERR_INVALID_ARG;
-    if (p->nx < 2 || (p->dim == 2 && p->ny < 2)) return P2M_ERR_INVALID_ARG;
-    if (p->np < 0) return P2M_ERR_INVALID_ARG;
-    if (!isfinite(p->lx) || (p->dim == 2 && !isfinite(p->ly))) return P2M_ERR_NONFINITE;
-    if (!(p->lx > 0.0) || (p->dim == 2 && !(p->ly > 0.0))) return P2M_ERR_RANGE;
-    const int ny = (p->dim == 2) ? p->ny : 1;
-    const int64_t nn = (int64_t)p->nx * ny;
-    if (nn >= ((int64_t)1 << 31) - 1 || p->np >= ((int64_t)1 << 31) - 1) return P2M_ERR_UNSUPPORTED;
-    if (p->np > 0 && (!p->x || (p->dim == 2 && !p->y))) return P2M_ERR_INVALID_ARG;
-    m.dim = p->dim;
-    m.nx = p->nx;
-    m.ny = ny;
-    m.nn = (int)nn;
-    m.np = (int)p->np;
-    m.inv_hx = (double)p->nx / p->lx;
-    m.inv_hy = (p->dim == 2) ? (double)p->ny / p->ly : 1.0;
-    m.cell_measure = (p->dim == 2) ? (p->lx / p->nx) * (p->ly / p->ny) : p->lx / p->nx;
-    const double area = (p->dim == 2) ? p->lx * p->ly : p->lx;
-    m.v_uniform = (p->np > 0) ? area / (double)p->np : 0.0;
-    return P2M_OK;
-}
-
 inline size_t tsize_of(const p2m_problem* p) { return p->dtype == P2M_F64 ? 8 : 4; }
 
 int cg_blocks_for(const Context* c, const Mesh& m, int dtype) {
@@ -709,14 +684,6 @@ p2m_solve_opts x1d_opts(const p2m_solve_opts* o, int n) {
     return r;
 }
 
-p2m_status check_opts(const p2m_solve_opts* opts) {
-    if (!opts) return P2M_ERR_INVALID_ARG;
-    if (!isfinite(opts->tol) || !isfinite(opts->inner_rtol)) return P2M_ERR_NONFINITE;
-    if (!(opts->tol > 0.0) || opts->inner_rtol < 0.0 || opts->inner_rtol >= 1.0) return P2M_ERR_RANGE;
-    if (opts->maxit < 0 || opts->max_refine < 0 || opts->reserved != 0) return P2M_ERR_INVALID_ARG;
-    if (opts->start < P2M_START_FLIP || opts->start > P2M_START_DELTA1D) return P2M_ERR_INVALID_ARG;
-    return P2M_OK;
-}
 
 }  // namespace
 
@@ -1604,19 +1571,16 @@ p2m_status p2m_plan_save(void* ctx, const char* path) {
     const Context* c = (const Context*)ctx;
     FILE* f = fopen(path, "w");
     if (!f) return P2M_ERR_INVALID_ARG;
-    fprintf(f, "{\n");
+    bool ok = fputs("{\n", f) >= 0;
     size_t i = 0, n = c->plans ? c->plans->plans.size() : 0;
     if (c->plans)
         for (const auto& kv : c->plans->plans) {
-            const p2m_plan& p = kv.second;
-            fprintf(f,
-                    "  \"%s\": {\"solver\": %d, \"groups\": %d, \"scatter_tile\": %d, "
-                    "\"inner_rtol\": %.17g, \"time_ms\": %.6f}%s\n",
-                    kv.first.c_str(), p.solver, p.groups, p.scatter_tile, p.inner_rtol, p.time_ms,
-                    ++i < n ? "," : "");
+            char line[512];
+            const int len = format_plan_line(line, sizeof line, kv.first, kv.second, ++i == n);
+            ok = ok && len > 0 && fputs(line, f) >= 0;
         }
-    fprintf(f, "}\n");
-    return fclose(f) == 0 ? P2M_OK : P2M_ERR_INVALID_ARG;
+    ok = ok && fputs("}\n", f) >= 0;
+    return (fclose(f) == 0 && ok) ? P2M_OK : P2M_ERR_INVALID_ARG;
 }
 
 p2m_status p2m_plan_load(void* ctx, const char* path) {
@@ -1628,18 +1592,11 @@ p2m_status p2m_plan_load(void* ctx, const char* path) {
     char line[512];
     p2m_status s = P2M_OK;
     while (fgets(line, sizeof line, f)) {
-        char key[128];
+        std::string key;
         p2m_plan p;
-        memset(&p, 0, sizeof(p));
-        const char* q = strchr(line, '"');
-        if (!q) continue;   // braces
-        if (sscanf(q,
-                   "\"%127[^\"]\": {\"solver\": %d, \"groups\": %d, \"scatter_tile\": %d, "
-                   "\"inner_rtol\": %lf, \"time_ms\": %lf}",
-                   key, &p.solver, &p.groups, &p.scatter_tile, &p.inner_rtol, &p.time_ms) != 6 ||
-            p.solver < P2M_SOLVER_AUTO || p.solver > P2M_SOLVER_RESIDENT_CHEB || p.groups < 0 ||
-            (p.scatter_tile != 0 && p.scatter_tile != 8) || !(p.inner_rtol < 1.0) ||
-            !isfinite(p.inner_rtol)) {
+        const PlanLine r = parse_plan_line(line, key, p);
+        if (r == kPlanSkip) continue;   // braces
+        if (r == kPlanBad) {
             s = P2M_ERR_INVALID_ARG;
             break;
         }

@@ -7,23 +7,12 @@
 #include <stddef.h>
 
 #include "../../include/p2m.h"
+#include "p2m_host.hpp"   // Mesh, the problem and option checks, the plan-file line format
 
 namespace p2m {
 
 constexpr int kMaxFields = 8;
 constexpr size_t kAlign = 256;
-
-// Geometry of one periodic structured problem, computed once on the host in FP64.
-struct Mesh {
-    int dim;          // 1 or 2
-    int nx, ny;       // ny == 1 in 1D
-    int nn;           // nodes = cells = nx*ny
-    int np;           // particles
-    double inv_hx;    // nx / lx   (one FP64 division on the host)
-    double inv_hy;    // ny / ly
-    double cell_measure;  // hx*hy (2D) or hx (1D): the mesh volume v_i of every node
-    double v_uniform;     // lx*ly/np (2D) or lx/np (1D): particle volume when none is given
-};
 
 template <typename T>
 struct Particles {
