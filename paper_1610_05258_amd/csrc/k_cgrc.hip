@@ -571,7 +571,6 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
                     pd[F + f] = dot_acc(pd[F + f], vr[f][j], uj);
                 }
             }
-            __syncthreads();
             block_sum_to<2 * F>(pd, red_lds, vals);
             publish_rws(imask);
         }
@@ -669,7 +668,8 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
                         pg[2 * F + f] = dot_acc(pg[2 * F + f], vr[f][j], vr[f][j]);
                     }
                 }
-                __syncthreads();
+                // no barrier before the block sum: it orders its own LDS use, and the
+                // planes are written next after the grid barrier
                 block_sum_to<3 * F>(pg, red_lds, vals);
                 publish_rws(imask);
             }
