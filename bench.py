@@ -555,6 +555,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the timed steps, copy MIB MiB device-to-device three times "
                          "(a kernel of known traffic for scaling memory counters)")
+    ap.add_argument("--leg", default=None,
+                    choices=("fluid", "zalesak", "tophat_1d", "learned", "plain_vs_production"),
+                    help="run only this leg (no headline) and print its JSON; for profiling one workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the path runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -564,6 +567,21 @@ def main():
     import torch
     from paper_1610_05258_amd import binding as B
     from paper_1610_05258_amd import workloads as wl
+
+    if args.leg is not None:
+        B.lib()
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        ctx = B.Context(0)
+        if args.leg == "plain_vs_production":
+            prob, vals = wl.taylor_green_2d(seed=2, n=args.n, ppc=8, steps=50, dt=1e-3)
+            res = plain_vs_combined_leg(B, ctx, prob, vals)
+        else:
+            res = dict(fluid=ns_leg, zalesak=zalesak_leg, tophat_1d=tophat_1d_leg,
+                       learned=learned_leg)[args.leg](B, ctx)
+        print(json.dumps({args.leg: res}), flush=True)
+        torch.cuda.synchronize()
+        ctx.close()
+        return
 
     B.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
