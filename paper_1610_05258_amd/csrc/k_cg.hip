@@ -169,6 +169,15 @@ __device__ __forceinline__ double recip(double d) { return 1.0 / d; }
 template <typename T, int DIM, int F>
 __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
     cg::grid_group grid = cg::this_grid();
+    // a grid of one workgroup (small problems) synchronises with the workgroup
+    // barrier, which also orders its global-memory accesses; the grid barrier's
+    // device-wide handshake would cost microseconds per step
+    auto gsync = [&]() {
+        if (gridDim.x == 1)
+            __syncthreads();
+        else
+            grid.sync();
+    };
     const Mesh& m = a.m;
     const int nn = m.nn;
     const int nblocks = gridDim.x;
@@ -234,7 +243,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
             atomicOr(&a.rep->flags, (uint32_t)P2M_FLAG_ORPHAN);
         }
     }
-    grid.sync();
+    gsync();
 
     for (int outer = 0;; ++outer) {
         // ---- R: fold the correction into x64 and evaluate r = b - M x64 in FP64 --
@@ -270,7 +279,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
             block_sum<kSlots>(part, lds);
             store_partials<kSlots>(a.partials + (phase & 1) * pstride, part);
         }
-        grid.sync();
+        gsync();
         grid_total<kSlots>(a.partials + (phase & 1) * pstride, nblocks, tot, lds);
         ++phase;
         if (threadIdx.x == 0) {
@@ -340,7 +349,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                 block_sum<kMaxFields>(part, lds);
                 store_partials<kMaxFields>(a.partials + (phase & 1) * pstride, part);
             }
-            grid.sync();
+            gsync();
             grid_total<kMaxFields>(a.partials + (phase & 1) * pstride, nblocks, tot, lds);
             ++phase;
             if (threadIdx.x == 0) {
@@ -381,7 +390,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                 block_sum<2 * kMaxFields>(part, lds);
                 store_partials<2 * kMaxFields>(a.partials + (phase & 1) * pstride, part);
             }
-            grid.sync();
+            gsync();
             grid_total<2 * kMaxFields>(a.partials + (phase & 1) * pstride, nblocks, tot, lds);
             ++phase;
             if (threadIdx.x == 0) {
