@@ -349,10 +349,11 @@ def zalesak_leg(B, ctx, steps=100, tol=1e-8):
     return out
 
 
-def ns_leg(B, ctx, n=256, ppc=4, t_end=0.25, tol=1e-8):
+def ns_leg(B, ctx, n=256, ppc=4, t_end=0.25, tol=1e-8, tune=True):
     """The particle fluid solver (Sec. 3.3): Taylor-Green vortex sheet, Re = 200, on an
     n x n mesh with ppc particles per cell, Courant number 0.5 (dt = h / 2), to
-    t_end; FLIP and mass assignment.  Timed: the whole run of steps on the device;
+    t_end; FLIP and mass assignment (its P2M solve plan tuned first).  Timed: the whole
+    run of steps on the device;
     reported with the velocity error of eq. (29) (uniform volumes) against the exact
     solution at t_end."""
     import torch
@@ -373,6 +374,12 @@ def ns_leg(B, ctx, n=256, ppc=4, t_end=0.25, tol=1e-8):
         mv = torch.empty((2, n * n), dtype=torch.float32, device="cuda")
         reps = torch.zeros((3, B.REPORT_BYTES), dtype=torch.uint8, device="cuda")
         ws = ctx.workspace(B.ns_workspace_size(ctx, d))
+        if code == B.NS_MASS and tune:
+            # the mass P2M's solve plan for this shape class, tuned on the first step's field
+            plan, _, _ = B.p2m_tune(ctx, d, V0, opts)
+            torch.cuda.synchronize()
+            out["mass_plan"] = dict(solver=int(plan.solver), inner_rtol=float(plan.inner_rtol),
+                                    tuned_ms=float(plan.time_ms))
 
         def run(k):
             d.x.copy_(X0)

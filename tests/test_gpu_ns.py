@@ -162,3 +162,52 @@ def test_argument_errors(B):
             B.p2m_ns_step(ctx, B.particles_from(rect, dtype=torch.float32), vel, B.NS_FLIP, 0.01, NU)
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 6])
+def test_tiny_meshes_against_the_oracle(B, n):
+    """Meshes of 2 to 6 nodes a side (a node's periodic neighbours repeat at 2; 3 and 6
+    take the solver path, 2 and 4 the FFT path), both assignments, one step."""
+    for method in ns.ASSIGN:
+        prob, a = tg_problem(n, 4, seed=40 + n)
+        dt = 0.5 / n
+        ctx = B.Context(0)
+        try:
+            x, y, vel, mv, reps = gpu_steps(B, ctx, prob, a, method, dt, 1)
+        finally:
+            ctx.close()
+        for r in reps:
+            assert not (r.flags & (B.FLAG_NOT_CONVERGED | B.FLAG_BREAKDOWN | B.FLAG_RANGE | B.FLAG_NONFINITE))
+        new, a_ref, U_ref = ns.step(f64(prob), a.astype(np.float64), method, dt, NU)
+        eU = rel_l2(mv, U_ref)
+        ex = max(torus_dist(x, new["x"]).max(), torus_dist(y, new["y"]).max())
+        say(f"[ns tiny {n}x{n} {method}] mesh velocity rel l2 {eU:.2e}, positions {ex:.2e}")
+        assert eU <= 5e-6 and ex <= 2e-7
+
+
+def test_no_particles_and_invalid_particles(B):
+    """No particle: the mesh velocity is 0 and nothing is written to the particles.  A
+    particle with a non-finite position is flagged and gets NaN velocity and position;
+    the others get the results of the run without it, to rounding (one more particle
+    can change the order of the floating-point sums)."""
+    prob, a = tg_problem(16, 2, seed=21)
+    ctx = B.Context(0)
+    try:
+        empty = dict(prob, x=np.zeros(0, np.float32), y=np.zeros(0, np.float32))
+        d0 = B.particles_from(empty, dtype=torch.float32)
+        v0 = torch.zeros((2, 0), dtype=torch.float32, device="cuda")
+        mv = torch.full((2, 256), 7.0, dtype=torch.float32, device="cuda")
+        _, reps = B.p2m_ns_step(ctx, d0, v0, B.NS_FLIP, 0.01, NU, mesh_vel=mv)
+        torch.cuda.synchronize()
+        assert torch.count_nonzero(mv).item() == 0
+        bad = dict(prob, x=np.concatenate([prob["x"], np.array([np.nan], np.float32)]),
+                   y=np.concatenate([prob["y"], np.array([0.5], np.float32)]))
+        abad = np.concatenate([a, np.zeros((2, 1), np.float32)], axis=1)
+        x1, y1, v1, _, r1 = gpu_steps(B, ctx, bad, abad, "flip", 1.0 / 32, 1)
+        x2, y2, v2, _, _ = gpu_steps(B, ctx, prob, a, "flip", 1.0 / 32, 1)
+    finally:
+        ctx.close()
+    assert r1[0].flags & B.FLAG_NONFINITE
+    assert np.isnan(v1[:, -1]).all() and np.isnan(x1[-1]) and np.isnan(y1[-1])
+    assert np.abs(v1[:, :-1] - v2).max() <= 1e-6
+    assert max(torus_dist(x1[:-1], x2).max(), torus_dist(y1[:-1], y2).max()) <= 1e-7
