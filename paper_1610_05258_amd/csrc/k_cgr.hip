@@ -43,7 +43,6 @@ struct RArgs {
     const float* w;    // [nn]
     float* xout;       // [F][nn]  start (USER) on entry, result on exit
     double* x64;       // [F][nn]  FP64 solution, owner-only
-    float* res;        // [F][nn]  FP32 residual of the last residual phase, owner-only
     float* pubR;       // [2][F][nn] published values of the boundary rows
     float* pubW;
     float* pubS;
@@ -93,7 +92,6 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
     auto rs_x64 = [&](int f) { return mkrs(a.x64 + (size_t)f * nn, fb8); };
     auto rs_d = [&](int f) { return mkrs(a.xout + (size_t)f * nn, fb4); };
     auto rs_b = [&](int f) { return mkrs(a.b + (size_t)f * nn, fb4); };
-    auto rs_res = [&](int f) { return mkrs(a.res + (size_t)f * nn, fb4); };
     auto rs_pubX = [&](int par, int f) { return mkrs(a.pubX + ((size_t)par * F + f) * nn, fb8); };
     auto rs_pub = [&](float* base, int par, int f) {
         return mkrs(base + ((size_t)par * F + f) * nn, fb4);
@@ -336,7 +334,7 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 if (s_done[f]) continue;
-                const rsrc_t rx = rs_x64(f), rb = rs_b(f), rr = rs_res(f);
+                const rsrc_t rx = rs_x64(f), rb = rs_b(f);
                 const rsrc_t rpr = rs_pub(a.pubR, ex, f), rpc = rs_col(ex);
                 // every load of the field is issued before the first LDS write or
                 // global store: the ring slot of this thread (at most one), then x and
@@ -384,9 +382,10 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     }
                 }
                 __syncthreads();
-                // the FP32 residual goes to the owner-only array res and is loaded
-                // into registers by the CG start; b was staged in LDS with x, so the
-                // loop issues no global load that would wait on its stores
+                // the FP32 residual replaces b in LDS (a node's b is read only by its
+                // own thread) and goes into the registers of the CG start; b was staged
+                // in LDS with x, so the loop issues no global load that would wait on
+                // its stores
 #pragma unroll 1
                 for (int j = 0; j < RNPT; ++j) {
                     if (!(amask & (1u << j))) continue;
@@ -400,12 +399,15 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
                     const double bk = (double)lb[q];
                     const double r64 = bk - mx;
                     const float rt = (float)r64;
-                    stf<kPlain>(rr, kk, rt);
+                    lb[q] = rt;
                     pr[f] = sq_acc(pr[f], r64);
                     if (outer == 0) pr[2 * F + f] = sq_acc(pr[2 * F + f], bk);
                     if (rmask & (1u << j)) stf<kCoherent>(rpr, kk, rt);
                     if (cmask & (1u << j)) st1f<kCoherent>(rpc, kk * (RS * 4), 4 * f, rt);
                 }
+#pragma unroll
+                for (int j = 0; j < RNPT; ++j)
+                    if (amask & (1u << j)) vr[f][j] = lb[qj(j)];
                 __syncthreads();
             }
             block_sum_to<3 * F>(pr, red_lds, vals);
@@ -441,15 +443,8 @@ __global__ __launch_bounds__(RBS) void k_cgr(RArgs a) {
         if (!imask) break;
 
         // ---- CG start: u = r / diag, w = M u, delta = (w, u), gamma = (r, u);
-        //      p = s = d = 0, and the ring copies of p and d ------------------------
-#pragma unroll
-        for (int f = 0; f < F; ++f) {
-            if (!(imask & (1u << f))) continue;
-            const rsrc_t rr = rs_res(f);
-#pragma unroll
-            for (int j = 0; j < RNPT; ++j)
-                if (amask & (1u << j)) vr[f][j] = ldf<kPlain>(rr, gk(j));
-        }
+        //      p = s = d = 0, and the ring copies of p and d (r is in registers
+        //      since the residual phase) ----------------------------------------
         if (threadIdx.x < nhalo) {
             const int h = threadIdx.x;
             int lc, lr;
@@ -717,7 +712,6 @@ size_t cgr_workspace_bytes(const Mesh& m, int F, int blocks) {
     auto al = [](size_t v) { return (v + kAlign - 1) / kAlign * kAlign; };
     size_t s = 0;
     s += al((size_t)F * m.nn * sizeof(double));           // x64
-    s += al((size_t)F * m.nn * sizeof(float));            // res
     s += 3 * al((size_t)2 * F * m.nn * sizeof(float));    // pubR, pubW, pubS
     s += al((size_t)2 * m.nn * rec_floats(F) * sizeof(float));   // pubC
     s += al((size_t)2 * F * m.nn * sizeof(double));       // pubX
@@ -761,7 +755,6 @@ hipError_t launch_cg_resident(const Mesh& m, int F, float* coef, float* b, const
     a.opts = opts;
     a.rep = rep;
     a.x64 = (double*)p; p += al((size_t)F * m.nn * sizeof(double));
-    a.res = (float*)p; p += al((size_t)F * m.nn * sizeof(float));
     a.pubR = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubW = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubS = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));

@@ -431,7 +431,7 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 if (s_done[f]) continue;
-                const rsrc_t rx = rs_x64(f), rpx = rs_pubX(f), rb = rs_b(f), rd = rs_d(f);
+                const rsrc_t rx = rs_x64(f), rpx = rs_pubX(f), rb = rs_b(f);
                 const rsrc_t rpr = rs_pub(a.pubR, ex, f), rpc = rs_col(ex);
                 int hq = -1;
                 double hx = 0.0;
@@ -468,12 +468,16 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
                     const double bk = (double)lb[q];
                     const double r64 = bk - mx;
                     const float rt = (float)r64;
-                    stf<kPlain>(rd, kk, rt);
+                    lb[q] = rt;   // replaces b (read by this thread only)
                     pr[f] = sq_acc(pr[f], r64);
                     if (outer == 0) pr[2 * F + f] = sq_acc(pr[2 * F + f], bk);
                     if (rmask & (1u << j)) stf<kCoherent>(rpr, kk, rt);
                     if (cmask & (1u << j)) st1f<kCoherent>(rpc, kk * (RS * 4), 4 * f, rt);
                 }
+                // the FP32 residual goes into the registers of the CG start
+#pragma unroll
+                for (int j = 0; j < RNPT; ++j)
+                    if (amask & (1u << j)) vr[f][j] = lb[qj(j)];
                 __syncthreads();
             }
             block_sum_to<3 * F>(pr, red_lds, vals);
@@ -514,14 +518,6 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
         // ---- CG start: y = D^-1 r (tile and two-deep ring), u = P r, w = M u,
         //      delta = (w, u), gamma = (r, u); p = s = d = 0 ------------------------
         uint32_t imask = inner_mask();
-#pragma unroll
-        for (int f = 0; f < F; ++f) {
-            if (!(imask & (1u << f))) continue;
-            const rsrc_t rd = rs_d(f);
-#pragma unroll
-            for (int j = 0; j < RNPT; ++j)
-                if (amask & (1u << j)) vr[f][j] = ldf<kPlain>(rd, gk(j));
-        }
         for (int h = threadIdx.x; h < nring2; h += RBS) {
             int lc, lr;
             if (!ring2_slot(h, txa, tya, lc, lr)) continue;
