@@ -181,7 +181,6 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
     const Mesh& m = a.m;
     const int nn = m.nn;
     const int nblocks = gridDim.x;
-    const size_t pstride = (size_t)nblocks * kSlots;
     const size_t xstride = (size_t)F * nn;
 
     __shared__ double lds[(kCgBlock / 64) * kSlots];
@@ -191,6 +190,26 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
     __shared__ int s_iters[F], s_refines[F], s_done[F], s_inner[F], s_zero[F], s_xb[F];
     __shared__ uint32_t s_flags;
     __shared__ int s_any;
+
+    // Totals of a phase's NV partials per thread into tot[0..NV): block sum, then
+    // over the blocks in the fixed order of grid_total.  A grid of one block takes
+    // its block sum as the total (what grid_total would add to it: zeros) and
+    // needs no global exchange.
+    auto phase_total = [&](auto& part, int ph) {
+        constexpr int NV = sizeof(part) / sizeof(double);
+        block_sum<NV>(part, lds);
+        if (nblocks == 1) {
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int j = 0; j < NV; ++j) tot[j] = part[j];
+            }
+            __syncthreads();
+        } else {
+            store_partials<NV>(a.partials + (ph & 1) * ((size_t)nblocks * kSlots), part);
+            grid.sync();
+            grid_total<NV>(a.partials + (ph & 1) * ((size_t)nblocks * kSlots), nblocks, tot, lds);
+        }
+    };
 
     if (threadIdx.x < F) {
         const int f = threadIdx.x;
@@ -247,12 +266,12 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
 
     for (int outer = 0;; ++outer) {
         // ---- R: fold the correction into x64 and evaluate r = b - M x64 in FP64 --
-        // slots: [f] ||r64||^2, [8+f] (r_T, u) with r_T = (T)r64, u = r_T / diag,
-        // [16+f] ||b||^2 (first pass)
+        // slots: [f] ||r64||^2, [F+f] (r_T, u) with r_T = (T)r64, u = r_T / diag,
+        // [2F+f] ||b||^2 (first pass)
         {
-            double part[kSlots];
+            double part[3 * F];
 #pragma unroll
-            for (int j = 0; j < kSlots; ++j) part[j] = 0.0;
+            for (int j = 0; j < 3 * F; ++j) part[j] = 0.0;
             for (int k = k0; k < nn; k += kstride) {
                 const Nbr n = neighbours<DIM>(m, k);
                 const Row<T> c = load_row<T, DIM>(a.coef, nn, n);
@@ -272,15 +291,12 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                     a.r[(size_t)f * nn + k] = rt;
                     a.x64[(s_xb[f] ^ 1) * xstride + (size_t)f * nn + k] = y(k);
                     part[f] += r64 * r64;
-                    part[kMaxFields + f] += (double)rt * (double)(rt * a.dinv[k]);
-                    if (outer == 0) part[2 * kMaxFields + f] += bk * bk;
+                    part[F + f] += (double)rt * (double)(rt * a.dinv[k]);
+                    if (outer == 0) part[2 * F + f] += bk * bk;
                 }
             }
-            block_sum<kSlots>(part, lds);
-            store_partials<kSlots>(a.partials + (phase & 1) * pstride, part);
+            phase_total(part, phase);
         }
-        gsync();
-        grid_total<kSlots>(a.partials + (phase & 1) * pstride, nblocks, tot, lds);
         ++phase;
         if (threadIdx.x == 0) {
             int any = 0;
@@ -288,7 +304,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                 if (s_done[f]) continue;
                 s_xb[f] ^= 1;  // the folded solution now lives in the other buffer
                 s_refines[f] += 1;
-                if (outer == 0) s_bb[f] = tot[2 * kMaxFields + f];
+                if (outer == 0) s_bb[f] = tot[2 * F + f];
                 const double bb = s_bb[f];
                 if (bb == 0.0) {  // b == 0: the solution is 0
                     s_zero[f] = 1;
@@ -305,7 +321,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                     if (!(relres <= a.opts.tol)) s_flags |= P2M_FLAG_NOT_CONVERGED;
                     continue;
                 }
-                s_rho[f] = tot[kMaxFields + f];
+                s_rho[f] = tot[F + f];
                 const double goal = 0.25 * a.opts.tol * a.opts.tol * bb;
                 const double rel = a.opts.inner_rtol * a.opts.inner_rtol * rr;
                 s_target[f] = goal > rel ? goal : rel;
@@ -322,9 +338,9 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
             // A: p_new = u + beta p_old with u = r / diag (at the node and its
             //    neighbours), q = M p_new
             {
-                double part[kMaxFields];
+                double part[F];
 #pragma unroll
-                for (int j = 0; j < kMaxFields; ++j) part[j] = 0.0;
+                for (int j = 0; j < F; ++j) part[j] = 0.0;
                 for (int k = k0; k < nn; k += kstride) {
                     const Nbr n = neighbours<DIM>(m, k);
                     const Row<T> c = load_row<T, DIM>(a.coef, nn, n);
@@ -346,11 +362,8 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                         part[f] += (double)pk * (double)qk;
                     }
                 }
-                block_sum<kMaxFields>(part, lds);
-                store_partials<kMaxFields>(a.partials + (phase & 1) * pstride, part);
+                phase_total(part, phase);
             }
-            gsync();
-            grid_total<kMaxFields>(a.partials + (phase & 1) * pstride, nblocks, tot, lds);
             ++phase;
             if (threadIdx.x == 0) {
                 for (int f = 0; f < F; ++f) {
@@ -370,9 +383,9 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
             // B: d += alpha p_new (d = alpha p_new on the first step), r -= alpha q;
             //    partials (r, u) and (r, r)
             {
-                double part[2 * kMaxFields];
+                double part[2 * F];
 #pragma unroll
-                for (int j = 0; j < 2 * kMaxFields; ++j) part[j] = 0.0;
+                for (int j = 0; j < 2 * F; ++j) part[j] = 0.0;
                 for (int k = k0; k < nn; k += kstride) {
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
@@ -384,20 +397,17 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                         const T rn = a.r[o] - al * a.q[o];
                         a.r[o] = rn;
                         part[f] += (double)rn * (double)(rn * a.dinv[k]);
-                        part[kMaxFields + f] += (double)rn * (double)rn;
+                        part[F + f] += (double)rn * (double)rn;
                     }
                 }
-                block_sum<2 * kMaxFields>(part, lds);
-                store_partials<2 * kMaxFields>(a.partials + (phase & 1) * pstride, part);
+                phase_total(part, phase);
             }
-            gsync();
-            grid_total<2 * kMaxFields>(a.partials + (phase & 1) * pstride, nblocks, tot, lds);
             ++phase;
             if (threadIdx.x == 0) {
                 int any = 0;
                 for (int f = 0; f < F; ++f) {
                     if (!s_inner[f]) continue;
-                    const double rho_new = tot[f], rr = tot[kMaxFields + f];
+                    const double rho_new = tot[f], rr = tot[F + f];
                     s_beta[f] = rho_new / s_rho[f];
                     s_rho[f] = rho_new;
                     s_iters[f] += 1;
