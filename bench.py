@@ -304,11 +304,13 @@ def tophat_1d_leg(B, ctx, calls=50):
     return out
 
 
-def zalesak_leg(B, ctx, steps=100, tol=1e-8):
+def zalesak_leg(B, ctx, steps=100, tol=1e-8, tune=True):
     """The slotted-disk workload: 256^2, 4 ppc, 100 steps of (mass_assign -> M2P) with
     the particle values carried from step to step.  The rotated FP32 positions of
     every step are computed on the host (exact FP64 rotation) and uploaded before
-    timing; the timed loop is the 100 steps on the device."""
+    timing; the timed loop is the 100 steps on the device, after the solve plan of
+    the shape class is tuned on the first step's input (unless a loaded plan covers
+    it)."""
     import torch
     from paper_1610_05258_amd import workloads as wl
     prob, a0, x64, y64 = wl.zalesak_2d(seed=1, n=256, ppc=4)
@@ -326,6 +328,12 @@ def zalesak_leg(B, ctx, steps=100, tol=1e-8):
     rep = ctx.new_report()
     nodal = torch.empty((1, 256 * 256), dtype=torch.float32, device="cuda")
     vals = [A0.clone(), torch.empty_like(A0)]
+    plan = None
+    if tune:
+        plan = ctx.plan(ds[0], 1)
+        if plan is None:
+            plan, _, _ = B.p2m_tune(ctx, ds[0], A0, opts)
+        torch.cuda.synchronize()
 
     def run():
         vals[0].copy_(A0)
@@ -345,6 +353,10 @@ def zalesak_leg(B, ctx, steps=100, tol=1e-8):
                steps=steps, steps_per_s=steps / wall, ms_per_step=wall / steps * 1e3,
                last_iters=int(r.iters[0]), last_rel_residual=float(r.rel_residual[0]),
                final_min=float(fin.min()), final_max=float(fin.max()))
+    if plan is not None:
+        out["plan"] = dict(solver=int(plan.solver), groups=int(plan.groups),
+                           scatter_tile=int(plan.scatter_tile), inner_rtol=float(plan.inner_rtol),
+                           tuned_ms=float(plan.time_ms))
     log(f"bench: zalesak {out['steps_per_s']:.0f} steps/s ({out['ms_per_step']:.3f} ms/step)")
     return out
 
