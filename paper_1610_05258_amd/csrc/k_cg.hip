@@ -510,6 +510,10 @@ hipError_t launch_cg(const Mesh& m, int F, T* coef, T* b, const T* w, T* x, int 
     void* args[] = {&a};
     const void* fn = (m.dim == 1) ? cg_kernel<T, 1>(F) : cg_kernel<T, 2>(F);
     if (!fn) return hipErrorInvalidValue;
+    // a one-workgroup grid synchronises with the workgroup barrier only (it never
+    // reaches the grid barrier), so it takes an ordinary launch and none of the
+    // cooperative launch's queue overhead
+    if (ws.blocks == 1) return hipLaunchKernel(fn, dim3(1), dim3(kCgBlock), args, 0, stream);
     return hipLaunchCooperativeKernel(fn, dim3(ws.blocks), dim3(kCgBlock), args, 0, stream);
 }
 template hipError_t launch_cg<float>(const Mesh&, int, float*, float*, const float*, float*, int,
