@@ -9,18 +9,16 @@
 //          and vector updates in T, every field sharing each coefficient read,
 //          and all dot products accumulated in FP64; the next outer step folds
 //          d into x64 in FP64.
-// The whole solve is one persistent cooperative kernel: grid-wide barriers
-// separate the phases; reductions are per-block FP64 partials that every block
-// sums in the same fixed order, so all blocks take identical decisions and the
-// result is deterministic.  Every loop is bounded (maxit, max_refine).
+// The whole solve is one persistent kernel: grid-wide barriers separate the
+// phases; reductions are per-block FP64 partials that every block sums in the
+// same fixed order, so all blocks take identical decisions and the result is
+// deterministic.  Every loop is bounded (maxit, max_refine), and so is every
+// wait in the grid barrier: a wait that times out ends the solve in every block
+// with the breakdown flag.
 //
 // Stencil storage (symmetric, periodic): D_k = M(k,k), E_k = M(k,k+x),
 // N_k = M(k,k+y), NE_k = M(k,k+x+y) in 2D; D_k, E_k = M(k,k+1) in 1D.
-#include "p2m_internal.hpp"
-
-#include <hip/hip_cooperative_groups.h>
-
-namespace cg = cooperative_groups;
+#include "cg_common.hpp"
 
 namespace p2m {
 
@@ -28,6 +26,49 @@ namespace {
 
 constexpr int kCgBlock = 256;
 constexpr int kSlots = 3 * kMaxFields;  // partial slots per block and phase
+// Grid-barrier words after the partials: the two-level counter tree of the tile
+// solvers (group counters, root, per-group release copies, abort flag), zeroed
+// before each launch.
+constexpr int kBarWords = 2 * kGroups * 32 + 2 * 32;
+constexpr size_t kBarBytes = (size_t)kBarWords * sizeof(unsigned);
+
+__device__ __forceinline__ RSync bar_of(unsigned* w) {
+    RSync s;
+    s.ctr = w;
+    s.root = w + kGroups * 32;
+    s.rel = w + kGroups * 32 + 32;
+    s.abort = w + 2 * kGroups * 32 + 32;
+    s.part = nullptr;
+    s.tot = nullptr;
+    return s;
+}
+
+// Grid-wide barrier number `epoch` (1, 2, ...) of a launch whose blocks are all
+// resident (the grid is sized from the occupancy).  The solve's vectors are
+// exchanged through ordinary cached stores, so the barrier orders them itself:
+// every wave waits for its own stores (the workgroup barrier does not), then one
+// thread writes the XCD's L2 back (agent-scope release), arrives at the counter
+// tree, waits for the release and invalidates the cached lines (agent-scope
+// acquire) before the block goes on.  Returns false after a wait timed out here
+// or in another block (the abort flag).
+__device__ bool grid_barrier(const RSync& s, unsigned epoch) {
+    __shared__ int s_ok;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (tree_arrive(s, epoch, gridDim.x)) tree_release(s, epoch);
+        const bool ok = tree_wait(s, epoch);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s_ok = ok ? 1 : 0;
+    }
+    __syncthreads();
+    return s_ok != 0;
+}
+
+__global__ void k_bar_clear(unsigned* w) {
+    for (int i = threadIdx.x; i < kBarWords; i += blockDim.x) w[i] = 0u;
+}
 
 template <typename T>
 struct CgArgs {
@@ -168,19 +209,22 @@ __device__ __forceinline__ double recip(double d) { return 1.0 / d; }
 
 template <typename T, int DIM, int F>
 __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
-    cg::grid_group grid = cg::this_grid();
-    // a grid of one workgroup (small problems) synchronises with the workgroup
-    // barrier, which also orders its global-memory accesses; the grid barrier's
-    // device-wide handshake would cost microseconds per step
-    auto gsync = [&]() {
-        if (gridDim.x == 1)
-            __syncthreads();
-        else
-            grid.sync();
-    };
     const Mesh& m = a.m;
     const int nn = m.nn;
     const int nblocks = gridDim.x;
+    const RSync bar =
+        bar_of((unsigned*)((char*)a.partials + (size_t)2 * nblocks * kSlots * sizeof(double)));
+    unsigned epoch = 0;
+    // a grid of one workgroup (small problems) synchronises with the workgroup
+    // barrier, which also orders its global-memory accesses; the grid barrier's
+    // device-wide handshake would cost microseconds per step
+    auto gsync = [&]() -> bool {
+        if (nblocks == 1) {
+            __syncthreads();
+            return true;
+        }
+        return grid_barrier(bar, ++epoch);
+    };
     const size_t xstride = (size_t)F * nn;
 
     __shared__ double lds[(kCgBlock / 64) * kSlots];
@@ -195,7 +239,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
     // over the blocks in the fixed order of grid_total.  A grid of one block takes
     // its block sum as the total (what grid_total would add to it: zeros) and
     // needs no global exchange.
-    auto phase_total = [&](auto& part, int ph) {
+    auto phase_total = [&](auto& part, int ph) -> bool {
         constexpr int NV = sizeof(part) / sizeof(double);
         block_sum<NV>(part, lds);
         if (nblocks == 1) {
@@ -204,11 +248,12 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                 for (int j = 0; j < NV; ++j) tot[j] = part[j];
             }
             __syncthreads();
-        } else {
-            store_partials<NV>(a.partials + (ph & 1) * ((size_t)nblocks * kSlots), part);
-            grid.sync();
-            grid_total<NV>(a.partials + (ph & 1) * ((size_t)nblocks * kSlots), nblocks, tot, lds);
+            return true;
         }
+        store_partials<NV>(a.partials + (ph & 1) * ((size_t)nblocks * kSlots), part);
+        if (!gsync()) return false;
+        grid_total<NV>(a.partials + (ph & 1) * ((size_t)nblocks * kSlots), nblocks, tot, lds);
+        return true;
     };
 
     if (threadIdx.x < F) {
@@ -262,9 +307,9 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
             atomicOr(&a.rep->flags, (uint32_t)P2M_FLAG_ORPHAN);
         }
     }
-    gsync();
+    bool alive = gsync();
 
-    for (int outer = 0;; ++outer) {
+    for (int outer = 0; alive; ++outer) {
         // ---- R: fold the correction into x64 and evaluate r = b - M x64 in FP64 --
         // slots: [f] ||r64||^2, [F+f] (r_T, u) with r_T = (T)r64, u = r_T / diag,
         // [2F+f] ||b||^2 (first pass)
@@ -295,9 +340,10 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                     if (outer == 0) part[2 * F + f] += bk * bk;
                 }
             }
-            phase_total(part, phase);
+            alive = phase_total(part, phase);
         }
         ++phase;
+        if (!alive) break;
         if (threadIdx.x == 0) {
             int any = 0;
             for (int f = 0; f < F; ++f) {
@@ -362,9 +408,10 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                         part[f] += (double)pk * (double)qk;
                     }
                 }
-                phase_total(part, phase);
+                alive = phase_total(part, phase);
             }
             ++phase;
+            if (!alive) break;
             if (threadIdx.x == 0) {
                 for (int f = 0; f < F; ++f) {
                     if (!s_inner[f]) continue;
@@ -400,9 +447,10 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                         part[F + f] += (double)rn * (double)rn;
                     }
                 }
-                phase_total(part, phase);
+                alive = phase_total(part, phase);
             }
             ++phase;
+            if (!alive) break;
             if (threadIdx.x == 0) {
                 int any = 0;
                 for (int f = 0; f < F; ++f) {
@@ -427,6 +475,9 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
         }
     }
 
+    // a timed-out barrier ends the solve: the last FP64 solution is the result
+    if (!alive && threadIdx.x == 0) s_flags |= P2M_FLAG_BREAKDOWN | P2M_FLAG_NOT_CONVERGED;
+    __syncthreads();
     // result: the FP64 solution rounded to T (0 for fields with b == 0)
     for (int k = k0; k < nn; k += kstride) {
 #pragma unroll
@@ -463,7 +514,10 @@ const void* cg_kernel(int F) {
 
 }  // namespace
 
-size_t cg_partials_bytes(int blocks) { return (size_t)2 * blocks * kSlots * sizeof(double); }
+// the partials, then the grid-barrier words
+size_t cg_partials_bytes(int blocks) {
+    return (size_t)2 * blocks * kSlots * sizeof(double) + kBarBytes;
+}
 
 template <typename T>
 int cg_max_blocks(int device) {
@@ -510,11 +564,18 @@ hipError_t launch_cg(const Mesh& m, int F, T* coef, T* b, const T* w, T* x, int 
     void* args[] = {&a};
     const void* fn = (m.dim == 1) ? cg_kernel<T, 1>(F) : cg_kernel<T, 2>(F);
     if (!fn) return hipErrorInvalidValue;
-    // a one-workgroup grid synchronises with the workgroup barrier only (it never
-    // reaches the grid barrier), so it takes an ordinary launch and none of the
-    // cooperative launch's queue overhead
-    if (ws.blocks == 1) return hipLaunchKernel(fn, dim3(1), dim3(kCgBlock), args, 0, stream);
-    return hipLaunchCooperativeKernel(fn, dim3(ws.blocks), dim3(kCgBlock), args, 0, stream);
+    // An ordinary launch: the stream has finished every earlier kernel, and the
+    // grid (at most the occupancy's blocks per compute unit, cg_max_blocks) is then
+    // resident as a whole.  The barrier is the kernel's own, with bounded waits; a
+    // cooperative launch added tens of microseconds of queue overhead per solve.
+    if (ws.blocks > 1) {
+        unsigned* bar =
+            (unsigned*)((char*)ws.partials + (size_t)2 * ws.blocks * kSlots * sizeof(double));
+        hipLaunchKernelGGL(k_bar_clear, dim3(1), dim3(256), 0, stream, bar);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipLaunchKernel(fn, dim3(ws.blocks), dim3(kCgBlock), args, 0, stream);
 }
 template hipError_t launch_cg<float>(const Mesh&, int, float*, float*, const float*, float*, int,
                                      const CgWorkspace&, const p2m_solve_opts&, p2m_report*,
