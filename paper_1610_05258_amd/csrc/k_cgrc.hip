@@ -24,7 +24,10 @@
 // y = D^-1 (r - alpha (w + beta s)) on the whole two-deep ring from its
 // neighbours' published (r, w, s) with the same FP32 operations the owners use,
 // then u on the tile and its one-deep ring, so every halo value is bit-identical
-// to its owner's.  Still one grid barrier per iteration.
+// to its owner's.  Still one grid barrier per iteration.  As in the Jacobi kernel,
+// each workgroup keeps the one-deep ring's copies of p and d (the owners' FP32
+// operations on the same values), so the correction of an inner solve is folded
+// into x inside the next residual phase, with no barrier of its own.
 #include "cg_common.hpp"
 
 namespace p2m {
@@ -37,6 +40,17 @@ constexpr int LH2 = RY + 2 * G2;
 constexpr int CW2 = RX + 2 * G2 - 1;     // coefficient region: [-G2, RX + G2 - 2] per axis
 constexpr int CH2 = RY + 2 * G2 - 1;
 constexpr int CN2 = CW2 * CH2;
+constexpr int NH1 = 2 * (RX + 2) + 2 * RY;   // one-deep ring slots of a full tile
+
+// the one-deep ring slot of local (lc, lr) in halo_slot's order, or -1
+__device__ __forceinline__ int ring1_index(int lc, int lr, int txa, int tya) {
+    const int row = txa + 2;
+    if (lr == -1 && lc >= -1 && lc <= txa) return lc + 1;
+    if (lr == tya && lc >= -1 && lc <= txa) return row + lc + 1;
+    if (lc == -1 && lr >= 0 && lr < tya) return 2 * row + lr;
+    if (lc == txa && lr >= 0 && lr < tya) return 2 * row + tya + lr;
+    return -1;
+}
 
 struct CArgs {
     Mesh m;
@@ -50,7 +64,7 @@ struct CArgs {
     float* pubW;
     float* pubS;
     float* pubC;
-    double* pubX;
+    double* pubX;      // [2][F][nn] published one-deep boundary of x64, by refinement parity
     RSync sy;
     int start;
     float c0, c1;      // the preconditioner polynomial
@@ -113,7 +127,7 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
     auto rs_x64 = [&](int f) { return mkrs(a.x64 + (size_t)f * nn, fb8); };
     auto rs_d = [&](int f) { return mkrs(a.xout + (size_t)f * nn, fb4); };
     auto rs_b = [&](int f) { return mkrs(a.b + (size_t)f * nn, fb4); };
-    auto rs_pubX = [&](int f) { return mkrs(a.pubX + (size_t)f * nn, fb8); };
+    auto rs_pubX = [&](int par, int f) { return mkrs(a.pubX + ((size_t)par * F + f) * nn, fb8); };
     auto rs_pub = [&](float* base, int par, int f) {
         return mkrs(base + ((size_t)par * F + f) * nn, fb4);
     };
@@ -129,11 +143,13 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
     float* lf = (float*)xbuf;
     double* ld64 = (double*)xbuf;
     float* lb = (float*)(ld64 + LH2 * LW2);
+    // the one-deep ring's copies of p (field f at f * NH1) and d (at (F + f) * NH1)
+    __shared__ float rpd[2 * F * NH1];
     __shared__ double red_lds[(RBS / 64) * kNV];
     __shared__ double vals[kNV];
     __shared__ double s_bb[F], s_gam[F], s_alpha[F], s_relres[F], s_target[F];
     __shared__ float s_af[F], s_bf[F];
-    __shared__ int s_iters[F], s_refines[F], s_done[F], s_inner[F], s_zero[F];
+    __shared__ int s_iters[F], s_refines[F], s_done[F], s_inner[F], s_zero[F], s_res[F];
     __shared__ uint32_t s_flags;
     __shared__ int s_any;
 
@@ -157,7 +173,7 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
     if (threadIdx.x < F) {
         const int f = threadIdx.x;
         s_iters[f] = 0; s_refines[f] = 0; s_done[f] = 0; s_inner[f] = 0; s_zero[f] = 0;
-        s_relres[f] = 0.0; s_bb[f] = 0.0;
+        s_res[f] = 0; s_relres[f] = 0.0; s_bb[f] = 0.0;
     }
     if (threadIdx.x == 0) s_flags = 0u;
 
@@ -278,7 +294,9 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
                     x0 = (double)px[f][j];
                 }
                 a.x64[o] = x0;
-                if (b1mask & (1u << j)) std8<kCoherent>(rs_pubX(f), k, x0);
+                // the start's one-deep boundary, read by the second residual phase
+                // (the first computes the ring's start itself)
+                if (b1mask & (1u << j)) std8<kCoherent>(rs_pubX(0, f), k, x0);
             }
             if (orphan && a.rep) {
                 atomicAdd(&a.rep->n_orphan, 1);
@@ -399,11 +417,15 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
     };
 
     for (int outer = 0; alive; ++outer) {
-        // ---- fold the correction into x64, publish the one-deep boundary x64 -----
+        // ---- fold (outer > 0): x64 += d, x rounded to FP32 stored as the result
+        //      (final if the next residual ends the field's solve, overwritten by a
+        //      later fold otherwise), the one-deep boundary of x published with the
+        //      parity of this refinement -------------------------------------------
+        const int pin = (outer + 1) & 1, pout = outer & 1;   // pubX parity read / written
 #pragma unroll
         for (int f = 0; f < F; ++f) {
             if (s_done[f] || outer == 0) continue;
-            const rsrc_t rx = rs_x64(f), rpx = rs_pubX(f);
+            const rsrc_t rx = rs_x64(f), ro = rs_d(f), rpx = rs_pubX(pout, f);
             double xo[RNPT];
 #pragma unroll
             for (int j = 0; j < RNPT; ++j) xo[j] = ldd<kPlain>(rx, (amask & (1u << j)) ? gk(j) : 0);
@@ -413,17 +435,19 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
                 const int kk = gk(j);
                 const double xv = xo[j] + (double)vd[f][j];
                 std8<kPlain>(rx, kk, xv);
+                stf<kPlain>(ro, kk, (float)xv);
                 if (b1mask & (1u << j)) std8<kCoherent>(rpx, kk, xv);
             }
 #pragma unroll
             for (int j = 0; j < RNPT; ++j) vd[f][j] = 0.f;
         }
-        __syncthreads();
-        alive = sync_reduce(a.sy, ++epoch, vals, 0, nblocks);
-        if (!alive) break;
 
-        // ---- R: r = b - M x64 in FP64 (one-deep ring); r_T = (float) r, published
-        //      on the two-deep bands --------------------------------------------------
+        // ---- R: r = b - M x in FP64 (one-deep ring) and r_T = (float) r, published
+        //      on the two-deep bands.  The ring's x is its owner's x of the previous
+        //      refinement (published with the other parity) plus the ring copy of
+        //      d, or (outer 0) the start computed from the inputs the owner computes
+        //      it from, so no barrier separates the fold (or the start) from the
+        //      residual. -------------------------------------------------------------
         {
             double pr[3 * F];
 #pragma unroll
@@ -431,13 +455,25 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
 #pragma unroll
             for (int f = 0; f < F; ++f) {
                 if (s_done[f]) continue;
-                const rsrc_t rx = rs_x64(f), rpx = rs_pubX(f), rb = rs_b(f);
+                const rsrc_t rx = rs_x64(f), rb = rs_b(f);
                 const rsrc_t rpr = rs_pub(a.pubR, ex, f), rpc = rs_col(ex);
+                // every load of the field is issued before the first LDS write or
+                // global store
                 int hq = -1;
                 double hx = 0.0;
                 if (has_r1) {
                     hq = lidx(r1c, r1r);
-                    hx = ldd<kCoherent>(rpx, gidx(m, i0, j0, r1c, r1r));
+                    const int gh = gidx(m, i0, j0, r1c, r1r);
+                    if (outer > 0) {
+                        hx = ldd<kCoherent>(rs_pubX(pin, f), gh) +
+                             (double)rpd[(F + f) * NH1 + threadIdx.x];
+                    } else if (a.start != P2M_START_ZERO) {
+                        const float wk = a.w[gh];
+                        const size_t o = (size_t)f * nn + gh;
+                        if (wk > 0.f)
+                            hx = a.start == P2M_START_FLIP ? (double)a.b[o] / (double)wk
+                                                           : (double)a.xout[o];
+                    }
                 }
                 double xo[RNPT];
                 float bo[RNPT];
@@ -489,6 +525,7 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
             for (int f = 0; f < F; ++f) {
                 if (s_done[f]) continue;
                 s_refines[f] += 1;
+                s_res[f] = outer > 0;
                 if (outer == 0) s_bb[f] = vals[2 * F + f];
                 const double bb = s_bb[f];
                 if (bb == 0.0) {
@@ -516,8 +553,17 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
         if (!s_any) break;
 
         // ---- CG start: y = D^-1 r (tile and two-deep ring), u = P r, w = M u,
-        //      delta = (w, u), gamma = (r, u); p = s = d = 0 ------------------------
+        //      delta = (w, u), gamma = (r, u); p = s = d = 0, and the ring copies of
+        //      p and d ------------------------------------------------------------
         uint32_t imask = inner_mask();
+        if (has_r1) {
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                if (!(imask & (1u << f))) continue;
+                rpd[f * NH1 + threadIdx.x] = 0.f;
+                rpd[(F + f) * NH1 + threadIdx.x] = 0.f;
+            }
+        }
         for (int h = threadIdx.x; h < nring2; h += RBS) {
             int lc, lr;
             if (!ring2_slot(h, txa, tya, lc, lr)) continue;
@@ -623,11 +669,21 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
                         so[f] = ldf<kCoherent>(rs_pub(a.pubS, ex, f), gh);
                     }
                 }
-                const float dh = dv[lidx(lc, lr)];
+                const int q = lidx(lc, lr);
+                const float dh = dv[q];
+                // a one-deep ring slot: its copies of p and d advance with the u it
+                // held (the planes hold u there until this overwrites it with y)
+                const int h1 = ring1_index(lc, lr, txa, tya);
 #pragma unroll
                 for (int f = 0; f < F; ++f) {
                     if (!(imask & (1u << f))) continue;
-                    lf[(size_t)f * LH2 * LW2 + lidx(lc, lr)] = halo_u(af[f], bf[f], dh, ro[f], wo[f], so[f]);
+                    float* L = lf + (size_t)f * LH2 * LW2;
+                    if (h1 >= 0) {
+                        const float pn = fmaf(bf[f], rpd[f * NH1 + h1], L[q]);
+                        rpd[f * NH1 + h1] = pn;
+                        rpd[(F + f) * NH1 + h1] = fmaf(af[f], pn, rpd[(F + f) * NH1 + h1]);
+                    }
+                    L[q] = halo_u(af[f], bf[f], dh, ro[f], wo[f], so[f]);
                 }
             }
             // local updates with the previous u (still in the planes), y = D^-1 r
@@ -707,18 +763,25 @@ __global__ __launch_bounds__(RBS) void k_cgrc(CArgs a) {
 
     if (!alive && threadIdx.x == 0) s_flags |= P2M_FLAG_BREAKDOWN | P2M_FLAG_NOT_CONVERGED;
     __syncthreads();
+    // result of the fields that no residual phase with outer > 0 ended (solved by
+    // the start, b == 0, or an aborted solve): the FP64 solution rounded to FP32, 0
+    // for fields with b == 0
     {
         float res[F][RNPT];
 #pragma unroll
-        for (int f = 0; f < F; ++f)
+        for (int f = 0; f < F; ++f) {
+            if (alive && s_res[f] && !s_zero[f]) continue;
 #pragma unroll
             for (int j = 0; j < RNPT; ++j)
                 if (amask & (1u << j)) res[f][j] = (float)ldd<kPlain>(rs_x64(f), gk(j));
+        }
 #pragma unroll
-        for (int f = 0; f < F; ++f)
+        for (int f = 0; f < F; ++f) {
+            if (alive && s_res[f] && !s_zero[f]) continue;
 #pragma unroll
             for (int j = 0; j < RNPT; ++j)
                 if (amask & (1u << j)) stf<kPlain>(rs_d(f), gk(j), s_zero[f] ? 0.f : res[f][j]);
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && a.rep) {
         for (int f = 0; f < F; ++f) {
@@ -804,14 +867,13 @@ hipError_t launch_cg_resident_cheb(const Mesh& m, int F, float* coef, float* b, 
     a.opts = opts;
     a.rep = rep;
     cgrc_coefficients(a.c0, a.c1);
-    // a carve-up that fits the Jacobi resident solve's workspace (cgr_workspace_bytes,
-    // which also holds that solve's residual array and second x exchange plane)
+    // the carve-up of the Jacobi resident solve's workspace (cgr_workspace_bytes)
     a.x64 = (double*)p; p += al((size_t)F * m.nn * sizeof(double));
     a.pubR = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubW = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubS = (float*)p; p += al((size_t)2 * F * m.nn * sizeof(float));
     a.pubC = (float*)p; p += al((size_t)2 * m.nn * rec_floats(F) * sizeof(float));
-    a.pubX = (double*)p; p += al((size_t)F * m.nn * sizeof(double));
+    a.pubX = (double*)p; p += al((size_t)2 * F * m.nn * sizeof(double));
     a.sy.ctr = (unsigned*)p; p += al((size_t)kGroups * 32 * sizeof(unsigned));
     a.sy.root = (unsigned*)p; p += al(32 * sizeof(unsigned));
     a.sy.rel = (unsigned*)p; p += al((size_t)kGroups * 32 * sizeof(unsigned));
