@@ -163,8 +163,15 @@ enum { P2M_SOLVER_AUTO = 0, P2M_SOLVER_STREAMING = 1, P2M_SOLVER_RESIDENT = 2, P
  *                      preceding workgroup's prefix (0: the default, 2^26); a
  *                      negative value ends every such wait at once, which
  *                      raises P2M_FLAG_BIN_TIMEOUT on any mesh of more than 2048
- *                      cells (for testing the timeout handling) */
-enum { P2M_OPT_SOLVER = 0, P2M_OPT_PLANS = 1, P2M_OPT_SCAN_SPIN = 2 };
+ *                      cells (for testing the timeout handling)
+ *   P2M_OPT_SOLVE_SPIN bound on the polls of a mass solve's grid-barrier wait
+ *                      (0: the default, 2^22); a negative value ends every such
+ *                      wait at once: a solve whose grid has more than one
+ *                      workgroup then stops at its first barrier with
+ *                      P2M_FLAG_BREAKDOWN | P2M_FLAG_NOT_CONVERGED and the last
+ *                      FP64 solution it held as the result (for testing the
+ *                      timeout handling; every kernel still runs to its end) */
+enum { P2M_OPT_SOLVER = 0, P2M_OPT_PLANS = 1, P2M_OPT_SCAN_SPIN = 2, P2M_OPT_SOLVE_SPIN = 3 };
 p2m_status p2m_set_option(void* ctx, int32_t option, int32_t value);
 
 /* Bytes of workspace that every call below needs for this problem and field count

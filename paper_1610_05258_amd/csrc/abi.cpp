@@ -53,6 +53,7 @@ struct Context {
     int solver_mode;        // P2M_SOLVER_*: AUTO or a forced solve kernel
     int use_plans;          // 1: apply tuned plans of the problem's shape class
     long scan_spin;         // bound of the binning scan's look-back wait (< 0: test hook)
+    long solve_spin;        // bound of a solve's grid-barrier wait (< 0: test hook)
     BatchCache* batch;      // created on the first batched call
     const float* learned;   // parameters of the learned start (device), or null
     PlanCache* plans;       // created on the first tuned or loaded plan
@@ -231,6 +232,7 @@ struct Prepared {
     hipStream_t stream;
     p2m_report* rep;
     long scan_spin;
+    long solve_spin;
     // the report still has to be zeroed: the first launch of the call does it
     // together with its own clearing work (one launch fewer per call)
     mutable bool clear_rep = false;
@@ -250,6 +252,7 @@ p2m_status prepare(void* ctx, const p2m_problem* prob, int F, void* ws, size_t w
     out.stream = (hipStream_t)stream;
     out.rep = rep ? rep : (p2m_report*)(out.ws + out.L.report);
     out.scan_spin = c->scan_spin;
+    out.solve_spin = c->solve_spin;
     return P2M_OK;
 }
 
@@ -318,7 +321,7 @@ p2m_status run_solve(const Context* c, const Prepared& pp, int F, T* b, const T*
     if (tiled && kind == P2M_SOLVER_RESIDENT_CHEB && cgrc_supported(pp.m, F, c->device)) {
         P2M_TRY(launch_cg_resident_cheb(pp.m, F, (float*)coef, (float*)b, (const float*)w,
                                         (float*)x, start, pp.ws + pp.L.resident, opts, pp.rep,
-                                        pp.clear_rep, pp.stream));
+                                        pp.clear_rep, pp.solve_spin, pp.stream));
         pp.clear_rep = false;
         return P2M_OK;
     }
@@ -327,7 +330,7 @@ p2m_status run_solve(const Context* c, const Prepared& pp, int F, T* b, const T*
         cgr_supported(pp.m, F, c->device)) {
         P2M_TRY(launch_cg_resident(pp.m, F, (float*)coef, (float*)b, (const float*)w, (float*)x,
                                    start, pp.ws + pp.L.resident, opts, pp.rep, pp.clear_rep,
-                                   pp.stream));
+                                   pp.solve_spin, pp.stream));
         pp.clear_rep = false;
         return P2M_OK;
     }
@@ -337,7 +340,8 @@ p2m_status run_solve(const Context* c, const Prepared& pp, int F, T* b, const T*
     }
     if (tiled && kind != P2M_SOLVER_STREAMING && cgt_grid(pp.m, F, ch.groups, c->device) > 0) {
         P2M_TRY(launch_cg_tiles(pp.m, F, (float*)coef, (float*)b, (const float*)w, (float*)x, start,
-                                pp.ws + pp.L.tiles, opts, pp.rep, ch.groups, c->device, pp.stream));
+                                pp.ws + pp.L.tiles, opts, pp.rep, ch.groups, c->device,
+                                pp.solve_spin, pp.stream));
         return P2M_OK;
     }
     CgWorkspace cw;
@@ -349,6 +353,7 @@ p2m_status run_solve(const Context* c, const Prepared& pp, int F, T* b, const T*
     cw.partials = (double*)(pp.ws + pp.L.partials);
     cw.dinv = pp.ws + pp.L.dinv;
     cw.blocks = cg_blocks_for(c, pp.m, sizeof(T) == 8 ? P2M_F64 : P2M_F32);
+    cw.spin = pp.solve_spin;
     P2M_TRY(launch_cg<T>(pp.m, F, coef, b, w, (T*)x, start, cw, opts, pp.rep, pp.stream));
     return P2M_OK;
 }
@@ -521,7 +526,7 @@ p2m_status plan_batch(const Context* c, const p2m_problem* probs, int nprob, int
 
 // The launch sequence of a batch on `stream` (captured into the batch graph).
 hipError_t enqueue_batch(const BatchPlan& P, char* ws, p2m_report* reps, const p2m_solve_opts& opts,
-                         long scan_spin, hipStream_t stream) {
+                         long scan_spin, long solve_spin, hipStream_t stream) {
     const BatchInst* inst = (const BatchInst*)ws;
     const int32_t* lmap = (const int32_t*)(ws + P.inst_b);
     const int32_t* amap = (const int32_t*)(ws + P.inst_b + P.lmap_b);
@@ -562,6 +567,7 @@ hipError_t enqueue_batch(const BatchPlan& P, char* ws, p2m_report* reps, const p
     bb.b = b;
     bb.w = w;
     bb.ws = ws + P.o_solve;
+    bb.spin = solve_spin;
     return launch_cg_batch(P.F, bb, (size_t)P.nn, P.grid, opts.start, opts, stream);
 }
 
@@ -642,6 +648,7 @@ p2m_status x1d_begin(void* ctx, const p2m_problem* prob, int F, void* ws, size_t
     pp.stream = (hipStream_t)stream;
     pp.rep = rep ? rep : (p2m_report*)(pp.ws + X.report);
     pp.scan_spin = c->scan_spin;
+    pp.solve_spin = c->solve_spin;
     pp.clear_rep = true;
     int32_t* perm = (int32_t*)(pp.ws + X.perm);
     int32_t* cs = (int32_t*)(pp.ws + X.cell_start);
@@ -666,6 +673,7 @@ CgWorkspace x1d_cg_ws(const Prepared& pp, const X1DLayout& X, const Context* c, 
     cw.partials = (double*)(pp.ws + X.part);
     cw.dinv = pp.ws + X.dinv;
     cw.blocks = cg_blocks_for(c, ms, P2M_F64);
+    cw.spin = pp.solve_spin;
     return cw;
 }
 
@@ -719,6 +727,7 @@ p2m_status p2m_create(void** ctx, int device) {
     c->solver_mode = P2M_SOLVER_AUTO;
     c->use_plans = 1;
     c->scan_spin = kScanSpinDefault;
+    c->solve_spin = kSolveSpinDefault;
     c->scratch = scratch_address(device);
     if (c->cg_blocks_f32 <= 0 || c->cg_blocks_f64 <= 0) {
         free(c);
@@ -743,6 +752,10 @@ p2m_status p2m_set_option(void* ctx, int32_t option, int32_t value) {
     }
     if (option == P2M_OPT_SCAN_SPIN) {
         c->scan_spin = value == 0 ? kScanSpinDefault : (long)value;
+        return P2M_OK;
+    }
+    if (option == P2M_OPT_SOLVE_SPIN) {
+        c->solve_spin = value == 0 ? kSolveSpinDefault : (long)value;
         return P2M_OK;
     }
     return P2M_ERR_INVALID_ARG;
@@ -1272,6 +1285,7 @@ p2m_status p2m_mass_assign_batched(void* ctx, const p2m_problem* probs, int32_t 
     put(&ws, sizeof(ws));
     put(&reps, sizeof(reps));
     put(&c->scan_spin, sizeof(c->scan_spin));
+    put(&c->solve_spin, sizeof(c->solve_spin));
     if (!bc.exec || key != bc.key) {
         bc.release();
         // the instance table and tile maps go to the head of the workspace
@@ -1286,7 +1300,8 @@ p2m_status p2m_mass_assign_batched(void* ctx, const p2m_problem* probs, int32_t 
         P2M_TRY(hipMemcpyAsync(ws, u, bc.upload.size(), hipMemcpyHostToDevice, strm));
         P2M_TRY(hipStreamSynchronize(strm));
         P2M_TRY(hipStreamBeginCapture(bc.capture, hipStreamCaptureModeThreadLocal));
-        hipError_t e = enqueue_batch(P, (char*)ws, reps, *opts, c->scan_spin, bc.capture);
+        hipError_t e = enqueue_batch(P, (char*)ws, reps, *opts, c->scan_spin, c->solve_spin,
+                                     bc.capture);
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(bc.capture, &graph);
         if (e != hipSuccess || e2 != hipSuccess || !graph) {

@@ -20,7 +20,6 @@ constexpr int LW = RX + 2;        // LDS row stride including the halo ring
 constexpr int LH = RY + 2;
 constexpr int kGroups = 16;       // fan-in of the first barrier level
 constexpr int kNV = 3 * kMaxFields;
-constexpr long kSpinMax = 1L << 22;
 
 struct RSync {
     unsigned* ctr;    // [kGroups * 32] group arrival counters (128-byte apart)
@@ -29,6 +28,7 @@ struct RSync {
     unsigned* abort;  // set on a timed-out wait
     double* part;     // [2][nblocks][kNV] per-workgroup partials
     double* tot;      // [2][kNV] totals
+    long spin;        // polls before a wait gives up (kSolveSpinDefault; < 0: at once)
 };
 // device-coherent (L2-bypassing) accesses for data that crosses workgroups
 __device__ __forceinline__ void st_c(float* p, float v) {
@@ -220,7 +220,7 @@ __device__ __forceinline__ bool tree_wait(const RSync& s, unsigned epoch) {
     long spins = 0;
     const unsigned* rel = s.rel + (blockIdx.x % kGroups) * 32;
     while (ld_c(rel) < epoch) {
-        if (ld_c(s.abort) != 0u || ++spins > kSpinMax) {
+        if (ld_c(s.abort) != 0u || ++spins > s.spin) {
             __hip_atomic_store(s.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }

@@ -32,8 +32,9 @@ constexpr int kSlots = 3 * kMaxFields;  // partial slots per block and phase
 constexpr int kBarWords = 2 * kGroups * 32 + 2 * 32;
 constexpr size_t kBarBytes = (size_t)kBarWords * sizeof(unsigned);
 
-__device__ __forceinline__ RSync bar_of(unsigned* w) {
+__device__ __forceinline__ RSync bar_of(unsigned* w, long spin) {
     RSync s;
+    s.spin = spin;
     s.ctr = w;
     s.root = w + kGroups * 32;
     s.rel = w + kGroups * 32 + 32;
@@ -85,6 +86,7 @@ struct CgArgs {
     T* dinv;           // [nn] inverse of the regularised diagonal (written here)
     const T* w;        // [nn] FLIP volumes (orphans: w == 0)
     int start;         // P2M_START_FLIP / ZERO / USER (xout holds the user start)
+    long spin;         // polls before a grid-barrier wait gives up (< 0: at once)
     p2m_solve_opts opts;
     p2m_report* rep;
 };
@@ -213,7 +215,8 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
     const int nn = m.nn;
     const int nblocks = gridDim.x;
     const RSync bar =
-        bar_of((unsigned*)((char*)a.partials + (size_t)2 * nblocks * kSlots * sizeof(double)));
+        bar_of((unsigned*)((char*)a.partials + (size_t)2 * nblocks * kSlots * sizeof(double)),
+               a.spin);
     unsigned epoch = 0;
     // a grid of one workgroup (small problems) synchronises with the workgroup
     // barrier, which also orders its global-memory accesses; the grid barrier's
@@ -559,6 +562,7 @@ hipError_t launch_cg(const Mesh& m, int F, T* coef, T* b, const T* w, T* x, int 
     a.q = (T*)ws.q;
     a.partials = ws.partials;
     a.dinv = (T*)ws.dinv;
+    a.spin = ws.spin;
     a.opts = opts;
     a.rep = rep;
     void* args[] = {&a};

@@ -917,7 +917,7 @@ int cgt_grid(const Mesh& m, int F, int groups, int device) {
 
 hipError_t launch_cg_tiles(const Mesh& m, int F, float* coef, float* b, const float* w, float* x,
                            int start, void* ws, const p2m_solve_opts& opts, p2m_report* rep,
-                           int groups, int device, hipStream_t stream) {
+                           int groups, int device, long spin, hipStream_t stream) {
     const int nt = single_tiles(m);
     const int G = cgt_grid(m, F, groups, device);
     if (G < 1) return hipErrorInvalidValue;
@@ -948,6 +948,7 @@ hipError_t launch_cg_tiles(const Mesh& m, int F, float* coef, float* b, const fl
     bb.b = b;
     bb.w = w;
     bb.ws = p;
+    bb.spin = spin;
     return launch_cg_batch(F, bb, (size_t)m.nn, G, start, opts, stream);
 }
 
@@ -988,6 +989,7 @@ hipError_t launch_cg_batch(int F, const BatchSolveBufs& bb, size_t nodes, int gr
     a.sy.abort = (unsigned*)p; p += al(32 * sizeof(unsigned));
     a.sy.part = (double*)p; p += al((size_t)2 * bb.ntiles * kNV * sizeof(double));
     a.sy.tot = (double*)p;
+    a.sy.spin = bb.spin;
     hipLaunchKernelGGL(k_sync_clear_b, dim3(1), dim3(512), 0, stream, a.sy.ctr, a.sy.root,
                        a.sy.rel, a.sy.abort);
     hipError_t e = hipGetLastError();

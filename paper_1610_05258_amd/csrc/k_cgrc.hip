@@ -852,7 +852,7 @@ bool cgrc_supported(const Mesh& m, int F, int device) {
 
 hipError_t launch_cg_resident_cheb(const Mesh& m, int F, float* coef, float* b, const float* w,
                                    float* x, int start, void* ws, const p2m_solve_opts& opts,
-                                   p2m_report* rep, bool clear_rep, hipStream_t stream) {
+                                   p2m_report* rep, bool clear_rep, long spin, hipStream_t stream) {
     auto al = [](size_t v) { return (v + kAlign - 1) / kAlign * kAlign; };
     const int blocks = cgr_tiles(m);
     char* p = (char*)ws;
@@ -880,6 +880,7 @@ hipError_t launch_cg_resident_cheb(const Mesh& m, int F, float* coef, float* b, 
     a.sy.abort = (unsigned*)p; p += al(32 * sizeof(unsigned));
     a.sy.part = (double*)p; p += al((size_t)2 * blocks * kNV * sizeof(double));
     a.sy.tot = (double*)p;
+    a.sy.spin = spin;
     hipLaunchKernelGGL(k_sync_clear_c, dim3(1), dim3(kGroups * 32), 0, stream, a.sy.ctr, a.sy.root,
                        a.sy.rel, a.sy.abort, clear_rep ? rep : (p2m_report*)nullptr);
     hipError_t e = hipGetLastError();

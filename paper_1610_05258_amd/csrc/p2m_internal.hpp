@@ -110,6 +110,7 @@ hipError_t launch_locate_count(const Mesh& m, Particles<T> P, int32_t* key, int3
 // up raises P2M_FLAG_BIN_TIMEOUT in reps[0..nrep) and sets an abort word in
 // scan_ws that the place kernels read
 constexpr long kScanSpinDefault = 1L << 26;
+constexpr long kSolveSpinDefault = 1L << 22;   // polls of a solve's grid-barrier wait
 size_t scan_workspace_bytes(int n);
 hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, void* scan_ws,
                                  long spin_max, p2m_report* reps, int nrep, hipStream_t stream);
@@ -183,11 +184,12 @@ struct CgWorkspace {
     double* partials; // [2][blocks][3*kMaxFields]
     void* dinv;       // [nn] T, inverse of the regularised diagonal
     int blocks;       // grid size of the persistent kernel
+    long spin = kSolveSpinDefault;   // bound of a grid-barrier wait (< 0: every wait ends at once)
 };
 size_t cg_partials_bytes(int blocks);
-// One persistent cooperative kernel: orphan regularisation of (coef, b) in
-// place, the start vector (FLIP b/w, zero, or the values in x), then the solve;
-// x receives the result.
+// One persistent kernel with its own grid barrier: orphan regularisation of
+// (coef, b) in place, the start vector (FLIP b/w, zero, or the values in x), then
+// the solve; x receives the result.
 template <typename T>
 hipError_t launch_cg(const Mesh& m, int F, T* coef, T* b, const T* w, T* x, int start,
                      const CgWorkspace& ws, const p2m_solve_opts& opts, p2m_report* rep,
@@ -204,14 +206,14 @@ bool cgr_supported(const Mesh& m, int F, int device);
 // clear_rep: the report the kernel writes is zeroed first (by the counter clear)
 hipError_t launch_cg_resident(const Mesh& m, int F, float* coef, float* b, const float* w,
                               float* x, int start, void* ws, const p2m_solve_opts& opts,
-                              p2m_report* rep, bool clear_rep, hipStream_t stream);
+                              p2m_report* rep, bool clear_rep, long spin, hipStream_t stream);
 
 // the register-resident solve with the degree-2 Chebyshev polynomial preconditioner
 // (k_cgrc.hip): same workspace as the Jacobi one (cgr_workspace_bytes)
 bool cgrc_supported(const Mesh& m, int F, int device);
 hipError_t launch_cg_resident_cheb(const Mesh& m, int F, float* coef, float* b, const float* w,
                                    float* x, int start, void* ws, const p2m_solve_opts& opts,
-                                   p2m_report* rep, bool clear_rep, hipStream_t stream);
+                                   p2m_report* rep, bool clear_rep, long spin, hipStream_t stream);
 
 // ---------------------------------------------------------------------------
 // batches (k_bin.hip, k_assemble.hip, k_cgb.hip)
@@ -250,6 +252,7 @@ struct BatchSolveBufs {
     float* b;              // [F][nn] at F*no
     const float* w;        // [nn] at no
     void* ws;              // cgb_workspace_bytes of scratch
+    long spin = kSolveSpinDefault;   // bound of a grid-barrier wait (< 0: every wait ends at once)
 };
 int cgb_grid(int F, int ntiles, int device);   // 0: does not fit
 size_t cgb_workspace_bytes(int F, int nprob, int ntiles, size_t nodes);
@@ -262,7 +265,7 @@ size_t cgt_workspace_bytes(const Mesh& m, int F);
 int cgt_grid(const Mesh& m, int F, int groups, int device);   // 0: not available
 hipError_t launch_cg_tiles(const Mesh& m, int F, float* coef, float* b, const float* w, float* x,
                            int start, void* ws, const p2m_solve_opts& opts, p2m_report* rep,
-                           int groups, int device, hipStream_t stream);
+                           int groups, int device, long spin, hipStream_t stream);
 
 // learned warm start (k_learn.hip); X rows are BF16 [.][160]
 hipError_t launch_learn_features(const Mesh& m, Particles<float> P, const float* values, int F,
