@@ -363,21 +363,44 @@ __global__ __launch_bounds__(kBlock) void k_scan_lookback(const int32_t* __restr
 // Every located particle goes to its slot cell_start[key] + rank.  With
 // fill_tail, slots [valid, np) (after every valid particle) are set to -1.
 // When the scan has aborted (abort word set), the binning is discarded instead:
-// cell_start[0..ncells] = 0 and perm[0..np) = -1, so every cell is empty.  The
-// grid covers max(np, ncells + 1) threads.
+// cell_start[0..ncells] = 0 and perm[0..np) = -1, so every cell is empty.  A
+// thread takes kPlaceItems indices, blockDim apart; the grid covers max(np,
+// ncells + 1) indices.  Its loads (the abort word, the valid count, keys and
+// ranks) go out together, then its cell_start gathers: two round trips per wave.
+constexpr int kPlaceItems = 4;
+
 __global__ void k_place(int np, const int32_t* __restrict__ key, const int32_t* __restrict__ rank,
                         int32_t* __restrict__ cell_start, int32_t* __restrict__ perm, int ncells,
                         int fill_tail, const unsigned* __restrict__ abort_word) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (__hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-        if (i < np) perm[i] = -1;
-        if (i <= ncells) cell_start[i] = 0;
+    const int i0 = blockIdx.x * blockDim.x * kPlaceItems + threadIdx.x;
+    const unsigned ab = __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int valid = fill_tail ? cell_start[ncells] : np;
+    int k[kPlaceItems], r[kPlaceItems];
+#pragma unroll
+    for (int u = 0; u < kPlaceItems; ++u) {
+        const int i = i0 + u * (int)blockDim.x;
+        k[u] = i < np ? key[i] : -1;
+        r[u] = i < np ? rank[i] : 0;
+    }
+    if (ab != 0u) {
+#pragma unroll
+        for (int u = 0; u < kPlaceItems; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            if (i < np) perm[i] = -1;
+            if (i <= ncells) cell_start[i] = 0;
+        }
         return;
     }
-    if (i >= np) return;
-    if (fill_tail && i >= cell_start[ncells]) perm[i] = -1;
-    const int k = key[i];
-    if (k >= 0) perm[cell_start[k] + rank[i]] = i;
+    int st[kPlaceItems];
+#pragma unroll
+    for (int u = 0; u < kPlaceItems; ++u) st[u] = k[u] >= 0 ? cell_start[k[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < kPlaceItems; ++u) {
+        const int i = i0 + u * (int)blockDim.x;
+        if (i >= np) continue;
+        if (i >= valid) perm[i] = -1;
+        if (k[u] >= 0) perm[st[u] + r[u]] = i;
+    }
 }
 
 // Every cell's slots sorted by original index.  A workgroup owns kBlock
@@ -610,9 +633,9 @@ hipError_t launch_exclusive_scan(const int32_t* counts, int32_t* out, int n, voi
 hipError_t launch_place(const Mesh& m, const int32_t* key, const int32_t* rank, int32_t* cell_start,
                         int32_t* perm, const void* scan_ws, hipStream_t stream) {
     if (m.np == 0) return hipSuccess;
-    const int nthreads = m.np > m.nn + 1 ? m.np : m.nn + 1;
-    hipLaunchKernelGGL(k_place, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, stream, m.np,
-                       key, rank, cell_start, perm, m.nn, 1, scan_ctr((void*)scan_ws, m.nn) + 1);
+    const int nidx = m.np > m.nn + 1 ? m.np : m.nn + 1;
+    hipLaunchKernelGGL(k_place, dim3(grid_for(nidx, kBlock * kPlaceItems)), dim3(kBlock), 0, stream,
+                       m.np, key, rank, cell_start, perm, m.nn, 1, scan_ctr((void*)scan_ws, m.nn) + 1);
     return hipGetLastError();
 }
 
@@ -636,9 +659,9 @@ hipError_t launch_place_flat(int np, int ncells, const int32_t* key, const int32
                              int32_t* cell_start, int32_t* perm, const void* scan_ws,
                              hipStream_t stream) {
     if (np == 0) return hipSuccess;
-    const int nthreads = np > ncells + 1 ? np : ncells + 1;
-    hipLaunchKernelGGL(k_place, dim3(grid_for(nthreads, kBlock)), dim3(kBlock), 0, stream, np, key,
-                       rank, cell_start, perm, ncells, 0, scan_ctr((void*)scan_ws, ncells) + 1);
+    const int nidx = np > ncells + 1 ? np : ncells + 1;
+    hipLaunchKernelGGL(k_place, dim3(grid_for(nidx, kBlock * kPlaceItems)), dim3(kBlock), 0, stream,
+                       np, key, rank, cell_start, perm, ncells, 0, scan_ctr((void*)scan_ws, ncells) + 1);
     return hipGetLastError();
 }
 
