@@ -451,7 +451,7 @@ def learned_leg(B, ctx, reps=5, tol=1e-6):
     res["workload"] = ("taylor-green 1024x1024, 8 ppc, random phase/amplitude, 200 RK2 disorder steps, "
                        f"held-out seed 20000, F=3, tol={tol:g}")
     res["learned_over_flip_time"] = res["learned"]["ms"] / res["flip"]["ms"]
-    res["verdict"] = ("the learned start saves no iteration over FLIP and costs its inference: slower"
+    res["outcome"] = ("the learned start saves no iteration over FLIP and costs its inference: slower"
                       if res["learned"]["ms"] > res["flip"]["ms"] else "the learned start is faster than FLIP")
     log(f"bench: learned start {res['learned']['ms']:.3f} ms {res['learned']['iters']} vs FLIP "
         f"{res['flip']['ms']:.3f} ms {res['flip']['iters']} vs zero {res['zero']['ms']:.3f} ms")
