@@ -67,10 +67,15 @@ enum {
     P2M_FLAG_RANGE = 1u << 3,            /* some position outside [0, L + h) */
     P2M_FLAG_NONFINITE = 1u << 4,        /* some position is NaN or infinite */
     P2M_FLAG_LEARNED_FALLBACK = 1u << 5, /* learned start was worse than FLIP and was replaced */
-    P2M_FLAG_BIN_TIMEOUT = 1u << 6       /* the binning scan's bounded wait for another workgroup
+    P2M_FLAG_BIN_TIMEOUT = 1u << 6,      /* the binning scan's bounded wait for another workgroup
                                             ended: the binning is discarded (every cell empty:
                                             cell_start all 0, perm all -1), so P2M results are 0
                                             (orphans) and M2P is unaffected; retry the call */
+    P2M_FLAG_TRIANGULATION = 1u << 7     /* p2m_x2d_*: the particle triangulation is incomplete
+                                            (a Voronoi cell not closed within the search radius,
+                                            more than P2M_X2D_MAXDEG neighbours, two particles at
+                                            one position, or neighbour lists that disagree); the
+                                            values that depend on it are NaN */
 };
 
 typedef enum { P2M_F32 = 0, P2M_F64 = 1 } p2m_dtype;
@@ -308,6 +313,68 @@ p2m_status p2m_x1d_interpolate(void* ctx, const p2m_problem* prob, int32_t kind,
 /* The particle volumes of eq. (4), vol_out [np] in caller order (NaN: not located). */
 p2m_status p2m_x1d_volumes(void* ctx, const p2m_problem* prob, void* vol_out, p2m_report* rep,
                            void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Paper-exact 2D assignment (Table 1 with the particle hats of Sec. 3.2: P1 hats
+ * on the periodic Delaunay triangulation of the particles; the Appendix-B rule
+ * for every overlap integral).  FP64 2D problems only (dtype P2M_F64, dim 2;
+ * prob->vol is ignored: the particle volumes are v_mu = int psi_mu, a third of the
+ * area of the triangles around mu).  Positions must be distinct.
+ *
+ * The triangulation is built on the device: every particle clips its Voronoi cell
+ * against the particles of the surrounding cells of the mesh, ring by ring, until
+ * no particle outside the searched rings can cut it (twice the farthest Voronoi
+ * vertex is within the searched radius; at most 8 rings); its Delaunay neighbours
+ * are the particles whose bisectors bound the cell, counter-clockwise.  Each
+ * triangle must then appear in the lists of its three vertices.
+ *   delta P2M      Abar_i = A(r_i): the particle interpolant of eq. (1) at the node,
+ *                  found by a walk through the triangulation from the nearest
+ *                  particle (eq. (9)).
+ *   FLIP / PIC     eqs. (11)-(12) / eq. (11) with the volumes above.
+ *   mass P2M       m Abar = b, b_j = int A psi_j by the Appendix-B rule on the mesh
+ *                  triangles (A at the vertices and edge midpoints, the quadratic
+ *                  through them integrated exactly against psi_j); m the
+ *                  consistent mesh mass matrix (hx hy / 2 on the diagonal, hx hy /
+ *                  12 to the six neighbours of the "/" split); mass-delta and full
+ *                  mass P2M of Table 1.
+ *   lumped P2M     b_i / (hx hy) (eq. (17)).
+ *   delta M2P      the mesh interpolant at the particle (eq. (10)).
+ *   mass M2P       m_part Abarbar = c, c_nu = int Abar psi_nu by the Appendix-B
+ *                  rule on the particle triangles, m_part the consistent particle
+ *                  mass matrix (|T|/6 on the diagonal, |T|/12 off it, summed over
+ *                  the triangles), eq. (20) (full mass).
+ *   lumped M2P     c_nu / v_nu (eq. (17)).
+ * Mass systems are solved by the FP64 streaming CG to opts->tol (NULL: 1e-14).
+ * Kinds are those of p2m_x1d_kind; the quadrature is always the Appendix-B rule.
+ * Each call synchronises `stream` once, after binning.  Particles that cannot be
+ * located are left out (P2M) and get NaN (M2P). rep (device) is required.
+ * --------------------------------------------------------------------------- */
+#define P2M_X2D_MAXDEG 32
+
+/* Workspace bytes of the calls below for this problem and field count. */
+p2m_status p2m_x2d_workspace_size(void* ctx, const p2m_problem* prob, int32_t nfields,
+                                  size_t* bytes);
+/* The triangulation, in caller particle numbers: deg_out [np] (0: not located or
+ * failed), nbr_out [np][P2M_X2D_MAXDEG] the neighbours counter-clockwise (-1 past
+ * deg), shift_out [np][P2M_X2D_MAXDEG] the image of each neighbour, packed as
+ * (sx + 128) | (sy + 128) << 8: neighbour j of mu sits at
+ * (x_nbr + sx lx, y_nbr + sy ly).  Consecutive neighbours j, j+1 (cyclic) span
+ * the counter-clockwise triangle (mu, nbr_j, nbr_j+1). */
+p2m_status p2m_x2d_triangulation(void* ctx, const p2m_problem* prob, int32_t* deg_out,
+                                 int32_t* nbr_out, int32_t* shift_out, p2m_report* rep, void* ws,
+                                 size_t ws_bytes, void* stream);
+/* The particle volumes int psi_mu, vol_out [np] in caller order (NaN: not located). */
+p2m_status p2m_x2d_volumes(void* ctx, const p2m_problem* prob, void* vol_out, p2m_report* rep,
+                           void* ws, size_t ws_bytes, void* stream);
+/* Particle -> mesh (kind DELTA, FLIP, PIC, MASS or LUMPED): nodal_out [F][nx ny]. */
+p2m_status p2m_x2d_assign(void* ctx, const p2m_problem* prob, int32_t kind, const void* values,
+                          int32_t nfields, const p2m_solve_opts* opts, void* nodal_out,
+                          p2m_report* rep, void* ws, size_t ws_bytes, void* stream);
+/* Mesh -> particle (kind DELTA, MASS or LUMPED): values_out [F][np] in caller order. */
+p2m_status p2m_x2d_interpolate(void* ctx, const p2m_problem* prob, int32_t kind,
+                               const void* nodal, int32_t nfields, const p2m_solve_opts* opts,
+                               void* values_out, p2m_report* rep, void* ws, size_t ws_bytes,
+                               void* stream);
 
 /* ---------------------------------------------------------------------------
  * Particle fluid solver: the Taylor-Green vortex sheet computation of Sec. 3.3

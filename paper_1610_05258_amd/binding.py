@@ -30,6 +30,7 @@ FLAG_RANGE = 1 << 3
 FLAG_NONFINITE = 1 << 4
 FLAG_LEARNED_FALLBACK = 1 << 5
 FLAG_BIN_TIMEOUT = 1 << 6
+FLAG_TRIANGULATION = 1 << 7
 REPORT_BYTES = 144
 MAX_FIELDS = 8
 SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT, SOLVER_TILES, SOLVER_RESIDENT_CHEB = 0, 1, 2, 3, 4
@@ -43,9 +44,12 @@ EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size
            "p2m_plan_get", "p2m_plan_get_batched",
            "p2m_plan_save", "p2m_plan_load", "p2m_plan_clear", "p2m_mass_assign_noalloc",
            "p2m_x1d_workspace_size", "p2m_x1d_assign", "p2m_x1d_interpolate", "p2m_x1d_volumes",
+           "p2m_x2d_workspace_size", "p2m_x2d_triangulation", "p2m_x2d_volumes", "p2m_x2d_assign",
+           "p2m_x2d_interpolate",
            "p2m_ns_workspace_size", "p2m_ns_step")
 QUAD_EXACT, QUAD_APPB = 0, 1
 X1D_DELTA, X1D_FLIP, X1D_PIC, X1D_MASS, X1D_LUMPED = 0, 1, 2, 3, 4
+X2D_MAXDEG = 32
 NS_FLIP, NS_MASS = 0, 1
 ERR_SCRATCH = 7
 SCRATCH_BYTES = 64 << 20
@@ -116,6 +120,13 @@ def lib():
         L.p2m_x1d_interpolate.argtypes = [vp, pprob, i32, i32, vp, i32, ctypes.POINTER(CSolveOpts), vp,
                                           vp, vp, sz, vp]
         L.p2m_x1d_volumes.argtypes = [vp, pprob, vp, vp, vp, sz, vp]
+        L.p2m_x2d_workspace_size.argtypes = [vp, pprob, i32, ctypes.POINTER(sz)]
+        L.p2m_x2d_triangulation.argtypes = [vp, pprob, vp, vp, vp, vp, vp, sz, vp]
+        L.p2m_x2d_volumes.argtypes = [vp, pprob, vp, vp, vp, sz, vp]
+        L.p2m_x2d_assign.argtypes = [vp, pprob, i32, vp, i32, ctypes.POINTER(CSolveOpts), vp, vp, vp,
+                                     sz, vp]
+        L.p2m_x2d_interpolate.argtypes = [vp, pprob, i32, vp, i32, ctypes.POINTER(CSolveOpts), vp, vp,
+                                          vp, sz, vp]
         L.p2m_ns_workspace_size.argtypes = [vp, pprob, ctypes.POINTER(sz)]
         L.p2m_ns_step.argtypes = [vp, pprob, i32, ctypes.c_double, ctypes.c_double,
                                   ctypes.POINTER(CSolveOpts), vp, vp, vp, vp, vp, vp, sz, vp]
@@ -510,6 +521,84 @@ def p2m_x1d_volumes(ctx: Context, prob: Particles, stream=None, ws=None, rep=Non
                                  ctypes.c_void_p(rep.data_ptr()), wp, wn, _stream_ptr(stream)),
            "p2m_x1d_volumes")
     return out
+
+
+def x2d_workspace_size(ctx, prob, F):
+    n = ctypes.c_size_t()
+    cp = prob.cstruct()
+    _check(lib().p2m_x2d_workspace_size(ctx.handle, ctypes.byref(cp), int(F), ctypes.byref(n)),
+           "p2m_x2d_workspace_size")
+    return int(n.value)
+
+
+def _x2d_ws(ctx, prob, F, ws):
+    if ws is None:
+        ws = ctx.workspace(x2d_workspace_size(ctx, prob, F))
+    return ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel())
+
+
+def p2m_x2d_triangulation(ctx: Context, prob: Particles, stream=None, ws=None, rep=None):
+    """Periodic Delaunay triangulation of the particles: (deg [np], nbr [np, X2D_MAXDEG],
+    shift [np, X2D_MAXDEG] packed (sx + 128) | (sy + 128) << 8, report tensor), int32."""
+    cp = prob.cstruct()
+    dev = prob.x.device
+    deg = torch.empty(prob.n_particles, dtype=torch.int32, device=dev)
+    nbr = torch.empty((prob.n_particles, X2D_MAXDEG), dtype=torch.int32, device=dev)
+    sh = torch.empty((prob.n_particles, X2D_MAXDEG), dtype=torch.int32, device=dev)
+    rep = ctx.new_report() if rep is None else rep
+    wp, wn = _x2d_ws(ctx, prob, 1, ws)
+    _check(lib().p2m_x2d_triangulation(ctx.handle, ctypes.byref(cp), ctypes.c_void_p(deg.data_ptr()),
+                                       ctypes.c_void_p(nbr.data_ptr()), ctypes.c_void_p(sh.data_ptr()),
+                                       ctypes.c_void_p(rep.data_ptr()), wp, wn, _stream_ptr(stream)),
+           "p2m_x2d_triangulation")
+    return deg, nbr, sh, rep
+
+
+def p2m_x2d_volumes(ctx: Context, prob: Particles, stream=None, ws=None, rep=None):
+    """Particle volumes int psi_mu on the particle triangulation, caller order (FP64)."""
+    cp = prob.cstruct()
+    out = torch.empty(prob.n_particles, dtype=torch.float64, device=prob.x.device)
+    rep = ctx.new_report() if rep is None else rep
+    wp, wn = _x2d_ws(ctx, prob, 1, ws)
+    _check(lib().p2m_x2d_volumes(ctx.handle, ctypes.byref(cp), ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(rep.data_ptr()), wp, wn, _stream_ptr(stream)),
+           "p2m_x2d_volumes")
+    return out, rep
+
+
+def p2m_x2d_assign(ctx: Context, prob: Particles, kind: int, values, opts=None, stream=None,
+                   ws=None, rep=None, out=None):
+    """Paper-exact 2D particle->mesh of kind X1D_* (the same kinds): (nodal [F, nn] FP64,
+    report tensor)."""
+    values, F = _values_tensor(values, prob)
+    cp = prob.cstruct()
+    if out is None:
+        out = torch.empty((F, prob.n_nodes), dtype=torch.float64, device=prob.x.device)
+    rep = ctx.new_report() if rep is None else rep
+    wp, wn = _x2d_ws(ctx, prob, F, ws)
+    _check(lib().p2m_x2d_assign(ctx.handle, ctypes.byref(cp), int(kind),
+                                ctypes.c_void_p(values.data_ptr()), F, _opts_ptr(opts),
+                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(rep.data_ptr()),
+                                wp, wn, _stream_ptr(stream)), "p2m_x2d_assign")
+    return out, rep
+
+
+def p2m_x2d_interpolate(ctx: Context, prob: Particles, kind: int, nodal, opts=None, stream=None,
+                        ws=None, rep=None, out=None):
+    """Paper-exact 2D mesh->particle of kind X1D_DELTA / X1D_MASS / X1D_LUMPED:
+    (values [F, np] FP64 in caller order, report tensor)."""
+    nodal = nodal.contiguous()
+    F = int(nodal.shape[0])
+    cp = prob.cstruct()
+    if out is None:
+        out = torch.empty((F, prob.n_particles), dtype=torch.float64, device=prob.x.device)
+    rep = ctx.new_report() if rep is None else rep
+    wp, wn = _x2d_ws(ctx, prob, F, ws)
+    _check(lib().p2m_x2d_interpolate(ctx.handle, ctypes.byref(cp), int(kind),
+                                     ctypes.c_void_p(nodal.data_ptr()), F, _opts_ptr(opts),
+                                     ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(rep.data_ptr()),
+                                     wp, wn, _stream_ptr(stream)), "p2m_x2d_interpolate")
+    return out, rep
 
 
 def ns_workspace_size(ctx: Context, prob: Particles) -> int:

@@ -692,6 +692,140 @@ p2m_solve_opts x1d_opts(const p2m_solve_opts* o, int n) {
     return r;
 }
 
+// ---------------------------------------------------------------------------
+// paper-exact 2D (k_x2d.hip)
+// ---------------------------------------------------------------------------
+struct X2DLayout {
+    size_t key, counts, scan, cell_start, perm;          // binning (as in Layout)
+    size_t xs, ys, cell, As, deg, nbr, nsh, vol, volc, H, b, bw, coef, ecol, w, x;
+    size_t r, p0, p1, q, x64, dinv, part, report, total;
+    int blocks;
+};
+
+X2DLayout make_x2d_layout(const Context* c, const Mesh& m, int F) {
+    X2DLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const size_t np = (size_t)m.np, n = (size_t)m.nn, K = np > n ? np : n, d8 = sizeof(double);
+    const size_t cap = P2M_X2D_MAXDEG, i4 = sizeof(int32_t);
+    Mesh mk = m;
+    mk.nn = (int)K;
+    L.blocks = cg_blocks_for(c, mk, P2M_F64);
+    L.key = take(2 * np * i4);
+    L.counts = take(n * i4);
+    L.scan = take(scan_workspace_bytes((int)n));   // right after counts: one fill clears both
+    L.cell_start = take((n + 1) * i4);
+    L.perm = take(np * i4);
+    L.xs = take(np * d8);
+    L.ys = take(np * d8);
+    L.cell = take(np * i4);
+    L.As = take((size_t)F * np * d8);
+    L.deg = take(np * i4);
+    L.nbr = take(np * cap * i4);
+    L.nsh = take(np * cap * i4);
+    L.vol = take(np * d8);
+    L.volc = take(np * d8);
+    L.H = take((size_t)F * 4 * n * d8);
+    L.b = take((size_t)F * K * d8);
+    L.bw = take(n * d8);
+    const size_t cm = 4 * n > (1 + cap) * np ? 4 * n : (1 + cap) * np;
+    L.coef = take(cm * d8);
+    L.ecol = take(cap * np * i4);
+    L.w = take(K * d8);
+    L.x = take((size_t)F * K * d8);
+    L.r = take((size_t)F * K * d8);
+    L.p0 = take((size_t)F * K * d8);
+    L.p1 = take((size_t)F * K * d8);
+    L.q = take((size_t)F * K * d8);
+    L.x64 = take((size_t)2 * F * K * d8);
+    L.dinv = take(K * d8);
+    L.part = take(cg_partials_bytes(L.blocks));
+    L.report = take(sizeof(p2m_report));
+    L.total = off;
+    return L;
+}
+
+p2m_status x2d_check(void* ctx, const p2m_problem* prob, int F, Mesh& m) {
+    if (!ctx || F < 1 || F > kMaxFields) return P2M_ERR_INVALID_ARG;
+    p2m_status s = check_problem(prob, m);
+    if (s != P2M_OK) return s;
+    if (m.dim != 2 || prob->dtype != P2M_F64) return P2M_ERR_UNSUPPORTED;
+    return P2M_OK;
+}
+
+// Validation, layout, binning, the located count N (one stream synchronisation)
+// and the triangulation; values (may be null) are gathered into binned order.
+p2m_status x2d_begin(void* ctx, const p2m_problem* prob, int F, const void* values, void* ws,
+                     size_t ws_bytes, void* stream, p2m_report* rep, Prepared& pp, X2DLayout& X,
+                     X2dArgs& A) {
+    Mesh m;
+    p2m_status s = x2d_check(ctx, prob, F, m);
+    if (s != P2M_OK) return s;
+    const Context* c = (const Context*)ctx;
+    X = make_x2d_layout(c, m, F);
+    if (!ws || ws_bytes < X.total || ((uintptr_t)ws) % kAlign) return P2M_ERR_WORKSPACE;
+    pp.m = m;
+    memset(&pp.L, 0, sizeof(pp.L));
+    pp.L.key = X.key;
+    pp.L.counts = X.counts;
+    pp.L.scan = X.scan;
+    pp.L.cell_start = X.cell_start;
+    pp.L.perm = X.perm;
+    pp.ws = (char*)ws;
+    pp.stream = (hipStream_t)stream;
+    pp.rep = rep ? rep : (p2m_report*)(pp.ws + X.report);
+    pp.scan_spin = c->scan_spin;
+    pp.solve_spin = c->solve_spin;
+    pp.clear_rep = true;
+    int32_t* perm = (int32_t*)(pp.ws + X.perm);
+    int32_t* cs = (int32_t*)(pp.ws + X.cell_start);
+    s = run_bin<double>(pp, prob, perm, cs);
+    if (s != P2M_OK) return s;
+    int32_t located = 0;
+    P2M_TRY(hipMemcpyAsync(&located, cs + m.nn, sizeof(int32_t), hipMemcpyDeviceToHost, pp.stream));
+    P2M_TRY(hipStreamSynchronize(pp.stream));
+    char* w8 = pp.ws;
+    A.m = m;
+    A.N = located;
+    A.F = F;
+    A.lx = prob->lx;
+    A.ly = prob->ly;
+    A.perm = perm;
+    A.cs = cs;
+    A.x = (const double*)prob->x;
+    A.y = (const double*)prob->y;
+    A.values = (const double*)values;
+    A.xs = (double*)(w8 + X.xs);
+    A.ys = (double*)(w8 + X.ys);
+    A.cell = (int32_t*)(w8 + X.cell);
+    A.As = (double*)(w8 + X.As);
+    A.deg = (int32_t*)(w8 + X.deg);
+    A.nbr = (int32_t*)(w8 + X.nbr);
+    A.nsh = (int32_t*)(w8 + X.nsh);
+    A.vol = (double*)(w8 + X.vol);
+    A.rep = pp.rep;
+    P2M_TRY(x2d_triangulate(A, pp.stream));
+    return P2M_OK;
+}
+
+CgWorkspace x2d_cg_ws(const Prepared& pp, const X2DLayout& X, const Context* c, const Mesh& ms) {
+    CgWorkspace cw;
+    cw.r = pp.ws + X.r;
+    cw.p0 = pp.ws + X.p0;
+    cw.p1 = pp.ws + X.p1;
+    cw.q = pp.ws + X.q;
+    cw.x64 = (double*)(pp.ws + X.x64);
+    cw.partials = (double*)(pp.ws + X.part);
+    cw.dinv = pp.ws + X.dinv;
+    cw.blocks = cg_blocks_for(c, ms, P2M_F64);
+    cw.spin = pp.solve_spin;
+    return cw;
+}
+
 
 }  // namespace
 
@@ -1195,6 +1329,162 @@ p2m_status p2m_x1d_volumes(void* ctx, const p2m_problem* prob, void* vol_out, p2
     P2M_TRY(x1d_setup(N, L, (const double*)(w8 + X.skey), (const int32_t*)(w8 + X.sidx), nullptr, 0,
                       pp.m.np, (double*)(w8 + X.gap), (double*)(w8 + X.vols), (double*)vol_out,
                       nullptr, pp.stream));
+    return P2M_OK;
+}
+
+p2m_status p2m_x2d_workspace_size(void* ctx, const p2m_problem* prob, int32_t nfields,
+                                  size_t* bytes) {
+    if (!bytes) return P2M_ERR_INVALID_ARG;
+    Mesh m;
+    p2m_status s = x2d_check(ctx, prob, nfields, m);
+    if (s != P2M_OK) return s;
+    *bytes = make_x2d_layout((const Context*)ctx, m, nfields).total;
+    return P2M_OK;
+}
+
+p2m_status p2m_x2d_triangulation(void* ctx, const p2m_problem* prob, int32_t* deg_out,
+                                 int32_t* nbr_out, int32_t* shift_out, p2m_report* rep, void* ws,
+                                 size_t ws_bytes, void* stream) {
+    if (!ctx || !rep || !deg_out || !nbr_out || !shift_out) return P2M_ERR_INVALID_ARG;
+    const Context* c = (const Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    Prepared pp;
+    X2DLayout X;
+    X2dArgs A;
+    p2m_status s = x2d_begin(ctx, prob, 1, nullptr, ws, ws_bytes, stream, rep, pp, X, A);
+    if (s != P2M_OK) return s;
+    P2M_TRY(x2d_export(A, deg_out, nbr_out, shift_out, pp.stream));
+    return P2M_OK;
+}
+
+p2m_status p2m_x2d_volumes(void* ctx, const p2m_problem* prob, void* vol_out, p2m_report* rep,
+                           void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !rep || !vol_out) return P2M_ERR_INVALID_ARG;
+    const Context* c = (const Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    Prepared pp;
+    X2DLayout X;
+    X2dArgs A;
+    p2m_status s = x2d_begin(ctx, prob, 1, nullptr, ws, ws_bytes, stream, rep, pp, X, A);
+    if (s != P2M_OK) return s;
+    P2M_TRY(x1d_scatter(A.N, 1, pp.m.np, A.perm, A.vol, (double*)vol_out, pp.stream));
+    return P2M_OK;
+}
+
+p2m_status p2m_x2d_assign(void* ctx, const p2m_problem* prob, int32_t kind, const void* values,
+                          int32_t nfields, const p2m_solve_opts* opts, void* nodal_out,
+                          p2m_report* rep, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !rep || !nodal_out) return P2M_ERR_INVALID_ARG;
+    if (kind < P2M_X1D_DELTA || kind > P2M_X1D_LUMPED) return P2M_ERR_INVALID_ARG;
+    if (opts && kind == P2M_X1D_MASS) {
+        p2m_status so = check_opts(opts);
+        if (so != P2M_OK) return so;
+    }
+    if (!prob || (prob->np > 0 && !values)) return P2M_ERR_INVALID_ARG;
+    const Context* c = (const Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    Prepared pp;
+    X2DLayout X;
+    X2dArgs A;
+    p2m_status s = x2d_begin(ctx, prob, nfields, values, ws, ws_bytes, stream, rep, pp, X, A);
+    if (s != P2M_OK) return s;
+    const Mesh& m = pp.m;
+    const int F = nfields;
+    char* w8 = pp.ws;
+    double* out = (double*)nodal_out;
+    if (kind == P2M_X1D_FLIP || kind == P2M_X1D_PIC) {
+        double* volc = (double*)(w8 + X.volc);
+        P2M_TRY(x1d_scatter(A.N, 1, m.np, A.perm, A.vol, volc, pp.stream));
+        Particles<double> P = particles_of<double>(prob);
+        P.vol = volc;
+        double* b = (double*)(w8 + X.b);
+        double* bw = (double*)(w8 + X.bw);
+        P2M_TRY(launch_assemble<double>(m, P, (const double*)values, F, A.perm, A.cs, b, bw,
+                                        nullptr, pp.stream));
+        P2M_TRY(launch_finalize<double>(m, F, b, bw, kind == P2M_X1D_PIC ? 1 : 0, out, pp.rep,
+                                        pp.stream));
+        return P2M_OK;
+    }
+    if (kind == P2M_X1D_DELTA) {
+        P2M_TRY(x2d_locate(A, false, out, pp.stream));
+        return P2M_OK;
+    }
+    double* H = (double*)(w8 + X.H);
+    double* b = (double*)(w8 + X.b);
+    P2M_TRY(x2d_locate(A, true, H, pp.stream));
+    P2M_TRY(x2d_rhs_mesh(A, H, b, pp.stream));
+    if (kind == P2M_X1D_LUMPED) {
+        P2M_TRY(x1d_div(m.nn, F, b, nullptr, m.cell_measure, out, pp.stream));
+        return P2M_OK;
+    }
+    double* coef = (double*)(w8 + X.coef);
+    double* wv = (double*)(w8 + X.w);
+    P2M_TRY(x2d_mass_mesh(A, coef, wv, pp.stream));
+    const p2m_solve_opts o = x1d_opts(opts, m.nn);
+    P2M_TRY(launch_cg<double>(m, F, coef, b, wv, out, P2M_START_FLIP, x2d_cg_ws(pp, X, c, m), o,
+                              pp.rep, pp.stream));
+    return P2M_OK;
+}
+
+p2m_status p2m_x2d_interpolate(void* ctx, const p2m_problem* prob, int32_t kind,
+                               const void* nodal, int32_t nfields, const p2m_solve_opts* opts,
+                               void* values_out, p2m_report* rep, void* ws, size_t ws_bytes,
+                               void* stream) {
+    if (!ctx || !rep || !nodal || !values_out) return P2M_ERR_INVALID_ARG;
+    if (kind != P2M_X1D_DELTA && kind != P2M_X1D_MASS && kind != P2M_X1D_LUMPED)
+        return P2M_ERR_INVALID_ARG;
+    if (opts && kind == P2M_X1D_MASS) {
+        p2m_status so = check_opts(opts);
+        if (so != P2M_OK) return so;
+    }
+    const Context* c = (const Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    if (kind == P2M_X1D_DELTA) {   // the mesh interpolant at the particles: no triangulation
+        Mesh m;
+        p2m_status s = x2d_check(ctx, prob, nfields, m);
+        if (s != P2M_OK) return s;
+        P2M_TRY(launch_report_clear(rep, (hipStream_t)stream));
+        P2M_TRY(launch_gather<double>(m, particles_of<double>(prob), (const double*)nodal,
+                                      nfields, (double*)values_out, rep, (hipStream_t)stream));
+        return P2M_OK;
+    }
+    Prepared pp;
+    X2DLayout X;
+    X2dArgs A;
+    p2m_status s = x2d_begin(ctx, prob, nfields, nullptr, ws, ws_bytes, stream, rep, pp, X, A);
+    if (s != P2M_OK) return s;
+    const Mesh& m = pp.m;
+    const int F = nfields, N = A.N;
+    char* w8 = pp.ws;
+    double* cvec = (double*)(w8 + X.b);
+    double* xs = (double*)(w8 + X.x);
+    P2M_TRY(x2d_rhs_part(A, (const double*)nodal, cvec, pp.stream));
+    if (kind == P2M_X1D_LUMPED) {
+        P2M_TRY(x1d_div(N, F, cvec, A.vol, 0.0, xs, pp.stream));
+    } else if (N > 0) {
+        double* coef = (double*)(w8 + X.coef);
+        int32_t* ecol = (int32_t*)(w8 + X.ecol);
+        P2M_TRY(x2d_mass_part(A, coef, ecol, pp.stream));
+        Mesh mp;
+        memset(&mp, 0, sizeof(mp));
+        mp.dim = 3;
+        mp.nx = N;
+        mp.ny = 1;
+        mp.nn = N;
+        mp.inv_hx = mp.inv_hy = 1.0;
+        mp.cell_measure = 1.0;
+        CgWorkspace cw = x2d_cg_ws(pp, X, c, mp);
+        cw.ell_col = ecol;
+        cw.ell_w = P2M_X2D_MAXDEG;
+        const p2m_solve_opts o = x1d_opts(opts, N);
+        P2M_TRY(launch_cg<double>(mp, F, coef, cvec, A.vol, xs, P2M_START_FLIP, cw, o, pp.rep,
+                                  pp.stream));
+    }
+    P2M_TRY(x1d_scatter(N, F, m.np, A.perm, xs, (double*)values_out, pp.stream));
     return P2M_OK;
 }
 

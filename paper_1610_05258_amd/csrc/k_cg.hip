@@ -17,7 +17,12 @@
 // with the breakdown flag.
 //
 // Stencil storage (symmetric, periodic): D_k = M(k,k), E_k = M(k,k+x),
-// N_k = M(k,k+y), NE_k = M(k,k+x+y) in 2D; D_k, E_k = M(k,k+1) in 1D.
+// N_k = M(k,k+y), NE_k = M(k,k+x+y) in 2D; D_k, E_k = M(k,k+1) in 1D.  The third
+// form (an irregular sparse matrix, the particle mass matrix of a triangulation)
+// keeps D_k and then every row's off-diagonal entries in up to `ew` slots, slot j
+// of row k at [nn + j nn + k] with its column in ecol[j nn + k] (-1 ends the row).
+#include <type_traits>
+
 #include "cg_common.hpp"
 
 namespace p2m {
@@ -87,6 +92,8 @@ struct CgArgs {
     const T* w;        // [nn] FLIP volumes (orphans: w == 0)
     int start;         // P2M_START_FLIP / ZERO / USER (xout holds the user start)
     long spin;         // polls before a grid-barrier wait gives up (< 0: at once)
+    const int32_t* ecol;  // columns of the sparse-row form ([ew][nn]), else unused
+    int ew;               // slots per row of that form
     p2m_solve_opts opts;
     p2m_report* rep;
 };
@@ -100,6 +107,10 @@ template <int DIM>
 __device__ __forceinline__ Nbr neighbours(const Mesh& m, int k) {
     Nbr n;
     n.k = k;
+    if (DIM == 3) {
+        n.xp = n.xm = n.yp = n.ym = n.pp = n.mm = k;
+        return n;
+    }
     if (DIM == 1) {
         n.xp = (k + 1 == m.nx) ? 0 : k + 1;
         n.xm = (k == 0) ? m.nx - 1 : k - 1;
@@ -128,6 +139,10 @@ template <typename T, int DIM>
 __device__ __forceinline__ Row<T> load_row(const T* __restrict__ coef, int nn, const Nbr& n) {
     Row<T> r;
     r.d = coef[n.k];
+    if (DIM == 3) {
+        r.e = r.ew = r.n = r.ns = r.ne = r.nesw = (T)0;
+        return r;
+    }
     r.e = coef[(size_t)nn + n.k];
     r.ew = coef[(size_t)nn + n.xm];
     if (DIM == 2) {
@@ -143,7 +158,18 @@ __device__ __forceinline__ Row<T> load_row(const T* __restrict__ coef, int nn, c
 
 // (M v)_k for a vector given by an accessor v(idx), in arithmetic type A
 template <int DIM, typename A, typename T, typename V>
-__device__ __forceinline__ A apply_row(const Row<T>& c, const Nbr& n, V&& v) {
+__device__ __forceinline__ A apply_row(const Row<T>& c, const Nbr& n, V&& v,
+                                       const T* __restrict__ coef, const int32_t* __restrict__ ecol,
+                                       int nn, int ew) {
+    if (DIM == 3) {
+        A s = (A)c.d * v(n.k);
+        for (int j = 0; j < ew; ++j) {
+            const int col = ecol[(size_t)j * nn + n.k];
+            if (col < 0) break;
+            s += (A)coef[(size_t)(j + 1) * nn + n.k] * v(col);
+        }
+        return s;
+    }
     A s = (A)c.d * v(n.k) + (A)c.e * v(n.xp) + (A)c.ew * v(n.xm);
     if (DIM == 2)
         s += (A)c.n * v(n.yp) + (A)c.ns * v(n.ym) + (A)c.ne * v(n.pp) + (A)c.nesw * v(n.mm);
@@ -332,7 +358,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                     auto y = [&](int idx) -> double {
                         return fold ? xf[idx] + (double)df[idx] : xf[idx];
                     };
-                    const double mx = apply_row<DIM, double>(c, n, y);
+                    const double mx = apply_row<DIM, double>(c, n, y, a.coef, a.ecol, nn, a.ew);
                     const double bk = (double)a.b[(size_t)f * nn + k];
                     const double r64 = bk - mx;
                     const T rt = (T)r64;
@@ -405,7 +431,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs<T> a) {
                             return first ? u : u + beta * pf[idx];
                         };
                         const T pk = pv(n.k);
-                        const T qk = apply_row<DIM, T>(c, n, pv);
+                        const T qk = apply_row<DIM, T>(c, n, pv, a.coef, a.ecol, nn, a.ew);
                         p_new[(size_t)f * nn + k] = pk;
                         a.q[(size_t)f * nn + k] = qk;
                         part[f] += (double)pk * (double)qk;
@@ -515,6 +541,17 @@ const void* cg_kernel(int F) {
     return nullptr;
 }
 
+// the sparse-row form is used by the FP64 solves only
+template <typename T>
+const void* cg_kernel_for(int dim, int F) {
+    if (dim == 1) return cg_kernel<T, 1>(F);
+    if (dim == 2) return cg_kernel<T, 2>(F);
+    if constexpr (std::is_same<T, double>::value) {
+        if (dim == 3) return cg_kernel<T, 3>(F);
+    }
+    return nullptr;
+}
+
 }  // namespace
 
 // the partials, then the grid-barrier words
@@ -529,9 +566,10 @@ int cg_max_blocks(int device) {
         return 0;
     int per = 1 << 30;
     for (int F = 1; F <= kMaxFields; ++F) {
-        for (int dim = 1; dim <= 2; ++dim) {
+        for (int dim = 1; dim <= 3; ++dim) {
             int b = 0;
-            const void* fn = dim == 1 ? cg_kernel<T, 1>(F) : cg_kernel<T, 2>(F);
+            const void* fn = cg_kernel_for<T>(dim, F);
+            if (!fn) continue;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, kCgBlock, 0) != hipSuccess)
                 return 0;
             if (b < per) per = b;
@@ -563,11 +601,13 @@ hipError_t launch_cg(const Mesh& m, int F, T* coef, T* b, const T* w, T* x, int 
     a.partials = ws.partials;
     a.dinv = (T*)ws.dinv;
     a.spin = ws.spin;
+    a.ecol = ws.ell_col;
+    a.ew = ws.ell_w;
     a.opts = opts;
     a.rep = rep;
     void* args[] = {&a};
-    const void* fn = (m.dim == 1) ? cg_kernel<T, 1>(F) : cg_kernel<T, 2>(F);
-    if (!fn) return hipErrorInvalidValue;
+    const void* fn = cg_kernel_for<T>(m.dim, F);
+    if (!fn || (m.dim == 3 && !ws.ell_col)) return hipErrorInvalidValue;
     // An ordinary launch: the stream has finished every earlier kernel, and the
     // grid (at most the occupancy's blocks per compute unit, cg_max_blocks) is then
     // resident as a whole.  The barrier is the kernel's own, with bounded waits; a

@@ -174,6 +174,38 @@ hipError_t x1d_div(int K, int F, const double* c, const double* d, double s, dou
 hipError_t x1d_scatter(int N, int F, int np, const int32_t* idx, const double* xs, double* out,
                        hipStream_t stream);
 
+// paper-exact 2D (k_x2d.hip); slot k = position in the binned order, N located
+struct X2dArgs {
+    Mesh m;
+    int N, F;
+    double lx, ly;
+    const int32_t* perm;   // [np] binned order
+    const int32_t* cs;     // [nn + 1] cell starts
+    const double* x;
+    const double* y;
+    const double* values;  // [F][np] or null
+    double* xs;            // [N] wrapped positions
+    double* ys;
+    int32_t* cell;         // [N]
+    double* As;            // [F][N] values in binned order
+    int32_t* deg;          // [N]
+    int32_t* nbr;          // [N][P2M_X2D_MAXDEG] neighbour slots, counter-clockwise
+    int32_t* nsh;          // [N][P2M_X2D_MAXDEG] packed image shifts
+    double* vol;           // [N] int psi_mu
+    p2m_report* rep;
+};
+hipError_t x2d_triangulate(const X2dArgs& a, hipStream_t stream);
+hipError_t x2d_export(const X2dArgs& a, int32_t* deg_out, int32_t* nbr_out, int32_t* sh_out,
+                      hipStream_t stream);
+// particle interpolant at the nodes (half = false: out [F][nn]) or on the
+// half-spacing grid (half = true: out [F][2ny][2nx])
+hipError_t x2d_locate(const X2dArgs& a, bool half, double* out, hipStream_t stream);
+hipError_t x2d_rhs_mesh(const X2dArgs& a, const double* H, double* b, hipStream_t stream);
+hipError_t x2d_nodes(const X2dArgs& a, const double* H, double* out, hipStream_t stream);
+hipError_t x2d_mass_mesh(const X2dArgs& a, double* coef, double* w, hipStream_t stream);
+hipError_t x2d_rhs_part(const X2dArgs& a, const double* nodal, double* c, hipStream_t stream);
+hipError_t x2d_mass_part(const X2dArgs& a, double* coef, int32_t* ecol, hipStream_t stream);
+
 // mass solve
 struct CgWorkspace {
     void* r;          // [F][nn] T
@@ -185,6 +217,8 @@ struct CgWorkspace {
     void* dinv;       // [nn] T, inverse of the regularised diagonal
     int blocks;       // grid size of the persistent kernel
     long spin = kSolveSpinDefault;   // bound of a grid-barrier wait (< 0: every wait ends at once)
+    const int32_t* ell_col = nullptr;  // sparse-row matrix (Mesh::dim == 3): columns [ell_w][nn]
+    int ell_w = 0;
 };
 size_t cg_partials_bytes(int blocks);
 // One persistent kernel with its own grid barrier: orphan regularisation of

@@ -1,0 +1,203 @@
+"""The paper-exact 2D methods on the GPU (Sec. 3.2: P1 hats on the periodic Delaunay
+triangulation of the particles; Appendix B in 2D; Sec. 2.4 eq. (20)) against the FP64
+oracle `oracle/paper2d.py`.
+
+* the triangulation: the set of triangles (particle numbers and image shifts, named
+  canonically) is identical to the oracle's, every triangle appears in the lists of
+  its three vertices, and no flag is raised;
+* the volumes int psi_mu, and every operator: delta, FLIP, PIC, mass and lumped P2M;
+  delta, full-mass and lumped M2P, per field at relative l2 <= 1e-12, except the mass
+  solves: their FP64 CG stops at ||r|| / ||b|| <= 1e-14, and the error is at most
+  kappa(m) times that (kappa(m_part) is 10 to 160 on these inputs), so 1e-11;
+* cases: rectangular cells, a 3 x 3 mesh whose search rings wrap onto the particles'
+  own images, one particle per cell, eight per cell, a non-square box, and a
+  96 x 96 mesh (36,864 particles: many workgroups and a ragged last one);
+* edge cases: a particle outside the box (flagged, left out, NaN in M2P), two particles
+  at one position (the triangulation flag), and no particles at all."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import paper2d as p2
+from paper_1610_05258_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1610_05258_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(B):
+    return B.Context(0)
+
+
+CASES = {
+    "rect_cells": (6, 6, 2, 1.0, 0.75, 5),
+    "tiny_3x3": (3, 3, 3, 2.0, 1.0, 1),
+    "one_per_cell": (12, 12, 1, 1.0, 1.0, 2),
+    "eight_per_cell": (16, 16, 8, 1.0, 1.0, 3),
+    "box_20x12": (20, 12, 4, 2 * np.pi, 1.3, 4),
+    "mesh_96": (96, 96, 4, 1.0, 1.0, 6),
+}
+
+
+def problem(B, name):
+    nx, ny, ppc, lx, ly, seed = CASES[name]
+    x, y = wl.stratified_2d(seed, nx, ny, ppc, lx, ly)
+    d = B.Particles(dim=2, nx=nx, ny=ny, lx=lx, ly=ly,
+                    x=torch.tensor(x, dtype=torch.float64, device="cuda"),
+                    y=torch.tensor(y, dtype=torch.float64, device="cuda"))
+    return x, y, d
+
+
+_ORACLE = {}
+
+
+def oracle_of(name, x, y):
+    if name not in _ORACLE:
+        nx, ny, ppc, lx, ly, seed = CASES[name]
+        _ORACLE[name] = p2.Paper2D(x, y, nx, ny, lx, ly)
+    return _ORACLE[name]
+
+
+def rel_l2(a, b):
+    a = np.atleast_2d(a)
+    b = np.atleast_2d(b)
+    return max(np.linalg.norm(a[f] - b[f]) / max(np.linalg.norm(b[f]), 1e-300)
+               for f in range(b.shape[0]))
+
+
+def triangles_of(deg, nbr, sh):
+    """Canonical names of the triangles (mu, n_j, n_j+1) of every list, and how often
+    each appears (three times in a consistent triangulation)."""
+    count = {}
+    for mu in range(deg.size):
+        d = int(deg[mu])
+        for j in range(d):
+            a, b = nbr[mu, j], nbr[mu, (j + 1) % d]
+            sa, sb = sh[mu, j], sh[mu, (j + 1) % d]
+            ids = np.array([mu, a, b])
+            s = np.array([[0, 0],
+                          [(sa & 255) - 128, ((sa >> 8) & 255) - 128],
+                          [(sb & 255) - 128, ((sb >> 8) & 255) - 128]])
+            key = p2._canonical(ids, s)
+            count[key] = count.get(key, 0) + 1
+    return count
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_triangulation_matches_oracle(B, ctx, name):
+    say(f"[x2d] triangulation {name}")
+    x, y, d = problem(B, name)
+    deg, nbr, sh, rep = B.p2m_x2d_triangulation(ctx, d)
+    r = B.read_report(rep, 1)
+    assert r.flags == 0, r.flags
+    count = triangles_of(deg.cpu().numpy(), nbr.cpu().numpy(), sh.cpu().numpy())
+    assert all(c == 3 for c in count.values())
+    P = oracle_of(name, x, y)
+    ref = {p2._canonical(P.tri[t], P.sh[t]) for t in range(P.tri.shape[0])}
+    assert set(count) == ref
+    vol, rep = B.p2m_x2d_volumes(ctx, d)
+    np.testing.assert_allclose(vol.cpu().numpy(), P.vol, rtol=1e-12)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_assign_kinds(B, ctx, name):
+    x, y, d = problem(B, name)
+    P = oracle_of(name, x, y)
+    g = np.random.Generator(np.random.PCG64(7))
+    A = np.stack([np.sin(2 * np.pi * x / CASES[name][3]) + 0.1 * g.standard_normal(x.size),
+                  g.standard_normal(x.size)])
+    v = torch.tensor(A, device="cuda")
+    ref = {B.X1D_DELTA: P.p2m_delta(A), B.X1D_FLIP: P.p2m_flip(A), B.X1D_PIC: P.p2m_pic(A),
+           B.X1D_MASS: P.p2m_mass(A), B.X1D_LUMPED: P.p2m_lumped(A)}
+    for kind, want in ref.items():
+        say(f"[x2d] assign {name} kind {kind}")
+        out, rep = B.p2m_x2d_assign(ctx, d, kind, v)
+        r = B.read_report(rep, 2)
+        assert r.flags == 0, (kind, r.flags)
+        bar = 1e-11 if kind == B.X1D_MASS else 1e-12
+        assert rel_l2(out.cpu().numpy(), want) <= bar, (kind, rel_l2(out.cpu().numpy(), want))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_interpolate_kinds(B, ctx, name):
+    x, y, d = problem(B, name)
+    P = oracle_of(name, x, y)
+    nx, ny = CASES[name][0], CASES[name][1]
+    g = np.random.Generator(np.random.PCG64(8))
+    gx, gy = P.node_xy()
+    nodal = np.stack([np.cos(2 * np.pi * gy / CASES[name][4]) + 0.1 * g.standard_normal(nx * ny),
+                      g.standard_normal(nx * ny)])
+    nod = torch.tensor(nodal, device="cuda")
+    ref = {B.X1D_DELTA: P.m2p_delta(nodal), B.X1D_MASS: P.m2p_mass(nodal),
+           B.X1D_LUMPED: P.m2p_lumped(nodal)}
+    for kind, want in ref.items():
+        say(f"[x2d] interpolate {name} kind {kind}")
+        out, rep = B.p2m_x2d_interpolate(ctx, d, kind, nod)
+        r = B.read_report(rep, 2)
+        assert r.flags == 0, (kind, r.flags)
+        bar = 1e-11 if kind == B.X1D_MASS else 1e-12
+        assert rel_l2(out.cpu().numpy(), want) <= bar, (kind, rel_l2(out.cpu().numpy(), want))
+
+
+def test_out_of_range_particle_left_out(B, ctx):
+    say("[x2d] out-of-range particle")
+    nx = ny = 8
+    x, y = wl.stratified_2d(9, nx, ny, 3, 1.0, 1.0)
+    xb = np.concatenate([x, [1.7]])
+    yb = np.concatenate([y, [0.5]])
+    d = B.Particles(dim=2, nx=nx, ny=ny, lx=1.0, ly=1.0,
+                    x=torch.tensor(xb, device="cuda"), y=torch.tensor(yb, device="cuda"))
+    P = p2.Paper2D(x, y, nx, ny, 1.0, 1.0)
+    A = np.random.Generator(np.random.PCG64(10)).standard_normal(x.size + 1)
+    out, rep = B.p2m_x2d_assign(ctx, d, B.X1D_MASS, torch.tensor(A[None], device="cuda"))
+    r = B.read_report(rep, 1)
+    assert r.flags & B.FLAG_RANGE and not r.flags & B.FLAG_TRIANGULATION
+    assert rel_l2(out.cpu().numpy(), P.p2m_mass(A[None, :-1])) <= 1e-11
+    nodal = np.random.Generator(np.random.PCG64(11)).standard_normal((1, nx * ny))
+    out, rep = B.p2m_x2d_interpolate(ctx, d, B.X1D_MASS, torch.tensor(nodal, device="cuda"))
+    o = out.cpu().numpy()[0]
+    assert np.isnan(o[-1])
+    assert rel_l2(o[:-1], P.m2p_mass(nodal)) <= 1e-11
+
+
+def test_duplicate_position_flagged(B, ctx):
+    say("[x2d] duplicate position")
+    nx = ny = 6
+    x, y = wl.stratified_2d(12, nx, ny, 2, 1.0, 1.0)
+    x = np.concatenate([x, x[:1]])
+    y = np.concatenate([y, y[:1]])
+    d = B.Particles(dim=2, nx=nx, ny=ny, lx=1.0, ly=1.0,
+                    x=torch.tensor(x, device="cuda"), y=torch.tensor(y, device="cuda"))
+    deg, nbr, sh, rep = B.p2m_x2d_triangulation(ctx, d)
+    r = B.read_report(rep, 1)
+    assert r.flags & B.FLAG_TRIANGULATION
+    assert int(deg[0]) == 0 and int(deg[-1]) == 0
+
+
+def test_no_particles(B, ctx):
+    say("[x2d] no particles")
+    d = B.Particles(dim=2, nx=4, ny=4, lx=1.0, ly=1.0,
+                    x=torch.zeros(0, dtype=torch.float64, device="cuda"),
+                    y=torch.zeros(0, dtype=torch.float64, device="cuda"))
+    out, rep = B.p2m_x2d_assign(ctx, d, B.X1D_DELTA, torch.zeros((1, 0), dtype=torch.float64,
+                                                                  device="cuda"))
+    r = B.read_report(rep, 1)
+    assert r.flags & B.FLAG_TRIANGULATION
+    assert torch.isnan(out).all()
