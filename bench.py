@@ -523,6 +523,96 @@ def plain_vs_combined_leg(B, ctx, prob, vals, reps=5, tol=1e-6):
     return res
 
 
+def exact2d_leg(B, ctx, n=90, ppc=1, steps=100, big_n=512, big_ppc=4, calls=5):
+    """Paper-exact 2D (Sec. 3.2: P1 hats on the periodic Delaunay triangulation of the
+    particles; Appendix-B rule; eq. (20)).
+
+    (1) The slotted-disk rotation at the paper's resolution: a 90 x 90 mesh (the paper's
+    H / box ratio), one particle per cell (stratified, seed 1), one revolution in 100
+    steps (the paper's dt = tau / 100).  Each step rotates the particles exactly (FP64,
+    host), then runs P2M and M2P of one Table 1 method on the GPU; the particles carry
+    the M2P values.  E1, E2 and L2 after the revolution (the Sec. 3.1 measures with the
+    Delaunay volumes), and the event-timed milliseconds per step.
+    (2) Throughput at 512 x 512, four particles per cell (1,048,576 particles): the
+    triangulation alone and the full-mass round trip (mass P2M, then mass M2P)."""
+    import math
+    import torch
+    from paper_1610_05258_amd import workloads as wl
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def dev(a):
+        return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+    x0, y0 = wl.stratified_2d(1, n, n, ppc, 1.0, 1.0)
+    a0 = wl.zalesak_disk(x0, y0)
+    pairs = dict(delta=(B.X1D_DELTA, B.X1D_DELTA), flip=(B.X1D_FLIP, B.X1D_DELTA),
+                 mass_delta=(B.X1D_MASS, B.X1D_DELTA), full_mass=(B.X1D_MASS, B.X1D_MASS))
+    d0 = B.Particles(dim=2, nx=n, ny=n, lx=1.0, ly=1.0, x=dev(x0), y=dev(y0))
+    v0 = B.p2m_x2d_volumes(ctx, d0)[0].cpu().numpy()
+    out = dict(workload=f"slotted disk, {n}x{n} P1 mesh on [0,1)^2, {ppc} stratified particle per cell "
+                        f"(seed 1), one revolution in {steps} steps, FP64")
+    for name, (kp, km) in pairs.items():
+        x, y = x0.copy(), y0.copy()
+        vals = dev(a0[None])
+        flags = 0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ms = 0.0
+        for _ in range(steps):
+            x, y = wl.zalesak_rotate(x, y, 2.0 * math.pi / steps)
+            d = B.Particles(dim=2, nx=n, ny=n, lx=1.0, ly=1.0, x=dev(x), y=dev(y))
+            torch.cuda.synchronize()
+            e0.record(stream)
+            nodal, rep = B.p2m_x2d_assign(ctx, d, kp, vals)
+            vals, rep2 = B.p2m_x2d_interpolate(ctx, d, km, nodal)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+            flags |= B.read_report(rep, 1).flags | B.read_report(rep2, 1).flags
+        vT = B.p2m_x2d_volumes(ctx, d)[0].cpu().numpy()
+        aT = vals.cpu().numpy()[0]
+        s1 = float(np.sum(v0 * a0))
+        s2 = float(np.sum(v0 * a0 * a0))
+        out[name] = dict(E1=(float(np.sum(vT * aT)) - s1) / s1,
+                         E2=(float(np.sum(vT * aT * aT)) - s2) / s2,
+                         L2=float(np.sqrt(np.sum(v0 * (aT - a0) ** 2) / s2)),
+                         ms_per_step=ms / steps, flags=flags)
+        log(f"bench: exact 2D {name}: E1 {out[name]['E1']:+.4f} E2 {out[name]['E2']:+.3f} "
+            f"L2 {out[name]['L2']:.3f}, {ms / steps:.3f} ms per step")
+    out["paper_table3"] = dict(delta=dict(E1=-0.005, E2=-0.29, L2=0.67),
+                               flip=dict(E1=0.0014, E2=-0.61, L2=0.67),
+                               mass_delta=dict(E2=-0.50, L2=0.61),
+                               full_mass=dict(E1=0.005, E2=-0.09, L2=0.30),
+                               note="the paper's 3x3 box and disk, particle count not stated: context")
+
+    xb, yb = wl.stratified_2d(7, big_n, big_n, big_ppc, 1.0, 1.0)
+    db = B.Particles(dim=2, nx=big_n, ny=big_n, lx=1.0, ly=1.0, x=dev(xb), y=dev(yb))
+    ab = dev(wl.zalesak_disk(xb, yb)[None])
+    ws = ctx.workspace(B.x2d_workspace_size(ctx, db, 1))
+    tri_ms = timed(lambda: B.p2m_x2d_triangulation(ctx, db, ws=ws), calls)
+    nb, _ = B.p2m_x2d_assign(ctx, db, B.X1D_MASS, ab, ws=ws)
+    p2m_ms = timed(lambda: B.p2m_x2d_assign(ctx, db, B.X1D_MASS, ab, ws=ws), calls)
+    m2p_ms = timed(lambda: B.p2m_x2d_interpolate(ctx, db, B.X1D_MASS, nb, ws=ws), calls)
+    npb = xb.size
+    out["throughput"] = dict(
+        workload=f"{big_n}x{big_n} mesh, {big_ppc} stratified particles per cell ({npb} particles), FP64",
+        triangulation_ms=tri_ms, particles_triangulated_per_s=npb / (tri_ms * 1e-3),
+        mass_p2m_ms=p2m_ms, mass_m2p_ms=m2p_ms)
+    log(f"bench: exact 2D at {big_n}^2 x {big_ppc}: triangulation {tri_ms:.3f} ms, mass P2M "
+        f"{p2m_ms:.3f} ms, mass M2P {m2p_ms:.3f} ms")
+    return out
+
+
 def m2p_leg(B, ctx, d, nodal, stream, ws, calls=20):
     """M2P interpolation of the solved fields back to the particles (one p2m_interpolate
     call with a workspace: report clear, node-major copy of the nodal values and
@@ -575,7 +665,8 @@ def main():
                     help="after the timed steps, copy MIB MiB device-to-device three times "
                          "(a kernel of known traffic for scaling memory counters)")
     ap.add_argument("--leg", default=None,
-                    choices=("fluid", "zalesak", "tophat_1d", "learned", "plain_vs_production"),
+                    choices=("fluid", "zalesak", "tophat_1d", "learned", "plain_vs_production",
+                             "exact2d"),
                     help="run only this leg (no headline) and print its JSON; for profiling one workload")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -596,7 +687,7 @@ def main():
             res = plain_vs_combined_leg(B, ctx, prob, vals)
         else:
             res = dict(fluid=ns_leg, zalesak=zalesak_leg, tophat_1d=tophat_1d_leg,
-                       learned=learned_leg)[args.leg](B, ctx)
+                       learned=learned_leg, exact2d=exact2d_leg)[args.leg](B, ctx)
         print(json.dumps({args.leg: res}), flush=True)
         torch.cuda.synchronize()
         ctx.close()
@@ -737,6 +828,7 @@ def main():
         result["tophat_1d"] = tophat_1d_leg(B, ctx)
         result["zalesak"] = zalesak_leg(B, ctx)
         result["fluid"] = ns_leg(B, ctx)
+        result["exact2d"] = exact2d_leg(B, ctx)
     if k_ref is not None:
         kk = max(k_ref)
         b_e2e = mass_assign_algorithmic_bytes(int(vals.shape[1]), nn, F, kk)

@@ -3,13 +3,12 @@
 //
 //   k_x2d_pos      binned order: wrapped positions, values and the cell of every
 //                  located particle (slot k = position in the binned order)
-//   k_x2d_star     per particle, its Voronoi cell by clipping a square with the
-//                  bisectors of the particles of the surrounding mesh cells, ring by
-//                  ring, until no particle outside the searched rings can cut it
-//                  (twice the farthest vertex within the searched radius).  The
-//                  bisectors that bound the cell name the Delaunay neighbours,
-//                  counter-clockwise; the volume int psi_mu is a third of the area of
-//                  the triangles (mu, n_j, n_j+1).
+//   k_x2d_star     per particle, its Delaunay neighbours counter-clockwise by gift
+//                  wrapping over the particles of the surrounding mesh cells, widened
+//                  ring by ring until no particle outside the searched rings can
+//                  change them (twice the largest circumradius within the searched
+//                  radius); the volume int psi_mu is a third of the area of the
+//                  triangles (mu, n_j, n_j+1).
 //   k_x2d_check    every triangle (mu, a, b) must appear in the lists of a and b too
 //   k_x2d_locate   the particle interpolant of eq. (1) at the points of a regular
 //                  grid (mesh nodes, or nodes and edge midpoints): the triangle that
@@ -29,7 +28,7 @@ namespace p2m {
 namespace {
 
 constexpr int kB = 128;
-constexpr int kCap = P2M_X2D_MAXDEG;   // neighbours per particle, vertices per Voronoi cell
+constexpr int kCap = P2M_X2D_MAXDEG;   // neighbours per particle
 constexpr int kRingMax = 8;            // mesh-cell rings searched around a particle
 constexpr int kWalkMax = 1024;         // triangles a point-location walk may visit
 
@@ -37,6 +36,7 @@ inline int grid_of(size_t n) { return (int)((n + kB - 1) / kB); }
 
 struct Geo {
     int nx, ny, N;
+    int r0;   // first ring count the triangulation tries
     double lx, ly, hx, hy, inv_hx, inv_hy;
 };
 
@@ -74,10 +74,33 @@ __global__ void k_x2d_pos(Geo g, const int32_t* __restrict__ perm, const double*
 }
 
 // ---------------------------------------------------------------------------
-// Voronoi cell of slot k.  The polygon is kept counter-clockwise around the
-// particle in coordinates relative to it; edge i runs from vertex i to vertex
-// i + 1 and carries the site whose bisector it lies on (slot, packed image shift;
-// -1 for the starting square).
+// The Delaunay neighbours of slot k, counter-clockwise, by gift wrapping over the
+// particles of the mesh cells within r rings of its own (coordinates relative to
+// the particle).  The nearest particle is a Delaunay neighbour.  From a neighbour
+// u, the next one is the particle c left of the edge (k, u) whose circle through
+// k, u and c has its centre first along the edge's bisector: centre
+// u / 2 + t (-u_y, u_x) with t = (|c|^2 - u.c) / (2 u x c), smallest t (an empty
+// circle).  The centres are the Voronoi vertices; when twice the largest circle
+// radius is within the searched radius (every particle left out is at least
+// r min(hx, hy) away), no particle outside the rings can change the result;
+// otherwise the search widens by a ring.
+template <typename Fn>
+__device__ __forceinline__ void for_candidates(const Geo& g, const int32_t* __restrict__ cs, int cx,
+                                               int cy, int r, Fn&& fn) {
+    for (int dy = -r; dy <= r; ++dy) {
+        const int ay = cy + dy;
+        const int sy = floor_div(ay, g.ny);
+        const int row = g.nx * (ay - sy * g.ny);
+        for (int dx = -r; dx <= r; ++dx) {
+            const int ax = cx + dx;
+            const int sx = floor_div(ax, g.nx);
+            const int cc = (ax - sx * g.nx) + row;
+            const int q1 = cs[cc + 1];
+            for (int q = cs[cc]; q < q1; ++q) fn(q, sx, sy);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kB) void k_x2d_star(Geo g, const double* __restrict__ xs,
                                                  const double* __restrict__ ys,
                                                  const int32_t* __restrict__ cell,
@@ -85,103 +108,86 @@ __global__ __launch_bounds__(kB) void k_x2d_star(Geo g, const double* __restrict
                                                  int32_t* __restrict__ deg, int32_t* __restrict__ nbr,
                                                  int32_t* __restrict__ nsh, double* __restrict__ vol,
                                                  p2m_report* rep) {
+    // plain rounding, no fused multiply-adds: the decisions below compare cross
+    // products of nearly parallel vectors, and the same expression must give the
+    // same result in every particle's computation
+#pragma clang fp contract(off)
     const int k = blockIdx.x * kB + threadIdx.x;
     if (k >= g.N) return;
     const double px = xs[k], py = ys[k];
     const int c = cell[k];
     const int cy = c / g.nx, cx = c - cy * g.nx;
     const double hmin = g.hx < g.hy ? g.hx : g.hy;
-    const double hmax = g.hx < g.hy ? g.hy : g.hx;
-
-    double vx[2][kCap], vy[2][kCap];
-    int lq[2][kCap], ls[2][kCap];
-    int cur = 0, n = 4;
-    const double S = 2.0 * (kRingMax + 1) * hmax;
-    vx[0][0] = -S; vy[0][0] = -S;
-    vx[0][1] = S;  vy[0][1] = -S;
-    vx[0][2] = S;  vy[0][2] = S;
-    vx[0][3] = -S; vy[0][3] = S;
-    for (int i = 0; i < 4; ++i) {
-        lq[0][i] = -1;
-        ls[0][i] = 0;
-    }
-    double rmax2 = 2.0 * S * S;
-    bool secure = false, bad = false;
-
-    for (int r = 0; r <= kRingMax && !secure && !bad; ++r) {
-        for (int dy = -r; dy <= r && !bad; ++dy) {
-            const bool edge_row = (dy == -r || dy == r);
-            const int step = edge_row ? 1 : 2 * r;   // interior rows: only the two ends
-            for (int dx = -r; dx <= r && !bad; dx += (step > 0 ? step : 1)) {
-                const int ax = cx + dx, ay = cy + dy;
-                const int sx = floor_div(ax, g.nx), sy = floor_div(ay, g.ny);
-                const int cc = (ax - sx * g.nx) + g.nx * (ay - sy * g.ny);
-                const int q1 = cs[cc + 1];
-                for (int q = cs[cc]; q < q1; ++q) {
-                    if (q == k && sx == 0 && sy == 0) continue;
-                    const double rx = (xs[q] - px) + sx * g.lx;
-                    const double ry = (ys[q] - py) + sy * g.ly;
-                    const double d2 = rx * rx + ry * ry;
-                    if (!(d2 > 0.0)) {   // two particles at one position
-                        bad = true;
-                        break;
-                    }
-                    if (0.25 * d2 >= rmax2) continue;   // its bisector misses the cell
-                    // clip by { v : v.r <= |r|^2 / 2 }
-                    const double hh = 0.5 * d2;
-                    const int nxt = cur ^ 1;
-                    int m = 0;
-                    double di = vx[cur][0] * rx + vy[cur][0] * ry - hh;
-                    for (int i = 0; i < n; ++i) {
-                        const int j = (i + 1 == n) ? 0 : i + 1;
-                        const double dj = vx[cur][j] * rx + vy[cur][j] * ry - hh;
-                        const bool ini = di <= 0.0, inj = dj <= 0.0;
-                        if (ini) {
-                            if (m >= kCap) {
-                                bad = true;
-                                break;
-                            }
-                            vx[nxt][m] = vx[cur][i];
-                            vy[nxt][m] = vy[cur][i];
-                            lq[nxt][m] = lq[cur][i];
-                            ls[nxt][m] = ls[cur][i];
-                            ++m;
-                        }
-                        if (ini != inj) {
-                            if (m >= kCap) {
-                                bad = true;
-                                break;
-                            }
-                            const double t = di / (di - dj);
-                            vx[nxt][m] = vx[cur][i] + t * (vx[cur][j] - vx[cur][i]);
-                            vy[nxt][m] = vy[cur][i] + t * (vy[cur][j] - vy[cur][i]);
-                            lq[nxt][m] = ini ? q : lq[cur][i];
-                            ls[nxt][m] = ini ? pack_shift(sx, sy) : ls[cur][i];
-                            ++m;
-                        }
-                        di = dj;
-                    }
-                    if (bad) break;
-                    cur = nxt;
-                    n = m;
-                    rmax2 = 0.0;
-                    for (int i = 0; i < n; ++i) {
-                        const double e = vx[cur][i] * vx[cur][i] + vy[cur][i] * vy[cur][i];
-                        rmax2 = e > rmax2 ? e : rmax2;
-                    }
-                }
-                if (step == 0) break;   // r == 0: the one cell
+    int n = 0;
+    bool ok = false, bad = false;
+    for (int r = g.r0; r <= kRingMax && !ok && !bad; ++r) {
+        // the nearest particle image
+        double best = 1e300, ux = 0.0, uy = 0.0;
+        int q0 = -1, s0 = 0;
+        for_candidates(g, cs, cx, cy, r, [&](int q, int sx, int sy) {
+            if (q == k && sx == 0 && sy == 0) return;
+            const double rx = (xs[q] - px) + sx * g.lx;
+            const double ry = (ys[q] - py) + sy * g.ly;
+            const double d2 = rx * rx + ry * ry;
+            if (!(d2 > 0.0)) bad = true;   // two particles at one position
+            if (d2 < best) {
+                best = d2;
+                q0 = q;
+                s0 = pack_shift(sx, sy);
+                ux = rx;
+                uy = ry;
             }
+        });
+        if (bad || q0 < 0) continue;
+        int cq = q0, csh = s0;
+        double rmax2 = 0.0;
+        bool closed = false;
+        n = 0;
+        while (n < kCap) {
+            nbr[(size_t)k * kCap + n] = cq;
+            nsh[(size_t)k * kCap + n] = csh;
+            ++n;
+            double bt = 1e300, vx = 0.0, vy = 0.0;
+            int nq = -1, ns = 0;
+            for_candidates(g, cs, cx, cy, r, [&](int q, int sx, int sy) {
+                if (q == k && sx == 0 && sy == 0) return;
+                if (q == cq && pack_shift(sx, sy) == csh) return;   // the edge's own end
+                const double rx = (xs[q] - px) + sx * g.lx;
+                const double ry = (ys[q] - py) + sy * g.ly;
+                const double cr = ux * ry - uy * rx;
+                if (!(cr > 0.0)) return;
+                const double t = (rx * rx + ry * ry - (ux * rx + uy * ry)) / (2.0 * cr);
+                if (t < bt) {
+                    bt = t;
+                    nq = q;
+                    ns = pack_shift(sx, sy);
+                    vx = rx;
+                    vy = ry;
+                }
+            });
+            if (nq < 0) break;   // nothing on the left: the cell is open at this radius
+            const double ox = 0.5 * ux - bt * uy, oy = 0.5 * uy + bt * ux;
+            const double rho2 = ox * ox + oy * oy;
+            rmax2 = rho2 > rmax2 ? rho2 : rmax2;
+            if (nq == q0 && ns == s0) {
+                closed = true;
+                break;
+            }
+            cq = nq;
+            csh = ns;
+            ux = vx;
+            uy = vy;
         }
-        // every particle not yet seen is at least r hmin away (the rings cover the
-        // cells within r of the particle's own); its bisector is then at least
-        // r hmin / 2 away and cannot cut a cell whose vertices are all closer
         const double reach = r * hmin * (1.0 - 1e-9);
-        if (r >= 1 && 4.0 * rmax2 <= reach * reach) secure = true;
+        ok = closed && n >= 3 && 4.0 * rmax2 <= reach * reach;
     }
-    if (!secure || bad || n < 3) {
+    if (!ok) {
         deg[k] = 0;
         vol[k] = __builtin_nan("");
+        for (int i = 0; i < kCap; ++i) {
+            nbr[(size_t)k * kCap + i] = -1;
+            nsh[(size_t)k * kCap + i] = 0;
+        }
         flag(rep, P2M_FLAG_TRIANGULATION);
         return;
     }
@@ -189,9 +195,7 @@ __global__ __launch_bounds__(kB) void k_x2d_star(Geo g, const double* __restrict
     double area2 = 0.0;
     double ax0 = 0.0, ay0 = 0.0, fx0 = 0.0, fy0 = 0.0;
     for (int i = 0; i < n; ++i) {
-        const int q = lq[cur][i], s = ls[cur][i];
-        nbr[(size_t)k * kCap + i] = q;
-        nsh[(size_t)k * kCap + i] = s;
+        const int q = nbr[(size_t)k * kCap + i], s = nsh[(size_t)k * kCap + i];
         const double rx = (xs[q] - px) + shift_x(s) * g.lx;
         const double ry = (ys[q] - py) + shift_y(s) * g.ly;
         if (i == 0) {
@@ -266,6 +270,7 @@ __global__ __launch_bounds__(kB) void k_x2d_locate(Geo g, int gx, int gy, double
                                                    const int32_t* __restrict__ nsh,
                                                    const double* __restrict__ As, int F,
                                                    double* __restrict__ out, p2m_report* rep) {
+#pragma clang fp contract(off)   // orientation signs in plain rounding
     const int P = blockIdx.x * kB + threadIdx.x;
     if (P >= gx * gy) return;
     const int J = P / gx, I = P - J * gx;
@@ -575,6 +580,9 @@ Geo geo_of(const Mesh& m, int N, double lx, double ly) {
     g.hy = ly / m.ny;
     g.inv_hx = m.inv_hx;
     g.inv_hy = m.inv_hy;
+    // dense particles (six or more per cell) usually close their cells within one
+    // ring, sparser ones within two
+    g.r0 = (m.nn > 0 && N >= 6 * (long)m.nn) ? 1 : 2;
     return g;
 }
 
