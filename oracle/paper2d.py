@@ -97,6 +97,51 @@ def periodic_delaunay(x, y, lx, ly):
     return tri, sh
 
 
+def local_star(x, y, lx, ly, mu, radius):
+    """Delaunay neighbours of particle mu (Sec. 3.2) from the particles within
+    ``radius`` of it (every periodic image), counter-clockwise from the nearest one:
+    a list of (particle id, sx, sy), or None when the patch is too small to decide
+    (some circle through mu and two neighbours reaches beyond the patch: a point
+    outside could then lie inside it)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    ids, sxs, sys_, px, py = [], [], [], [], []
+    for sy in (-1, 0, 1):
+        for sx in (-1, 0, 1):
+            dx = x + sx * lx - x[mu]
+            dy = y + sy * ly - y[mu]
+            keep = dx * dx + dy * dy <= radius * radius
+            ids.append(np.nonzero(keep)[0])
+            sxs.append(np.full(keep.sum(), sx))
+            sys_.append(np.full(keep.sum(), sy))
+            px.append(dx[keep])
+            py.append(dy[keep])
+    ids, sxs, sys_ = np.concatenate(ids), np.concatenate(sxs), np.concatenate(sys_)
+    pts = np.stack([np.concatenate(px), np.concatenate(py)], axis=1)
+    me = np.nonzero((ids == mu) & (sxs == 0) & (sys_ == 0))[0][0]
+    d = Delaunay(pts)
+    star = set()
+    rmax = 0.0
+    for t in d.simplices[(d.simplices == me).any(axis=1)]:
+        P = pts[t]
+        a = P[1] - P[0]
+        b = P[2] - P[0]
+        den = 2.0 * (a[0] * b[1] - a[1] * b[0])
+        ux = (b[1] * (a @ a) - a[1] * (b @ b)) / den
+        uy = (a[0] * (b @ b) - b[0] * (a @ a)) / den
+        cx, cy = P[0][0] + ux, P[0][1] + uy
+        rmax = max(rmax, np.hypot(cx, cy))          # circumradius seen from mu (on the circle)
+        star.update(int(v) for v in t if v != me)
+    if 2.0 * rmax > radius:
+        return None
+    star = list(star)
+    ang = np.arctan2(pts[star, 1], pts[star, 0])
+    order = [star[i] for i in np.argsort(ang)]
+    near = min(range(len(order)), key=lambda i: pts[order[i]] @ pts[order[i]])
+    order = order[near:] + order[:near]
+    return [(int(ids[v]), int(sxs[v]), int(sys_[v])) for v in order]
+
+
 def triangle_vertices(x, y, lx, ly, tri, sh):
     """Unrolled vertex coordinates [T, 3] (X, Y) of the triangles."""
     X = np.asarray(x, dtype=np.float64)[tri] + sh[..., 0] * lx

@@ -84,23 +84,80 @@ __global__ void k_x2d_pos(Geo g, const int32_t* __restrict__ perm, const double*
 // radius is within the searched radius (every particle left out is at least
 // r min(hx, hy) away), no particle outside the rings can change the result;
 // otherwise the search widens by a ring.
-template <typename Fn>
-__device__ __forceinline__ void for_candidates(const Geo& g, const int32_t* __restrict__ cs, int cx,
-                                               int cy, int r, Fn&& fn) {
-    for (int dy = -r; dy <= r; ++dy) {
-        const int ay = cy + dy;
-        const int sy = floor_div(ay, g.ny);
-        const int row = g.nx * (ay - sy * g.ny);
-        for (int dx = -r; dx <= r; ++dx) {
-            const int ax = cx + dx;
-            const int sx = floor_div(ax, g.nx);
-            const int cc = (ax - sx * g.nx) + row;
+// One particle per group of G lanes: each lane scans every G-th cell of the
+// search square, and the group agrees on the winner of every scan with a
+// butterfly of lane exchanges (every lane ends with the same winner: the
+// comparison of two candidates evaluates the same two products on both lanes).
+struct Cand {
+    double n, d;     // key n / d (d > 0)
+    double vx, vy;   // position relative to the particle
+    int q, s;        // slot and packed image shift; q < 0: none
+};
+
+// a before b: smaller key, ties to the smaller (slot, shift)
+__device__ __forceinline__ bool before_cand(const Cand& a, const Cand& b) {
+    if (a.q < 0) return false;
+    if (b.q < 0) return true;
+    const double l = a.n * b.d, r = b.n * a.d;
+    if (l != r) return l < r;
+    return a.q != b.q ? a.q < b.q : a.s < b.s;
+}
+
+template <int G>
+__device__ __forceinline__ Cand group_min(Cand v) {
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1) {
+        Cand o;
+        o.n = __shfl_xor(v.n, m, G);
+        o.d = __shfl_xor(v.d, m, G);
+        o.vx = __shfl_xor(v.vx, m, G);
+        o.vy = __shfl_xor(v.vy, m, G);
+        o.q = __shfl_xor(v.q, m, G);
+        o.s = __shfl_xor(v.s, m, G);
+        if (before_cand(o, v)) v = o;
+    }
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ int group_or(int v) {
+#pragma unroll
+    for (int m = G / 2; m >= 1; m >>= 1) v |= __shfl_xor(v, m, G);
+    return v;
+}
+
+// the particles of every G-th cell of the (2r + 1)^2 square around (cx, cy),
+// starting at this lane's cell
+template <int G, typename Fn>
+__device__ __forceinline__ void for_lane_candidates(const Geo& g, const int32_t* __restrict__ cs,
+                                                    int cx, int cy, int r, int lane, Fn&& fn) {
+    if constexpr (G == 1) {   // row by row
+        for (int dy = -r; dy <= r; ++dy) {
+            const int ay = cy + dy;
+            const int sy = floor_div(ay, g.ny);
+            const int row = g.nx * (ay - sy * g.ny);
+            for (int dx = -r; dx <= r; ++dx) {
+                const int ax = cx + dx;
+                const int sx = floor_div(ax, g.nx);
+                const int cc = (ax - sx * g.nx) + row;
+                const int q1 = cs[cc + 1];
+                for (int q = cs[cc]; q < q1; ++q) fn(q, sx, sy);
+            }
+        }
+    } else {   // cells lane, lane + G, ... of the square in row-major order
+        const int side = 2 * r + 1, ncell = side * side;
+        for (int ci = lane; ci < ncell; ci += G) {
+            const int dyy = ci / side, dxx = ci - dyy * side;
+            const int ax = cx + dxx - r, ay = cy + dyy - r;
+            const int sx = floor_div(ax, g.nx), sy = floor_div(ay, g.ny);
+            const int cc = (ax - sx * g.nx) + g.nx * (ay - sy * g.ny);
             const int q1 = cs[cc + 1];
             for (int q = cs[cc]; q < q1; ++q) fn(q, sx, sy);
         }
     }
 }
 
+template <int G>
 __global__ __launch_bounds__(kB) void k_x2d_star(Geo g, const double* __restrict__ xs,
                                                  const double* __restrict__ ys,
                                                  const int32_t* __restrict__ cell,
@@ -112,92 +169,111 @@ __global__ __launch_bounds__(kB) void k_x2d_star(Geo g, const double* __restrict
     // products of nearly parallel vectors, and the same expression must give the
     // same result in every particle's computation
 #pragma clang fp contract(off)
-    const int k = blockIdx.x * kB + threadIdx.x;
-    if (k >= g.N) return;
+    const int tid = blockIdx.x * kB + threadIdx.x;
+    const int k = tid / G, lane = tid - k * G;
+    if (k >= g.N) return;   // the whole group
     const double px = xs[k], py = ys[k];
     const int c = cell[k];
     const int cy = c / g.nx, cx = c - cy * g.nx;
     const double hmin = g.hx < g.hy ? g.hx : g.hy;
+    int32_t* nk = nbr + (size_t)k * kCap;
+    int32_t* sk = nsh + (size_t)k * kCap;
     int n = 0;
     bool ok = false, bad = false;
     for (int r = g.r0; r <= kRingMax && !ok && !bad; ++r) {
         // the nearest particle image
-        double best = 1e300, ux = 0.0, uy = 0.0;
-        int q0 = -1, s0 = 0;
-        for_candidates(g, cs, cx, cy, r, [&](int q, int sx, int sy) {
+        Cand b;
+        b.q = -1;
+        int dup = 0;
+        for_lane_candidates<G>(g, cs, cx, cy, r, lane, [&](int q, int sx, int sy) {
             if (q == k && sx == 0 && sy == 0) return;
-            const double rx = (xs[q] - px) + sx * g.lx;
-            const double ry = (ys[q] - py) + sy * g.ly;
-            const double d2 = rx * rx + ry * ry;
-            if (!(d2 > 0.0)) bad = true;   // two particles at one position
-            if (d2 < best) {
-                best = d2;
-                q0 = q;
-                s0 = pack_shift(sx, sy);
-                ux = rx;
-                uy = ry;
-            }
+            Cand e;
+            e.vx = (xs[q] - px) + sx * g.lx;
+            e.vy = (ys[q] - py) + sy * g.ly;
+            e.n = e.vx * e.vx + e.vy * e.vy;
+            e.d = 1.0;
+            e.q = q;
+            e.s = pack_shift(sx, sy);
+            if (!(e.n > 0.0)) dup = 1;   // two particles at one position
+            if (before_cand(e, b)) b = e;
         });
-        if (bad || q0 < 0) continue;
+        b = group_min<G>(b);
+        bad = group_or<G>(dup) != 0;
+        if (bad || b.q < 0) continue;
+        const int q0 = b.q, s0 = b.s;
         int cq = q0, csh = s0;
-        double rmax2 = 0.0;
+        double ux = b.vx, uy = b.vy, rmax2 = 0.0;
         bool closed = false;
         n = 0;
         while (n < kCap) {
-            nbr[(size_t)k * kCap + n] = cq;
-            nsh[(size_t)k * kCap + n] = csh;
+            if (lane == 0) {
+                nk[n] = cq;
+                sk[n] = csh;
+            }
             ++n;
-            double bt = 1e300, vx = 0.0, vy = 0.0;
-            int nq = -1, ns = 0;
-            for_candidates(g, cs, cx, cy, r, [&](int q, int sx, int sy) {
+            // the particle left of (k, u) whose circle through k and u has its centre
+            // first along the bisector: t = num / den, den = 2 u x c > 0
+            Cand e;
+            e.q = -1;
+            for_lane_candidates<G>(g, cs, cx, cy, r, lane, [&](int q, int sx, int sy) {
                 if (q == k && sx == 0 && sy == 0) return;
-                if (q == cq && pack_shift(sx, sy) == csh) return;   // the edge's own end
+                const int sh = pack_shift(sx, sy);
+                if (q == cq && sh == csh) return;   // the edge's own end
                 const double rx = (xs[q] - px) + sx * g.lx;
                 const double ry = (ys[q] - py) + sy * g.ly;
                 const double cr = ux * ry - uy * rx;
                 if (!(cr > 0.0)) return;
-                const double t = (rx * rx + ry * ry - (ux * rx + uy * ry)) / (2.0 * cr);
-                if (t < bt) {
-                    bt = t;
-                    nq = q;
-                    ns = pack_shift(sx, sy);
-                    vx = rx;
-                    vy = ry;
-                }
+                Cand f;
+                f.n = rx * rx + ry * ry - (ux * rx + uy * ry);
+                f.d = 2.0 * cr;
+                f.vx = rx;
+                f.vy = ry;
+                f.q = q;
+                f.s = sh;
+                if (before_cand(f, e)) e = f;
             });
-            if (nq < 0) break;   // nothing on the left: the cell is open at this radius
+            e = group_min<G>(e);
+            if (e.q < 0) break;   // nothing on the left: the cell is open at this radius
+            const double bt = e.n / e.d;
             const double ox = 0.5 * ux - bt * uy, oy = 0.5 * uy + bt * ux;
             const double rho2 = ox * ox + oy * oy;
             rmax2 = rho2 > rmax2 ? rho2 : rmax2;
-            if (nq == q0 && ns == s0) {
+            if (e.q == q0 && e.s == s0) {
                 closed = true;
                 break;
             }
-            cq = nq;
-            csh = ns;
-            ux = vx;
-            uy = vy;
+            cq = e.q;
+            csh = e.s;
+            ux = e.vx;
+            uy = e.vy;
         }
         const double reach = r * hmin * (1.0 - 1e-9);
         ok = closed && n >= 3 && 4.0 * rmax2 <= reach * reach;
     }
     if (!ok) {
-        deg[k] = 0;
-        vol[k] = __builtin_nan("");
-        for (int i = 0; i < kCap; ++i) {
-            nbr[(size_t)k * kCap + i] = -1;
-            nsh[(size_t)k * kCap + i] = 0;
+        for (int i = lane; i < kCap; i += G) {
+            nk[i] = -1;
+            sk[i] = 0;
         }
-        flag(rep, P2M_FLAG_TRIANGULATION);
+        if (lane == 0) {
+            deg[k] = 0;
+            vol[k] = __builtin_nan("");
+            flag(rep, P2M_FLAG_TRIANGULATION);
+        }
         return;
     }
+    for (int i = n + lane; i < kCap; i += G) {
+        nk[i] = -1;
+        sk[i] = 0;
+    }
+    if (lane != 0) return;
     deg[k] = n;
     double area2 = 0.0;
     double ax0 = 0.0, ay0 = 0.0, fx0 = 0.0, fy0 = 0.0;
     for (int i = 0; i < n; ++i) {
-        const int q = nbr[(size_t)k * kCap + i], s = nsh[(size_t)k * kCap + i];
-        const double rx = (xs[q] - px) + shift_x(s) * g.lx;
-        const double ry = (ys[q] - py) + shift_y(s) * g.ly;
+        const int q = nk[i], sh = sk[i];
+        const double rx = (xs[q] - px) + shift_x(sh) * g.lx;
+        const double ry = (ys[q] - py) + shift_y(sh) * g.ly;
         if (i == 0) {
             fx0 = rx;
             fy0 = ry;
@@ -208,10 +284,6 @@ __global__ __launch_bounds__(kB) void k_x2d_star(Geo g, const double* __restrict
         ay0 = ry;
     }
     area2 += ax0 * fy0 - ay0 * fx0;
-    for (int i = n; i < kCap; ++i) {
-        nbr[(size_t)k * kCap + i] = -1;
-        nsh[(size_t)k * kCap + i] = 0;
-    }
     vol[k] = area2 / 6.0;   // a third of the triangles' total area (area2 / 2)
 }
 
@@ -600,8 +672,34 @@ hipError_t x2d_triangulate(const X2dArgs& a, hipStream_t stream) {
     hipLaunchKernelGGL(k_x2d_pos, dim3(grid_of(a.N)), dim3(kB), 0, stream, g, a.perm, a.x, a.y,
                        a.values, a.F, a.m.np, a.xs, a.ys, a.cell, a.As);
     X2D_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_x2d_star, dim3(grid_of(a.N)), dim3(kB), 0, stream, g, a.xs, a.ys, a.cell,
-                       a.cs, a.deg, a.nbr, a.nsh, a.vol, a.rep);
+    // lanes per particle: about 2^19 lanes in flight (what 256 compute units hold),
+    // at most 16; with more particles than that a particle has one lane
+    int G = 1;
+    while (G < 16 && (size_t)a.N * G < ((size_t)1 << 19)) G *= 2;
+    if ((size_t)a.N * G > (size_t)INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid(grid_of((size_t)a.N * G));
+    switch (G) {
+        case 1:
+            hipLaunchKernelGGL(k_x2d_star<1>, grid, dim3(kB), 0, stream, g, a.xs, a.ys, a.cell, a.cs,
+                               a.deg, a.nbr, a.nsh, a.vol, a.rep);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_x2d_star<2>, grid, dim3(kB), 0, stream, g, a.xs, a.ys, a.cell, a.cs,
+                               a.deg, a.nbr, a.nsh, a.vol, a.rep);
+            break;
+        case 4:
+            hipLaunchKernelGGL(k_x2d_star<4>, grid, dim3(kB), 0, stream, g, a.xs, a.ys, a.cell, a.cs,
+                               a.deg, a.nbr, a.nsh, a.vol, a.rep);
+            break;
+        case 8:
+            hipLaunchKernelGGL(k_x2d_star<8>, grid, dim3(kB), 0, stream, g, a.xs, a.ys, a.cell, a.cs,
+                               a.deg, a.nbr, a.nsh, a.vol, a.rep);
+            break;
+        default:
+            hipLaunchKernelGGL(k_x2d_star<16>, grid, dim3(kB), 0, stream, g, a.xs, a.ys, a.cell,
+                               a.cs, a.deg, a.nbr, a.nsh, a.vol, a.rep);
+            break;
+    }
     X2D_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_x2d_check, dim3(grid_of(a.N)), dim3(kB), 0, stream, g, a.deg, a.nbr, a.nsh,
                        a.rep);

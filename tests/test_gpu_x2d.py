@@ -201,3 +201,31 @@ def test_no_particles(B, ctx):
     r = B.read_report(rep, 1)
     assert r.flags & B.FLAG_TRIANGULATION
     assert torch.isnan(out).all()
+
+
+@pytest.mark.parametrize("n,ppc", [(1024, 1), (256, 4), (128, 8), (128, 4)])
+def test_large_triangulation_sampled(B, ctx, n, ppc):
+    """At 1,048,576 / 262,144 / 131,072 / 65,536 particles (the launch gives 1, 2, 4 and
+    8 lanes to a particle; the smaller cases above take 16): no flag, every triangle in
+    its three lists (sum of degrees 6 N on the torus), volumes summing to the box, and
+    100 sampled particles' neighbour lists equal to the oracle's one-particle Delaunay
+    patch, in order."""
+    say(f"[x2d] large triangulation {n}^2 x {ppc}")
+    x, y = wl.stratified_2d(20 + ppc, n, n, ppc, 1.0, 1.0)
+    d = B.Particles(dim=2, nx=n, ny=n, lx=1.0, ly=1.0,
+                    x=torch.tensor(x, device="cuda"), y=torch.tensor(y, device="cuda"))
+    deg, nbr, sh, rep = B.p2m_x2d_triangulation(ctx, d)
+    assert B.read_report(rep, 1).flags == 0
+    deg = deg.cpu().numpy()
+    assert int(deg.sum()) == 6 * x.size
+    vol, rep = B.p2m_x2d_volumes(ctx, d)
+    assert abs(float(vol.sum()) - 1.0) <= 1e-11
+    nbr = nbr.cpu().numpy()
+    sh = sh.cpu().numpy()
+    g = np.random.Generator(np.random.PCG64(n))
+    for mu in g.choice(x.size, 100, replace=False):
+        want = p2.local_star(x, y, 1.0, 1.0, int(mu), 8.0 / n)
+        assert want is not None
+        got = [(int(nbr[mu, j]), int((sh[mu, j] & 255) - 128), int(((sh[mu, j] >> 8) & 255) - 128))
+               for j in range(int(deg[mu]))]
+        assert got == want, (mu, got, want)

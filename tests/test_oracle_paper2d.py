@@ -225,3 +225,26 @@ def test_conservation_and_flip_volumes():
     np.testing.assert_allclose((Abb * P.vol).sum(axis=1), P.particle_rhs(nodal).sum(axis=1),
                                rtol=1e-11)
     np.testing.assert_allclose(P.p2m_flip(A), p1.flip(dict(P.prob), A)[0], rtol=1e-13)
+
+
+def test_local_star_matches_periodic_triangulation():
+    """The one-particle patch form gives each particle's neighbours of the full
+    periodic triangulation (in counter-clockwise order)."""
+    x, y = wl.stratified_2d(15, 10, 10, 3, 1.0, 1.0)
+    tri, sh = p2.periodic_delaunay(x, y, 1.0, 1.0)
+    for mu in range(0, x.size, 7):
+        star = p2.local_star(x, y, 1.0, 1.0, mu, 0.45)
+        assert star is not None
+        want = set()
+        for t in range(tri.shape[0]):
+            for a in range(3):
+                if tri[t, a] == mu:
+                    for b in range(3):
+                        if b != a:
+                            want.add((int(tri[t, b]), *(int(v) for v in sh[t, b] - sh[t, a])))
+        assert set(star) == want
+        # counter-clockwise: consecutive neighbours turn left around mu
+        for (i0, sx0, sy0), (i1, sx1, sy1) in zip(star, star[1:] + star[:1]):
+            ax, ay = x[i0] + sx0 - x[mu], y[i0] + sy0 - y[mu]
+            bx, by = x[i1] + sx1 - x[mu], y[i1] + sy1 - y[mu]
+            assert ax * by - ay * bx > 0
