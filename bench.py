@@ -145,6 +145,33 @@ def cpu_baseline(prob, vals, min_seconds=10.0):
                        f"{os.cpu_count()} host cores")
 
 
+def cpu_baseline_exact2d(n=90, ppc=1, min_seconds=5.0):
+    """The FP64 oracle's paper-exact 2D full-mass round trip (oracle/paper2d.py as it
+    stands: periodic Delaunay of the particles, Appendix-B right-hand sides, FFT mesh
+    solve, sparse LU particle solve) on the first step of the exact2d leg's slotted
+    disk, repeated until min_seconds have passed, one thread."""
+    import math
+    from threadpoolctl import threadpool_limits
+    from oracle import paper2d
+    from paper_1610_05258_amd import workloads as wl
+    x, y = wl.stratified_2d(1, n, n, ppc, 1.0, 1.0)
+    a = wl.zalesak_disk(x, y)
+    x, y = wl.zalesak_rotate(x, y, 2.0 * math.pi / 100)
+    runs, dt = 0, 0.0
+    with threadpool_limits(limits=1):
+        while dt < min_seconds or runs == 0:
+            t0 = time.perf_counter()
+            P = paper2d.Paper2D(x, y, n, n, 1.0, 1.0)
+            P.m2p_mass(P.p2m_mass(a[None]))
+            dt += time.perf_counter() - t0
+            runs += 1
+    return dict(value=runs / dt, unit="full-mass round trips/s", cores=1, kind="oracle",
+                ms_per_step=dt / runs * 1e3,
+                sample=f"the exact2d leg's first slotted-disk step ({n}x{n}, {ppc} particle per cell): "
+                       f"{runs} FP64 oracle round trips (triangulation, mass P2M, full-mass M2P) in "
+                       f"{dt:.2f} s on 1 thread of {os.cpu_count()} host cores")
+
+
 def batched_leg(B, ctx, check, tune, reps=10, tol=1e-9):
     """The uneven batch as one graph launch, and as one call per problem.  With `tune`
     the batch's inner_rtol is tuned first (unless a loaded plan covers it); the single
@@ -818,6 +845,10 @@ def main():
         log(f"bench: accuracy {result['accuracy']['rel_l2']}, K_ref {k_ref}")
         log("bench: CPU baseline (oracle on the full input, one thread)")
         result["cpu_baseline"] = cpu_baseline(prob, vals)
+        if not args.no_extra:
+            result["cpu_baseline"]["exact2d"] = cpu_baseline_exact2d()
+            log(f"bench: oracle full-mass round trip (90^2, exact 2D) "
+                f"{result['cpu_baseline']['exact2d']['ms_per_step']:.1f} ms on 1 thread")
     if not args.no_batch:
         result["batched"] = batched_leg(B, ctx, check=not args.no_cpu, tune=not args.no_tune)
         if args.save_plans:
