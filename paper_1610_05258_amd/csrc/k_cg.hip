@@ -21,6 +21,7 @@
 // form (an irregular sparse matrix, the particle mass matrix of a triangulation)
 // keeps D_k and then every row's off-diagonal entries in up to `ew` slots, slot j
 // of row k at [nn + j nn + k] with its column in ecol[j nn + k] (-1 ends the row).
+#include <atomic>
 #include <type_traits>
 
 #include "cg_common.hpp"
@@ -559,25 +560,49 @@ size_t cg_partials_bytes(int blocks) {
     return (size_t)2 * blocks * kSlots * sizeof(double) + kBarBytes;
 }
 
+namespace {
+
+// Workgroups of one solve variant that are resident at once on the device: its
+// occupancy per compute unit (at most 2) times the compute units.  Kept per
+// device and variant after the first query.
+constexpr int kMaxDevices = 16;
+
 template <typename T>
-int cg_max_blocks(int device) {
-    int cus = 0;
+int cg_variant_blocks(int device, int dim, int F) {
+    static std::atomic<int> cache[kMaxDevices][4][kMaxFields + 1];
+    const bool cached = device >= 0 && device < kMaxDevices;
+    if (cached) {
+        const int v = cache[device][dim][F].load(std::memory_order_relaxed);
+        if (v > 0) return v;
+    }
+    int cus = 0, b = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
         return 0;
-    int per = 1 << 30;
+    const void* fn = cg_kernel_for<T>(dim, F);
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, kCgBlock, 0) != hipSuccess)
+        return 0;
+    if (b > 2) b = 2;
+    if (b < 1) return 0;
+    if (cached) cache[device][dim][F].store(b * cus, std::memory_order_relaxed);
+    return b * cus;
+}
+
+}  // namespace
+
+// The largest grid any variant may take (workspace layouts are sized for it); a
+// launch takes at most its own variant's resident grid.
+template <typename T>
+int cg_max_blocks(int device) {
+    int most = 0;
     for (int F = 1; F <= kMaxFields; ++F) {
         for (int dim = 1; dim <= 3; ++dim) {
-            int b = 0;
-            const void* fn = cg_kernel_for<T>(dim, F);
-            if (!fn) continue;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, fn, kCgBlock, 0) != hipSuccess)
-                return 0;
-            if (b < per) per = b;
+            if (!cg_kernel_for<T>(dim, F)) continue;
+            const int v = cg_variant_blocks<T>(device, dim, F);
+            if (v <= 0) return 0;
+            if (v > most) most = v;
         }
     }
-    if (per > 2) per = 2;
-    if (per < 1) return 0;
-    return per * cus;
+    return most;
 }
 template int cg_max_blocks<float>(int);
 template int cg_max_blocks<double>(int);
@@ -609,17 +634,24 @@ hipError_t launch_cg(const Mesh& m, int F, T* coef, T* b, const T* w, T* x, int 
     const void* fn = cg_kernel_for<T>(m.dim, F);
     if (!fn || (m.dim == 3 && !ws.ell_col)) return hipErrorInvalidValue;
     // An ordinary launch: the stream has finished every earlier kernel, and the
-    // grid (at most the occupancy's blocks per compute unit, cg_max_blocks) is then
-    // resident as a whole.  The barrier is the kernel's own, with bounded waits; a
-    // cooperative launch added tens of microseconds of queue overhead per solve.
-    if (ws.blocks > 1) {
+    // grid (at most this variant's occupancy per compute unit) is then resident as
+    // a whole.  The barrier is the kernel's own, with bounded waits; a cooperative
+    // launch added tens of microseconds of queue overhead per solve.  The grid
+    // never exceeds ws.blocks, which the partials were sized for.
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return e;
+    const int resident = cg_variant_blocks<T>(device, m.dim, F);
+    if (resident <= 0) return hipErrorInvalidValue;
+    const int blocks = ws.blocks < resident ? ws.blocks : resident;
+    if (blocks > 1) {
         unsigned* bar =
-            (unsigned*)((char*)ws.partials + (size_t)2 * ws.blocks * kSlots * sizeof(double));
+            (unsigned*)((char*)ws.partials + (size_t)2 * blocks * kSlots * sizeof(double));
         hipLaunchKernelGGL(k_bar_clear, dim3(1), dim3(256), 0, stream, bar);
-        const hipError_t e = hipGetLastError();
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return hipLaunchKernel(fn, dim3(ws.blocks), dim3(kCgBlock), args, 0, stream);
+    return hipLaunchKernel(fn, dim3(blocks), dim3(kCgBlock), args, 0, stream);
 }
 template hipError_t launch_cg<float>(const Mesh&, int, float*, float*, const float*, float*, int,
                                      const CgWorkspace&, const p2m_solve_opts&, p2m_report*,
