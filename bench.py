@@ -557,8 +557,9 @@ def exact2d_leg(B, ctx, n=90, ppc=1, steps=100, big_n=512, big_ppc=4, calls=5):
     (1) The slotted-disk rotation at the paper's resolution: a 90 x 90 mesh (the paper's
     H / box ratio), one particle per cell (stratified, seed 1), one revolution in 100
     steps (the paper's dt = tau / 100).  Each step rotates the particles exactly (FP64,
-    host), then runs P2M and M2P of one Table 1 method on the GPU; the particles carry
-    the M2P values.  E1, E2 and L2 after the revolution (the Sec. 3.1 measures with the
+    host), then runs P2M and M2P of one Table 1 method on the GPU in one call
+    (p2m_x2d_round_trip: one binning and triangulation); the particles carry the M2P
+    values.  E1, E2 and L2 after the revolution (the Sec. 3.1 measures with the
     Delaunay volumes), and the event-timed milliseconds per step.
     (2) Throughput at 512 x 512, four particles per cell (1,048,576 particles): the
     triangulation alone and the full-mass round trip (mass P2M, then mass M2P)."""
@@ -600,12 +601,12 @@ def exact2d_leg(B, ctx, n=90, ppc=1, steps=100, big_n=512, big_ppc=4, calls=5):
             d = B.Particles(dim=2, nx=n, ny=n, lx=1.0, ly=1.0, x=dev(x), y=dev(y))
             torch.cuda.synchronize()
             e0.record(stream)
-            nodal, rep = B.p2m_x2d_assign(ctx, d, kp, vals)
-            vals, rep2 = B.p2m_x2d_interpolate(ctx, d, km, nodal)
+            nodal, vals, reps = B.p2m_x2d_round_trip(ctx, d, kp, km, vals)
             e1.record(stream)
             torch.cuda.synchronize()
             ms += e0.elapsed_time(e1)
-            flags |= B.read_report(rep, 1).flags | B.read_report(rep2, 1).flags
+            flags |= (B.Report.decode(reps[0].cpu().numpy().tobytes(), 1).flags
+                      | B.Report.decode(reps[1].cpu().numpy().tobytes(), 1).flags)
         vT = B.p2m_x2d_volumes(ctx, d)[0].cpu().numpy()
         aT = vals.cpu().numpy()[0]
         s1 = float(np.sum(v0 * a0))
@@ -630,13 +631,14 @@ def exact2d_leg(B, ctx, n=90, ppc=1, steps=100, big_n=512, big_ppc=4, calls=5):
     nb, _ = B.p2m_x2d_assign(ctx, db, B.X1D_MASS, ab, ws=ws)
     p2m_ms = timed(lambda: B.p2m_x2d_assign(ctx, db, B.X1D_MASS, ab, ws=ws), calls)
     m2p_ms = timed(lambda: B.p2m_x2d_interpolate(ctx, db, B.X1D_MASS, nb, ws=ws), calls)
+    rt_ms = timed(lambda: B.p2m_x2d_round_trip(ctx, db, B.X1D_MASS, B.X1D_MASS, ab, ws=ws), calls)
     npb = xb.size
     out["throughput"] = dict(
         workload=f"{big_n}x{big_n} mesh, {big_ppc} stratified particles per cell ({npb} particles), FP64",
         triangulation_ms=tri_ms, particles_triangulated_per_s=npb / (tri_ms * 1e-3),
-        mass_p2m_ms=p2m_ms, mass_m2p_ms=m2p_ms)
+        mass_p2m_ms=p2m_ms, mass_m2p_ms=m2p_ms, full_mass_round_trip_ms=rt_ms)
     log(f"bench: exact 2D at {big_n}^2 x {big_ppc}: triangulation {tri_ms:.3f} ms, mass P2M "
-        f"{p2m_ms:.3f} ms, mass M2P {m2p_ms:.3f} ms")
+        f"{p2m_ms:.3f} ms, mass M2P {m2p_ms:.3f} ms, full-mass round trip {rt_ms:.3f} ms")
     return out
 
 

@@ -375,6 +375,16 @@ p2m_status p2m_x2d_interpolate(void* ctx, const p2m_problem* prob, int32_t kind,
                                const void* nodal, int32_t nfields, const p2m_solve_opts* opts,
                                void* values_out, p2m_report* rep, void* ws, size_t ws_bytes,
                                void* stream);
+/* One Table 1 pair at one set of positions (the per-step projection of Sec. 3.2):
+ * p2m_x2d_assign of kind_p2m into nodal_out [F][nx ny], then p2m_x2d_interpolate
+ * of kind_m2p (DELTA, MASS or LUMPED) of nodal_out into values_out [F][np], with
+ * one binning and one triangulation.  reps (device) holds two reports: reps[0]
+ * the binning and triangulation flags and the P2M solve, reps[1] the M2P solve.
+ * The results equal those of the two separate calls. */
+p2m_status p2m_x2d_round_trip(void* ctx, const p2m_problem* prob, int32_t kind_p2m,
+                              int32_t kind_m2p, const void* values, int32_t nfields,
+                              const p2m_solve_opts* opts, void* nodal_out, void* values_out,
+                              p2m_report* reps, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Particle fluid solver: the Taylor-Green vortex sheet computation of Sec. 3.3

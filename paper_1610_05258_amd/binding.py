@@ -45,7 +45,7 @@ EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size
            "p2m_plan_save", "p2m_plan_load", "p2m_plan_clear", "p2m_mass_assign_noalloc",
            "p2m_x1d_workspace_size", "p2m_x1d_assign", "p2m_x1d_interpolate", "p2m_x1d_volumes",
            "p2m_x2d_workspace_size", "p2m_x2d_triangulation", "p2m_x2d_volumes", "p2m_x2d_assign",
-           "p2m_x2d_interpolate",
+           "p2m_x2d_interpolate", "p2m_x2d_round_trip",
            "p2m_ns_workspace_size", "p2m_ns_step")
 QUAD_EXACT, QUAD_APPB = 0, 1
 X1D_DELTA, X1D_FLIP, X1D_PIC, X1D_MASS, X1D_LUMPED = 0, 1, 2, 3, 4
@@ -127,6 +127,8 @@ def lib():
                                      sz, vp]
         L.p2m_x2d_interpolate.argtypes = [vp, pprob, i32, vp, i32, ctypes.POINTER(CSolveOpts), vp, vp,
                                           vp, sz, vp]
+        L.p2m_x2d_round_trip.argtypes = [vp, pprob, i32, i32, vp, i32, ctypes.POINTER(CSolveOpts), vp,
+                                         vp, vp, vp, sz, vp]
         L.p2m_ns_workspace_size.argtypes = [vp, pprob, ctypes.POINTER(sz)]
         L.p2m_ns_step.argtypes = [vp, pprob, i32, ctypes.c_double, ctypes.c_double,
                                   ctypes.POINTER(CSolveOpts), vp, vp, vp, vp, vp, vp, sz, vp]
@@ -599,6 +601,28 @@ def p2m_x2d_interpolate(ctx: Context, prob: Particles, kind: int, nodal, opts=No
                                      ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(rep.data_ptr()),
                                      wp, wn, _stream_ptr(stream)), "p2m_x2d_interpolate")
     return out, rep
+
+
+def p2m_x2d_round_trip(ctx: Context, prob: Particles, kind_p2m: int, kind_m2p: int, values,
+                       opts=None, stream=None, ws=None, reps=None, nodal=None, out=None):
+    """Paper-exact 2D P2M of kind_p2m then M2P of kind_m2p at one set of positions, one
+    binning and triangulation: (nodal [F, nn], values [F, np], reports [2, REPORT_BYTES])."""
+    values, F = _values_tensor(values, prob)
+    cp = prob.cstruct()
+    dev = prob.x.device
+    if nodal is None:
+        nodal = torch.empty((F, prob.n_nodes), dtype=torch.float64, device=dev)
+    if out is None:
+        out = torch.empty((F, prob.n_particles), dtype=torch.float64, device=dev)
+    if reps is None:
+        reps = torch.zeros((2, REPORT_BYTES), dtype=torch.uint8, device=dev)
+    wp, wn = _x2d_ws(ctx, prob, F, ws)
+    _check(lib().p2m_x2d_round_trip(ctx.handle, ctypes.byref(cp), int(kind_p2m), int(kind_m2p),
+                                    ctypes.c_void_p(values.data_ptr()), F, _opts_ptr(opts),
+                                    ctypes.c_void_p(nodal.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.c_void_p(reps.data_ptr()), wp, wn, _stream_ptr(stream)),
+           "p2m_x2d_round_trip")
+    return nodal, out, reps
 
 
 def ns_workspace_size(ctx: Context, prob: Particles) -> int:

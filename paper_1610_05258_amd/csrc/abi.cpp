@@ -826,6 +826,104 @@ CgWorkspace x2d_cg_ws(const Prepared& pp, const X2DLayout& X, const Context* c, 
     return cw;
 }
 
+p2m_status x2d_check_p2m(const p2m_problem* prob, int32_t kind, const void* values,
+                         const p2m_solve_opts* opts) {
+    if (kind < P2M_X1D_DELTA || kind > P2M_X1D_LUMPED) return P2M_ERR_INVALID_ARG;
+    if (opts && kind == P2M_X1D_MASS) {
+        p2m_status so = check_opts(opts);
+        if (so != P2M_OK) return so;
+    }
+    if (!prob || (prob->np > 0 && !values)) return P2M_ERR_INVALID_ARG;
+    return P2M_OK;
+}
+
+p2m_status x2d_check_m2p(int32_t kind, const p2m_solve_opts* opts) {
+    if (kind != P2M_X1D_DELTA && kind != P2M_X1D_MASS && kind != P2M_X1D_LUMPED)
+        return P2M_ERR_INVALID_ARG;
+    if (opts && kind == P2M_X1D_MASS) {
+        p2m_status so = check_opts(opts);
+        if (so != P2M_OK) return so;
+    }
+    return P2M_OK;
+}
+
+// P2M of one kind after x2d_begin; the mass solve reports to rep
+p2m_status x2d_run_p2m(const Context* c, const Prepared& pp, const X2DLayout& X, const X2dArgs& A,
+                       const p2m_problem* prob, int32_t kind, const void* values,
+                       const p2m_solve_opts* opts, double* out, p2m_report* rep) {
+    const Mesh& m = pp.m;
+    const int F = A.F;
+    char* w8 = pp.ws;
+    if (kind == P2M_X1D_FLIP || kind == P2M_X1D_PIC) {
+        double* volc = (double*)(w8 + X.volc);
+        P2M_TRY(x1d_scatter(A.N, 1, m.np, A.perm, A.vol, volc, pp.stream));
+        Particles<double> P = particles_of<double>(prob);
+        P.vol = volc;
+        double* b = (double*)(w8 + X.b);
+        double* bw = (double*)(w8 + X.bw);
+        P2M_TRY(launch_assemble<double>(m, P, (const double*)values, F, A.perm, A.cs, b, bw,
+                                        nullptr, pp.stream));
+        P2M_TRY(launch_finalize<double>(m, F, b, bw, kind == P2M_X1D_PIC ? 1 : 0, out, rep,
+                                        pp.stream));
+        return P2M_OK;
+    }
+    if (kind == P2M_X1D_DELTA) {
+        P2M_TRY(x2d_locate(A, false, out, pp.stream));
+        return P2M_OK;
+    }
+    double* H = (double*)(w8 + X.H);
+    double* b = (double*)(w8 + X.b);
+    P2M_TRY(x2d_locate(A, true, H, pp.stream));
+    P2M_TRY(x2d_rhs_mesh(A, H, b, pp.stream));
+    if (kind == P2M_X1D_LUMPED) {
+        P2M_TRY(x1d_div(m.nn, F, b, nullptr, m.cell_measure, out, pp.stream));
+        return P2M_OK;
+    }
+    double* coef = (double*)(w8 + X.coef);
+    double* wv = (double*)(w8 + X.w);
+    P2M_TRY(x2d_mass_mesh(A, coef, wv, pp.stream));
+    const p2m_solve_opts o = x1d_opts(opts, m.nn);
+    P2M_TRY(launch_cg<double>(m, F, coef, b, wv, out, P2M_START_FLIP, x2d_cg_ws(pp, X, c, m), o,
+                              rep, pp.stream));
+    return P2M_OK;
+}
+
+// M2P of kind MASS or LUMPED after x2d_begin; the mass solve reports to rep
+p2m_status x2d_run_m2p(const Context* c, const Prepared& pp, const X2DLayout& X, const X2dArgs& A,
+                       const p2m_problem* prob, int32_t kind, const double* nodal,
+                       const p2m_solve_opts* opts, double* values_out, p2m_report* rep) {
+    (void)prob;
+    const Mesh& m = pp.m;
+    const int F = A.F, N = A.N;
+    char* w8 = pp.ws;
+    double* cvec = (double*)(w8 + X.b);
+    double* xs = (double*)(w8 + X.x);
+    P2M_TRY(x2d_rhs_part(A, nodal, cvec, pp.stream));
+    if (kind == P2M_X1D_LUMPED) {
+        P2M_TRY(x1d_div(N, F, cvec, A.vol, 0.0, xs, pp.stream));
+    } else if (N > 0) {
+        double* coef = (double*)(w8 + X.coef);
+        int32_t* ecol = (int32_t*)(w8 + X.ecol);
+        P2M_TRY(x2d_mass_part(A, coef, ecol, pp.stream));
+        Mesh mp;
+        memset(&mp, 0, sizeof(mp));
+        mp.dim = 3;
+        mp.nx = N;
+        mp.ny = 1;
+        mp.nn = N;
+        mp.inv_hx = mp.inv_hy = 1.0;
+        mp.cell_measure = 1.0;
+        CgWorkspace cw = x2d_cg_ws(pp, X, c, mp);
+        cw.ell_col = ecol;
+        cw.ell_w = P2M_X2D_MAXDEG;
+        const p2m_solve_opts o = x1d_opts(opts, N);
+        P2M_TRY(launch_cg<double>(mp, F, coef, cvec, A.vol, xs, P2M_START_FLIP, cw, o, rep,
+                                  pp.stream));
+    }
+    P2M_TRY(x1d_scatter(N, F, m.np, A.perm, xs, values_out, pp.stream));
+    return P2M_OK;
+}
+
 
 }  // namespace
 
@@ -1377,56 +1475,17 @@ p2m_status p2m_x2d_assign(void* ctx, const p2m_problem* prob, int32_t kind, cons
                           int32_t nfields, const p2m_solve_opts* opts, void* nodal_out,
                           p2m_report* rep, void* ws, size_t ws_bytes, void* stream) {
     if (!ctx || !rep || !nodal_out) return P2M_ERR_INVALID_ARG;
-    if (kind < P2M_X1D_DELTA || kind > P2M_X1D_LUMPED) return P2M_ERR_INVALID_ARG;
-    if (opts && kind == P2M_X1D_MASS) {
-        p2m_status so = check_opts(opts);
-        if (so != P2M_OK) return so;
-    }
-    if (!prob || (prob->np > 0 && !values)) return P2M_ERR_INVALID_ARG;
+    p2m_status s = x2d_check_p2m(prob, kind, values, opts);
+    if (s != P2M_OK) return s;
     const Context* c = (const Context*)ctx;
     DeviceGuard g(c->device);
     if (!g.ok) return P2M_ERR_HIP;
     Prepared pp;
     X2DLayout X;
     X2dArgs A;
-    p2m_status s = x2d_begin(ctx, prob, nfields, values, ws, ws_bytes, stream, rep, pp, X, A);
+    s = x2d_begin(ctx, prob, nfields, values, ws, ws_bytes, stream, rep, pp, X, A);
     if (s != P2M_OK) return s;
-    const Mesh& m = pp.m;
-    const int F = nfields;
-    char* w8 = pp.ws;
-    double* out = (double*)nodal_out;
-    if (kind == P2M_X1D_FLIP || kind == P2M_X1D_PIC) {
-        double* volc = (double*)(w8 + X.volc);
-        P2M_TRY(x1d_scatter(A.N, 1, m.np, A.perm, A.vol, volc, pp.stream));
-        Particles<double> P = particles_of<double>(prob);
-        P.vol = volc;
-        double* b = (double*)(w8 + X.b);
-        double* bw = (double*)(w8 + X.bw);
-        P2M_TRY(launch_assemble<double>(m, P, (const double*)values, F, A.perm, A.cs, b, bw,
-                                        nullptr, pp.stream));
-        P2M_TRY(launch_finalize<double>(m, F, b, bw, kind == P2M_X1D_PIC ? 1 : 0, out, pp.rep,
-                                        pp.stream));
-        return P2M_OK;
-    }
-    if (kind == P2M_X1D_DELTA) {
-        P2M_TRY(x2d_locate(A, false, out, pp.stream));
-        return P2M_OK;
-    }
-    double* H = (double*)(w8 + X.H);
-    double* b = (double*)(w8 + X.b);
-    P2M_TRY(x2d_locate(A, true, H, pp.stream));
-    P2M_TRY(x2d_rhs_mesh(A, H, b, pp.stream));
-    if (kind == P2M_X1D_LUMPED) {
-        P2M_TRY(x1d_div(m.nn, F, b, nullptr, m.cell_measure, out, pp.stream));
-        return P2M_OK;
-    }
-    double* coef = (double*)(w8 + X.coef);
-    double* wv = (double*)(w8 + X.w);
-    P2M_TRY(x2d_mass_mesh(A, coef, wv, pp.stream));
-    const p2m_solve_opts o = x1d_opts(opts, m.nn);
-    P2M_TRY(launch_cg<double>(m, F, coef, b, wv, out, P2M_START_FLIP, x2d_cg_ws(pp, X, c, m), o,
-                              pp.rep, pp.stream));
-    return P2M_OK;
+    return x2d_run_p2m(c, pp, X, A, prob, kind, values, opts, (double*)nodal_out, pp.rep);
 }
 
 p2m_status p2m_x2d_interpolate(void* ctx, const p2m_problem* prob, int32_t kind,
@@ -1434,18 +1493,14 @@ p2m_status p2m_x2d_interpolate(void* ctx, const p2m_problem* prob, int32_t kind,
                                void* values_out, p2m_report* rep, void* ws, size_t ws_bytes,
                                void* stream) {
     if (!ctx || !rep || !nodal || !values_out) return P2M_ERR_INVALID_ARG;
-    if (kind != P2M_X1D_DELTA && kind != P2M_X1D_MASS && kind != P2M_X1D_LUMPED)
-        return P2M_ERR_INVALID_ARG;
-    if (opts && kind == P2M_X1D_MASS) {
-        p2m_status so = check_opts(opts);
-        if (so != P2M_OK) return so;
-    }
+    p2m_status s = x2d_check_m2p(kind, opts);
+    if (s != P2M_OK) return s;
     const Context* c = (const Context*)ctx;
     DeviceGuard g(c->device);
     if (!g.ok) return P2M_ERR_HIP;
     if (kind == P2M_X1D_DELTA) {   // the mesh interpolant at the particles: no triangulation
         Mesh m;
-        p2m_status s = x2d_check(ctx, prob, nfields, m);
+        s = x2d_check(ctx, prob, nfields, m);
         if (s != P2M_OK) return s;
         P2M_TRY(launch_report_clear(rep, (hipStream_t)stream));
         P2M_TRY(launch_gather<double>(m, particles_of<double>(prob), (const double*)nodal,
@@ -1455,37 +1510,39 @@ p2m_status p2m_x2d_interpolate(void* ctx, const p2m_problem* prob, int32_t kind,
     Prepared pp;
     X2DLayout X;
     X2dArgs A;
-    p2m_status s = x2d_begin(ctx, prob, nfields, nullptr, ws, ws_bytes, stream, rep, pp, X, A);
+    s = x2d_begin(ctx, prob, nfields, nullptr, ws, ws_bytes, stream, rep, pp, X, A);
     if (s != P2M_OK) return s;
-    const Mesh& m = pp.m;
-    const int F = nfields, N = A.N;
-    char* w8 = pp.ws;
-    double* cvec = (double*)(w8 + X.b);
-    double* xs = (double*)(w8 + X.x);
-    P2M_TRY(x2d_rhs_part(A, (const double*)nodal, cvec, pp.stream));
-    if (kind == P2M_X1D_LUMPED) {
-        P2M_TRY(x1d_div(N, F, cvec, A.vol, 0.0, xs, pp.stream));
-    } else if (N > 0) {
-        double* coef = (double*)(w8 + X.coef);
-        int32_t* ecol = (int32_t*)(w8 + X.ecol);
-        P2M_TRY(x2d_mass_part(A, coef, ecol, pp.stream));
-        Mesh mp;
-        memset(&mp, 0, sizeof(mp));
-        mp.dim = 3;
-        mp.nx = N;
-        mp.ny = 1;
-        mp.nn = N;
-        mp.inv_hx = mp.inv_hy = 1.0;
-        mp.cell_measure = 1.0;
-        CgWorkspace cw = x2d_cg_ws(pp, X, c, mp);
-        cw.ell_col = ecol;
-        cw.ell_w = P2M_X2D_MAXDEG;
-        const p2m_solve_opts o = x1d_opts(opts, N);
-        P2M_TRY(launch_cg<double>(mp, F, coef, cvec, A.vol, xs, P2M_START_FLIP, cw, o, pp.rep,
-                                  pp.stream));
+    return x2d_run_m2p(c, pp, X, A, prob, kind, (const double*)nodal, opts,
+                       (double*)values_out, pp.rep);
+}
+
+p2m_status p2m_x2d_round_trip(void* ctx, const p2m_problem* prob, int32_t kind_p2m,
+                              int32_t kind_m2p, const void* values, int32_t nfields,
+                              const p2m_solve_opts* opts, void* nodal_out, void* values_out,
+                              p2m_report* reps, void* ws, size_t ws_bytes, void* stream) {
+    if (!ctx || !reps || !nodal_out || !values_out) return P2M_ERR_INVALID_ARG;
+    p2m_status s = x2d_check_p2m(prob, kind_p2m, values, opts);
+    if (s != P2M_OK) return s;
+    s = x2d_check_m2p(kind_m2p, opts);
+    if (s != P2M_OK) return s;
+    const Context* c = (const Context*)ctx;
+    DeviceGuard g(c->device);
+    if (!g.ok) return P2M_ERR_HIP;
+    Prepared pp;
+    X2DLayout X;
+    X2dArgs A;
+    s = x2d_begin(ctx, prob, nfields, values, ws, ws_bytes, stream, reps, pp, X, A);
+    if (s != P2M_OK) return s;
+    s = x2d_run_p2m(c, pp, X, A, prob, kind_p2m, values, opts, (double*)nodal_out, reps);
+    if (s != P2M_OK) return s;
+    P2M_TRY(launch_report_clear(reps + 1, pp.stream));
+    if (kind_m2p == P2M_X1D_DELTA) {
+        P2M_TRY(launch_gather<double>(pp.m, particles_of<double>(prob), (const double*)nodal_out,
+                                      nfields, (double*)values_out, reps + 1, pp.stream));
+        return P2M_OK;
     }
-    P2M_TRY(x1d_scatter(N, F, m.np, A.perm, xs, (double*)values_out, pp.stream));
-    return P2M_OK;
+    return x2d_run_m2p(c, pp, X, A, prob, kind_m2p, (const double*)nodal_out, opts,
+                       (double*)values_out, reps + 1);
 }
 
 p2m_status p2m_mass_solve(void* ctx, const p2m_problem* prob, int32_t nfields, void* b, const void* w,

@@ -229,3 +229,25 @@ def test_large_triangulation_sampled(B, ctx, n, ppc):
         got = [(int(nbr[mu, j]), int((sh[mu, j] & 255) - 128), int(((sh[mu, j] >> 8) & 255) - 128))
                for j in range(int(deg[mu]))]
         assert got == want, (mu, got, want)
+
+
+@pytest.mark.parametrize("name", ["rect_cells", "mesh_96"])
+def test_round_trip_equals_separate_calls(B, ctx, name):
+    """p2m_x2d_round_trip (one binning and triangulation) gives the bits of
+    p2m_x2d_assign followed by p2m_x2d_interpolate, for every Table 1 pair."""
+    x, y, d = problem(B, name)
+    g = np.random.Generator(np.random.PCG64(9))
+    v = torch.tensor(g.standard_normal((2, x.size)), device="cuda")
+    pairs = [(B.X1D_DELTA, B.X1D_DELTA), (B.X1D_FLIP, B.X1D_DELTA), (B.X1D_PIC, B.X1D_LUMPED),
+             (B.X1D_MASS, B.X1D_DELTA), (B.X1D_MASS, B.X1D_MASS), (B.X1D_LUMPED, B.X1D_LUMPED)]
+    for kp, km in pairs:
+        say(f"[x2d] round trip {name} {kp} {km}")
+        nodal, back, reps = B.p2m_x2d_round_trip(ctx, d, kp, km, v)
+        n1, r1 = B.p2m_x2d_assign(ctx, d, kp, v)
+        b1, r2 = B.p2m_x2d_interpolate(ctx, d, km, n1)
+        assert torch.equal(nodal, n1) and torch.equal(back, b1), (kp, km)
+        ra = B.Report.decode(reps[0].cpu().numpy().tobytes(), 2)
+        rb = B.Report.decode(reps[1].cpu().numpy().tobytes(), 2)
+        assert ra.flags == B.read_report(r1, 2).flags and rb.flags == B.read_report(r2, 2).flags
+        assert list(ra.iters) == list(B.read_report(r1, 2).iters)
+        assert list(rb.iters) == list(B.read_report(r2, 2).iters)
