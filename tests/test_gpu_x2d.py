@@ -251,3 +251,25 @@ def test_round_trip_equals_separate_calls(B, ctx, name):
         assert ra.flags == B.read_report(r1, 2).flags and rb.flags == B.read_report(r2, 2).flags
         assert list(ra.iters) == list(B.read_report(r1, 2).iters)
         assert list(rb.iters) == list(B.read_report(r2, 2).iters)
+
+
+@pytest.mark.parametrize("F", [5, 8])
+def test_many_fields_full_mass(B, ctx, F):
+    """F = 5 and F = 8 fields (the widest solve variants) through the full-mass round trip
+    and lumped P2M, per field against the oracle."""
+    name = "box_20x12"
+    x, y, d = problem(B, name)
+    P = oracle_of(name, x, y)
+    g = np.random.Generator(np.random.PCG64(F))
+    A = g.standard_normal((F, x.size))
+    v = torch.tensor(A, device="cuda")
+    say(f"[x2d] {F} fields")
+    nodal, back, reps = B.p2m_x2d_round_trip(ctx, d, B.X1D_MASS, B.X1D_MASS, v)
+    want_nodal = P.p2m_mass(A)
+    assert rel_l2(nodal.cpu().numpy(), want_nodal) <= 1e-11
+    assert rel_l2(back.cpu().numpy(), P.m2p_mass(nodal.cpu().numpy())) <= 1e-11
+    for r in (0, 1):
+        rr = B.Report.decode(reps[r].cpu().numpy().tobytes(), F)
+        assert rr.flags == 0 and (rr.iters > 0).all()
+    out, rep = B.p2m_x2d_assign(ctx, d, B.X1D_LUMPED, v)
+    assert rel_l2(out.cpu().numpy(), P.p2m_lumped(A)) <= 1e-12
