@@ -890,9 +890,8 @@ p2m_status x2d_run_p2m(const Context* c, const Prepared& pp, const X2DLayout& X,
 
 // M2P of kind MASS or LUMPED after x2d_begin; the mass solve reports to rep
 p2m_status x2d_run_m2p(const Context* c, const Prepared& pp, const X2DLayout& X, const X2dArgs& A,
-                       const p2m_problem* prob, int32_t kind, const double* nodal,
-                       const p2m_solve_opts* opts, double* values_out, p2m_report* rep) {
-    (void)prob;
+                       int32_t kind, const double* nodal, const p2m_solve_opts* opts,
+                       double* values_out, p2m_report* rep) {
     const Mesh& m = pp.m;
     const int F = A.F, N = A.N;
     char* w8 = pp.ws;
@@ -1512,8 +1511,8 @@ p2m_status p2m_x2d_interpolate(void* ctx, const p2m_problem* prob, int32_t kind,
     X2dArgs A;
     s = x2d_begin(ctx, prob, nfields, nullptr, ws, ws_bytes, stream, rep, pp, X, A);
     if (s != P2M_OK) return s;
-    return x2d_run_m2p(c, pp, X, A, prob, kind, (const double*)nodal, opts,
-                       (double*)values_out, pp.rep);
+    return x2d_run_m2p(c, pp, X, A, kind, (const double*)nodal, opts, (double*)values_out,
+                       pp.rep);
 }
 
 p2m_status p2m_x2d_round_trip(void* ctx, const p2m_problem* prob, int32_t kind_p2m,
@@ -1541,7 +1540,7 @@ p2m_status p2m_x2d_round_trip(void* ctx, const p2m_problem* prob, int32_t kind_p
                                       nfields, (double*)values_out, reps + 1, pp.stream));
         return P2M_OK;
     }
-    return x2d_run_m2p(c, pp, X, A, prob, kind_m2p, (const double*)nodal_out, opts,
+    return x2d_run_m2p(c, pp, X, A, kind_m2p, (const double*)nodal_out, opts,
                        (double*)values_out, reps + 1);
 }
 

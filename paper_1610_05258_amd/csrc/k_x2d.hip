@@ -604,17 +604,6 @@ __global__ void k_x2d_mmesh(int nn, double cm, double* __restrict__ coef, double
     w[k] = cm;
 }
 
-// node values of a half-spacing grid H [F][2ny][2nx] (the delta P2M)
-__global__ void k_x2d_nodes(Geo g, int F, const double* __restrict__ H, double* __restrict__ out) {
-    const int k = blockIdx.x * kB + threadIdx.x;
-    const int nn = g.nx * g.ny;
-    if (k >= nn) return;
-    const int j = k / g.nx, i = k - j * g.nx;
-    const size_t gxy = (size_t)4 * nn;
-    for (int f = 0; f < F; ++f)
-        out[(size_t)f * nn + k] = H[(size_t)f * gxy + (size_t)(2 * j) * (2 * g.nx) + 2 * i];
-}
-
 // caller-order triangulation (deg, neighbours as caller numbers, shifts)
 __global__ void k_x2d_export(Geo g, const int32_t* __restrict__ perm, const int32_t* __restrict__ deg,
                              const int32_t* __restrict__ nbr, const int32_t* __restrict__ nsh,
@@ -732,12 +721,6 @@ hipError_t x2d_locate(const X2dArgs& a, bool half, double* out, hipStream_t stre
 hipError_t x2d_rhs_mesh(const X2dArgs& a, const double* H, double* b, hipStream_t stream) {
     const Geo g = geo_of(a.m, a.N, a.lx, a.ly);
     hipLaunchKernelGGL(k_x2d_rhs_mesh, dim3(grid_of(a.m.nn)), dim3(kB), 0, stream, g, a.F, H, b);
-    return hipGetLastError();
-}
-
-hipError_t x2d_nodes(const X2dArgs& a, const double* H, double* out, hipStream_t stream) {
-    const Geo g = geo_of(a.m, a.N, a.lx, a.ly);
-    hipLaunchKernelGGL(k_x2d_nodes, dim3(grid_of(a.m.nn)), dim3(kB), 0, stream, g, a.F, H, out);
     return hipGetLastError();
 }
 

@@ -201,7 +201,6 @@ hipError_t x2d_export(const X2dArgs& a, int32_t* deg_out, int32_t* nbr_out, int3
 // half-spacing grid (half = true: out [F][2ny][2nx])
 hipError_t x2d_locate(const X2dArgs& a, bool half, double* out, hipStream_t stream);
 hipError_t x2d_rhs_mesh(const X2dArgs& a, const double* H, double* b, hipStream_t stream);
-hipError_t x2d_nodes(const X2dArgs& a, const double* H, double* out, hipStream_t stream);
 hipError_t x2d_mass_mesh(const X2dArgs& a, double* coef, double* w, hipStream_t stream);
 hipError_t x2d_rhs_part(const X2dArgs& a, const double* nodal, double* c, hipStream_t stream);
 hipError_t x2d_mass_part(const X2dArgs& a, double* coef, int32_t* ecol, hipStream_t stream);
