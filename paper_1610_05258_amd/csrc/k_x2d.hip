@@ -288,11 +288,20 @@ __global__ __launch_bounds__(kB) void k_x2d_star(Geo g, const double* __restrict
 }
 
 // position of neighbour entry j of slot u among u's list, or -1
+// (a list is kCap = 32 words, 128 bytes, in a 256-byte aligned workspace: four
+// entries per 16-byte load)
 __device__ __forceinline__ int find_entry(const int32_t* __restrict__ nbr,
                                           const int32_t* __restrict__ nsh, int du, int u, int q,
                                           int s) {
-    for (int j = 0; j < du; ++j)
-        if (nbr[(size_t)u * kCap + j] == q && nsh[(size_t)u * kCap + j] == s) return j;
+    const int4* nb = (const int4*)(nbr + (size_t)u * kCap);
+    const int4* ns = (const int4*)(nsh + (size_t)u * kCap);
+    for (int j = 0; j < du; j += 4) {
+        const int4 a = nb[j >> 2], b = ns[j >> 2];
+        if (a.x == q && b.x == s) return j;
+        if (j + 1 < du && a.y == q && b.y == s) return j + 1;
+        if (j + 2 < du && a.z == q && b.z == s) return j + 2;
+        if (j + 3 < du && a.w == q && b.w == s) return j + 3;
+    }
     return -1;
 }
 
