@@ -25,7 +25,7 @@ psi_i the P1 hats of the "/"-split square mesh.  Everything here is FP64:
   int lambda_1^a lambda_2^b lambda_3^c = 2|T| a! b! c! / (a+b+c+2)! this is
   |T| (Q_a/30 - (Q_b + Q_c)/60 + 2 (Q_ab + Q_ac)/15 + Q_bc/15).
   P2M integrates A over the mesh triangles, M2P integrates Abar over the particle
-  triangles (the "equivalent procedure" for eq. (20)).
+  triangles (the same rule applied to the inverse projection, eq. (20)).
 
 Methods (Table 1 rows): delta, FLIP and PIC (Sec. 2.3 with the Delaunay volumes),
 mass-delta and full mass, and the two lumped variants.
