@@ -273,3 +273,18 @@ def test_many_fields_full_mass(B, ctx, F):
         assert rr.flags == 0 and (rr.iters > 0).all()
     out, rep = B.p2m_x2d_assign(ctx, d, B.X1D_LUMPED, v)
     assert rel_l2(out.cpu().numpy(), P.p2m_lumped(A)) <= 1e-12
+
+
+def test_deterministic(B, ctx):
+    """Two full-mass round trips and two triangulations of the same input give the same
+    bits (no accumulation depends on scheduling: the only atomic is the flag word)."""
+    x, y, d = problem(B, "mesh_96")
+    v = torch.tensor(np.random.Generator(np.random.PCG64(13)).standard_normal((3, x.size)),
+                     device="cuda")
+    n1, b1, _ = B.p2m_x2d_round_trip(ctx, d, B.X1D_MASS, B.X1D_MASS, v)
+    n2, b2, _ = B.p2m_x2d_round_trip(ctx, d, B.X1D_MASS, B.X1D_MASS, v)
+    assert torch.equal(n1, n2) and torch.equal(b1, b2)
+    t1 = B.p2m_x2d_triangulation(ctx, d)
+    t2 = B.p2m_x2d_triangulation(ctx, d)
+    for a, b in zip(t1[:3], t2[:3]):
+        assert torch.equal(a, b)
