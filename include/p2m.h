@@ -344,8 +344,11 @@ p2m_status p2m_x1d_volumes(void* ctx, const p2m_problem* prob, void* vol_out, p2
  *                  mass matrix (|T|/6 on the diagonal, |T|/12 off it, summed over
  *                  the triangles), eq. (20) (full mass).
  *   lumped M2P     c_nu / v_nu (eq. (17)).
- * Mass systems are solved by the FP64 streaming CG to opts->tol (NULL: 1e-14).
- * Kinds are those of p2m_x1d_kind; the quadrature is always the Appendix-B rule.
+ * The mesh mass system is solved directly by a 2D FFT in FP64 when both sides are
+ * powers of two up to 2048 (it is circulant; the report then shows 0 iterations),
+ * otherwise, like the particle mass system, by the FP64 streaming CG to opts->tol
+ * (NULL: 1e-14).  Kinds are those of p2m_x1d_kind; the quadrature is always the
+ * Appendix-B rule.
  * Each call synchronises `stream` once, after binning.  Particles that cannot be
  * located are left out (P2M) and get NaN (M2P). rep (device) is required.
  * --------------------------------------------------------------------------- */

@@ -697,7 +697,7 @@ p2m_solve_opts x1d_opts(const p2m_solve_opts* o, int n) {
 // ---------------------------------------------------------------------------
 struct X2DLayout {
     size_t key, counts, scan, cell_start, perm;          // binning (as in Layout)
-    size_t xs, ys, cell, As, deg, nbr, nsh, vol, volc, H, b, bw, coef, ecol, w, x;
+    size_t xs, ys, cell, As, deg, nbr, nsh, vol, volc, H, b, bw, coef, ecol, w, x, fft;
     size_t r, p0, p1, q, x64, dinv, part, report, total;
     int blocks;
 };
@@ -737,6 +737,7 @@ X2DLayout make_x2d_layout(const Context* c, const Mesh& m, int F) {
     L.ecol = take(cap * np * i4);
     L.w = take(K * d8);
     L.x = take((size_t)F * K * d8);
+    L.fft = take(ns_fft_supported(m) ? fft_workspace_bytes(m, F) : 0);
     L.r = take((size_t)F * K * d8);
     L.p0 = take((size_t)F * K * d8);
     L.p1 = take((size_t)F * K * d8);
@@ -877,6 +878,11 @@ p2m_status x2d_run_p2m(const Context* c, const Prepared& pp, const X2DLayout& X,
     P2M_TRY(x2d_rhs_mesh(A, H, b, pp.stream));
     if (kind == P2M_X1D_LUMPED) {
         P2M_TRY(x1d_div(m.nn, F, b, nullptr, m.cell_measure, out, pp.stream));
+        return P2M_OK;
+    }
+    if (ns_fft_supported(m)) {   // circulant: a direct FP64 solve by the 2D FFT
+        P2M_TRY(launch_fft_solve<double>(m, F, m.cell_measure, kFftMass, b, out, w8 + X.fft,
+                                         pp.stream));
         return P2M_OK;
     }
     double* coef = (double*)(w8 + X.coef);

@@ -183,9 +183,9 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
 // rows of length n = 2^logn, one per workgroup; sign -1 forward, +1 inverse
-// (unnormalised); REAL_IN reads floats (imaginary part 0), REAL_OUT writes the
-// real part times scale as floats
-template <bool REAL_IN, bool REAL_OUT>
+// (unnormalised); REAL_IN reads reals of type R (imaginary part 0), REAL_OUT writes
+// the real part times scale as R
+template <bool REAL_IN, bool REAL_OUT, typename R>
 __global__ void k_fft_rows(const void* __restrict__ in, void* __restrict__ out, int n, int logn,
                            double sign, double scale) {
     extern __shared__ double2 fsh[];
@@ -193,7 +193,7 @@ __global__ void k_fft_rows(const void* __restrict__ in, void* __restrict__ out, 
     double2* y = fsh + n;
     const size_t base = (size_t)blockIdx.x * n;
     for (int t = threadIdx.x; t < n; t += blockDim.x)
-        x[t] = REAL_IN ? make_double2((double)((const float*)in)[base + t], 0.0)
+        x[t] = REAL_IN ? make_double2((double)((const R*)in)[base + t], 0.0)
                        : ((const double2*)in)[base + t];
     __syncthreads();
     const int half = n >> 1;
@@ -216,7 +216,7 @@ __global__ void k_fft_rows(const void* __restrict__ in, void* __restrict__ out, 
     }
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         if (REAL_OUT)
-            ((float*)out)[base + t] = (float)(x[t].x * scale);
+            ((R*)out)[base + t] = (R)(x[t].x * scale);
         else
             ((double2*)out)[base + t] = x[t];
     }
@@ -239,16 +239,24 @@ __global__ void k_transpose_c(const double2* __restrict__ in, double2* __restric
 }
 
 // spectrum [nb][nx][ny] (row kx, column ky) divided by the system's eigenvalue:
-// 1 + s lam (viscous) or lam (pressure; the zero mode set to 0)
-__global__ void k_fft_divide(double2* __restrict__ a, int nx, int ny, int nb, double s, int pressure) {
+// 1 + s lam (viscous), lam (pressure; the zero mode set to 0), or the consistent
+// P1 mass matrix of the "/" split, s (1/2 + (cos tx + cos ty + cos(tx + ty)) / 6)
+// with s = hx hy (mass)
+__global__ void k_fft_divide(double2* __restrict__ a, int nx, int ny, int nb, double s, int mode) {
     const size_t nn = (size_t)nx * ny;
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nn * nb) return;
     const size_t e = t % nn;
     const int kx = (int)(e / ny), ky = (int)(e % ny);
-    const double lam = 4.0 - 2.0 * cospi(2.0 * kx / nx) - 2.0 * cospi(2.0 * ky / ny);
     double2 v = a[t];
-    if (pressure) {
+    if (mode == kFftMass) {
+        const double m = s * (0.5 + (cospi(2.0 * kx / nx) + cospi(2.0 * ky / ny) +
+                                     cospi(2.0 * kx / nx + 2.0 * ky / ny)) / 6.0);
+        a[t] = make_double2(v.x / m, v.y / m);
+        return;
+    }
+    const double lam = 4.0 - 2.0 * cospi(2.0 * kx / nx) - 2.0 * cospi(2.0 * ky / ny);
+    if (mode == kFftPressure) {
         if (kx == 0 && ky == 0) v = make_double2(0.0, 0.0);
         else v = make_double2(v.x / lam, v.y / lam);
     } else {
@@ -273,12 +281,15 @@ bool ns_fft_supported(const Mesh& m) {
     return m.dim == 2 && pow2(m.nx) && pow2(m.ny) && m.nx <= kFftMaxN && m.ny <= kFftMaxN;
 }
 
-size_t ns_fft_workspace_bytes(const Mesh& m) { return (size_t)2 * 2 * m.nn * sizeof(double2); }
+size_t ns_fft_workspace_bytes(const Mesh& m) { return fft_workspace_bytes(m, 2); }
 
-hipError_t launch_ns_fft_solve(const Mesh& m, int nb, double s, int pressure, const float* rhs,
-                               float* x, void* ws, hipStream_t stream) {
+size_t fft_workspace_bytes(const Mesh& m, int nb) { return (size_t)2 * nb * m.nn * sizeof(double2); }
+
+template <typename Real>
+hipError_t launch_fft_solve(const Mesh& m, int nb, double s, int mode, const Real* rhs, Real* x,
+                            void* ws, hipStream_t stream) {
     double2* fa = (double2*)ws;
-    double2* fb = fa + (size_t)2 * m.nn;
+    double2* fb = fa + (size_t)nb * m.nn;
     const int nx = m.nx, ny = m.ny, lx = ilog2(nx), ly = ilog2(ny);
     auto rows = [&](int n, int nrows, const void* in, void* out, double sign, double scale,
                     bool real_in, bool real_out) {
@@ -286,13 +297,13 @@ hipError_t launch_ns_fft_solve(const Mesh& m, int nb, double s, int pressure, co
         const size_t shm = (size_t)2 * n * sizeof(double2);
         const int lg = ilog2(n);
         if (real_in)
-            hipLaunchKernelGGL((k_fft_rows<true, false>), dim3(nrows), dim3(threads), shm, stream, in, out, n,
-                               lg, sign, scale);
+            hipLaunchKernelGGL((k_fft_rows<true, false, Real>), dim3(nrows), dim3(threads), shm, stream, in, out,
+                               n, lg, sign, scale);
         else if (real_out)
-            hipLaunchKernelGGL((k_fft_rows<false, true>), dim3(nrows), dim3(threads), shm, stream, in, out, n,
-                               lg, sign, scale);
+            hipLaunchKernelGGL((k_fft_rows<false, true, Real>), dim3(nrows), dim3(threads), shm, stream, in, out,
+                               n, lg, sign, scale);
         else
-            hipLaunchKernelGGL((k_fft_rows<false, false>), dim3(nrows), dim3(threads), shm, stream, in, out,
+            hipLaunchKernelGGL((k_fft_rows<false, false, Real>), dim3(nrows), dim3(threads), shm, stream, in, out,
                                n, lg, sign, scale);
         return hipGetLastError();
     };
@@ -308,11 +319,19 @@ hipError_t launch_ns_fft_solve(const Mesh& m, int nb, double s, int pressure, co
     if ((e = transpose(fa, fb, ny, nx)) != hipSuccess) return e;
     if ((e = rows(ny, nb * nx, fb, fa, -1.0, 1.0, false, false)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_fft_divide, dim3(grid_of(nb * m.nn, 256)), dim3(256), 0, stream, fa, nx, ny, nb,
-                       s, pressure);
+                       s, mode);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = rows(ny, nb * nx, fa, fb, 1.0, 1.0, false, false)) != hipSuccess) return e;
     if ((e = transpose(fb, fa, nx, ny)) != hipSuccess) return e;
     return rows(nx, nb * ny, fa, x, 1.0, 1.0 / ((double)nx * ny), false, true);
+}
+template hipError_t launch_fft_solve<double>(const Mesh&, int, double, int, const double*, double*,
+                                             void*, hipStream_t);
+
+hipError_t launch_ns_fft_solve(const Mesh& m, int nb, double s, int pressure, const float* rhs,
+                               float* x, void* ws, hipStream_t stream) {
+    return launch_fft_solve<float>(m, nb, s, pressure ? kFftPressure : kFftViscous, rhs, x, ws,
+                                   stream);
 }
 
 hipError_t launch_ns_coef(const Mesh& m, float s, float* cv, float* wv, float* cp, float* wp,

@@ -288,3 +288,20 @@ def test_deterministic(B, ctx):
     t2 = B.p2m_x2d_triangulation(ctx, d)
     for a, b in zip(t1[:3], t2[:3]):
         assert torch.equal(a, b)
+
+
+def test_mass_p2m_fft_on_power_of_two_mesh(B, ctx):
+    """On a 32 x 16 mesh (power-of-two sides, rectangular box) the mesh mass system is
+    solved directly by the 2D FFT (0 iterations in the report); the result matches the
+    oracle's (an FFT solve too, written independently) and the CG path's bar."""
+    nx, ny, lx, ly = 32, 16, 2.0, 1.0
+    x, y = wl.stratified_2d(17, nx, ny, 4, lx, ly)
+    d = B.Particles(dim=2, nx=nx, ny=ny, lx=lx, ly=ly,
+                    x=torch.tensor(x, device="cuda"), y=torch.tensor(y, device="cuda"))
+    P = p2.Paper2D(x, y, nx, ny, lx, ly)
+    A = np.random.Generator(np.random.PCG64(18)).standard_normal((3, x.size))
+    say("[x2d] FFT mass P2M")
+    out, rep = B.p2m_x2d_assign(ctx, d, B.X1D_MASS, torch.tensor(A, device="cuda"))
+    r = B.read_report(rep, 3)
+    assert r.flags == 0 and (r.iters == 0).all()
+    assert rel_l2(out.cpu().numpy(), P.p2m_mass(A)) <= 1e-12
