@@ -345,7 +345,8 @@ p2m_status p2m_x1d_volumes(void* ctx, const p2m_problem* prob, void* vol_out, p2
  *                  the triangles), eq. (20) (full mass).
  *   lumped M2P     c_nu / v_nu (eq. (17)).
  * The mesh mass system is solved directly by a 2D FFT in FP64 when both sides are
- * powers of two up to 2048 (it is circulant; the report then shows 0 iterations),
+ * at most 1024 or powers of two up to 2048 (it is circulant; the report then shows
+ * 0 iterations),
  * otherwise, like the particle mass system, by the FP64 streaming CG to opts->tol
  * (NULL: 1e-14).  Kinds are those of p2m_x1d_kind; the quadrature is always the
  * Appendix-B rule.

@@ -737,7 +737,7 @@ X2DLayout make_x2d_layout(const Context* c, const Mesh& m, int F) {
     L.ecol = take(cap * np * i4);
     L.w = take(K * d8);
     L.x = take((size_t)F * K * d8);
-    L.fft = take(ns_fft_supported(m) ? fft_workspace_bytes(m, F) : 0);
+    L.fft = take(fft_supported(m) ? fft_workspace_bytes(m, F) : 0);
     L.r = take((size_t)F * K * d8);
     L.p0 = take((size_t)F * K * d8);
     L.p1 = take((size_t)F * K * d8);
@@ -880,7 +880,7 @@ p2m_status x2d_run_p2m(const Context* c, const Prepared& pp, const X2DLayout& X,
         P2M_TRY(x1d_div(m.nn, F, b, nullptr, m.cell_measure, out, pp.stream));
         return P2M_OK;
     }
-    if (ns_fft_supported(m)) {   // circulant: a direct FP64 solve by the 2D FFT
+    if (fft_supported(m)) {   // circulant: a direct FP64 solve by the 2D discrete Fourier transform
         P2M_TRY(launch_fft_solve<double>(m, F, m.cell_measure, kFftMass, b, out, w8 + X.fft,
                                          pp.stream));
         return P2M_OK;

@@ -169,33 +169,25 @@ __global__ void k_ns_advect(Mesh m, double lx, double ly, double dt, const float
 }
 
 // ---------------------------------------------------------------------------
-// Direct solves of the two mesh systems when both mesh sides are powers of two:
+// Direct solves of the mesh systems by the 2D discrete Fourier transform:
 // I + s K and K are circulant on the periodic mesh, diagonal in the 2D discrete
 // Fourier basis with eigenvalues 1 + s lam and lam, lam(kx, ky) = 4 - 2 cos(2 pi
 // kx / nx) - 2 cos(2 pi ky / ny) (the five-point symbol); K's zero mode is the
 // constant, left at 0 (zero-mean pressure).  Transforms in FP64: row transforms
-// of one length per workgroup (radix-2 Stockham in LDS, natural order in and out),
-// a tiled transpose between the two directions.
+// of one length per workgroup (radix-2 Stockham in LDS, natural order in and out;
+// other lengths by Bluestein's algorithm over a power-of-two convolution), a tiled
+// transpose between the two directions.  The fluid step takes them for
+// power-of-two sides only.
 // ---------------------------------------------------------------------------
 constexpr int kFftMaxN = 2048;   // 2n complex doubles of LDS = 64 KB
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 
-// rows of length n = 2^logn, one per workgroup; sign -1 forward, +1 inverse
-// (unnormalised); REAL_IN reads reals of type R (imaginary part 0), REAL_OUT writes
-// the real part times scale as R
-template <bool REAL_IN, bool REAL_OUT, typename R>
-__global__ void k_fft_rows(const void* __restrict__ in, void* __restrict__ out, int n, int logn,
-                           double sign, double scale) {
-    extern __shared__ double2 fsh[];
-    double2* x = fsh;
-    double2* y = fsh + n;
-    const size_t base = (size_t)blockIdx.x * n;
-    for (int t = threadIdx.x; t < n; t += blockDim.x)
-        x[t] = REAL_IN ? make_double2((double)((const R*)in)[base + t], 0.0)
-                       : ((const double2*)in)[base + t];
-    __syncthreads();
+// radix-2 Stockham transform of x[0..n), n = 2^logn, in LDS (y: scratch of the
+// same size); the result ends in x (the two pointers are swapped per pass).  The
+// workgroup's threads share the work; the caller synchronises before.
+__device__ __forceinline__ void fft_lds(double2*& x, double2*& y, int n, int logn, double sign) {
     const int half = n >> 1;
     for (int ls = 0; ls < logn; ++ls) {
         const int ns = 1 << ls;
@@ -214,11 +206,97 @@ __global__ void k_fft_rows(const void* __restrict__ in, void* __restrict__ out, 
         x = y;
         y = t;
     }
+}
+
+// rows of length n = 2^logn, one per workgroup; sign -1 forward, +1 inverse
+// (unnormalised); REAL_IN reads reals of type R (imaginary part 0), REAL_OUT writes
+// the real part times scale as R
+template <bool REAL_IN, bool REAL_OUT, typename R>
+__global__ void k_fft_rows(const void* __restrict__ in, void* __restrict__ out, int n, int logn,
+                           double sign, double scale) {
+    extern __shared__ double2 fsh[];
+    double2* x = fsh;
+    double2* y = fsh + n;
+    const size_t base = (size_t)blockIdx.x * n;
+    for (int t = threadIdx.x; t < n; t += blockDim.x)
+        x[t] = REAL_IN ? make_double2((double)((const R*)in)[base + t], 0.0)
+                       : ((const double2*)in)[base + t];
+    __syncthreads();
+    fft_lds(x, y, n, logn, sign);
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         if (REAL_OUT)
             ((R*)out)[base + t] = (R)(x[t].x * scale);
         else
             ((double2*)out)[base + t] = x[t];
+    }
+}
+
+// Rows of any length n <= kFftMaxN / 2 by Bluestein's chirp-z algorithm: with
+// c_j = exp(-i pi j^2 / n), the DFT is X_k = c_k sum_j (x_j c_j) conj(c_{k-j}), a
+// circular convolution of length M = 2^logm >= 2n - 1 done by two radix-2
+// transforms and the transform bhat of the chirp (k_fft_chirp).  The inverse
+// (sign +1) conjugates on the way in and out.  Arguments as k_fft_rows.
+__device__ __forceinline__ double2 chirp(int j, int n) {
+    double sn, cs;
+    sincospi(-(double)(((long long)j * j) % (2LL * n)) / (double)n, &sn, &cs);
+    return make_double2(cs, sn);
+}
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// bhat = FFT_M(b), b_m = conj(c_m) for 0 <= m < n, b_{M-m} = conj(c_m) for
+// 0 < m < n, 0 elsewhere; one workgroup
+__global__ void k_fft_chirp(double2* __restrict__ bhat, int n, int m, int logm) {
+    extern __shared__ double2 fsh[];
+    double2* x = fsh;
+    double2* y = fsh + m;
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+        const int j = t < n ? t : (t > m - n ? m - t : -1);
+        double2 v = make_double2(0.0, 0.0);
+        if (j >= 0) {
+            const double2 c = chirp(j, n);
+            v = make_double2(c.x, -c.y);
+        }
+        x[t] = v;
+    }
+    __syncthreads();
+    fft_lds(x, y, m, logm, -1.0);
+    for (int t = threadIdx.x; t < m; t += blockDim.x) bhat[t] = x[t];
+}
+
+template <bool REAL_IN, bool REAL_OUT, typename R>
+__global__ void k_fft_rows_chirp(const void* __restrict__ in, void* __restrict__ out, int n, int m,
+                                 int logm, const double2* __restrict__ bhat, double sign,
+                                 double scale) {
+    extern __shared__ double2 fsh[];
+    double2* x = fsh;
+    double2* y = fsh + m;
+    const size_t base = (size_t)blockIdx.x * n;
+    const bool inv = sign > 0.0;
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+        double2 v = make_double2(0.0, 0.0);
+        if (t < n) {
+            v = REAL_IN ? make_double2((double)((const R*)in)[base + t], 0.0)
+                        : ((const double2*)in)[base + t];
+            if (inv) v.y = -v.y;
+            v = cmul(v, chirp(t, n));
+        }
+        x[t] = v;
+    }
+    __syncthreads();
+    fft_lds(x, y, m, logm, -1.0);
+    for (int t = threadIdx.x; t < m; t += blockDim.x) x[t] = cmul(x[t], bhat[t]);
+    __syncthreads();
+    fft_lds(x, y, m, logm, 1.0);
+    const double im = 1.0 / (double)m;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        double2 v = cmul(x[t], chirp(t, n));
+        v = make_double2(v.x * im, (inv ? -v.y : v.y) * im);
+        if (REAL_OUT)
+            ((R*)out)[base + t] = (R)(v.x * scale);
+        else
+            ((double2*)out)[base + t] = v;
     }
 }
 
@@ -283,16 +361,61 @@ bool ns_fft_supported(const Mesh& m) {
 
 size_t ns_fft_workspace_bytes(const Mesh& m) { return fft_workspace_bytes(m, 2); }
 
-size_t fft_workspace_bytes(const Mesh& m, int nb) { return (size_t)2 * nb * m.nn * sizeof(double2); }
+// a side the row transforms take: a power of two up to kFftMaxN, or any length up
+// to kFftMaxN / 2 (Bluestein, convolution length at most kFftMaxN)
+static bool fft_side(int n) {
+    return n >= 2 && (((n & (n - 1)) == 0 && n <= kFftMaxN) || 2 * n - 1 <= kFftMaxN);
+}
+
+bool fft_supported(const Mesh& m) { return m.dim == 2 && fft_side(m.nx) && fft_side(m.ny); }
+
+// two complex planes of nb fields, then the chirp transforms of the two sides
+size_t fft_workspace_bytes(const Mesh& m, int nb) {
+    return ((size_t)2 * nb * m.nn + 2 * kFftMaxN) * sizeof(double2);
+}
 
 template <typename Real>
 hipError_t launch_fft_solve(const Mesh& m, int nb, double s, int mode, const Real* rhs, Real* x,
                             void* ws, hipStream_t stream) {
     double2* fa = (double2*)ws;
     double2* fb = fa + (size_t)nb * m.nn;
+    double2* chirp_tab[2] = {fb + (size_t)nb * m.nn, fb + (size_t)nb * m.nn + kFftMaxN};
+    auto conv_len = [](int n) {
+        int lg = 0;
+        while ((1 << lg) < 2 * n - 1) ++lg;
+        return lg;
+    };
+    // the chirp transform of each side that is not a power of two (x: table 0, y: 1)
+    const int sides[2] = {m.nx, m.ny};
+    for (int d = 0; d < 2; ++d) {
+        const int n = sides[d];
+        if ((n & (n - 1)) == 0) continue;
+        const int lg = conv_len(n), mm = 1 << lg;
+        const int threads = mm / 2 < 256 ? (mm / 2 < 64 ? 64 : mm / 2) : 256;
+        hipLaunchKernelGGL(k_fft_chirp, dim3(1), dim3(threads), (size_t)2 * mm * sizeof(double2),
+                           stream, chirp_tab[d], n, mm, lg);
+        const hipError_t e0 = hipGetLastError();
+        if (e0 != hipSuccess) return e0;
+    }
     const int nx = m.nx, ny = m.ny, lx = ilog2(nx), ly = ilog2(ny);
     auto rows = [&](int n, int nrows, const void* in, void* out, double sign, double scale,
                     bool real_in, bool real_out) {
+        if ((n & (n - 1)) != 0) {   // Bluestein
+            const int lg = conv_len(n), mm = 1 << lg;
+            const int threads = mm / 2 < 256 ? (mm / 2 < 64 ? 64 : mm / 2) : 256;
+            const size_t shm = (size_t)2 * mm * sizeof(double2);
+            const double2* tab = chirp_tab[n == m.nx ? 0 : 1];
+            if (real_in)
+                hipLaunchKernelGGL((k_fft_rows_chirp<true, false, Real>), dim3(nrows), dim3(threads), shm,
+                                   stream, in, out, n, mm, lg, tab, sign, scale);
+            else if (real_out)
+                hipLaunchKernelGGL((k_fft_rows_chirp<false, true, Real>), dim3(nrows), dim3(threads), shm,
+                                   stream, in, out, n, mm, lg, tab, sign, scale);
+            else
+                hipLaunchKernelGGL((k_fft_rows_chirp<false, false, Real>), dim3(nrows), dim3(threads),
+                                   shm, stream, in, out, n, mm, lg, tab, sign, scale);
+            return hipGetLastError();
+        }
         const int threads = n / 2 < 256 ? (n / 2 < 64 ? 64 : n / 2) : 256;
         const size_t shm = (size_t)2 * n * sizeof(double2);
         const int lg = ilog2(n);

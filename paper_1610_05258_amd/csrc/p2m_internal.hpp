@@ -333,7 +333,9 @@ size_t ns_fft_workspace_bytes(const Mesh& m);   // for nb <= 2
 // the same 2D FFT solve for nb right-hand sides of type R (mode: kFftViscous
 // (I + s K), kFftPressure (K, zero mean), kFftMass (the consistent P1 mass matrix
 // of the "/" split with s = hx hy)); workspace fft_workspace_bytes(m, nb)
+// Sides: powers of two up to 2048, other lengths up to 1024 (fft_supported).
 enum { kFftViscous = 0, kFftPressure = 1, kFftMass = 2 };
+bool fft_supported(const Mesh& m);
 size_t fft_workspace_bytes(const Mesh& m, int nb);
 template <typename R>
 hipError_t launch_fft_solve(const Mesh& m, int nb, double s, int mode, const R* rhs, R* x,

@@ -268,9 +268,10 @@ def test_many_fields_full_mass(B, ctx, F):
     want_nodal = P.p2m_mass(A)
     assert rel_l2(nodal.cpu().numpy(), want_nodal) <= 1e-11
     assert rel_l2(back.cpu().numpy(), P.m2p_mass(nodal.cpu().numpy())) <= 1e-11
-    for r in (0, 1):
-        rr = B.Report.decode(reps[r].cpu().numpy().tobytes(), F)
-        assert rr.flags == 0 and (rr.iters > 0).all()
+    rp = B.Report.decode(reps[0].cpu().numpy().tobytes(), F)
+    rm = B.Report.decode(reps[1].cpu().numpy().tobytes(), F)
+    assert rp.flags == 0 and (rp.iters == 0).all()    # the mesh system by the FFT
+    assert rm.flags == 0 and (rm.iters > 0).all()     # the particle system by CG
     out, rep = B.p2m_x2d_assign(ctx, d, B.X1D_LUMPED, v)
     assert rel_l2(out.cpu().numpy(), P.p2m_lumped(A)) <= 1e-12
 
@@ -290,11 +291,13 @@ def test_deterministic(B, ctx):
         assert torch.equal(a, b)
 
 
-def test_mass_p2m_fft_on_power_of_two_mesh(B, ctx):
-    """On a 32 x 16 mesh (power-of-two sides, rectangular box) the mesh mass system is
-    solved directly by the 2D FFT (0 iterations in the report); the result matches the
-    oracle's (an FFT solve too, written independently) and the CG path's bar."""
-    nx, ny, lx, ly = 32, 16, 2.0, 1.0
+@pytest.mark.parametrize("nx,ny", [(32, 16), (90, 90), (30, 17)])
+def test_mass_p2m_fft(B, ctx, nx, ny):
+    """The mesh mass system solved directly by the 2D discrete Fourier transform (0
+    iterations in the report): power-of-two sides by radix 2, 90 and 30 x 17 by
+    Bluestein's algorithm; the result matches the oracle's (an FFT solve too,
+    written independently)."""
+    lx, ly = 2.0, 1.0
     x, y = wl.stratified_2d(17, nx, ny, 4, lx, ly)
     d = B.Particles(dim=2, nx=nx, ny=ny, lx=lx, ly=ly,
                     x=torch.tensor(x, device="cuda"), y=torch.tensor(y, device="cuda"))
