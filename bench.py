@@ -444,7 +444,47 @@ def ns_leg(B, ctx, n=256, ppc=4, t_end=0.25, tol=1e-8, tune=True):
         log(f"bench: fluid {name}: {out[name]['ms_per_step']:.3f} ms/step, L2 error at t={t_end:g} {err:.3e}, "
             f"last step iterations {out[name]['last_step_iters']}")
     out["mass_over_flip_error"] = out["mass"]["l2_error"] / out["flip"]["l2_error"]
+    out["side_not_power_of_two"] = ns_fft_vs_solver(B, ctx, tol=tol)
     return out
+
+
+def ns_fft_vs_solver(B, ctx, n=192, ppc=4, steps=8, tol=1e-8):
+    """One mesh side that is not a power of two (192): FLIP steps of the fluid solver
+    with its viscous and pressure systems by the 2D FFT (Bluestein's algorithm for
+    the rows) and by the iterative mass-matrix solver (P2M_OPT_FFT off), ms per step
+    and the largest difference of the mesh velocities after `steps` steps."""
+    import torch
+    from paper_1610_05258_amd import workloads as wl
+    nu, dt = 0.005, 0.5 / n
+    opts = B.solve_opts(tol=tol, maxit=4000, max_refine=20)
+    res = dict(workload=f"taylor-green vortex sheet, {n}x{n}, {ppc} ppc, FLIP, {steps} steps")
+    mvs = {}
+    for name, fft in (("fft", True), ("solver", False)):
+        prob, vel0 = wl.tg_fluid_2d(seed=4, n=n, ppc=ppc)
+        d = B.particles_from(prob, dtype=torch.float32)
+        vel = torch.as_tensor(vel0).cuda()
+        mv = torch.empty((2, n * n), dtype=torch.float32, device="cuda")
+        reps = torch.zeros((3, B.REPORT_BYTES), dtype=torch.uint8, device="cuda")
+        ctx.set_fft(fft)
+        try:
+            ws = ctx.workspace(B.ns_workspace_size(ctx, d))
+            B.p2m_ns_step(ctx, d, vel, B.NS_FLIP, dt, nu, opts, mesh_vel=mv, reps=reps, ws=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps - 1):
+                B.p2m_ns_step(ctx, d, vel, B.NS_FLIP, dt, nu, opts, mesh_vel=mv, reps=reps, ws=ws)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        finally:
+            ctx.set_fft(True)
+        r = B.read_report(reps[2], 1)
+        mvs[name] = mv.cpu().numpy().astype(np.float64)
+        res[name] = dict(ms_per_step=wall / (steps - 1) * 1e3, pressure_iters=int(r.iters[0]))
+    res["mesh_velocity_max_diff"] = float(np.abs(mvs["fft"] - mvs["solver"]).max())
+    log(f"bench: fluid at {n}^2 (side not a power of two): FFT {res['fft']['ms_per_step']:.3f} ms/step, "
+        f"solver {res['solver']['ms_per_step']:.3f} ms/step ({res['solver']['pressure_iters']} pressure "
+        f"iterations), max velocity difference {res['mesh_velocity_max_diff']:.1e}")
+    return res
 
 
 def learned_leg(B, ctx, reps=5, tol=1e-6):

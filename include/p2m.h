@@ -175,8 +175,14 @@ enum { P2M_SOLVER_AUTO = 0, P2M_SOLVER_STREAMING = 1, P2M_SOLVER_RESIDENT = 2, P
  *                      workgroup then stops at its first barrier with
  *                      P2M_FLAG_BREAKDOWN | P2M_FLAG_NOT_CONVERGED and the last
  *                      FP64 solution it held as the result (for testing the
- *                      timeout handling; every kernel still runs to its end) */
-enum { P2M_OPT_SOLVER = 0, P2M_OPT_PLANS = 1, P2M_OPT_SCAN_SPIN = 2, P2M_OPT_SOLVE_SPIN = 3 };
+ *                      timeout handling; every kernel still runs to its end)
+ *   P2M_OPT_FFT        1 (default): the circulant mesh systems of p2m_ns_step and
+ *                      the paper-exact 2D mass P2M are solved directly by the 2D
+ *                      discrete Fourier transform when both mesh sides are at most
+ *                      1024 or powers of two up to 2048; 0: always by the iterative
+ *                      mass-matrix solver */
+enum { P2M_OPT_SOLVER = 0, P2M_OPT_PLANS = 1, P2M_OPT_SCAN_SPIN = 2, P2M_OPT_SOLVE_SPIN = 3,
+       P2M_OPT_FFT = 4 };
 p2m_status p2m_set_option(void* ctx, int32_t option, int32_t value);
 
 /* Bytes of workspace that every call below needs for this problem and field count

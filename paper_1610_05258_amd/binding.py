@@ -34,7 +34,7 @@ FLAG_TRIANGULATION = 1 << 7
 REPORT_BYTES = 144
 MAX_FIELDS = 8
 SOLVER_AUTO, SOLVER_STREAMING, SOLVER_RESIDENT, SOLVER_TILES, SOLVER_RESIDENT_CHEB = 0, 1, 2, 3, 4
-OPT_SOLVER, OPT_PLANS, OPT_SCAN_SPIN, OPT_SOLVE_SPIN = 0, 1, 2, 3
+OPT_SOLVER, OPT_PLANS, OPT_SCAN_SPIN, OPT_SOLVE_SPIN, OPT_FFT = 0, 1, 2, 3, 4
 
 EXPORTS = ("p2m_status_string", "p2m_create", "p2m_destroy", "p2m_workspace_size", "p2m_bin",
            "p2m_assemble", "p2m_assign", "p2m_interpolate", "p2m_mass_assign", "p2m_mass_solve",
@@ -288,6 +288,11 @@ class Context:
     def set_scan_spin(self, value: int):
         """Bound of the binning scan's wait (0: default; < 0: end every wait at once)."""
         _check(lib().p2m_set_option(self.handle, OPT_SCAN_SPIN, int(value)), "p2m_set_option")
+
+    def set_fft(self, on: bool):
+        """Direct FFT solves of the circulant mesh systems where the sides allow (default)
+        or always the iterative mass-matrix solver."""
+        _check(lib().p2m_set_option(self.handle, OPT_FFT, 1 if on else 0), "p2m_set_option")
 
     def set_solve_spin(self, value: int):
         """Bound of a mass solve's grid-barrier wait (0: default; < 0: end every wait at once)."""

@@ -54,6 +54,7 @@ struct Context {
     int use_plans;          // 1: apply tuned plans of the problem's shape class
     long scan_spin;         // bound of the binning scan's look-back wait (< 0: test hook)
     long solve_spin;        // bound of a solve's grid-barrier wait (< 0: test hook)
+    int fft;                // 1: circulant mesh systems by the 2D FFT where the sides allow
     BatchCache* batch;      // created on the first batched call
     const float* learned;   // parameters of the learned start (device), or null
     PlanCache* plans;       // created on the first tuned or loaded plan
@@ -880,7 +881,7 @@ p2m_status x2d_run_p2m(const Context* c, const Prepared& pp, const X2DLayout& X,
         P2M_TRY(x1d_div(m.nn, F, b, nullptr, m.cell_measure, out, pp.stream));
         return P2M_OK;
     }
-    if (fft_supported(m)) {   // circulant: a direct FP64 solve by the 2D discrete Fourier transform
+    if (c->fft && fft_supported(m)) {   // circulant: a direct FP64 solve by the 2D DFT
         P2M_TRY(launch_fft_solve<double>(m, F, m.cell_measure, kFftMass, b, out, w8 + X.fft,
                                          pp.stream));
         return P2M_OK;
@@ -965,6 +966,7 @@ p2m_status p2m_create(void** ctx, int device) {
     c->use_plans = 1;
     c->scan_spin = kScanSpinDefault;
     c->solve_spin = kSolveSpinDefault;
+    c->fft = 1;
     c->scratch = scratch_address(device);
     if (c->cg_blocks_f32 <= 0 || c->cg_blocks_f64 <= 0) {
         free(c);
@@ -993,6 +995,11 @@ p2m_status p2m_set_option(void* ctx, int32_t option, int32_t value) {
     }
     if (option == P2M_OPT_SOLVE_SPIN) {
         c->solve_spin = value == 0 ? kSolveSpinDefault : (long)value;
+        return P2M_OK;
+    }
+    if (option == P2M_OPT_FFT) {
+        if (value != 0 && value != 1) return P2M_ERR_INVALID_ARG;
+        c->fft = value;
         return P2M_OK;
     }
     return P2M_ERR_INVALID_ARG;
@@ -1153,7 +1160,7 @@ NsLayout make_ns_layout(size_t base, const Mesh& m) {
     N.wp = take(nn * sizeof(float));
     N.rhs = take(nn * sizeof(float));
     N.p = take(nn * sizeof(float));
-    N.fft = take(ns_fft_supported(m) ? ns_fft_workspace_bytes(m) : 0);
+    N.fft = take(fft_supported(m) ? fft_workspace_bytes(m, 2) : 0);
     N.total = off;
     return N;
 }
@@ -1224,12 +1231,12 @@ p2m_status p2m_ns_step(void* ctx, const p2m_problem* prob, int32_t assign, doubl
     }
     if (s != P2M_OK) return s;
     // 2. viscous step (I + s K) U* = Ubar (report 1); 3. pressure K p = -(1/dt) D U*
-    //    (report 2).  Power-of-two sides: both by 2D FFT, exactly (zero-mean pressure;
-    //    the reports show no iteration).  Otherwise by the mass-matrix solver, node 0
-    //    holding the pressure at 0; a Poisson system needs O(n) CG iterations, so the
-    //    pressure solve's cap is at least 64 per mesh side.
+    //    (report 2).  Sides the FFT takes (P2M_OPT_FFT on): both by 2D FFT, exactly
+    //    (zero-mean pressure; the reports show no iteration).  Otherwise by the
+    //    mass-matrix solver, node 0 holding the pressure at 0; a Poisson system needs
+    //    O(n) CG iterations, so the pressure solve's cap is at least 64 per mesh side.
     const double sv = dt * nu / (h * h);
-    if (ns_fft_supported(m)) {
+    if (c->fft && fft_supported(m)) {
         P2M_TRY(launch_report_clear(&reps[1], pp.stream));
         P2M_TRY(launch_report_clear(&reps[2], pp.stream));
         P2M_TRY(launch_ns_fft_solve(m, 2, sv, 0, ubar, ustar, w + N.fft, pp.stream));

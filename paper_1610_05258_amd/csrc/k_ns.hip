@@ -176,8 +176,7 @@ __global__ void k_ns_advect(Mesh m, double lx, double ly, double dt, const float
 // constant, left at 0 (zero-mean pressure).  Transforms in FP64: row transforms
 // of one length per workgroup (radix-2 Stockham in LDS, natural order in and out;
 // other lengths by Bluestein's algorithm over a power-of-two convolution), a tiled
-// transpose between the two directions.  The fluid step takes them for
-// power-of-two sides only.
+// transpose between the two directions.
 // ---------------------------------------------------------------------------
 constexpr int kFftMaxN = 2048;   // 2n complex doubles of LDS = 64 KB
 
@@ -354,12 +353,6 @@ inline int ilog2(int n) {
 
 }  // namespace
 
-bool ns_fft_supported(const Mesh& m) {
-    auto pow2 = [](int n) { return n >= 2 && (n & (n - 1)) == 0; };
-    return m.dim == 2 && pow2(m.nx) && pow2(m.ny) && m.nx <= kFftMaxN && m.ny <= kFftMaxN;
-}
-
-size_t ns_fft_workspace_bytes(const Mesh& m) { return fft_workspace_bytes(m, 2); }
 
 // a side the row transforms take: a power of two up to kFftMaxN, or any length up
 // to kFftMaxN / 2 (Bluestein, convolution length at most kFftMaxN)

@@ -328,8 +328,6 @@ hipError_t launch_ns_div(const Mesh& m, double scale, int pin, const float* U, f
                          hipStream_t stream);
 // direct solve of nb right-hand sides of the viscous (I + s K, pressure = 0) or the
 // pressure system (K, zero-mean solution) by 2D FFT; power-of-two sides <= 2048
-bool ns_fft_supported(const Mesh& m);
-size_t ns_fft_workspace_bytes(const Mesh& m);   // for nb <= 2
 // the same 2D FFT solve for nb right-hand sides of type R (mode: kFftViscous
 // (I + s K), kFftPressure (K, zero mean), kFftMass (the consistent P1 mass matrix
 // of the "/" split with s = hx hy)); workspace fft_workspace_bytes(m, nb)
@@ -341,7 +339,7 @@ template <typename R>
 hipError_t launch_fft_solve(const Mesh& m, int nb, double s, int mode, const R* rhs, R* x,
                             void* ws, hipStream_t stream);
 hipError_t launch_ns_fft_solve(const Mesh& m, int nb, double s, int pressure, const float* rhs,
-                               float* x, void* ws, hipStream_t stream);
+                               float* x, void* ws, hipStream_t stream);   // workspace for nb <= 2
 hipError_t launch_ns_correct(const Mesh& m, double factor, const float* Us, const float* p,
                              float* Un, hipStream_t stream);
 hipError_t launch_ns_advect(const Mesh& m, double lx, double ly, double dt, const float* x,

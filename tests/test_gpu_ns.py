@@ -71,23 +71,24 @@ def gpu_steps(B, ctx, prob, a, method, dt, steps, tol=1e-8):
 
 
 @pytest.mark.parametrize("method", ns.ASSIGN)
-@pytest.mark.parametrize("n", [32, 48, 256])
-def test_one_step_against_the_oracle(B, method, n):
-    """Power-of-two sides solve the two mesh systems by FFT (no iteration), 48 x 48
-    by the mass-matrix solver (node 0 holding the pressure)."""
+@pytest.mark.parametrize("n,fft", [(32, True), (48, True), (48, False), (256, True)])
+def test_one_step_against_the_oracle(B, method, n, fft):
+    """The two mesh systems solved by the 2D FFT (no iteration; 32 and 256 radix 2,
+    48 by Bluestein's algorithm), and with P2M_OPT_FFT off by the mass-matrix solver
+    (node 0 holding the pressure)."""
     prob, a = tg_problem(n, 2, seed=7)
     dt = 0.5 / n
-    say(f"[ns one step] {method} {n}x{n}, {prob['x'].size} particles")
+    say(f"[ns one step] {method} {n}x{n}, fft {fft}, {prob['x'].size} particles")
     ctx = B.Context(0)
     try:
+        ctx.set_fft(fft)
         x, y, vel, mv, reps = gpu_steps(B, ctx, prob, a, method, dt, 1)
     finally:
         ctx.close()
     for k, r in enumerate(reps):
         say(f"  report {k}: iters {r.iters[:2].tolist()} refines {r.refines[:2].tolist()} flags {r.flags}")
         assert not (r.flags & (B.FLAG_NOT_CONVERGED | B.FLAG_BREAKDOWN | B.FLAG_RANGE | B.FLAG_NONFINITE))
-    pow2 = (n & (n - 1)) == 0
-    assert (reps[2].iters[0] == 0) if pow2 else (reps[2].iters[0] > 0)
+    assert (reps[2].iters[0] == 0) if fft else (reps[2].iters[0] > 0)
     new, a_ref, U_ref = ns.step(f64(prob), a.astype(np.float64), method, dt, NU)
     eU, ea = rel_l2(mv, U_ref), rel_l2(vel, a_ref)
     ex = max(torus_dist(x, new["x"]).max(), torus_dist(y, new["y"]).max())
@@ -164,15 +165,18 @@ def test_argument_errors(B):
         ctx.close()
 
 
-@pytest.mark.parametrize("n", [2, 3, 4, 6])
-def test_tiny_meshes_against_the_oracle(B, n):
-    """Meshes of 2 to 6 nodes a side (a node's periodic neighbours repeat at 2; 3 and 6
-    take the solver path, 2 and 4 the FFT path), both assignments, one step."""
+@pytest.mark.parametrize("n,fft", [(2, True), (3, True), (3, False), (4, True), (6, True),
+                                   (6, False), (2, False)])
+def test_tiny_meshes_against_the_oracle(B, n, fft):
+    """Meshes of 2 to 6 nodes a side (a node's periodic neighbours repeat at 2), by the
+    FFT (3 and 6 by Bluestein's algorithm) and by the solver, both assignments, one
+    step."""
     for method in ns.ASSIGN:
         prob, a = tg_problem(n, 4, seed=40 + n)
         dt = 0.5 / n
         ctx = B.Context(0)
         try:
+            ctx.set_fft(fft)
             x, y, vel, mv, reps = gpu_steps(B, ctx, prob, a, method, dt, 1)
         finally:
             ctx.close()

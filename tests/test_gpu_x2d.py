@@ -308,3 +308,21 @@ def test_mass_p2m_fft(B, ctx, nx, ny):
     r = B.read_report(rep, 3)
     assert r.flags == 0 and (r.iters == 0).all()
     assert rel_l2(out.cpu().numpy(), P.p2m_mass(A)) <= 1e-12
+
+
+def test_mass_p2m_solver_path(B):
+    """With P2M_OPT_FFT off the mesh mass system goes through the streaming CG (the path
+    of meshes the FFT does not take): the same result within the solve's bar."""
+    x, y, d = problem(B, "box_20x12")
+    P = oracle_of("box_20x12", x, y)
+    A = np.random.Generator(np.random.PCG64(19)).standard_normal((2, x.size))
+    ctx = B.Context(0)
+    try:
+        ctx.set_fft(False)
+        say("[x2d] mass P2M by CG")
+        out, rep = B.p2m_x2d_assign(ctx, d, B.X1D_MASS, torch.tensor(A, device="cuda"))
+        r = B.read_report(rep, 2)
+    finally:
+        ctx.close()
+    assert r.flags == 0 and (r.iters > 0).all()
+    assert rel_l2(out.cpu().numpy(), P.p2m_mass(A)) <= 1e-11
