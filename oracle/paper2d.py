@@ -142,6 +142,45 @@ def local_star(x, y, lx, ly, mu, radius):
     return [(int(ids[v]), int(sxs[v]), int(sys_[v])) for v in order]
 
 
+def local_interpolant(x, y, lx, ly, values, qx, qy, radius):
+    """The particle interpolant of eq. (1) at one point (qx, qy) from the Delaunay
+    triangulation of the particles within ``radius`` of it (every periodic image), or
+    None when the patch is too small to decide (the triangle holding the point has a
+    circle reaching beyond the patch, so a point outside could lie inside it)."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    ids, px, py = [], [], []
+    for sy in (-1, 0, 1):
+        for sx in (-1, 0, 1):
+            dx = x + sx * lx - qx
+            dy = y + sy * ly - qy
+            keep = dx * dx + dy * dy <= radius * radius
+            ids.append(np.nonzero(keep)[0])
+            px.append(dx[keep])
+            py.append(dy[keep])
+    ids = np.concatenate(ids)
+    pts = np.stack([np.concatenate(px), np.concatenate(py)], axis=1)
+    d = Delaunay(pts)
+    s = int(d.find_simplex(np.zeros((1, 2)))[0])
+    if s < 0:
+        return None
+    t = d.simplices[s]
+    P = pts[t]
+    a = P[1] - P[0]
+    b = P[2] - P[0]
+    den = 2.0 * (a[0] * b[1] - a[1] * b[0])
+    ux = (b[1] * (a @ a) - a[1] * (b @ b)) / den
+    uy = (a[0] * (b @ b) - b[0] * (a @ a)) / den
+    cx, cy = P[0][0] + ux, P[0][1] + uy
+    if np.hypot(cx, cy) + np.hypot(ux, uy) > radius:
+        return None
+    T = d.transform[s]
+    l12 = T[:2, :] @ (np.zeros(2) - T[2, :])
+    lam = np.array([l12[0], l12[1], 1.0 - l12.sum()])
+    values = np.atleast_2d(np.asarray(values, dtype=np.float64))
+    return (values[:, ids[t]] * lam).sum(axis=1)
+
+
 def triangle_vertices(x, y, lx, ly, tri, sh):
     """Unrolled vertex coordinates [T, 3] (X, Y) of the triangles."""
     X = np.asarray(x, dtype=np.float64)[tri] + sh[..., 0] * lx

@@ -326,3 +326,25 @@ def test_mass_p2m_solver_path(B):
         ctx.close()
     assert r.flags == 0 and (r.iters > 0).all()
     assert rel_l2(out.cpu().numpy(), P.p2m_mass(A)) <= 1e-11
+
+
+def test_large_delta_sampled(B, ctx):
+    """delta P2M at 512 x 512 with 4 particles per cell (1,048,576 particles, the walk
+    from the nearest particle over a large triangulation): 100 sampled nodes equal the
+    oracle's particle interpolant computed from a Delaunay patch around each node."""
+    n, ppc = 512, 4
+    say(f"[x2d] large delta {n}^2 x {ppc}")
+    x, y = wl.stratified_2d(31, n, n, ppc, 1.0, 1.0)
+    d = B.Particles(dim=2, nx=n, ny=n, lx=1.0, ly=1.0,
+                    x=torch.tensor(x, device="cuda"), y=torch.tensor(y, device="cuda"))
+    A = np.sin(2 * np.pi * x) * np.cos(4 * np.pi * y) + 0.1 * np.random.Generator(
+        np.random.PCG64(32)).standard_normal(x.size)
+    out, rep = B.p2m_x2d_assign(ctx, d, B.X1D_DELTA, torch.tensor(A[None], device="cuda"))
+    assert B.read_report(rep, 1).flags == 0
+    out = out.cpu().numpy()[0]
+    g = np.random.Generator(np.random.PCG64(33))
+    for node in g.choice(n * n, 100, replace=False):
+        j, i = divmod(int(node), n)
+        want = p2.local_interpolant(x, y, 1.0, 1.0, A, i / n, j / n, 8.0 / n)
+        assert want is not None
+        assert abs(out[node] - want[0]) <= 1e-12 * max(1.0, abs(want[0])), (node, out[node], want)

@@ -248,3 +248,18 @@ def test_local_star_matches_periodic_triangulation():
             ax, ay = x[i0] + sx0 - x[mu], y[i0] + sy0 - y[mu]
             bx, by = x[i1] + sx1 - x[mu], y[i1] + sy1 - y[mu]
             assert ax * by - ay * bx > 0
+
+
+def test_local_interpolant_matches_full_interpolant():
+    """The one-point patch form gives the full periodic interpolant's value."""
+    x, y = wl.stratified_2d(16, 12, 12, 2, 1.0, 1.0)
+    interp = p2.ParticleInterpolant(x, y, 1.0, 1.0)
+    g = np.random.Generator(np.random.PCG64(5))
+    A = g.standard_normal((2, x.size))
+    qx = g.uniform(0, 1.0, 40)
+    qy = g.uniform(0, 1.0, 40)
+    full = interp(A, qx, qy)
+    for q in range(qx.size):
+        v = p2.local_interpolant(x, y, 1.0, 1.0, A, qx[q], qy[q], 0.4)
+        assert v is not None
+        np.testing.assert_allclose(v, full[:, q], rtol=1e-12, atol=1e-13)
