@@ -103,6 +103,16 @@ __device__ __forceinline__ bool before_cand(const Cand& a, const Cand& b) {
     return a.q != b.q ? a.q < b.q : a.s < b.s;
 }
 
+// a found candidate before the wrap's best so far: one lane per particle scans in a
+// fixed order, and equal keys there mean four points on one circle (a triangulation
+// that is not unique), so the first found stands; a group breaks ties as above so
+// that its winner does not depend on how the cells were dealt to its lanes
+template <int G>
+__device__ __forceinline__ bool before_wrap(const Cand& a, const Cand& b) {
+    if constexpr (G == 1) return b.q < 0 || a.n * b.d < b.n * a.d;
+    return before_cand(a, b);
+}
+
 template <int G>
 __device__ __forceinline__ Cand group_min(Cand v) {
 #pragma unroll
@@ -230,7 +240,7 @@ __global__ __launch_bounds__(kB) void k_x2d_star(Geo g, const double* __restrict
                 f.vy = ry;
                 f.q = q;
                 f.s = sh;
-                if (before_cand(f, e)) e = f;
+                if (before_wrap<G>(f, e)) e = f;
             });
             e = group_min<G>(e);
             if (e.q < 0) break;   // nothing on the left: the cell is open at this radius
